@@ -1,0 +1,929 @@
+/* FP64 oracle: element derivatives and the VBD time step (test infrastructure).
+ *
+ * Compiled twice: with OR_COMPLEX=0 (real, public names) and OR_COMPLEX=1
+ * (double complex, names with suffix _cs) for complex-step derivatives.
+ * Branches (pivoting, clamps, contact activity, skip test) are decided on real
+ * parts so the complex build stays analytic in its inputs.
+ *
+ * Element derivatives take the textbook route: Psi(F) -> P = dPsi/dF ->
+ * d2Psi/dF2 (9x9), contracted with dF/dx_k = m_k (x) I.  No closed-form
+ * shortcut is used here.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "vbd_oracle.h"
+
+#if OR_COMPLEX
+typedef double _Complex R;
+#define RE(a) creal(a)
+#define RSQRT(a) csqrt(a)
+#define FN(n) n##_cs
+#else
+typedef double R;
+#define RE(a) (a)
+#define RSQRT(a) sqrt(a)
+#define FN(n) n
+#endif
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const int LC[3][3][3] = {  /* Levi-Civita symbol */
+    {{0, 0, 0}, {0, 0, 1}, {0, -1, 0}},
+    {{0, 0, -1}, {0, 0, 0}, {1, 0, 0}},
+    {{0, 1, 0}, {-1, 0, 0}, {0, 0, 0}},
+};
+
+/* ---------------------------------------------------------------------------
+ * Stable Neo-Hookean tet without the logarithmic term (Sec. 5, citing Smith
+ * et al. 2018):  Psi = mu/2 (tr F^T F - 3) + lam/2 (J - alpha)^2,
+ * alpha = 1 + mu/lam, J = det F, F = D_s Dm^{-1}.  Element energy V * Psi.
+ * Lame parameters from (E, nu) by the textbook conversion.
+ * ------------------------------------------------------------------------- */
+static void lame_R(R E, double nu, R *mu, R *lam)
+{
+    *mu = E / (2.0 * (1.0 + nu));
+    *lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+}
+
+/* m_l = gradient of the barycentric shape function of vertex l:
+ * m_1..m_3 = rows of Dm^{-1}, m_0 = -(m_1 + m_2 + m_3), so F = sum_l x_l m_l^T. */
+static void shape_grads(const double B[9], double m[4][3])
+{
+    for (int b = 0; b < 3; ++b) {
+        m[1][b] = B[0 * 3 + b];
+        m[2][b] = B[1 * 3 + b];
+        m[3][b] = B[2 * 3 + b];
+        m[0][b] = -(m[1][b] + m[2][b] + m[3][b]);
+    }
+}
+
+static void tet_F(const R x[4][3], const double B[9], R F[3][3])
+{
+    /* F = D_s B with D_s = [x1-x0, x2-x0, x3-x0] (columns) */
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            R s = 0;
+            for (int c = 0; c < 3; ++c) s += (x[c + 1][a] - x[0][a]) * B[c * 3 + b];
+            F[a][b] = s;
+        }
+}
+
+static R det3(const R F[3][3])
+{
+    R s = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+                if (LC[i][j][k]) s += LC[i][j][k] * F[0][i] * F[1][j] * F[2][k];
+    return s;
+}
+
+/* cofactor matrix: cof_ab = 1/2 eps_acd eps_bef F_ce F_df  (= dJ/dF_ab) */
+static void cof3(const R F[3][3], R C[3][3])
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            R s = 0;
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) {
+                    if (!LC[a][c][d]) continue;
+                    for (int e = 0; e < 3; ++e)
+                        for (int f = 0; f < 3; ++f)
+                            if (LC[b][e][f]) s += 0.5 * LC[a][c][d] * LC[b][e][f] * F[c][e] * F[d][f];
+                }
+            C[a][b] = s;
+        }
+}
+
+static R psi_R(const R F[3][3], R mu, R lam)
+{
+    R alpha = 1.0 + mu / lam;
+    R Ic = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Ic += F[a][b] * F[a][b];
+    R J = det3(F);
+    return 0.5 * mu * (Ic - 3.0) + 0.5 * lam * (J - alpha) * (J - alpha);
+}
+
+/* P = dPsi/dF = mu F + lam (J - alpha) cof(F) */
+static void P_of_F(const R F[3][3], R mu, R lam, R P[3][3])
+{
+    R alpha = 1.0 + mu / lam;
+    R C[3][3];
+    cof3(F, C);
+    R J = det3(F);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) P[a][b] = mu * F[a][b] + lam * (J - alpha) * C[a][b];
+}
+
+/* D[ab][ce] = d2Psi/dF_ab dF_ce
+ *           = mu d_ac d_be + lam cof_ab cof_ce + lam (J-alpha) dcof_ab/dF_ce,
+ * dcof_ab/dF_ce = sum_df eps_acd eps_bef F_df. */
+static void dPdF(const R F[3][3], R mu, R lam, R D[9][9])
+{
+    R alpha = 1.0 + mu / lam;
+    R C[3][3];
+    cof3(F, C);
+    R J = det3(F);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c)
+                for (int e = 0; e < 3; ++e) {
+                    R dc = 0;
+                    for (int d = 0; d < 3; ++d)
+                        for (int f = 0; f < 3; ++f)
+                            if (LC[a][c][d] && LC[b][e][f]) dc += LC[a][c][d] * LC[b][e][f] * F[d][f];
+                    R v = lam * C[a][b] * C[c][e] + lam * (J - alpha) * dc;
+                    if (a == c && b == e) v += mu;
+                    D[a * 3 + b][c * 3 + e] = v;
+                }
+}
+
+/* gradient dE/dx_k and Hessian block d2E/dx_k dx_l of one tet */
+static void tet_grad_k(const R F[3][3], const double m[4][3], double vol, R mu, R lam,
+                       int k, R g[3])
+{
+    R P[3][3];
+    P_of_F(F, mu, lam, P);
+    for (int c = 0; c < 3; ++c) {
+        R s = 0;
+        for (int b = 0; b < 3; ++b) s += P[c][b] * m[k][b];
+        g[c] = vol * s;
+    }
+}
+
+static void tet_hess_kl(const R D[9][9], const double m[4][3], double vol, int k, int l,
+                        R Hb[3][3])
+{
+    for (int c = 0; c < 3; ++c)
+        for (int e = 0; e < 3; ++e) {
+            R s = 0;
+            for (int b = 0; b < 3; ++b)
+                for (int f = 0; f < 3; ++f) s += D[c * 3 + b][e * 3 + f] * m[k][b] * m[l][f];
+            Hb[c][e] = vol * s;
+        }
+}
+
+/* ---------------------------------------------------------------------------
+ * Linear spring E = k/2 (l - L)^2, l = |x_a - x_b| (Sec. 5, Sec. 6.1).
+ * dl/dx_a = d/l, d2l/dx_a2 = (I - d d^T / l^2) / l.
+ * ------------------------------------------------------------------------- */
+static void spring_block(const R xa[3], const R xb[3], double L, double k, R g[3], R Hb[3][3])
+{
+    R d[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
+    R l = RSQRT(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    R u[3] = {d[0] / l, d[1] / l, d[2] / l};
+    for (int a = 0; a < 3; ++a) g[a] = k * (l - L) * u[a];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            R d2l = ((a == b ? 1.0 : 0.0) - u[a] * u[b]) / l;
+            Hb[a][b] = k * (u[a] * u[b] + (l - L) * d2l);
+        }
+}
+
+/* ---------------------------------------------------------------------------
+ * Gaussian elimination with partial pivoting on a 3x3 system.  Returns det(A)
+ * (product of pivots with the permutation sign); x is valid when det != 0.
+ * ------------------------------------------------------------------------- */
+static R solve3(const R Ain[3][3], const R bin[3], R x[3])
+{
+    R A[3][4];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) A[r][c] = Ain[r][c];
+        A[r][3] = bin[r];
+    }
+    R det = 1.0;
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(RE(A[r][col])) > fabs(RE(A[piv][col]))) piv = r;
+        if (piv != col) {
+            for (int c = 0; c < 4; ++c) { R t = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = t; }
+            det = -det;
+        }
+        det *= A[col][col];
+        if (RE(A[col][col]) == 0.0) { x[0] = x[1] = x[2] = 0; return 0.0; }
+        for (int r = col + 1; r < 3; ++r) {
+            R fct = A[r][col] / A[col][col];
+            for (int c = col; c < 4; ++c) A[r][c] -= fct * A[col][c];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        R s = A[r][3];
+        for (int c = r + 1; c < 3; ++c) s -= A[r][c] * x[c];
+        x[r] = s / A[r][r];
+    }
+    return det;
+}
+
+/* skip rule of Sec. 3.2: |det H| <= eps, with eps = det_eps_rel * ||H||_F^3 */
+static int skip_solve(const R H[3][3], R det, double eps_rel)
+{
+    double fn = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) fn += RE(H[a][b]) * RE(H[a][b]);
+    fn = sqrt(fn);
+    return fabs(RE(det)) <= eps_rel * fn * fn * fn;
+}
+
+/* ---------------------------------------------------------------------------
+ * Incidence lists: for each vertex the incident tets (tet, slot) and springs
+ * (spring, other end), each in ascending element id.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t *tet_row, *tet_ent;   /* ent = tet*4 + slot */
+    int32_t *spr_row, *spr_ent;   /* ent = spring*2 + end */
+} Inc;
+
+static void inc_build(const oracle_model *M, Inc *ic)
+{
+    int nv = M->n_verts;
+    ic->tet_row = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    ic->spr_row = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int t = 0; t < M->n_tets; ++t)
+        for (int s = 0; s < 4; ++s) ic->tet_row[M->tets[t * 4 + s] + 1]++;
+    for (int e = 0; e < M->n_springs; ++e)
+        for (int s = 0; s < 2; ++s) ic->spr_row[M->springs[e * 2 + s] + 1]++;
+    for (int i = 0; i < nv; ++i) {
+        ic->tet_row[i + 1] += ic->tet_row[i];
+        ic->spr_row[i + 1] += ic->spr_row[i];
+    }
+    ic->tet_ent = (int32_t *)malloc(sizeof(int32_t) * ((size_t)ic->tet_row[nv] + 1));
+    ic->spr_ent = (int32_t *)malloc(sizeof(int32_t) * ((size_t)ic->spr_row[nv] + 1));
+    int32_t *fill = (int32_t *)calloc((size_t)nv, sizeof(int32_t));
+    for (int t = 0; t < M->n_tets; ++t)
+        for (int s = 0; s < 4; ++s) {
+            int v = M->tets[t * 4 + s];
+            ic->tet_ent[ic->tet_row[v] + fill[v]++] = t * 4 + s;
+        }
+    memset(fill, 0, sizeof(int32_t) * (size_t)nv);
+    for (int e = 0; e < M->n_springs; ++e)
+        for (int s = 0; s < 2; ++s) {
+            int v = M->springs[e * 2 + s];
+            ic->spr_ent[ic->spr_row[v] + fill[v]++] = e * 2 + s;
+        }
+    free(fill);
+}
+
+static void inc_free(Inc *ic)
+{
+    free(ic->tet_row); free(ic->tet_ent); free(ic->spr_row); free(ic->spr_ent);
+}
+
+/* ---------------------------------------------------------------------------
+ * Local system of vertex i (Eq. VBDForce / VBDHessian, damping Eq.
+ * VBDForceWithDamping / VBDHessianWithDamping on material elements,
+ * penalty contact Eq. collisionEnergy with the normal held fixed, IPC-style
+ * friction Eq. IPC_friction with the approximate Hessian).
+ * xi_over: optional replacement of x_i (used to evaluate after an update).
+ * ------------------------------------------------------------------------- */
+static void local_system(const oracle_model *M, const oracle_params *P, const Inc *ic, int i,
+                         const R *x, const R *xi_over, const R *y, const R *xt, const R *E,
+                         R f[3], R H[3][3], int *in_contact)
+{
+    const double h = P->h;
+    const double mh2 = M->mass[i] / (h * h);
+    R xi[3];
+    for (int a = 0; a < 3; ++a) xi[a] = xi_over ? xi_over[a] : x[3 * i + a];
+    for (int a = 0; a < 3; ++a) {
+        f[a] = -mh2 * (xi[a] - y[3 * i + a]);
+        for (int b = 0; b < 3; ++b) H[a][b] = (a == b) ? mh2 : 0.0;
+    }
+    const double kdh = P->kd / h;
+    for (int e = ic->tet_row[i]; e < ic->tet_row[i + 1]; ++e) {
+        int t = ic->tet_ent[e] >> 2, k = ic->tet_ent[e] & 3;
+        R xl[4][3];
+        for (int l = 0; l < 4; ++l) {
+            int vl = M->tets[t * 4 + l];
+            for (int a = 0; a < 3; ++a) xl[l][a] = (vl == i) ? xi[a] : x[3 * vl + a];
+        }
+        double m[4][3];
+        shape_grads(M->Dminv + 9 * t, m);
+        R F[3][3], D[9][9], g[3], Hb[3][3], mu, lam;
+        lame_R(E[t], M->nu, &mu, &lam);
+        tet_F((const R(*)[3])xl, M->Dminv + 9 * t, F);
+        tet_grad_k((const R(*)[3])F, (const double(*)[3])m, M->vol[t], mu, lam, k, g);
+        dPdF((const R(*)[3])F, mu, lam, D);
+        tet_hess_kl((const R(*)[9])D, (const double(*)[3])m, M->vol[t], k, k, Hb);
+        for (int a = 0; a < 3; ++a) {
+            f[a] -= g[a];
+            for (int b = 0; b < 3; ++b) H[a][b] += Hb[a][b];
+        }
+        if (P->kd != 0.0) {
+            for (int a = 0; a < 3; ++a) {
+                R s = 0;
+                for (int b = 0; b < 3; ++b) s += Hb[a][b] * (xi[b] - xt[3 * i + b]);
+                f[a] -= kdh * s;
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) H[a][b] += kdh * Hb[a][b];
+        }
+    }
+    for (int e = ic->spr_row[i]; e < ic->spr_row[i + 1]; ++e) {
+        int s = ic->spr_ent[e] >> 1, end = ic->spr_ent[e] & 1;
+        int o = M->springs[2 * s + (1 - end)];
+        R xo[3] = {x[3 * o], x[3 * o + 1], x[3 * o + 2]};
+        R g[3], Hb[3][3];
+        spring_block(xi, xo, M->spring_rest[s], M->spring_k, g, Hb);
+        for (int a = 0; a < 3; ++a) {
+            f[a] -= g[a];
+            for (int b = 0; b < 3; ++b) H[a][b] += Hb[a][b];
+        }
+        if (P->kd != 0.0) {
+            for (int a = 0; a < 3; ++a) {
+                R sm = 0;
+                for (int b = 0; b < 3; ++b) sm += Hb[a][b] * (xi[b] - xt[3 * i + b]);
+                f[a] -= kdh * sm;
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) H[a][b] += kdh * Hb[a][b];
+        }
+    }
+    /* contacts against analytic spheres and planes, at the current iterate */
+    int nobs = P->n_spheres + P->n_planes;
+    for (int o = 0; o < nobs; ++o) {
+        R n[3], pen;
+        if (o < P->n_spheres) {
+            const double *s = P->spheres + 4 * o;
+            R r[3] = {xi[0] - s[0], xi[1] - s[1], xi[2] - s[2]};
+            R dist = RSQRT(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            for (int a = 0; a < 3; ++a) n[a] = r[a] / dist;
+            pen = s[3] + P->contact_thickness - dist;
+        } else {
+            const double *pl = P->planes + 4 * (o - P->n_spheres);
+            for (int a = 0; a < 3; ++a) n[a] = pl[a];
+            pen = P->contact_thickness - (pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] - pl[3]);
+        }
+        if (!(RE(pen) > 0.0)) continue;
+        *in_contact = 1;
+        /* E_c = 1/2 k_c pen^2 with pen = (x_b - x_i).n and n fixed:
+         * dE/dx_i = -k_c pen n, d2E/dx_i2 = k_c n n^T */
+        for (int a = 0; a < 3; ++a) {
+            f[a] += P->contact_k * pen * n[a];
+            for (int b = 0; b < 3; ++b) H[a][b] += P->contact_k * n[a] * n[b];
+        }
+        if (P->friction_mu > 0.0) {
+            /* relative tangential displacement u = (I - n n^T)(x_i - x_i^t)
+             * (the obstacle is static); lambda = contact force magnitude */
+            R dx[3] = {xi[0] - xt[3 * i], xi[1] - xt[3 * i + 1], xi[2] - xt[3 * i + 2]};
+            R dn = dx[0] * n[0] + dx[1] * n[1] + dx[2] * n[2];
+            R u[3] = {dx[0] - dn * n[0], dx[1] - dn * n[1], dx[2] - dn * n[2]};
+            R un = RSQRT(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            double hev = h * P->friction_eps_v;
+            R f1_over_u; /* f1(u)/u, f1 as in Eq. IPC_friction */
+            if (RE(un) < hev) f1_over_u = 2.0 / hev - un / (hev * hev);
+            else f1_over_u = 1.0 / un;
+            R lamc = P->contact_k * pen;
+            R s = P->friction_mu * lamc * f1_over_u;
+            for (int a = 0; a < 3; ++a) {
+                f[a] -= s * u[a];
+                for (int b = 0; b < 3; ++b) H[a][b] += s * ((a == b ? 1.0 : 0.0) - n[a] * n[b]);
+            }
+        }
+    }
+}
+
+/* variational energy G (Eq. VariantionalFormOfImplicitEuler); grad/hess optional */
+static double energy_G_impl(const oracle_model *M, const oracle_params *P, const R *x,
+                            const R *y, const R *E, double *grad, double *hess)
+{
+    const int nv = M->n_verts, n3 = 3 * nv;
+    const double h2 = P->h * P->h;
+    double G = 0;
+    if (grad) memset(grad, 0, sizeof(double) * (size_t)n3);
+    if (hess) memset(hess, 0, sizeof(double) * (size_t)n3 * (size_t)n3);
+    for (int i = 0; i < nv; ++i) {
+        if (M->pinned[i]) continue;
+        double mh2 = M->mass[i] / h2;
+        for (int a = 0; a < 3; ++a) {
+            double d = RE(x[3 * i + a]) - RE(y[3 * i + a]);
+            G += 0.5 * mh2 * d * d;
+            if (grad) grad[3 * i + a] += mh2 * d;
+            if (hess) hess[(size_t)(3 * i + a) * n3 + 3 * i + a] += mh2;
+        }
+    }
+    for (int t = 0; t < M->n_tets; ++t) {
+        R xl[4][3];
+        for (int l = 0; l < 4; ++l)
+            for (int a = 0; a < 3; ++a) xl[l][a] = RE(x[3 * M->tets[4 * t + l] + a]);
+        R F[3][3], mu, lam;
+        lame_R(RE(E[t]), M->nu, &mu, &lam);
+        tet_F((const R(*)[3])xl, M->Dminv + 9 * t, F);
+        G += M->vol[t] * RE(psi_R((const R(*)[3])F, mu, lam));
+        if (grad || hess) {
+            double m[4][3];
+            shape_grads(M->Dminv + 9 * t, m);
+            R D[9][9];
+            dPdF((const R(*)[3])F, mu, lam, D);
+            for (int k = 0; k < 4; ++k) {
+                int vk = M->tets[4 * t + k];
+                if (grad) {
+                    R g[3];
+                    tet_grad_k((const R(*)[3])F, (const double(*)[3])m, M->vol[t], mu, lam, k, g);
+                    for (int a = 0; a < 3; ++a) grad[3 * vk + a] += RE(g[a]);
+                }
+                if (hess)
+                    for (int l = 0; l < 4; ++l) {
+                        int vl = M->tets[4 * t + l];
+                        R Hb[3][3];
+                        tet_hess_kl((const R(*)[9])D, (const double(*)[3])m, M->vol[t], k, l, Hb);
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b)
+                                hess[(size_t)(3 * vk + a) * n3 + 3 * vl + b] += RE(Hb[a][b]);
+                    }
+            }
+        }
+    }
+    for (int s = 0; s < M->n_springs; ++s) {
+        int va = M->springs[2 * s], vb = M->springs[2 * s + 1];
+        R xa[3], xb[3];
+        for (int a = 0; a < 3; ++a) { xa[a] = RE(x[3 * va + a]); xb[a] = RE(x[3 * vb + a]); }
+        R d[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
+        double l = sqrt(RE(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+        G += 0.5 * M->spring_k * (l - M->spring_rest[s]) * (l - M->spring_rest[s]);
+        if (grad || hess) {
+            R g[3], Hb[3][3];
+            spring_block(xa, xb, M->spring_rest[s], M->spring_k, g, Hb);
+            for (int a = 0; a < 3; ++a) {
+                if (grad) { grad[3 * va + a] += RE(g[a]); grad[3 * vb + a] -= RE(g[a]); }
+                if (hess)
+                    for (int b = 0; b < 3; ++b) {
+                        double v = RE(Hb[a][b]);
+                        hess[(size_t)(3 * va + a) * n3 + 3 * va + b] += v;
+                        hess[(size_t)(3 * vb + a) * n3 + 3 * vb + b] += v;
+                        hess[(size_t)(3 * va + a) * n3 + 3 * vb + b] -= v;
+                        hess[(size_t)(3 * vb + a) * n3 + 3 * va + b] -= v;
+                    }
+            }
+        }
+    }
+    int nobs = P->n_spheres + P->n_planes;
+    for (int i = 0; i < nv && nobs > 0; ++i) {
+        if (M->pinned[i]) continue;
+        double xi[3] = {RE(x[3 * i]), RE(x[3 * i + 1]), RE(x[3 * i + 2])};
+        for (int o = 0; o < nobs; ++o) {
+            double n[3], pen;
+            if (o < P->n_spheres) {
+                const double *s = P->spheres + 4 * o;
+                double r[3] = {xi[0] - s[0], xi[1] - s[1], xi[2] - s[2]};
+                double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                for (int a = 0; a < 3; ++a) n[a] = r[a] / dist;
+                pen = s[3] + P->contact_thickness - dist;
+            } else {
+                const double *pl = P->planes + 4 * (o - P->n_spheres);
+                for (int a = 0; a < 3; ++a) n[a] = pl[a];
+                pen = P->contact_thickness - (pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] - pl[3]);
+            }
+            if (!(pen > 0.0)) continue;
+            G += 0.5 * P->contact_k * pen * pen;
+            for (int a = 0; a < 3; ++a) {
+                if (grad) grad[3 * i + a] -= P->contact_k * pen * n[a];
+                if (hess)
+                    for (int b = 0; b < 3; ++b)
+                        hess[(size_t)(3 * i + a) * n3 + 3 * i + b] += P->contact_k * n[a] * n[b];
+            }
+        }
+    }
+    return G;
+}
+
+/* y = x^t + h v^t + h^2 a_ext (Eq. inertia) */
+static void predict_R(const oracle_model *M, const oracle_params *P, const R *x, const R *v, R *y)
+{
+    const double h = P->h;
+    for (int i = 0; i < M->n_verts; ++i)
+        for (int a = 0; a < 3; ++a)
+            y[3 * i + a] = x[3 * i + a] + h * v[3 * i + a] + h * h * P->gravity[a];
+}
+
+/* Initial guess (Sec. 3.7): options (a) previous position, (b) inertia,
+ * (c) inertia and acceleration (= y), (d) adaptive.  Pinned vertices: x^t.
+ * For (d), a_t = (v^t - v^{t-1})/h, a_ext^t = a_t . a_hat, and the factor
+ * a~ = 1 if a_ext^t > |a_ext|, 0 if a_ext^t < 0, a_ext^t/|a_ext| otherwise. */
+static void init_R(const oracle_model *M, const oracle_params *P, const R *xt, const R *v,
+                   const R *vp, const R *y, R *x)
+{
+    const double h = P->h;
+    const double *g = P->gravity;
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int i = 0; i < M->n_verts; ++i) {
+        for (int a = 0; a < 3; ++a) x[3 * i + a] = xt[3 * i + a];
+        if (M->pinned[i]) continue;
+        switch (P->init_mode) {
+        case OR_INIT_PREV:
+            break;
+        case OR_INIT_INERTIA:
+            for (int a = 0; a < 3; ++a) x[3 * i + a] = xt[3 * i + a] + h * v[3 * i + a];
+            break;
+        case OR_INIT_Y:
+            for (int a = 0; a < 3; ++a) x[3 * i + a] = y[3 * i + a];
+            break;
+        default: {
+            R at = 0;
+            if (gn > 0.0)
+                for (int a = 0; a < 3; ++a) at += (v[3 * i + a] - vp[3 * i + a]) / h * (g[a] / gn);
+            R atil;
+            if (gn == 0.0) atil = 0.0;
+            else if (RE(at) > gn) atil = 1.0;
+            else if (RE(at) < 0.0) atil = 0.0;
+            else atil = at / gn;
+            for (int a = 0; a < 3; ++a)
+                x[3 * i + a] = xt[3 * i + a] + h * v[3 * i + a] + h * h * atil * g[a];
+        }
+        }
+    }
+}
+
+static int check_args(const oracle_model *M, const oracle_params *P)
+{
+    if (!M || !P || P->h <= 0.0 || P->n_iters < 0 || M->n_verts < 0) return -1;
+    if (M->n_tets > 0 && (!M->tets || !M->Dminv || !M->vol)) return -1;
+    if (M->n_springs > 0 && (!M->springs || !M->spring_rest)) return -1;
+    if (!M->mass || !M->pinned || !M->colors) return -1;
+    return 0;
+}
+
+/* Chebyshev weights (Eq. accelerator): omega_1 = 1, omega_2 = 2/(2-rho^2),
+ * omega_n = 4/(4 - rho^2 omega_{n-1}). */
+static double cheb_omega(int n, double rho, double prev)
+{
+    if (n <= 1) return 1.0;
+    if (n == 2) return 2.0 / (2.0 - rho * rho);
+    return 4.0 / (4.0 - rho * rho * prev);
+}
+
+/* One VBD time step, following Alg. 1 in order. */
+int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *v, R *vprev,
+                        const R *E, const int32_t *order, double *G_trace,
+                        int32_t track_local_grad, oracle_stats *st)
+{
+    if (check_args(M, P)) return -1;
+    const int nv = M->n_verts, C = M->n_colors;
+    const size_t n3 = 3 * (size_t)nv;
+    Inc inc;
+    inc_build(M, &inc);
+    R *xt = (R *)malloc(sizeof(R) * n3 + 1), *y = (R *)malloc(sizeof(R) * n3 + 1);
+    R *xnew = (R *)malloc(sizeof(R) * n3 + 1);
+    R *pr1 = NULL, *pr2 = NULL;
+    uint8_t *collided = (uint8_t *)calloc((size_t)nv + 1, 1);
+    memcpy(xt, x, sizeof(R) * n3);
+
+    /* vertices of each color in processing order */
+    int32_t *crow = (int32_t *)calloc((size_t)C + 2, sizeof(int32_t));
+    int32_t *clist = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nv + 1));
+    for (int i = 0; i < nv; ++i) crow[M->colors[i] + 1]++;
+    for (int c = 0; c < C; ++c) crow[c + 1] += crow[c];
+    {
+        int32_t *fill = (int32_t *)calloc((size_t)C + 1, sizeof(int32_t));
+        for (int q = 0; q < nv; ++q) {
+            int i = order ? order[q] : q;
+            int c = M->colors[i];
+            clist[crow[c] + fill[c]++] = i;
+        }
+        free(fill);
+    }
+
+    predict_R(M, P, xt, v, y);                       /* Alg. 1: y */
+    init_R(M, P, xt, v, vprev, y, x);                /* Alg. 1: initial guess */
+    memcpy(xnew, x, sizeof(R) * n3);
+    if (P->cheb_rho > 0.0) {
+        pr1 = (R *)malloc(sizeof(R) * n3 + 1);
+        pr2 = (R *)malloc(sizeof(R) * n3 + 1);
+        memcpy(pr1, x, sizeof(R) * n3);
+        memcpy(pr2, x, sizeof(R) * n3);
+    }
+    int64_t n_upd = 0, n_skip = 0, n_con = 0;
+    double max_lg = 0.0, omega = 1.0;
+
+    for (int it = 1; it <= P->n_iters; ++it) {
+        for (int c = 0; c < C; ++c) {
+            const int cb = crow[c], ce = crow[c + 1];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_upd, n_skip, n_con) reduction(max : max_lg)
+#endif
+            for (int q = cb; q < ce; ++q) {
+                int i = clist[q];
+                if (M->pinned[i]) continue;
+                R f[3], H[3][3], dx[3];
+                int con = 0;
+                local_system(M, P, &inc, i, x, NULL, y, xt, E, f, H, &con);
+                if (con) { collided[i] = 1; n_con++; }
+                R det = solve3((const R(*)[3])H, f, dx);
+                n_upd++;
+                if (skip_solve((const R(*)[3])H, det, P->det_eps_rel)) {
+                    n_skip++;
+                    for (int a = 0; a < 3; ++a) xnew[3 * i + a] = x[3 * i + a];
+                    continue;
+                }
+                for (int a = 0; a < 3; ++a) xnew[3 * i + a] = x[3 * i + a] + dx[a];
+                if (track_local_grad) {
+                    R f2[3], H2[3][3];
+                    int con2 = 0;
+                    local_system(M, P, &inc, i, x, xnew + 3 * i, y, xt, E, f2, H2, &con2);
+                    double gmax = 0;
+                    for (int a = 0; a < 3; ++a) gmax = fmax(gmax, fabs(RE(f2[a])));
+                    if (gmax > max_lg) max_lg = gmax;
+                }
+            }
+            /* copy updated positions of this color back (x_new buffer, Sec. 3.9) */
+            for (int q = cb; q < ce; ++q) {
+                int i = clist[q];
+                for (int a = 0; a < 3; ++a) x[3 * i + a] = xnew[3 * i + a];
+            }
+            if (G_trace && !OR_COMPLEX)
+                G_trace[(size_t)(it - 1) * C + c] = energy_G_impl(M, P, x, y, E, NULL, NULL);
+        }
+        if (P->cheb_rho > 0.0) {
+            /* accelerated iteration, skipping vertices that collided in this step */
+            omega = cheb_omega(it, P->cheb_rho, omega);
+            for (int i = 0; i < nv; ++i) {
+                if (M->pinned[i] || collided[i]) continue;
+                for (int a = 0; a < 3; ++a)
+                    x[3 * i + a] = omega * (x[3 * i + a] - pr2[3 * i + a]) + pr2[3 * i + a];
+            }
+            memcpy(pr2, pr1, sizeof(R) * n3);
+            memcpy(pr1, x, sizeof(R) * n3);
+            memcpy(xnew, x, sizeof(R) * n3);
+        }
+    }
+    /* Eq. velocity_update; the state's previous velocity becomes v^t */
+    for (size_t q = 0; q < n3; ++q) {
+        R vn = (x[q] - xt[q]) / P->h;
+        vprev[q] = v[q];
+        v[q] = vn;
+    }
+    if (st) {
+        st->n_updates += n_upd;
+        st->n_skips += n_skip;
+        st->n_contacts += n_con;
+        if (max_lg > st->max_local_grad) st->max_local_grad = max_lg;
+    }
+    free(xt); free(y); free(xnew); free(pr1); free(pr2); free(collided);
+    free(crow); free(clist);
+    inc_free(&inc);
+    return 0;
+}
+
+#if !OR_COMPLEX
+/* ------------------------------- real-only API ---------------------------- */
+void oracle_lame(double E, double nu, double *mu, double *lam) { lame_R(E, nu, mu, lam); }
+
+double oracle_tet_energy(const double x[12], const double Dminv[9], double vol, double mu,
+                         double lam)
+{
+    double xl[4][3], F[3][3];
+    memcpy(xl, x, sizeof(xl));
+    tet_F((const double(*)[3])xl, Dminv, F);
+    return vol * psi_R((const double(*)[3])F, mu, lam);
+}
+
+void oracle_tet_derivs(const double x[12], const double Dminv[9], double vol, double mu,
+                       double lam, double grad[12], double hess[144])
+{
+    double xl[4][3], F[3][3], D[9][9], m[4][3];
+    memcpy(xl, x, sizeof(xl));
+    shape_grads(Dminv, m);
+    tet_F((const double(*)[3])xl, Dminv, F);
+    dPdF((const double(*)[3])F, mu, lam, D);
+    for (int k = 0; k < 4; ++k) {
+        tet_grad_k((const double(*)[3])F, (const double(*)[3])m, vol, mu, lam, k, grad + 3 * k);
+        for (int l = 0; l < 4; ++l) {
+            double Hb[3][3];
+            tet_hess_kl((const double(*)[9])D, (const double(*)[3])m, vol, k, l, Hb);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) hess[(3 * k + a) * 12 + 3 * l + b] = Hb[a][b];
+        }
+    }
+}
+
+double oracle_spring_energy(const double xa[3], const double xb[3], double L, double k)
+{
+    double d[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
+    double l = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    return 0.5 * k * (l - L) * (l - L);
+}
+
+void oracle_spring_derivs(const double xa[3], const double xb[3], double L, double k,
+                          double grad[6], double hess[36])
+{
+    double g[3], Hb[3][3];
+    spring_block(xa, xb, L, k, g, Hb);
+    for (int a = 0; a < 3; ++a) {
+        grad[a] = g[a];
+        grad[3 + a] = -g[a];
+        for (int b = 0; b < 3; ++b) {
+            hess[a * 6 + b] = Hb[a][b];
+            hess[(3 + a) * 6 + 3 + b] = Hb[a][b];
+            hess[a * 6 + 3 + b] = -Hb[a][b];
+            hess[(3 + a) * 6 + b] = -Hb[a][b];
+        }
+    }
+}
+
+void oracle_predict(const oracle_model *M, const oracle_params *P, const double *x,
+                    const double *v, double *y)
+{
+    predict_R(M, P, x, v, y);
+}
+
+double oracle_energy_G(const oracle_model *M, const oracle_params *P, const double *x,
+                       const double *y, const double *tet_E, double *grad, double *hess)
+{
+    return energy_G_impl(M, P, x, y, tet_E, grad, hess);
+}
+
+/* d2J/dx_k dx_l: (M_kl)_ac = sum_b,e (m_k)_b (m_l)_e dcof_ab/dF_ce,
+ * with dcof_ab/dF_ce = sum_df eps_acd eps_bef F_df. */
+static void d2J_kl(const double F[3][3], const double m[4][3], int k, int l, double Mk[3][3])
+{
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int b = 0; b < 3; ++b)
+                for (int e = 0; e < 3; ++e) {
+                    double dc = 0;
+                    for (int d = 0; d < 3; ++d)
+                        for (int f = 0; f < 3; ++f)
+                            if (LC[a][c][d] && LC[b][e][f]) dc += LC[a][c][d] * LC[b][e][f] * F[d][f];
+                    s += m[k][b] * m[l][e] * dc;
+                }
+            Mk[a][c] = s;
+        }
+}
+
+/* Reverse mode of one step, explicit form.  Each local update is
+ *   x_i' = x_i + D,  D = H_i^{-1} f_i,
+ * with f_i, H_i evaluated at the state before the color pass.  For an input z,
+ *   dD = H^{-1} (df/dz - dH/dz D) dz,
+ * so with w = H^{-1} xbar_i:  zbar += (df/dz)^T w - (dH/dz : w D^T).
+ * For a tet with vertex i in slot k:
+ *   df/dx_i = -H_i, dH_i/dx_i = 0 (J is affine in x_k, so c_k = cof(F) m_k
+ *   does not depend on x_k),
+ *   df/dx_j = -K_kj,  dH/dx_j : w D^T = V lam [(c.D) M^T w + (c.w) M^T D]
+ *   with c = c_k, M = d2J/dx_k dx_j  (H_kk = V(mu |m_k|^2 I + lam c c^T)),
+ *   df/dy_i = m/h^2 I,  df/dE_t = -grad_k U_t / E_t,  dH/dE_t = H_t,kk / E_t.
+ * Then the adjoints of the initial guess and of y are applied. */
+int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, const double *x_t,
+                             const double *v_t, const double *v_prev, const double *E,
+                             const double *gx_out, const double *gv_out, const double *gvp_out,
+                             double *gx_in, double *gv_in, double *gvp_in, double *g_E)
+{
+    if (check_args(M, P)) return -1;
+    if (M->n_springs > 0 || P->n_spheres > 0 || P->n_planes > 0 || P->kd != 0.0 ||
+        P->cheb_rho > 0.0)
+        return -2;
+    const int nv = M->n_verts, C = M->n_colors, N = P->n_iters;
+    const size_t n3 = 3 * (size_t)nv;
+    const double h = P->h;
+    Inc inc;
+    inc_build(M, &inc);
+    double *S = (double *)malloc(sizeof(double) * n3 * (size_t)(N + 1) + 8);
+    double *y = (double *)malloc(sizeof(double) * n3 + 8);
+    double *x = (double *)malloc(sizeof(double) * n3 + 8);
+    double *xnew = (double *)malloc(sizeof(double) * n3 + 8);
+    double *cur = (double *)malloc(sizeof(double) * n3 + 8);
+    double *xb = (double *)calloc(n3 + 1, sizeof(double));
+    double *yb = (double *)calloc(n3 + 1, sizeof(double));
+    double *xtb = (double *)calloc(n3 + 1, sizeof(double));
+    double *vb = (double *)calloc(n3 + 1, sizeof(double));
+    double *vpb = (double *)calloc(n3 + 1, sizeof(double));
+
+    /* forward recompute with a snapshot after every iteration */
+    predict_R(M, P, x_t, v_t, y);
+    init_R(M, P, x_t, v_t, v_prev, y, x);
+    memcpy(S, x, sizeof(double) * n3);
+    memcpy(xnew, x, sizeof(double) * n3);
+    for (int it = 1; it <= N; ++it) {
+        for (int c = 0; c < C; ++c) {
+            for (int i = 0; i < nv; ++i) {
+                if (M->colors[i] != c || M->pinned[i]) continue;
+                double f[3], H[3][3], dx[3];
+                int con = 0;
+                local_system(M, P, &inc, i, x, NULL, y, x_t, E, f, H, &con);
+                double det = solve3((const double(*)[3])H, f, dx);
+                for (int a = 0; a < 3; ++a)
+                    xnew[3 * i + a] = skip_solve((const double(*)[3])H, det, P->det_eps_rel)
+                                          ? x[3 * i + a] : x[3 * i + a] + dx[a];
+            }
+            for (int i = 0; i < nv; ++i)
+                if (M->colors[i] == c)
+                    for (int a = 0; a < 3; ++a) x[3 * i + a] = xnew[3 * i + a];
+        }
+        memcpy(S + n3 * (size_t)it, x, sizeof(double) * n3);
+    }
+
+    /* outputs: x^{t+1} = x^(N), v^{t+1} = (x^(N) - x^t)/h, v_out_prev = v^t */
+    for (size_t q = 0; q < n3; ++q) {
+        xb[q] = gx_out[q] + gv_out[q] / h;
+        xtb[q] = -gv_out[q] / h;
+        vb[q] = gvp_out[q];
+    }
+    for (int it = N; it >= 1; --it) {
+        const double *Sn = S + n3 * (size_t)it, *Sp = S + n3 * (size_t)(it - 1);
+        for (int c = C - 1; c >= 0; --c) {
+            /* state before color pass c of iteration it */
+            for (int l = 0; l < nv; ++l)
+                for (int a = 0; a < 3; ++a)
+                    cur[3 * l + a] = (M->colors[l] < c) ? Sn[3 * l + a] : Sp[3 * l + a];
+            for (int i = 0; i < nv; ++i) {
+                if (M->colors[i] != c || M->pinned[i]) continue;
+                double f[3], H[3][3], D[3], w[3];
+                int con = 0;
+                local_system(M, P, &inc, i, cur, NULL, y, x_t, E, f, H, &con);
+                double det = solve3((const double(*)[3])H, f, D);
+                if (skip_solve((const double(*)[3])H, det, P->det_eps_rel)) continue;
+                double g[3] = {xb[3 * i], xb[3 * i + 1], xb[3 * i + 2]};
+                solve3((const double(*)[3])H, g, w);
+                for (int a = 0; a < 3; ++a) {
+                    double Hw = H[a][0] * w[0] + H[a][1] * w[1] + H[a][2] * w[2];
+                    xb[3 * i + a] = g[a] - Hw;
+                    yb[3 * i + a] += M->mass[i] / (h * h) * w[a];
+                }
+                for (int e = inc.tet_row[i]; e < inc.tet_row[i + 1]; ++e) {
+                    int t = inc.tet_ent[e] >> 2, k = inc.tet_ent[e] & 3;
+                    double xl[4][3], F[3][3], Dm[9][9], Cf[3][3], m[4][3], mu, lam;
+                    for (int l = 0; l < 4; ++l)
+                        for (int a = 0; a < 3; ++a) xl[l][a] = cur[3 * M->tets[4 * t + l] + a];
+                    shape_grads(M->Dminv + 9 * t, m);
+                    lame_R(E[t], M->nu, &mu, &lam);
+                    tet_F((const double(*)[3])xl, M->Dminv + 9 * t, F);
+                    dPdF((const double(*)[3])F, mu, lam, Dm);
+                    cof3((const double(*)[3])F, Cf);
+                    double ck[3];
+                    for (int a = 0; a < 3; ++a)
+                        ck[a] = Cf[a][0] * m[k][0] + Cf[a][1] * m[k][1] + Cf[a][2] * m[k][2];
+                    double cD = ck[0] * D[0] + ck[1] * D[1] + ck[2] * D[2];
+                    double cw = ck[0] * w[0] + ck[1] * w[1] + ck[2] * w[2];
+                    double V = M->vol[t];
+                    for (int j = 0; j < 4; ++j) {
+                        if (j == k) continue;
+                        int vj = M->tets[4 * t + j];
+                        double K[3][3], Mkj[3][3];
+                        tet_hess_kl((const double(*)[9])Dm, (const double(*)[3])m, V, k, j, K);
+                        d2J_kl((const double(*)[3])F, (const double(*)[3])m, k, j, Mkj);
+                        for (int e2 = 0; e2 < 3; ++e2) {
+                            double Ktw = 0, Mtw = 0, MtD = 0;
+                            for (int a = 0; a < 3; ++a) {
+                                Ktw += K[a][e2] * w[a];
+                                Mtw += Mkj[a][e2] * w[a];
+                                MtD += Mkj[a][e2] * D[a];
+                            }
+                            xb[3 * vj + e2] += -Ktw - V * lam * (cD * Mtw + cw * MtD);
+                        }
+                    }
+                    double gk[3], Hkk[3][3];
+                    tet_grad_k((const double(*)[3])F, (const double(*)[3])m, V, mu, lam, k, gk);
+                    tet_hess_kl((const double(*)[9])Dm, (const double(*)[3])m, V, k, k, Hkk);
+                    double s = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        double HD = Hkk[a][0] * D[0] + Hkk[a][1] * D[1] + Hkk[a][2] * D[2];
+                        s += w[a] * (gk[a] + HD);
+                    }
+                    g_E[t] += -s / E[t];
+                }
+            }
+        }
+    }
+    /* adjoint of the initial guess (Sec. 3.7) */
+    const double *gr = P->gravity;
+    const double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+    for (int i = 0; i < nv; ++i) {
+        double *b = xb + 3 * i;
+        for (int a = 0; a < 3; ++a) xtb[3 * i + a] += b[a];
+        if (M->pinned[i]) continue;
+        if (P->init_mode == OR_INIT_PREV) continue;
+        for (int a = 0; a < 3; ++a) vb[3 * i + a] += h * b[a];
+        if (P->init_mode == OR_INIT_ADAPTIVE && gn > 0.0) {
+            double at = 0;
+            for (int a = 0; a < 3; ++a) at += (v_t[3 * i + a] - v_prev[3 * i + a]) / h * (gr[a] / gn);
+            if (at > 0.0 && at < gn) {
+                /* x = ... + h^2 (at/gn) g, d(at)/dv = ghat/h, d(at)/dvp = -ghat/h */
+                double s = h * h * (gr[0] * b[0] + gr[1] * b[1] + gr[2] * b[2]) / gn;
+                for (int a = 0; a < 3; ++a) {
+                    vb[3 * i + a] += s * gr[a] / gn / h;
+                    vpb[3 * i + a] -= s * gr[a] / gn / h;
+                }
+            }
+        }
+    }
+    /* adjoint of y = x^t + h v^t + h^2 a_ext */
+    for (int i = 0; i < nv; ++i) {
+        if (M->pinned[i]) continue;
+        for (int a = 0; a < 3; ++a) {
+            xtb[3 * i + a] += yb[3 * i + a];
+            vb[3 * i + a] += h * yb[3 * i + a];
+        }
+    }
+    memcpy(gx_in, xtb, sizeof(double) * n3);
+    memcpy(gv_in, vb, sizeof(double) * n3);
+    memcpy(gvp_in, vpb, sizeof(double) * n3);
+    free(S); free(y); free(x); free(xnew); free(cur);
+    free(xb); free(yb); free(xtb); free(vb); free(vpb);
+    inc_free(&inc);
+    return 0;
+}
+#endif

@@ -1,0 +1,127 @@
+/* FP64 oracle: preprocessing (test infrastructure only).
+ * Greedy vertex coloring (Sec. 3.9), rest-shape data and lumped masses. */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "vbd_oracle.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct { int32_t a, b; } Pair;
+
+static int pair_cmp(const void *p, const void *q)
+{
+    const Pair *x = (const Pair *)p, *y = (const Pair *)q;
+    if (x->a != y->a) return x->a < y->a ? -1 : 1;
+    if (x->b != y->b) return x->b < y->b ? -1 : 1;
+    return 0;
+}
+
+/* Sec. 3.9: color vertices so that no force element uses two vertices of the
+ * same color.  Adjacency = every pair of distinct vertices sharing a tet or a
+ * spring.  First-fit greedy: vertices in ascending id, each takes the smallest
+ * color not used by an already colored neighbour. */
+int32_t oracle_color_greedy(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                            int32_t n_springs, const int32_t *springs, int32_t *colors)
+{
+    size_t np = (size_t)n_tets * 12 + (size_t)n_springs * 2;
+    Pair *pr = (Pair *)malloc(sizeof(Pair) * (np + 1));
+    size_t q = 0;
+    for (int t = 0; t < n_tets; ++t)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (a != b) { pr[q].a = tets[4 * t + a]; pr[q].b = tets[4 * t + b]; ++q; }
+    for (int s = 0; s < n_springs; ++s) {
+        pr[q].a = springs[2 * s]; pr[q].b = springs[2 * s + 1]; ++q;
+        pr[q].a = springs[2 * s + 1]; pr[q].b = springs[2 * s]; ++q;
+    }
+    qsort(pr, q, sizeof(Pair), pair_cmp);
+    int32_t *row = (int32_t *)calloc((size_t)n_verts + 1, sizeof(int32_t));
+    for (size_t k = 0; k < q; ++k) row[pr[k].a + 1]++;
+    for (int i = 0; i < n_verts; ++i) row[i + 1] += row[i];
+    int32_t n_colors = 0;
+    int32_t *used = (int32_t *)calloc((size_t)n_verts + 2, sizeof(int32_t));
+    for (int v = 0; v < n_verts; ++v) {
+        /* mark colors of lower-id neighbours with the stamp v+1 */
+        for (int k = row[v]; k < row[v + 1]; ++k) {
+            int u = pr[k].b;
+            if (u < v) used[colors[u]] = v + 1;
+        }
+        int c = 0;
+        while (used[c] == v + 1) ++c;
+        colors[v] = c;
+        if (c + 1 > n_colors) n_colors = c + 1;
+    }
+    free(used); free(row); free(pr);
+    return n_colors;
+}
+
+/* D_m = [X1-X0, X2-X0, X3-X0]; Dminv by Gauss-Jordan elimination with partial
+ * pivoting; V = |det D_m| / 6. */
+int32_t oracle_tet_rest(int32_t n_tets, const int32_t *tets, const double *rest,
+                        double *Dminv, double *vol)
+{
+    for (int t = 0; t < n_tets; ++t) {
+        double A[3][6];
+        const double *X0 = rest + 3 * tets[4 * t];
+        for (int c = 0; c < 3; ++c) {
+            const double *Xc = rest + 3 * tets[4 * t + c + 1];
+            for (int r = 0; r < 3; ++r) A[r][c] = Xc[r] - X0[r];
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) A[r][3 + c] = (r == c) ? 1.0 : 0.0;
+        double det = 1.0, scale = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) scale = fmax(scale, fabs(A[r][c]));
+        for (int col = 0; col < 3; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < 3; ++r)
+                if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+            if (piv != col) {
+                for (int c = 0; c < 6; ++c) { double tmp = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = tmp; }
+                det = -det;
+            }
+            double p = A[col][col];
+            det *= p;
+            if (fabs(p) <= 1e-300) return -1 - t;
+            for (int c = 0; c < 6; ++c) A[col][c] /= p;
+            for (int r = 0; r < 3; ++r) {
+                if (r == col) continue;
+                double fct = A[r][col];
+                for (int c = 0; c < 6; ++c) A[r][c] -= fct * A[col][c];
+            }
+        }
+        if (fabs(det) <= 1e-12 * scale * scale * scale) return -1 - t;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Dminv[9 * t + 3 * r + c] = A[r][3 + c];
+        vol[t] = fabs(det) / 6.0;
+    }
+    return 0;
+}
+
+void oracle_lumped_mass(int32_t n_verts, int32_t n_tets, const int32_t *tets, const double *vol,
+                        double density, double *mass)
+{
+    memset(mass, 0, sizeof(double) * (size_t)n_verts);
+    for (int t = 0; t < n_tets; ++t)
+        for (int a = 0; a < 4; ++a) mass[tets[4 * t + a]] += density * vol[t] / 4.0;
+}
+
+void oracle_spring_rest(int32_t n_springs, const int32_t *springs, const double *rest, double *L)
+{
+    for (int s = 0; s < n_springs; ++s) {
+        const double *a = rest + 3 * springs[2 * s], *b = rest + 3 * springs[2 * s + 1];
+        double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+        L[s] = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+}
+
+void oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}

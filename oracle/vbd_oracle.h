@@ -1,0 +1,127 @@
+/* FP64 reference ("oracle") for the Vertex Block Descent time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, sequential CPU
+ * implementation of what the GPU library computes.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it; the product
+ * path never does.  It shares no code, headers or tables with the HIP library.
+ *
+ * Paper: A. H. Chen, Z. Liu, Y. Yang, C. Yuksel, "Vertex Block Descent",
+ * ACM TOG 43(4), 2024.  Each function names the passage it follows.
+ *
+ * All floating point is IEEE double.  The forward step is also compiled in
+ * double complex (suffix _cs) so that tests can take complex-step directional
+ * derivatives (Squire & Trapp 1998) of a whole rollout.
+ */
+#ifndef VBD_ORACLE_H
+#define VBD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_INIT_PREV = 0, OR_INIT_INERTIA = 1, OR_INIT_Y = 2, OR_INIT_ADAPTIVE = 3 };
+
+typedef struct {
+    int32_t n_verts, n_tets, n_springs, n_colors;
+    const int32_t *tets;        /* [n_tets*4] */
+    const int32_t *springs;     /* [n_springs*2] or NULL */
+    const double  *Dminv;       /* [n_tets*9] row-major inverse of the rest edge matrix */
+    const double  *vol;         /* [n_tets] rest volume */
+    const double  *spring_rest; /* [n_springs] rest length */
+    const double  *mass;        /* [n_verts] */
+    const uint8_t *pinned;      /* [n_verts] 0/1 */
+    const int32_t *colors;      /* [n_verts] */
+    double nu;                  /* Poisson ratio (tets) */
+    double spring_k;            /* spring stiffness */
+} oracle_model;
+
+typedef struct {
+    double h;
+    int32_t n_iters;
+    double gravity[3];
+    int32_t init_mode;
+    double det_eps_rel;
+    double contact_k, contact_thickness;
+    int32_t n_spheres; const double *spheres;  /* [n*4] cx cy cz R */
+    int32_t n_planes;  const double *planes;   /* [n*4] nx ny nz offset, unit normal */
+    double kd;                 /* Rayleigh damping (Sec. 3.3) */
+    double cheb_rho;           /* Chebyshev spectral radius (Sec. 3.8), 0 = off */
+    double friction_mu, friction_eps_v;        /* Sec. 3.6 */
+} oracle_params;
+
+typedef struct {
+    int64_t n_updates;       /* local solves attempted on free vertices */
+    int64_t n_skips;         /* solves skipped by the determinant test */
+    double  max_local_grad;  /* max |grad_i G_i| right after an update (if tracked) */
+    int64_t n_contacts;      /* local solves with at least one active contact */
+} oracle_stats;
+
+/* ---- preprocessing (real only) ------------------------------------------ */
+/* Greedy first-fit vertex coloring in ascending vertex id over the adjacency
+ * of all material elements (Sec. 3.9).  Returns the number of colors. */
+int32_t oracle_color_greedy(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                            int32_t n_springs, const int32_t *springs, int32_t *colors);
+/* Rest edge matrix inverse and volume per tet; returns 0, or -1-t for the first
+ * degenerate tet t. */
+int32_t oracle_tet_rest(int32_t n_tets, const int32_t *tets, const double *rest,
+                        double *Dminv, double *vol);
+/* Lumped mass: each tet adds density*V/4 to each of its vertices. */
+void oracle_lumped_mass(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                        const double *vol, double density, double *mass);
+void oracle_spring_rest(int32_t n_springs, const int32_t *springs, const double *rest,
+                        double *L);
+
+/* ---- element energies and derivatives (real) ------------------------------ */
+void   oracle_lame(double E, double nu, double *mu, double *lam);
+double oracle_tet_energy(const double x[12], const double Dminv[9], double vol,
+                         double mu, double lam);
+/* full 12-gradient and 12x12 Hessian of one tet (row-major) */
+void   oracle_tet_derivs(const double x[12], const double Dminv[9], double vol,
+                         double mu, double lam, double grad[12], double hess[144]);
+double oracle_spring_energy(const double xa[3], const double xb[3], double L, double k);
+void   oracle_spring_derivs(const double xa[3], const double xb[3], double L, double k,
+                            double grad[6], double hess[36]);
+
+/* ---- one time step (Alg. 1) --------------------------------------------- */
+/* In place: (x, v, vprev) = (x^t, v^t, v^{t-1}) -> (x^{t+1}, v^{t+1}, v^t).
+ * order: optional processing order of vertices inside each color (NULL =
+ * ascending id).  G_trace: optional [n_iters*n_colors] variational energy
+ * after each color pass.  track_local_grad: record max |grad_i G_i| after each
+ * update.  Returns 0, or <0 on bad arguments. */
+int32_t oracle_step(const oracle_model *M, const oracle_params *P,
+                    double *x, double *v, double *vprev, const double *tet_E,
+                    const int32_t *order, double *G_trace, int32_t track_local_grad,
+                    oracle_stats *st);
+int32_t oracle_step_cs(const oracle_model *M, const oracle_params *P,
+                       double _Complex *x, double _Complex *v, double _Complex *vprev,
+                       const double _Complex *tet_E, const int32_t *order,
+                       double *G_trace, int32_t track_local_grad, oracle_stats *st);
+
+/* Inertia target y = x^t + h v^t + h^2 a_ext (Eq. inertia). */
+void oracle_predict(const oracle_model *M, const oracle_params *P,
+                    const double *x, const double *v, double *y);
+/* Variational energy G (Eq. VariantionalFormOfImplicitEuler), its gradient
+ * [3n] and (if hess != NULL) dense Hessian [3n x 3n].  Inertia over free
+ * vertices; contacts with the normal held fixed (Sec. 3.5). */
+double oracle_energy_G(const oracle_model *M, const oracle_params *P,
+                       const double *x, const double *y, const double *tet_E,
+                       double *grad, double *hess);
+
+/* ---- reverse mode of one step ---------------------------------------------- */
+/* Adjoint of oracle_step for tets + inertia + pins (no springs, contacts,
+ * damping or acceleration: returns -2 then).  Recomputes the step's iterates
+ * from (x_t, v_t, v_prev).  Inputs: adjoints of (x^{t+1}, v^{t+1}, v^t_out).
+ * Outputs: adjoints of (x^t, v^t, v^{t-1}); g_E is accumulated (+=). */
+int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P,
+                             const double *x_t, const double *v_t, const double *v_prev,
+                             const double *tet_E,
+                             const double *gx_out, const double *gv_out, const double *gvp_out,
+                             double *gx_in, double *gv_in, double *gvp_in, double *g_E);
+
+void oracle_set_threads(int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
