@@ -1,0 +1,325 @@
+#!/usr/bin/env python3
+"""Benchmark of the VBD hot path on one MI355X.
+
+Headline: vertex-updates/s of the 65^3-vertex tet cube (274,625 vertices,
+1,572,864 stable Neo-Hookean tets, per-tet E log-uniform in [1e4, 1e6] Pa,
+h = 1/60 s, 100 VBD iterations per frame, greedy coloring, adaptive init),
+FP32 state on the GPU, inputs resident in HBM.  A vertex update is one local
+solve of a free vertex; value = free vertices x iterations x frames / time.
+
+Also measured in the same run (JSON "extra"): every launch mode on the cube,
+the batched 512-mesh workload (persistent hipGraph launch vs the plain kernel
+mesh by mesh), the adjoint (forward + backward of the 33^3 differentiable
+workload), the 1024^2 mass-spring cloth with contacts, and a STREAM-like copy
+probe.  "roofline" is the color-solve kernel's algorithmic HBM bytes per
+launch over its average launch time (HIP events on the launch stream);
+"cpu_baseline" is the FP64 oracle timed on a bounded sample of the cube.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+       [--no-cpu-baseline] [--mode auto|plain|graph|persistent|persistent_graph]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+MODES = {"plain": 0, "graph": 1, "persistent": 2, "persistent_graph": 3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="auto", choices=["auto"] + list(MODES))
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--profile-only", default="",
+                    help="run only one workload for a profiler: cube|batch|adjoint|cloth|copy")
+    return ap.parse_args()
+
+
+def state(w, dev):
+    import torch
+    x = torch.tensor(w.x0, dtype=torch.float32, device=dev).contiguous()
+    v = torch.tensor(w.v0, dtype=torch.float32, device=dev).contiguous()
+    E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).contiguous()
+    return x, v, v.clone(), E
+
+
+def time_frames(topo, w, mode, steps, warmup, dev, autotune=True):
+    """Time `steps` frames after `warmup` frames; returns (seconds, updates/frame)."""
+    import torch
+    x, v, vp, E = state(w, dev)
+    if autotune:
+        topo.autotune(x, v, vp, E, w.params, mode)
+    for _ in range(warmup):
+        topo.step(x, v, vp, E, w.params, mode)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        topo.step(x, v, vp, E, w.params, mode)
+    b.record()
+    torch.cuda.synchronize()
+    topo.check()
+    if not bool(torch.isfinite(x).all()):
+        raise RuntimeError("non-finite positions after the timed frames")
+    free = int((w.pinned == 0).sum())
+    return a.elapsed_time(b) / 1e3, free * w.params.n_iters
+
+
+def kernel_roofline(topo, w, dev, frames=3):
+    """Average color-solve launch time and algorithmic bytes (plain launches)."""
+    import torch
+    x, v, vp, E = state(w, dev)
+    topo.step(x, v, vp, E, w.params, MODES["plain"])
+    topo.profile_enable(True)
+    topo.profile_read(reset=True)
+    for _ in range(frames):
+        topo.step(x, v, vp, E, w.params, MODES["plain"])
+    torch.cuda.synchronize()
+    st = topo.profile_read(reset=True)
+    topo.profile_enable(False)
+    avg_ms = st["total_ms"] / st["n_launches"]
+    avg_bytes = st["total_bytes"] / st["n_launches"]
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    return dict(avg_ms=avg_ms, avg_bytes=avg_bytes, achieved_gbs=achieved,
+                launches=st["n_launches"],
+                updates_per_s=st["n_vertex_updates"] / (st["total_ms"] * 1e-3))
+
+
+def kernel_traffic():
+    """Measured HBM bytes per launch from committed rocprofv3 counter runs,
+    valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic_solve_tet_cube65.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2403_06321_amd", "csrc", "vbd_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, iters):
+    import oracle as O
+    import dataclasses
+    threads = min(16, os.cpu_count() or 1)
+    O.set_threads(threads)
+    m = O.Model.from_workload(w)
+    p = dataclasses.replace(w.params, n_iters=iters)
+    t0 = time.perf_counter()
+    O.step(m, p, w.x0, w.v0, w.v0, w.tet_E)
+    dt = time.perf_counter() - t0
+    free = int((w.pinned == 0).sum())
+    return dict(value=free * iters / dt, unit="vertex-updates/s", cores=threads, kind="oracle",
+                sample=f"65^3 cube, 1 frame x {iters} iterations, FP64, {threads} threads, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2403_06321_amd import workloads as W
+    from paper_2403_06321_amd.api import Topology, probe_copy
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    if args.profile_only == "copy":
+        n = 1 << 28   # 1 GiB of float32
+        src = torch.ones(n, device=dev); dst = torch.empty_like(src)
+        for _ in range(5):
+            probe_copy(dst, src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * 4 * n}))
+        return
+
+    # ---------------------------------------------------------- headline ----
+    w = W.config_large_cube()
+    log(f"[bench] building topology: {w.name}, {w.n_verts} verts, {w.n_tets} tets")
+    t0 = time.perf_counter()
+    topo = Topology.from_workload(w)
+    log(f"[bench] topology built in {time.perf_counter() - t0:.1f} s, {topo.n_colors} colors")
+    if args.profile_only == "cube":
+        secs, upd = time_frames(topo, w, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
+        print(json.dumps({"profile": "cube", "ms_per_frame": secs / args.steps * 1e3}))
+        return
+    modes = list(MODES) if args.mode == "auto" else [args.mode]
+    per_mode = {}
+    for name in modes:
+        secs, upd = time_frames(topo, w, MODES[name], min(args.steps, 20) if args.mode == "auto" else args.steps,
+                                args.warmup, dev)
+        n = min(args.steps, 20) if args.mode == "auto" else args.steps
+        per_mode[name] = dict(updates_per_s=upd * n / secs, ms_per_frame=secs / n * 1e3,
+                              config=topo.launch_config)
+        log(f"[bench] cube mode {name}: {per_mode[name]['updates_per_s']:.3e} v-upd/s, "
+            f"{per_mode[name]['ms_per_frame']:.2f} ms/frame, cfg {topo.launch_config}")
+    best = max(per_mode, key=lambda k: per_mode[k]["updates_per_s"])
+    # the timed run of the headline, in the best mode
+    topo.autotune(*state(w, dev), w.params, MODES[best])
+    secs, upd = time_frames(topo, w, MODES[best], args.steps, args.warmup, dev, autotune=False)
+    value = upd * args.steps / secs
+    ms_per_step = secs / args.steps * 1e3
+    log(f"[bench] headline ({best}): {value:.3e} v-upd/s, {ms_per_step:.3f} ms/frame")
+    roof = kernel_roofline(topo, w, dev)
+    log(f"[bench] solve kernel: {roof['avg_ms'] * 1e3:.1f} us/launch, "
+        f"{roof['avg_bytes'] / 1e6:.2f} MB/launch, {roof['achieved_gbs']:.0f} GB/s")
+    traffic = kernel_traffic()
+
+    out = {
+        "metric": "VBD vertex-updates/s, 65^3-vertex stable Neo-Hookean tet cube (100 iterations/frame)",
+        "value": value,
+        "unit": "vertex-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "tet cube 65x65x65 vertices (274,625 verts, 1,572,864 tets), "
+                               "per-tet E log-uniform [1e4,1e6] Pa, nu 0.3, h 1/60 s, 100 iterations x "
+                               "frames, 8 greedy colors, bottom face pinned",
+                   "launch_mode": best, "launch_config": topo.launch_config,
+                   "free_vertices": int((w.pinned == 0).sum()), "iterations": w.params.n_iters},
+        "roofline": {"bound": "hbm", "achieved": roof["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": roof["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "k_solve<tets> (one color phase)",
+                     "avg_launch_us": roof["avg_ms"] * 1e3,
+                     "algorithmic_bytes_per_launch": roof["avg_bytes"]},
+    }
+    del topo
+    torch.cuda.empty_cache()
+
+    extra = {"cube_modes": per_mode}
+    if not args.no_extras:
+        # copy probe: achievable streaming bandwidth
+        n = 1 << 28
+        src = torch.ones(n, device=dev); dst = torch.empty_like(src)
+        probe_copy(dst, src); torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            probe_copy(dst, src)
+        b.record(); torch.cuda.synchronize()
+        extra["copy_probe_gbs"] = 10 * 8 * n / (a.elapsed_time(b) * 1e-3) / 1e9
+        del src, dst
+        log(f"[bench] copy probe {extra['copy_probe_gbs']:.0f} GB/s")
+        extra.update(extras(dev, W, Topology))
+    out["extra"] = extra
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(W.config_large_cube(), args.cpu_iters)
+        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} v-upd/s ({out['cpu_baseline']['sample']})")
+    print(json.dumps(out))
+
+
+def extras(dev, W, Topology):
+    import torch
+    res = {}
+    # batched: 512 meshes, persistent hipGraph vs the plain kernel mesh by mesh
+    wb = W.config_batch()
+    log(f"[bench] batch: {wb.n_meshes} meshes, {wb.n_verts} verts, {wb.n_tets} tets")
+    t0 = time.perf_counter()
+    tb = Topology.from_workload(wb)
+    log(f"[bench] batch topology {time.perf_counter() - t0:.1f} s, {tb.n_colors} colors")
+    secs, upd = time_frames(tb, wb, MODES["persistent_graph"], 10, 2, dev)
+    res["batched_persistent_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100,
+                                           config=tb.launch_config)
+    secs, upd = time_frames(tb, wb, MODES["graph"], 10, 2, dev)
+    res["batched_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100,
+                                config=tb.launch_config)
+    log(f"[bench] batched persistent graph {res['batched_persistent_graph']['updates_per_s']:.3e}, "
+        f"graph {res['batched_graph']['updates_per_s']:.3e} v-upd/s")
+    roof = kernel_roofline(tb, wb, dev, frames=1)
+    res["batched_solve_kernel"] = dict(avg_launch_us=roof["avg_ms"] * 1e3,
+                                       achieved_gbs=roof["achieved_gbs"],
+                                       frac=roof["achieved_gbs"] / HBM_PEAK_GBS)
+    del tb
+    # plain kernel, mesh by mesh (one topology per mesh, plain launches), 1 frame
+    vo, to = wb.offsets()
+    tops, sts = [], []
+    for k in range(wb.n_meshes):
+        sub = W.subset_meshes(wb, [k])
+        tops.append(Topology.from_workload(sub))
+        sts.append(state(sub, dev))
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for t, (x, v, vp, E) in zip(tops, sts):
+        t.step(x, v, vp, E, wb.params, MODES["plain"])
+    b.record(); torch.cuda.synchronize()
+    upd = int(wb.n_verts) * wb.params.n_iters
+    res["batched_plain_mesh_by_mesh"] = dict(updates_per_s=upd / (a.elapsed_time(b) * 1e-3),
+                                             ms_per_frame=a.elapsed_time(b))
+    log(f"[bench] plain mesh by mesh {res['batched_plain_mesh_by_mesh']['updates_per_s']:.3e} v-upd/s")
+    del tops, sts
+    torch.cuda.empty_cache()
+    # adjoint: differentiable 33^3 workload, forward + backward through 30 frames
+    from paper_2403_06321_amd.api import Rollout
+    wd = W.config_differentiable()
+    td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
+    x0, v0, _, E = state(wd, dev)
+    v0.requires_grad_(True); E.requires_grad_(True)
+    target = torch.tensor(wd.target, dtype=torch.float32, device=dev)
+
+    def fwd_bwd():
+        xT, _ = Rollout.apply(x0, v0, E, td, wd.params, wd.frames)
+        loss = ((xT.mean(0) - target) ** 2).sum()
+        loss.backward()
+        return loss
+
+    fwd_bwd(); torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(3):
+        fwd_bwd()
+    b.record(); torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 3
+    free = int((wd.pinned == 0).sum())
+    upd = free * wd.params.n_iters * wd.frames
+    x, v, vp, E2 = state(wd, dev)
+    a.record()
+    for _ in range(wd.frames):
+        td.step(x, v, vp, E2, wd.params, MODES["plain"])
+    b.record(); torch.cuda.synchronize()
+    ms_fwd = a.elapsed_time(b)
+    res["adjoint"] = dict(forward_backward_ms=ms, forward_only_ms=ms_fwd,
+                          updates_per_s_forward_backward=upd / (ms * 1e-3),
+                          updates_per_s_forward=upd / (ms_fwd * 1e-3),
+                          workload="33^3 cube, 30 frames x 20 iterations, loss on final centroid")
+    log(f"[bench] adjoint fwd+bwd {ms:.1f} ms, forward {ms_fwd:.1f} ms")
+    del td
+    # cloth
+    wc = W.config_cloth()
+    tc = Topology.from_workload(wc)
+    secs, upd = time_frames(tc, wc, MODES["persistent_graph"], 10, 3, dev)
+    res["cloth_persistent_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
+    secs, upd = time_frames(tc, wc, MODES["graph"], 10, 3, dev)
+    res["cloth_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
+    log(f"[bench] cloth {res['cloth_persistent_graph']['updates_per_s']:.3e} / "
+        f"{res['cloth_graph']['updates_per_s']:.3e} v-upd/s")
+    return res
+
+
+if __name__ == "__main__":
+    main()

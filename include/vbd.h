@@ -1,0 +1,230 @@
+/* vbd.h - C ABI of the MI355X (gfx950) Vertex Block Descent library.
+ *
+ * Method: A. H. Chen, Z. Liu, Y. Yang, C. Yuksel, "Vertex Block Descent",
+ * ACM TOG 43(4), 2024.  One call of vbd_step advances every mesh of a
+ * topology by one implicit-Euler time step (Sec. 3.1, Eq.
+ * VariantionalFormOfImplicitEuler) using the per-color Gauss-Seidel vertex
+ * updates of Alg. 1.
+ *
+ * Conventions
+ *   - Every call returns a vbd_status: VBD_OK (0) or a negative error code.
+ *     vbd_last_error() returns a thread-local, library-owned, NUL-terminated
+ *     message for the last failing call on this thread (valid until the next
+ *     call on the thread).
+ *   - Host pointers are read during the call only; the caller keeps ownership.
+ *   - Device memory is always caller-owned (for example torch tensors).  The
+ *     library never allocates device memory: it works inside one workspace
+ *     bound by vbd_bind_workspace.
+ *   - Device state buffers are float32, row-major [n_verts][3] in the
+ *     ORIGINAL vertex order.  The library keeps its own color-sorted copies in
+ *     the workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Compute calls are asynchronous with respect to the host.
+ *   - A topology may be used by one host thread at a time.
+ */
+#ifndef VBD_H
+#define VBD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vbd_topology_s *vbd_topology;
+
+typedef enum {
+    VBD_OK = 0,
+    VBD_E_INVALID_ARG = -1,   /* NULL pointer, bad size, bad parameter value */
+    VBD_E_TOPOLOGY = -2,      /* id out of range, repeated vertex in an element,
+                                 degenerate rest tet, zero-length spring,
+                                 element crossing meshes */
+    VBD_E_NOT_COLORED = -3,   /* vbd_workspace_size/bind/step before vbd_color */
+    VBD_E_NO_WORKSPACE = -4,  /* step before bind, or workspace too small */
+    VBD_E_HIP = -5,           /* HIP runtime failure (message has hipGetErrorString) */
+    VBD_E_UNSUPPORTED = -6,   /* a feature combination this entry point does not do */
+    VBD_E_NONFINITE = -7,     /* reserved: non-finite state detected by vbd_check */
+    VBD_E_DEVICE = -8         /* a device-side guard fired (see vbd_check) */
+} vbd_status;
+
+/* Initial guess options of Sec. 3.7: (a) previous position, (b) inertia,
+ * (c) inertia and acceleration (= y), (d) adaptive (default). */
+enum { VBD_INIT_PREV = 0, VBD_INIT_INERTIA = 1, VBD_INIT_Y = 2, VBD_INIT_ADAPTIVE = 3 };
+
+/* Launch modes of vbd_step.
+ *   PLAIN            host loop of kernel launches: per color one solve kernel
+ *   GRAPH            the same launch sequence captured once into a hipGraph and
+ *                    replayed (re-captured when pointers or parameters change)
+ *   PERSISTENT       one persistent kernel runs all iterations and colors with
+ *                    a device-wide barrier between color phases
+ *   PERSISTENT_GRAPH the persistent launch plus its pre/post kernels in a hipGraph */
+enum { VBD_LAUNCH_PLAIN = 0, VBD_LAUNCH_GRAPH = 1, VBD_LAUNCH_PERSISTENT = 2,
+       VBD_LAUNCH_PERSISTENT_GRAPH = 3 };
+
+/* Mesh description (host memory).  A batch is a concatenation of meshes that
+ * share no vertices; element ids are global vertex ids. */
+typedef struct {
+    int32_t n_verts, n_tets, n_springs;
+    int32_t n_meshes;              /* >= 1 */
+    const int64_t *vert_offsets;   /* [n_meshes+1] or NULL when n_meshes == 1 */
+    const int64_t *tet_offsets;    /* [n_meshes+1] or NULL when n_meshes == 1 */
+    const int32_t *tets;           /* [n_tets][4] or NULL when n_tets == 0 */
+    const int32_t *springs;        /* [n_springs][2] or NULL when n_springs == 0 */
+    const double *rest_pos;        /* [n_verts][3] FP64 rest shape */
+    const double *spring_rest;     /* [n_springs] or NULL -> rest distance */
+    double spring_k;               /* spring stiffness (N/m), global */
+    const double *mass;            /* [n_verts] or NULL -> lumped: each tet adds
+                                      density*V/4 to each of its vertices */
+    double density;                /* kg/m^3, used for lumped masses */
+    double poisson_nu;             /* Poisson ratio of all tets, 0 <= nu < 0.5 */
+    const uint8_t *pinned;         /* [n_verts] 0/1 or NULL (none pinned) */
+} vbd_mesh_desc;
+
+/* Validates the description and precomputes, in FP64, each tet's inverse
+ * rest edge matrix and rest volume (F = D_s D_m^{-1}, V = |det D_m|/6) and
+ * the lumped vertex masses.  Host only, synchronous.  Errors:
+ * VBD_E_INVALID_ARG, VBD_E_TOPOLOGY (|det D_m| <= 1e-12 * (max edge)^3 counts
+ * as degenerate).  *out receives a library-owned handle. */
+vbd_status vbd_build_topology(const vbd_mesh_desc *desc, vbd_topology *out);
+
+/* Greedy vertex coloring (Sec. 3.9): no force element (tet, spring) may use
+ * two vertices of one color; first-fit in ascending vertex id.  Then builds
+ * the color-sorted vertex permutation (free vertices by (color, id), pinned
+ * vertices last by id) and the incidence CSR of every free vertex.  Host,
+ * synchronous.  colors_out: host [n_verts] or NULL. */
+vbd_status vbd_color(vbd_topology topo, int32_t *n_colors_out, int32_t *colors_out);
+
+/* Device bytes the workspace needs.  max_backward_iters: largest n_iters that
+ * vbd_step_backward will be called with (0 = forward only). */
+vbd_status vbd_workspace_size(vbd_topology topo, int32_t max_backward_iters, size_t *bytes);
+
+/* Binds caller-owned device memory (>= vbd_workspace_size bytes, 256-byte
+ * aligned) and uploads the topology into it on `stream`.  The memory must
+ * stay valid until the topology is destroyed or rebound.  The upload goes
+ * through host staging and finishes before the call returns. */
+vbd_status vbd_bind_workspace(vbd_topology topo, void *dev_ptr, size_t bytes, void *stream);
+
+/* Read-only queries of host-side topology arrays (tests of bit-exactness). */
+enum {
+    VBD_Q_COUNTS = 0,       /* int64[8]: n_verts, n_tets, n_springs, n_colors, n_free,
+                               tet CSR entries, spring CSR entries, n_meshes */
+    VBD_Q_COLORS = 1,       /* int32[n_verts] */
+    VBD_Q_PERM = 2,         /* int32[n_verts]: permuted slot -> original id */
+    VBD_Q_COLOR_OFFSETS = 3,/* int32[n_colors+1] over the free permuted slots */
+    VBD_Q_TET_ROWS = 4,     /* int32[n_free+1] */
+    VBD_Q_TET_ENTRIES = 5,  /* int32[entries]: (tet << 2) | slot, ascending tet */
+    VBD_Q_SPRING_ROWS = 6,  /* int32[n_free+1] */
+    VBD_Q_SPRING_NBRS = 7,  /* int32[entries]: original id of the other end */
+    VBD_Q_MASS = 8,         /* double[n_verts] lumped or given masses (original order) */
+    VBD_Q_DMINV = 9,        /* double[n_tets][9] */
+    VBD_Q_VOLUME = 10,      /* double[n_tets] */
+    VBD_Q_PHASE_BYTES = 11  /* double[n_colors]: algorithmic HBM bytes of one color solve */
+};
+vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
+vbd_status vbd_topology_destroy(vbd_topology topo);
+
+/* Parameters of one time step (FP32, the kernels' precision). */
+typedef struct {
+    float h;                       /* time step (s), > 0 */
+    int32_t n_iters;               /* VBD iterations n_max, >= 1 */
+    float gravity[3];              /* external acceleration a_ext */
+    int32_t init_mode;             /* VBD_INIT_* */
+    float det_eps_rel;             /* skip a vertex iff |det H| <= det_eps_rel*||H||_F^3 */
+    float contact_k;               /* penalty stiffness k_c (Sec. 3.5) */
+    float contact_thickness;       /* contact distance delta */
+    int32_t n_spheres;             /* <= 8 */
+    const float *spheres;          /* host [n_spheres][4]: cx, cy, cz, R */
+    int32_t n_planes;              /* <= 8 */
+    const float *planes;           /* host [n_planes][4]: nx, ny, nz, offset (n.x = offset);
+                                      the normal is normalised by the library */
+    float kd;                      /* Rayleigh damping coefficient (Sec. 3.3) */
+    float cheb_rho;                /* Chebyshev spectral radius (Sec. 3.8), 0 = off */
+    float friction_mu;             /* friction coefficient mu_c (Sec. 3.6), 0 = off */
+    float friction_eps_v;          /* friction velocity threshold eps_v */
+    int32_t spring_psd;            /* 0: spring Hessian as is (Sec. 3.2, no projection);
+                                      1: transverse stiffness k(1 - L/l) clamped at 0,
+                                      the exact PSD projection of a spring block */
+    int32_t launch_mode;           /* VBD_LAUNCH_* */
+} vbd_step_params;
+
+/* One implicit-Euler time step of every mesh (Alg. 1):
+ *   S^t = (x^t, v^t, v^{t-1}) -> S^{t+1} = (x^{t+1}, v^{t+1}, v^t), in place.
+ * y = x^t + h v^t + h^2 a_ext (Eq. inertia); initial guess (Sec. 3.7);
+ * n_iters sweeps over the colors in ascending order, each free vertex of a
+ * color solving H_i dx = f_i (Eq. VBDLocalSystem, VBDForce, VBDHessian) over
+ * its tets, springs and active contacts; optional Chebyshev acceleration
+ * after each sweep; v^{t+1} = (x^{t+1} - x^t)/h (Eq. velocity_update).
+ * x, v, v_prev: device float [n_verts][3]; tet_E: device float [n_tets]
+ * Young's modulus per tet (may be NULL when n_tets == 0).  Pinned vertices
+ * keep x^t and get v = 0.  Errors: VBD_E_NOT_COLORED, VBD_E_NO_WORKSPACE,
+ * VBD_E_INVALID_ARG, VBD_E_HIP. */
+vbd_status vbd_step(vbd_topology topo, const vbd_step_params *params, float *x, float *v,
+                    float *v_prev, const float *tet_E, void *stream);
+
+/* Reverse mode of one vbd_step (tets + inertia + pins; springs, contacts,
+ * damping and acceleration give VBD_E_UNSUPPORTED).  Recomputes the step's
+ * iterates from the checkpoint S^t = (x_t, v_t, v_prev) and runs the adjoint
+ * of the color sweeps in reverse order (n = N..1, colors descending), then the
+ * adjoints of the initial guess and of y.  Each local update is the exact
+ * minimiser of the vertex energy G_i (Eq. VBDEnergy; G_i is quadratic in x_i
+ * for these tets), so its derivative is taken by the implicit function
+ * theorem at the updated position.
+ * Inputs gx_out, gv_out, gvp_out: adjoints of (x^{t+1}, v^{t+1}, v^t) as
+ * device float [n_verts][3].  Outputs gx_in, gv_in, gvp_in: adjoints of
+ * (x^t, v^t, v^{t-1}) (overwritten); g_tet_E: device float [n_tets],
+ * ACCUMULATED (+=).  The workspace must have been sized with
+ * max_backward_iters >= params->n_iters. */
+vbd_status vbd_step_backward(vbd_topology topo, const vbd_step_params *params,
+                             const float *x_t, const float *v_t, const float *v_prev,
+                             const float *tet_E, const float *gx_out, const float *gv_out,
+                             const float *gvp_out, float *gx_in, float *gv_in, float *gvp_in,
+                             float *g_tet_E, void *stream);
+
+/* Kernel launch configuration of the color solve. */
+typedef struct {
+    int32_t lanes_per_vertex;   /* 4, 8, 16 or 32 lanes of a wave64 per vertex */
+    int32_t block_size;         /* 64..1024, multiple of 64 */
+    int32_t xcd_remap;          /* 1: give each XCD a contiguous range of blocks */
+    int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */
+} vbd_launch_config;
+vbd_status vbd_get_launch_config(vbd_topology topo, vbd_launch_config *cfg);
+vbd_status vbd_set_launch_config(vbd_topology topo, const vbd_launch_config *cfg);
+
+/* Autotuner: times the color-solve sweep for each candidate configuration on
+ * this topology (predict from the given state, then sweeps on the library's
+ * internal copy; the caller's x, v, v_prev are not modified) and keeps the
+ * fastest.  Results are cached in-process per (device arch, size bucket,
+ * element kinds, launch mode); a cached entry is reused without timing.
+ * Synchronizes `stream`. */
+vbd_status vbd_autotune(vbd_topology topo, const vbd_step_params *params, const float *x,
+                        const float *v, const float *v_prev, const float *tet_E, void *stream);
+
+/* Per-launch timing of the hot kernel (hipEvents on the launch stream).
+ * When enabled, vbd_step records an event pair around every color-solve
+ * launch (or around the persistent kernel).  vbd_profile_read synchronizes
+ * and reports totals since the last reset. */
+typedef struct {
+    int64_t n_launches;        /* timed hot-kernel launches */
+    double total_ms;           /* summed event time of those launches */
+    double total_bytes;        /* summed algorithmic HBM bytes of those launches */
+    int64_t n_vertex_updates;  /* local solves of free vertices inside them */
+} vbd_profile_stats;
+vbd_status vbd_profile_enable(vbd_topology topo, int32_t enable);
+vbd_status vbd_profile_read(vbd_topology topo, vbd_profile_stats *out, int32_t reset);
+
+/* Reads the device-side guard flags (persistent barrier time-out) on
+ * `stream` (synchronizes).  VBD_E_DEVICE if a guard fired since the last
+ * check; the flag is then cleared. */
+vbd_status vbd_check(vbd_topology topo, void *stream);
+
+/* Device copy probe: copies n_bytes (multiple of 16) from src to dst with
+ * the library's own streaming kernel; used to measure achievable HBM
+ * bandwidth and to calibrate traffic counters. */
+vbd_status vbd_probe_copy(void *dst, const void *src, size_t n_bytes, void *stream);
+
+const char *vbd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -72,7 +72,8 @@ class _Params(C.Structure):
                 ("n_spheres", C.c_int32), ("spheres", C.c_void_p),
                 ("n_planes", C.c_int32), ("planes", C.c_void_p),
                 ("kd", C.c_double), ("cheb_rho", C.c_double),
-                ("friction_mu", C.c_double), ("friction_eps_v", C.c_double)]
+                ("friction_mu", C.c_double), ("friction_eps_v", C.c_double),
+                ("spring_psd", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -202,7 +203,7 @@ def _params(p):
                 int(p.init_mode), float(p.det_eps_rel), float(p.contact_k),
                 float(p.contact_thickness), 0 if sph is None else sph.shape[0], _ptr(sph),
                 0 if pl is None else pl.shape[0], _ptr(pl), float(p.kd), float(p.cheb_rho),
-                float(p.friction_mu), float(p.friction_eps_v))
+                float(p.friction_mu), float(p.friction_eps_v), int(bool(getattr(p, "spring_psd", False))))
     return s, (sph, pl)
 
 

@@ -172,16 +172,21 @@ static void tet_hess_kl(const R D[9][9], const double m[4][3], double vol, int k
  * Linear spring E = k/2 (l - L)^2, l = |x_a - x_b| (Sec. 5, Sec. 6.1).
  * dl/dx_a = d/l, d2l/dx_a2 = (I - d d^T / l^2) / l.
  * ------------------------------------------------------------------------- */
-static void spring_block(const R xa[3], const R xb[3], double L, double k, R g[3], R Hb[3][3])
+static void spring_block(const R xa[3], const R xb[3], double L, double k, int psd, R g[3],
+                         R Hb[3][3])
 {
     R d[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
     R l = RSQRT(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     R u[3] = {d[0] / l, d[1] / l, d[2] / l};
     for (int a = 0; a < 3; ++a) g[a] = k * (l - L) * u[a];
+    /* psd: the block has eigenvalues k (along u) and k (l - L)/l (twice,
+     * across u); clamping the latter at 0 is its exact PSD projection */
+    R tr = (l - L);
+    if (psd && RE(tr) < 0.0) tr = 0.0;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             R d2l = ((a == b ? 1.0 : 0.0) - u[a] * u[b]) / l;
-            Hb[a][b] = k * (u[a] * u[b] + (l - L) * d2l);
+            Hb[a][b] = k * (u[a] * u[b] + tr * d2l);
         }
 }
 
@@ -328,7 +333,7 @@ static void local_system(const oracle_model *M, const oracle_params *P, const In
         int o = M->springs[2 * s + (1 - end)];
         R xo[3] = {x[3 * o], x[3 * o + 1], x[3 * o + 2]};
         R g[3], Hb[3][3];
-        spring_block(xi, xo, M->spring_rest[s], M->spring_k, g, Hb);
+        spring_block(xi, xo, M->spring_rest[s], M->spring_k, P->spring_psd, g, Hb);
         for (int a = 0; a < 3; ++a) {
             f[a] -= g[a];
             for (int b = 0; b < 3; ++b) H[a][b] += Hb[a][b];
@@ -447,7 +452,7 @@ static double energy_G_impl(const oracle_model *M, const oracle_params *P, const
         G += 0.5 * M->spring_k * (l - M->spring_rest[s]) * (l - M->spring_rest[s]);
         if (grad || hess) {
             R g[3], Hb[3][3];
-            spring_block(xa, xb, M->spring_rest[s], M->spring_k, g, Hb);
+            spring_block(xa, xb, M->spring_rest[s], M->spring_k, P->spring_psd, g, Hb);
             for (int a = 0; a < 3; ++a) {
                 if (grad) { grad[3 * va + a] += RE(g[a]); grad[3 * vb + a] -= RE(g[a]); }
                 if (hess)
@@ -711,7 +716,7 @@ void oracle_spring_derivs(const double xa[3], const double xb[3], double L, doub
                           double grad[6], double hess[36])
 {
     double g[3], Hb[3][3];
-    spring_block(xa, xb, L, k, g, Hb);
+    spring_block(xa, xb, L, k, 0, g, Hb);
     for (int a = 0; a < 3; ++a) {
         grad[a] = g[a];
         grad[3 + a] = -g[a];
@@ -799,6 +804,9 @@ int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, cons
     memcpy(xnew, x, sizeof(double) * n3);
     for (int it = 1; it <= N; ++it) {
         for (int c = 0; c < C; ++c) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
             for (int i = 0; i < nv; ++i) {
                 if (M->colors[i] != c || M->pinned[i]) continue;
                 double f[3], H[3][3], dx[3];
@@ -829,6 +837,11 @@ int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, cons
             for (int l = 0; l < nv; ++l)
                 for (int a = 0; a < 3; ++a)
                     cur[3 * l + a] = (M->colors[l] < c) ? Sn[3 * l + a] : Sp[3 * l + a];
+            /* vertices of one color are independent; their scatters into
+             * neighbours (other colors) are summed with atomic adds */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
             for (int i = 0; i < nv; ++i) {
                 if (M->colors[i] != c || M->pinned[i]) continue;
                 double f[3], H[3][3], D[3], w[3];
@@ -872,7 +885,11 @@ int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, cons
                                 Mtw += Mkj[a][e2] * w[a];
                                 MtD += Mkj[a][e2] * D[a];
                             }
-                            xb[3 * vj + e2] += -Ktw - V * lam * (cD * Mtw + cw * MtD);
+                            const double add = -Ktw - V * lam * (cD * Mtw + cw * MtD);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                            xb[3 * vj + e2] += add;
                         }
                     }
                     double gk[3], Hkk[3][3];

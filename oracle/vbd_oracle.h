@@ -48,6 +48,7 @@ typedef struct {
     double kd;                 /* Rayleigh damping (Sec. 3.3) */
     double cheb_rho;           /* Chebyshev spectral radius (Sec. 3.8), 0 = off */
     double friction_mu, friction_eps_v;        /* Sec. 3.6 */
+    int32_t spring_psd;        /* 1: clamp the transverse spring stiffness at 0 */
 } oracle_params;
 
 typedef struct {

@@ -1,0 +1,968 @@
+// Host side of the VBD library: C ABI, topology preprocessing (FP64 rest
+// data, greedy coloring, color-sorted CSR), workspace layout, step
+// orchestration (plain / hipGraph / persistent), autotuner and profiling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vbd.h"
+#include "vbd_internal.h"
+
+using namespace vbd;
+
+namespace {
+
+thread_local std::string g_err;
+
+vbd_status fail(vbd_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(VBD_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t rec, tet_row, tet_ent, spr_row, spr_ent, perm, mass, color_off;
+    size_t x, xt, y, prev1, prev2, collided, flags;
+    size_t snaps, xbar, ybar, xtbar, vbar;
+    size_t total;
+    int max_bwd_iters;
+};
+
+struct GraphKey {
+    const void *x, *v, *vp, *E;
+    void *stream;
+    std::vector<uint32_t> params;
+    bool operator==(const GraphKey &o) const
+    {
+        return x == o.x && v == o.v && vp == o.vp && E == o.E && stream == o.stream && params == o.params;
+    }
+};
+
+struct ProfileEvent {
+    hipEvent_t a, b;
+    double bytes;
+    int64_t updates;
+};
+
+}  // namespace
+
+struct vbd_topology_s {
+    // description
+    int nv = 0, nt = 0, ns = 0, n_meshes = 1;
+    std::vector<int64_t> vert_off, tet_off;
+    std::vector<int32_t> tets, springs;
+    std::vector<double> rest, spring_L, mass, Dminv, vol;
+    std::vector<uint8_t> pinned;
+    double nu = 0.3, spring_k = 0.0;
+    // coloring and CSR
+    bool colored = false;
+    int n_colors = 0, n_free = 0;
+    std::vector<int32_t> colors, perm, iperm, color_off;
+    std::vector<int32_t> tet_row, tet_ent, spr_row, spr_nbr_orig;
+    std::vector<float> spr_len;
+    std::vector<double> phase_bytes;
+    std::vector<int64_t> phase_updates;
+    // device
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay{};
+    bool bound = false;
+    DevTopo dev{};
+    int n_cu = 0;
+    std::string arch;
+    LaunchCfg cfg{8, 256, 1, 0};
+    // graph cache
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;   // library-owned stream used only for capture
+    GraphKey gkey{};
+    bool have_graph = false;
+    // profiling
+    bool profiling = false;
+    std::vector<ProfileEvent> events;
+    vbd_profile_stats acc{};
+    ~vbd_topology_s()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (auto &e : events) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    }
+};
+
+namespace {
+
+// ----------------------------------------------------------------- layout --
+Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes ? bytes : 1); return o; };
+    const size_t nv = (size_t)T.nv;
+    L.rec = take(sizeof(TetRec) * (size_t)T.nt);
+    L.tet_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
+    L.tet_ent = take(sizeof(int32_t) * T.tet_ent.size());
+    L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
+    L.spr_ent = take(sizeof(int2) * T.spr_nbr_orig.size());
+    L.perm = take(sizeof(int32_t) * nv);
+    L.mass = take(sizeof(float) * nv);
+    L.color_off = take(sizeof(int32_t) * (size_t)(T.n_colors + 1));
+    L.x = take(sizeof(float4) * nv);
+    L.xt = take(sizeof(float4) * nv);
+    L.y = take(sizeof(float4) * nv);
+    L.prev1 = take(sizeof(float4) * nv);
+    L.prev2 = take(sizeof(float4) * nv);
+    L.collided = take(nv);
+    L.flags = take(sizeof(uint32_t) * 64);
+    L.max_bwd_iters = max_bwd_iters;
+    if (max_bwd_iters > 0) {
+        L.snaps = take(sizeof(float4) * nv * (size_t)(max_bwd_iters + 1));
+        L.xbar = take(sizeof(float4) * nv);
+        L.ybar = take(sizeof(float4) * nv);
+        L.xtbar = take(sizeof(float4) * nv);
+        L.vbar = take(sizeof(float4) * nv);
+    }
+    L.total = off;
+    return L;
+}
+
+void set_dev_pointers(vbd_topology_s &T)
+{
+    char *b = T.ws;
+    const Layout &L = T.lay;
+    DevTopo &D = T.dev;
+    D.rec = (TetRec *)(b + L.rec);
+    D.tet_row = (const int *)(b + L.tet_row);
+    D.tet_ent = (const int *)(b + L.tet_ent);
+    D.spr_row = (const int *)(b + L.spr_row);
+    D.spr_ent = (const int2 *)(b + L.spr_ent);
+    D.perm = (const int *)(b + L.perm);
+    D.mass = (const float *)(b + L.mass);
+    D.color_off = (const int *)(b + L.color_off);
+    D.x = (float4 *)(b + L.x);
+    D.xt = (float4 *)(b + L.xt);
+    D.y = (float4 *)(b + L.y);
+    D.prev1 = (float4 *)(b + L.prev1);
+    D.prev2 = (float4 *)(b + L.prev2);
+    D.collided = (unsigned char *)(b + L.collided);
+    D.flags = (unsigned *)(b + L.flags);
+    D.snaps = L.max_bwd_iters > 0 ? (float4 *)(b + L.snaps) : nullptr;
+    D.xbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xbar) : nullptr;
+    D.ybar = L.max_bwd_iters > 0 ? (float4 *)(b + L.ybar) : nullptr;
+    D.xtbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xtbar) : nullptr;
+    D.vbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.vbar) : nullptr;
+    D.n_verts = T.nv;
+    D.n_tets = T.nt;
+    D.n_free = T.n_free;
+    D.n_colors = T.n_colors;
+}
+
+// ------------------------------------------------------------- validation --
+vbd_status validate_params(const vbd_topology_s &T, const vbd_step_params *p)
+{
+    if (!p) return fail(VBD_E_INVALID_ARG, "params is NULL");
+    if (!(p->h > 0.f) || !std::isfinite(p->h)) return fail(VBD_E_INVALID_ARG, "h must be > 0");
+    if (p->n_iters < 1) return fail(VBD_E_INVALID_ARG, "n_iters must be >= 1");
+    if (p->init_mode < 0 || p->init_mode > 3) return fail(VBD_E_INVALID_ARG, "bad init_mode");
+    if (p->n_spheres < 0 || p->n_spheres > kMaxObstacles || p->n_planes < 0 ||
+        p->n_planes > kMaxObstacles)
+        return fail(VBD_E_INVALID_ARG, "at most %d spheres and %d planes", kMaxObstacles, kMaxObstacles);
+    if ((p->n_spheres > 0 && !p->spheres) || (p->n_planes > 0 && !p->planes))
+        return fail(VBD_E_INVALID_ARG, "obstacle array is NULL");
+    if (p->launch_mode < 0 || p->launch_mode > 3) return fail(VBD_E_INVALID_ARG, "bad launch_mode");
+    if (p->cheb_rho < 0.f || p->cheb_rho >= 1.f) return fail(VBD_E_INVALID_ARG, "cheb_rho must be in [0,1)");
+    if (p->kd < 0.f || p->friction_mu < 0.f || p->contact_k < 0.f)
+        return fail(VBD_E_INVALID_ARG, "kd, friction_mu, contact_k must be >= 0");
+    if (p->friction_mu > 0.f && !(p->friction_eps_v > 0.f))
+        return fail(VBD_E_INVALID_ARG, "friction_eps_v must be > 0");
+    (void)T;
+    return VBD_OK;
+}
+
+StepConsts make_consts(const vbd_topology_s &T, const vbd_step_params *p)
+{
+    StepConsts K{};
+    K.h = p->h;
+    K.inv_h = 1.0f / p->h;
+    K.gx = p->gravity[0]; K.gy = p->gravity[1]; K.gz = p->gravity[2];
+    K.gnorm = std::sqrt(K.gx * K.gx + K.gy * K.gy + K.gz * K.gz);
+    K.init_mode = p->init_mode;
+    K.det_eps_rel = p->det_eps_rel;
+    K.kc = p->contact_k;
+    K.delta = p->contact_thickness;
+    K.kd_over_h = p->kd / p->h;
+    K.fric_mu = p->friction_mu;
+    K.fric_hev = p->h * p->friction_eps_v;
+    K.cheb_rho = p->cheb_rho;
+    const double nu = T.nu;
+    const double k_mu = 1.0 / (2.0 * (1.0 + nu));
+    const double k_lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    K.k_mu = (float)k_mu;
+    K.k_lam = (float)k_lam;
+    K.alpha = (float)(1.0 + k_mu / k_lam);
+    K.spring_k = (float)T.spring_k;
+    K.spring_psd = p->spring_psd ? 1 : 0;
+    K.n_spheres = p->n_spheres;
+    K.n_planes = p->n_planes;
+    for (int i = 0; i < p->n_spheres; ++i)
+        K.spheres[i] = make_float4(p->spheres[4 * i], p->spheres[4 * i + 1], p->spheres[4 * i + 2],
+                                   p->spheres[4 * i + 3]);
+    for (int i = 0; i < p->n_planes; ++i) {
+        const float *q = p->planes + 4 * i;
+        const float n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        const float s = n > 0.f ? 1.0f / n : 0.f;
+        K.planes[i] = make_float4(q[0] * s, q[1] * s, q[2] * s, q[3] * s);
+    }
+    return K;
+}
+
+// --------------------------------------------------------------- coloring --
+// First-fit greedy over the union adjacency of tets and springs, vertices in
+// ascending id; neighbour colors are tracked in a growable bitset.
+void greedy_color(vbd_topology_s &T)
+{
+    const int nv = T.nv;
+    std::vector<std::vector<int32_t>> adj(nv);
+    for (int t = 0; t < T.nt; ++t) {
+        const int32_t *q = &T.tets[4 * (size_t)t];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (a != b && q[b] < q[a]) adj[q[a]].push_back(q[b]);
+    }
+    for (int s = 0; s < T.ns; ++s) {
+        const int a = T.springs[2 * (size_t)s], b = T.springs[2 * (size_t)s + 1];
+        if (b < a) adj[a].push_back(b);
+        else adj[b].push_back(a);
+    }
+    T.colors.assign(nv, 0);
+    int nc = 0;
+    std::vector<uint64_t> used;
+    for (int v = 0; v < nv; ++v) {
+        used.assign((size_t)(nc / 64 + 1), 0ull);
+        for (int32_t u : adj[v]) {
+            const int c = T.colors[u];
+            used[(size_t)c >> 6] |= 1ull << (c & 63);
+        }
+        int c = 0;
+        for (size_t w = 0; w < used.size(); ++w) {
+            if (~used[w]) {
+                c = (int)(w * 64) + __builtin_ctzll(~used[w]);
+                break;
+            }
+            c = (int)((w + 1) * 64);
+        }
+        T.colors[v] = c;
+        nc = std::max(nc, c + 1);
+    }
+    T.n_colors = nc;
+}
+
+void build_csr(vbd_topology_s &T)
+{
+    const int nv = T.nv;
+    // permutation: free vertices by (color, id), then pinned by id
+    std::vector<int32_t> count(T.n_colors + 1, 0);
+    int n_free = 0;
+    for (int v = 0; v < nv; ++v)
+        if (!T.pinned[v]) { count[T.colors[v] + 1]++; ++n_free; }
+    T.color_off.assign(T.n_colors + 1, 0);
+    for (int c = 0; c < T.n_colors; ++c) T.color_off[c + 1] = T.color_off[c] + count[c + 1];
+    T.n_free = n_free;
+    T.perm.assign(nv, 0);
+    T.iperm.assign(nv, 0);
+    std::vector<int32_t> fill(T.color_off.begin(), T.color_off.end());
+    int pin_slot = n_free;
+    for (int v = 0; v < nv; ++v) {
+        const int slot = T.pinned[v] ? pin_slot++ : fill[T.colors[v]]++;
+        T.perm[slot] = v;
+        T.iperm[v] = slot;
+    }
+    // tet incidence of free vertices, ascending tet id
+    std::vector<int32_t> deg(n_free + 1, 0);
+    for (int t = 0; t < T.nt; ++t)
+        for (int k = 0; k < 4; ++k) {
+            const int s = T.iperm[T.tets[4 * (size_t)t + k]];
+            if (s < n_free) deg[s + 1]++;
+        }
+    T.tet_row.assign(n_free + 1, 0);
+    for (int s = 0; s < n_free; ++s) T.tet_row[s + 1] = T.tet_row[s] + deg[s + 1];
+    T.tet_ent.assign((size_t)T.tet_row[n_free], 0);
+    std::vector<int32_t> pos(T.tet_row.begin(), T.tet_row.end() - 1);
+    for (int t = 0; t < T.nt; ++t)
+        for (int k = 0; k < 4; ++k) {
+            const int s = T.iperm[T.tets[4 * (size_t)t + k]];
+            if (s < n_free) T.tet_ent[pos[s]++] = (t << 2) | k;
+        }
+    // spring incidence, ascending spring id
+    std::vector<int32_t> sdeg(n_free + 1, 0);
+    for (int e = 0; e < T.ns; ++e)
+        for (int k = 0; k < 2; ++k) {
+            const int s = T.iperm[T.springs[2 * (size_t)e + k]];
+            if (s < n_free) sdeg[s + 1]++;
+        }
+    T.spr_row.assign(n_free + 1, 0);
+    for (int s = 0; s < n_free; ++s) T.spr_row[s + 1] = T.spr_row[s] + sdeg[s + 1];
+    T.spr_nbr_orig.assign((size_t)T.spr_row[n_free], 0);
+    T.spr_len.assign((size_t)T.spr_row[n_free], 0.f);
+    std::vector<int32_t> spos(T.spr_row.begin(), T.spr_row.end() - 1);
+    for (int e = 0; e < T.ns; ++e)
+        for (int k = 0; k < 2; ++k) {
+            const int s = T.iperm[T.springs[2 * (size_t)e + k]];
+            if (s < n_free) {
+                T.spr_nbr_orig[spos[s]] = T.springs[2 * (size_t)e + 1 - k];
+                T.spr_len[spos[s]] = (float)T.spring_L[e];
+                spos[s]++;
+            }
+        }
+    // algorithmic bytes of one color solve: 64 B tet record + 4 B CSR entry per
+    // tet pair, 8 B per spring entry, 4 B row offset and 48 B own state
+    // (x read, y read, x write) per vertex, 16 B per distinct neighbour position.
+    T.phase_bytes.assign(T.n_colors, 0.0);
+    T.phase_updates.assign(T.n_colors, 0);
+    std::vector<int32_t> stamp(nv, -1);
+    for (int c = 0; c < T.n_colors; ++c) {
+        double bytes = 0;
+        int64_t distinct = 0;
+        for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
+            const int pairs = T.tet_row[s + 1] - T.tet_row[s];
+            const int sp = T.spr_row[s + 1] - T.spr_row[s];
+            bytes += 68.0 * pairs + 8.0 * sp + 4.0 + 48.0;
+            for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
+                const int t = T.tet_ent[e] >> 2;
+                for (int k = 0; k < 4; ++k) {
+                    const int u = T.iperm[T.tets[4 * (size_t)t + k]];
+                    if (u != s && stamp[u] != c) { stamp[u] = c; ++distinct; }
+                }
+            }
+            for (int e = T.spr_row[s]; e < T.spr_row[s + 1]; ++e) {
+                const int u = T.iperm[T.spr_nbr_orig[e]];
+                if (stamp[u] != c) { stamp[u] = c; ++distinct; }
+            }
+        }
+        T.phase_bytes[c] = bytes + 16.0 * (double)distinct;
+        T.phase_updates[c] = T.color_off[c + 1] - T.color_off[c];
+    }
+}
+
+// --------------------------------------------------------------- profiling --
+vbd_status prof_begin(vbd_topology_s &T, hipStream_t s, ProfileEvent &ev)
+{
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventRecord(ev.a, s));
+    (void)T;
+    return VBD_OK;
+}
+
+// ------------------------------------------------------------ enqueue step --
+vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
+                        float *x, float *v, float *vp, const float *E, hipStream_t s,
+                        bool persistent, bool in_capture)
+{
+    const bool tets = T.nt > 0, springs = T.ns > 0;
+    HIP_TRY(launch_material(T.dev, E, K, s));
+    HIP_TRY(launch_predict(T.dev, x, v, vp, K, persistent, s));
+    const bool prof = T.profiling && !in_capture;
+    if (persistent) {
+        ProfileEvent ev{};
+        if (prof) {
+            vbd_status st = prof_begin(T, s, ev);
+            if (st) return st;
+        }
+        int grid = 0;
+        HIP_TRY(launch_persistent(T.dev, K, p->n_iters, tets, springs, T.cfg, T.n_cu,
+                                  /*cooperative=*/!in_capture, s, &grid));
+        if (prof) {
+            HIP_TRY(hipEventRecord(ev.b, s));
+            double bytes = 0;
+            int64_t upd = 0;
+            for (int c = 0; c < T.n_colors; ++c) { bytes += T.phase_bytes[c]; upd += T.phase_updates[c]; }
+            ev.bytes = bytes * p->n_iters;
+            ev.updates = upd * p->n_iters;
+            T.events.push_back(ev);
+        }
+    } else {
+        for (int it = 1; it <= p->n_iters; ++it) {
+            for (int c = 0; c < T.n_colors; ++c) {
+                ProfileEvent ev{};
+                if (prof) {
+                    vbd_status st = prof_begin(T, s, ev);
+                    if (st) return st;
+                }
+                HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], tets, springs, T.cfg, s));
+                if (prof) {
+                    HIP_TRY(hipEventRecord(ev.b, s));
+                    ev.bytes = T.phase_bytes[c];
+                    ev.updates = T.phase_updates[c];
+                    T.events.push_back(ev);
+                }
+            }
+            if (p->cheb_rho > 0.f) HIP_TRY(launch_cheb(T.dev, K, it, s));
+        }
+    }
+    HIP_TRY(launch_finalize(T.dev, x, v, vp, K, s));
+    return VBD_OK;
+}
+
+GraphKey make_key(const vbd_step_params *p, const void *x, const void *v, const void *vp,
+                  const void *E, void *stream)
+{
+    GraphKey k;
+    k.x = x; k.v = v; k.vp = vp; k.E = E; k.stream = stream;
+    auto push = [&](const void *src, size_t n) {
+        const uint32_t *w = (const uint32_t *)src;
+        for (size_t i = 0; i < n / 4; ++i) k.params.push_back(w[i]);
+    };
+    push(&p->h, 4); push(&p->n_iters, 4); push(p->gravity, 12); push(&p->init_mode, 4);
+    push(&p->det_eps_rel, 4); push(&p->contact_k, 4); push(&p->contact_thickness, 4);
+    push(&p->n_spheres, 4); if (p->n_spheres) push(p->spheres, 16 * (size_t)p->n_spheres);
+    push(&p->n_planes, 4); if (p->n_planes) push(p->planes, 16 * (size_t)p->n_planes);
+    push(&p->kd, 4); push(&p->cheb_rho, 4); push(&p->friction_mu, 4); push(&p->friction_eps_v, 4);
+    push(&p->spring_psd, 4);
+    push(&p->launch_mode, 4);
+    return k;
+}
+
+// autotune cache: (arch, log2 size buckets, kinds, persistent) -> config
+std::mutex g_tune_mu;
+std::map<std::tuple<std::string, int, int, int, int, int>, LaunchCfg> g_tune_cache;
+
+int log2_bucket(int64_t n)
+{
+    int b = 0;
+    while (n > 1) { n >>= 1; ++b; }
+    return b;
+}
+
+}  // namespace
+
+// ===================================================================== ABI ==
+extern "C" {
+
+const char *vbd_last_error(void) { return g_err.c_str(); }
+
+vbd_status vbd_build_topology(const vbd_mesh_desc *d, vbd_topology *out)
+{
+    if (!d || !out) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (d->n_verts < 0 || d->n_tets < 0 || d->n_springs < 0 || d->n_meshes < 1)
+        return fail(VBD_E_INVALID_ARG, "negative counts or n_meshes < 1");
+    if (d->n_verts > 0 && !d->rest_pos) return fail(VBD_E_INVALID_ARG, "rest_pos is NULL");
+    if (d->n_tets > 0 && !d->tets) return fail(VBD_E_INVALID_ARG, "tets is NULL");
+    if (d->n_springs > 0 && !d->springs) return fail(VBD_E_INVALID_ARG, "springs is NULL");
+    if (d->n_tets > (1 << 29)) return fail(VBD_E_INVALID_ARG, "too many tets (max 2^29)");
+    if (!(d->poisson_nu >= 0.0 && d->poisson_nu < 0.5) && d->n_tets > 0)
+        return fail(VBD_E_INVALID_ARG, "poisson_nu must be in [0, 0.5)");
+    if (d->n_meshes > 1 && (!d->vert_offsets || !d->tet_offsets))
+        return fail(VBD_E_INVALID_ARG, "batched description needs vert_offsets and tet_offsets");
+    auto *T = new vbd_topology_s();
+    T->nv = d->n_verts; T->nt = d->n_tets; T->ns = d->n_springs; T->n_meshes = d->n_meshes;
+    T->nu = d->poisson_nu;
+    T->spring_k = d->spring_k;
+    T->rest.assign(d->rest_pos, d->rest_pos + 3 * (size_t)d->n_verts);
+    if (d->n_tets) T->tets.assign(d->tets, d->tets + 4 * (size_t)d->n_tets);
+    if (d->n_springs) T->springs.assign(d->springs, d->springs + 2 * (size_t)d->n_springs);
+    T->pinned.assign(d->n_verts, 0);
+    if (d->pinned)
+        for (int i = 0; i < d->n_verts; ++i) T->pinned[i] = d->pinned[i] ? 1 : 0;
+    if (d->n_meshes > 1) {
+        T->vert_off.assign(d->vert_offsets, d->vert_offsets + d->n_meshes + 1);
+        T->tet_off.assign(d->tet_offsets, d->tet_offsets + d->n_meshes + 1);
+    } else {
+        T->vert_off = {0, d->n_verts};
+        T->tet_off = {0, d->n_tets};
+    }
+    auto reject = [&](vbd_status s, const char *fmt, auto... a) {
+        delete T;
+        return fail(s, fmt, a...);
+    };
+    if (T->vert_off.front() != 0 || T->vert_off.back() != d->n_verts || T->tet_off.front() != 0 ||
+        T->tet_off.back() != d->n_tets)
+        return reject(VBD_E_INVALID_ARG, "offsets must start at 0 and end at the counts");
+    for (int m = 0; m < T->n_meshes; ++m)
+        if (T->vert_off[m + 1] < T->vert_off[m] || T->tet_off[m + 1] < T->tet_off[m])
+            return reject(VBD_E_INVALID_ARG, "offsets must be non-decreasing");
+    // tets: ids in range, distinct, inside their mesh; FP64 rest data
+    T->Dminv.assign(9 * (size_t)T->nt, 0.0);
+    T->vol.assign(T->nt, 0.0);
+    for (int m = 0; m < T->n_meshes; ++m) {
+        for (int64_t t = T->tet_off[m]; t < T->tet_off[m + 1]; ++t) {
+            const int32_t *q = &T->tets[4 * (size_t)t];
+            for (int a = 0; a < 4; ++a) {
+                if (q[a] < T->vert_off[m] || q[a] >= T->vert_off[m + 1])
+                    return reject(VBD_E_TOPOLOGY, "tet %lld vertex %d out of range of mesh %d",
+                                  (long long)t, q[a], m);
+                for (int b = 0; b < a; ++b)
+                    if (q[a] == q[b]) return reject(VBD_E_TOPOLOGY, "tet %lld repeats vertex %d", (long long)t, q[a]);
+            }
+            double D[3][3];
+            double lmax = 0.0;
+            for (int c = 0; c < 3; ++c)
+                for (int r = 0; r < 3; ++r) {
+                    D[r][c] = T->rest[3 * (size_t)q[c + 1] + r] - T->rest[3 * (size_t)q[0] + r];
+                    lmax = std::max(lmax, std::fabs(D[r][c]));
+                }
+            // adjugate inverse
+            const double A00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+            const double A01 = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+            const double A02 = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+            const double A10 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+            const double A11 = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+            const double A12 = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+            const double A20 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+            const double A21 = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+            const double A22 = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+            const double det = D[0][0] * A00 + D[0][1] * A10 + D[0][2] * A20;
+            if (!(std::fabs(det) > 1e-12 * lmax * lmax * lmax))
+                return reject(VBD_E_TOPOLOGY, "tet %lld is degenerate in the rest shape", (long long)t);
+            const double inv = 1.0 / det;
+            const double Ai[9] = {A00, A01, A02, A10, A11, A12, A20, A21, A22};
+            for (int k = 0; k < 9; ++k) T->Dminv[9 * (size_t)t + k] = Ai[k] * inv;
+            T->vol[t] = std::fabs(det) / 6.0;
+        }
+    }
+    // springs
+    T->spring_L.assign(T->ns, 0.0);
+    for (int s = 0; s < T->ns; ++s) {
+        const int a = T->springs[2 * (size_t)s], b = T->springs[2 * (size_t)s + 1];
+        if (a < 0 || a >= T->nv || b < 0 || b >= T->nv)
+            return reject(VBD_E_TOPOLOGY, "spring %d endpoint out of range", s);
+        if (a == b) return reject(VBD_E_TOPOLOGY, "spring %d connects a vertex to itself", s);
+        double L;
+        if (d->spring_rest) {
+            L = d->spring_rest[s];
+        } else {
+            double d2 = 0;
+            for (int r = 0; r < 3; ++r) {
+                const double dd = T->rest[3 * (size_t)a + r] - T->rest[3 * (size_t)b + r];
+                d2 += dd * dd;
+            }
+            L = std::sqrt(d2);
+        }
+        if (!(L > 0.0)) return reject(VBD_E_TOPOLOGY, "spring %d has zero rest length", s);
+        T->spring_L[s] = L;
+    }
+    // masses
+    if (d->mass) {
+        T->mass.assign(d->mass, d->mass + d->n_verts);
+    } else {
+        T->mass.assign(T->nv, 0.0);
+        for (int t = 0; t < T->nt; ++t)
+            for (int a = 0; a < 4; ++a) T->mass[T->tets[4 * (size_t)t + a]] += d->density * T->vol[t] / 4.0;
+    }
+    for (int i = 0; i < T->nv; ++i)
+        if (!(T->mass[i] > 0.0) && !T->pinned[i])
+            return reject(VBD_E_TOPOLOGY, "free vertex %d has no mass", i);
+    *out = T;
+    return VBD_OK;
+}
+
+vbd_status vbd_color(vbd_topology T, int32_t *n_colors_out, int32_t *colors_out)
+{
+    if (!T) return fail(VBD_E_INVALID_ARG, "NULL topology");
+    if (!T->colored) {
+        greedy_color(*T);
+        build_csr(*T);
+        T->colored = true;
+    }
+    if (n_colors_out) *n_colors_out = T->n_colors;
+    if (colors_out) std::copy(T->colors.begin(), T->colors.end(), colors_out);
+    return VBD_OK;
+}
+
+vbd_status vbd_workspace_size(vbd_topology T, int32_t max_backward_iters, size_t *bytes)
+{
+    if (!T || !bytes) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color first");
+    if (max_backward_iters < 0) return fail(VBD_E_INVALID_ARG, "max_backward_iters < 0");
+    *bytes = make_layout(*T, max_backward_iters).total;
+    return VBD_OK;
+}
+
+vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void *stream)
+{
+    if (!T || !dev_ptr) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color first");
+    if ((uintptr_t)dev_ptr % kAlign) return fail(VBD_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    // the largest backward iteration count that fits
+    Layout L0 = make_layout(*T, 0);
+    if (bytes < L0.total) return fail(VBD_E_NO_WORKSPACE, "workspace too small: %zu < %zu", bytes, L0.total);
+    int nb = 0;
+    {
+        // largest backward iteration count whose layout fits: estimate from
+        // the snapshot size (an upper bound), then step down until it fits
+        Layout L1 = make_layout(*T, 1);
+        const size_t snap = sizeof(float4) * (size_t)T->nv;
+        if (bytes >= L1.total) nb = 2 + (int)std::min<size_t>((bytes - L1.total) / (snap ? snap : 1), 1 << 20);
+        while (nb > 0 && make_layout(*T, nb).total > bytes) --nb;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    T->n_cu = prop.multiProcessorCount;
+    T->arch = prop.gcnArchName;
+    T->ws = (char *)dev_ptr;
+    T->ws_bytes = bytes;
+    T->lay = make_layout(*T, nb);
+    set_dev_pointers(*T);
+    // host staging of every static array
+    std::vector<TetRec> rec(T->nt);
+    for (int t = 0; t < T->nt; ++t) {
+        const int32_t *q = &T->tets[4 * (size_t)t];
+        const double *B = &T->Dminv[9 * (size_t)t];
+        rec[t].ids = make_int4(T->iperm[q[0]], T->iperm[q[1]], T->iperm[q[2]], T->iperm[q[3]]);
+        rec[t].b0 = make_float4((float)B[0], (float)B[1], (float)B[2], (float)B[3]);
+        rec[t].b1 = make_float4((float)B[4], (float)B[5], (float)B[6], (float)B[7]);
+        rec[t].b2 = make_float4((float)B[8], 0.f, 0.f, (float)T->vol[t]);
+    }
+    std::vector<int2> spr(T->spr_nbr_orig.size());
+    for (size_t e = 0; e < spr.size(); ++e) {
+        float L = T->spr_len[e];
+        int bits;
+        std::memcpy(&bits, &L, 4);
+        spr[e] = make_int2(T->iperm[T->spr_nbr_orig[e]], bits);
+    }
+    std::vector<float> massp(T->nv);
+    for (int sl = 0; sl < T->nv; ++sl) massp[sl] = (float)T->mass[T->perm[sl]];
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(T->ws + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIP_TRY(up(T->lay.rec, rec.data(), sizeof(TetRec) * rec.size()));
+    HIP_TRY(up(T->lay.tet_row, T->tet_row.data(), 4 * T->tet_row.size()));
+    HIP_TRY(up(T->lay.tet_ent, T->tet_ent.data(), 4 * T->tet_ent.size()));
+    HIP_TRY(up(T->lay.spr_row, T->spr_row.data(), 4 * T->spr_row.size()));
+    HIP_TRY(up(T->lay.spr_ent, spr.data(), sizeof(int2) * spr.size()));
+    HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));
+    HIP_TRY(up(T->lay.mass, massp.data(), 4 * massp.size()));
+    HIP_TRY(up(T->lay.color_off, T->color_off.data(), 4 * T->color_off.size()));
+    HIP_TRY(launch_zero_u32(T->dev.flags, 64, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    T->bound = true;
+    if (T->have_graph) {
+        (void)hipGraphExecDestroy(T->gexec);
+        (void)hipGraphDestroy(T->graph);
+        T->gexec = nullptr; T->graph = nullptr; T->have_graph = false;
+    }
+    return VBD_OK;
+}
+
+vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t bytes)
+{
+    if (!T || !out) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    auto give = [&](const void *src, size_t n) -> vbd_status {
+        if (bytes < n) return fail(VBD_E_INVALID_ARG, "output buffer too small (%zu < %zu)", bytes, n);
+        if (n) std::memcpy(out, src, n);
+        return VBD_OK;
+    };
+    if (what == VBD_Q_COUNTS) {
+        int64_t c[8] = {T->nv, T->nt, T->ns, T->n_colors, T->n_free, (int64_t)T->tet_ent.size(),
+                        (int64_t)T->spr_nbr_orig.size(), T->n_meshes};
+        return give(c, sizeof(c));
+    }
+    if (what == VBD_Q_MASS) return give(T->mass.data(), 8 * T->mass.size());
+    if (what == VBD_Q_DMINV) return give(T->Dminv.data(), 8 * T->Dminv.size());
+    if (what == VBD_Q_VOLUME) return give(T->vol.data(), 8 * T->vol.size());
+    if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color first");
+    switch (what) {
+    case VBD_Q_COLORS: return give(T->colors.data(), 4 * T->colors.size());
+    case VBD_Q_PERM: return give(T->perm.data(), 4 * T->perm.size());
+    case VBD_Q_COLOR_OFFSETS: return give(T->color_off.data(), 4 * T->color_off.size());
+    case VBD_Q_TET_ROWS: return give(T->tet_row.data(), 4 * T->tet_row.size());
+    case VBD_Q_TET_ENTRIES: return give(T->tet_ent.data(), 4 * T->tet_ent.size());
+    case VBD_Q_SPRING_ROWS: return give(T->spr_row.data(), 4 * T->spr_row.size());
+    case VBD_Q_SPRING_NBRS: return give(T->spr_nbr_orig.data(), 4 * T->spr_nbr_orig.size());
+    case VBD_Q_PHASE_BYTES: return give(T->phase_bytes.data(), 8 * T->phase_bytes.size());
+    default: return fail(VBD_E_INVALID_ARG, "unknown query %d", what);
+    }
+}
+
+vbd_status vbd_topology_destroy(vbd_topology T)
+{
+    delete T;
+    return VBD_OK;
+}
+
+static vbd_status check_ready(vbd_topology T)
+{
+    if (!T) return fail(VBD_E_INVALID_ARG, "NULL topology");
+    if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color before stepping");
+    if (!T->bound) return fail(VBD_E_NO_WORKSPACE, "call vbd_bind_workspace before stepping");
+    return VBD_OK;
+}
+
+vbd_status vbd_step(vbd_topology T, const vbd_step_params *p, float *x, float *v, float *vp,
+                    const float *E, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if ((st = validate_params(*T, p))) return st;
+    if (T->nv > 0 && (!x || !v || !vp)) return fail(VBD_E_INVALID_ARG, "state pointer is NULL");
+    if (T->nt > 0 && !E) return fail(VBD_E_INVALID_ARG, "tet_E is NULL");
+    const StepConsts K = make_consts(*T, p);
+    hipStream_t s = (hipStream_t)stream;
+    const int mode = p->launch_mode;
+    const bool persistent = mode == VBD_LAUNCH_PERSISTENT || mode == VBD_LAUNCH_PERSISTENT_GRAPH;
+    if (T->nv == 0) return VBD_OK;
+    if (mode == VBD_LAUNCH_PLAIN || mode == VBD_LAUNCH_PERSISTENT || T->profiling)
+        return enqueue_step(*T, p, K, x, v, vp, E, s, persistent, false);
+    // graph modes: capture once per (pointers, parameters, stream), replay after
+    GraphKey key = make_key(p, x, v, vp, E, stream);
+    if (!T->have_graph || !(key == T->gkey)) {
+        if (T->have_graph) {
+            (void)hipGraphExecDestroy(T->gexec);
+            (void)hipGraphDestroy(T->graph);
+            T->have_graph = false;
+        }
+        // capture on a library-owned stream (the caller's may be the null
+        // stream, which cannot be captured); the graph is launched on `s`
+        if (!T->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&T->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(T->cap_stream, hipStreamCaptureModeThreadLocal));
+        vbd_status cs = enqueue_step(*T, p, K, x, v, vp, E, T->cap_stream, persistent, true);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(T->cap_stream, &g);
+        if (cs != VBD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ce != hipSuccess) return fail(VBD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+        HIP_TRY(hipGraphInstantiate(&T->gexec, g, nullptr, nullptr, 0));
+        T->graph = g;
+        T->gkey = key;
+        T->have_graph = true;
+    }
+    HIP_TRY(hipGraphLaunch(T->gexec, s));
+    return VBD_OK;
+}
+
+vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const float *x_t,
+                             const float *v_t, const float *v_prev, const float *E,
+                             const float *gx_out, const float *gv_out, const float *gvp_out,
+                             float *gx_in, float *gv_in, float *gvp_in, float *g_E, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if ((st = validate_params(*T, p))) return st;
+    if (T->ns > 0 || p->n_spheres > 0 || p->n_planes > 0 || p->kd != 0.f || p->cheb_rho > 0.f ||
+        p->friction_mu > 0.f)
+        return fail(VBD_E_UNSUPPORTED, "backward supports tets, inertia and pins only");
+    if (p->n_iters > T->lay.max_bwd_iters)
+        return fail(VBD_E_NO_WORKSPACE, "workspace holds %d backward iterations, need %d",
+                    T->lay.max_bwd_iters, p->n_iters);
+    if (T->nv == 0) return VBD_OK;
+    if (!x_t || !v_t || !v_prev || !gx_out || !gv_out || !gvp_out || !gx_in || !gv_in || !gvp_in ||
+        (T->nt > 0 && (!E || !g_E)))
+        return fail(VBD_E_INVALID_ARG, "NULL array");
+    const StepConsts K = make_consts(*T, p);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nv = (size_t)T->nv;
+    // forward recompute, snapshot n = iterate after iteration n
+    DevTopo D = T->dev;
+    D.x = D.snaps;
+    HIP_TRY(launch_material(D, E, K, s));
+    HIP_TRY(launch_predict(D, x_t, v_t, v_prev, K, false, s));
+    for (int it = 1; it <= p->n_iters; ++it) {
+        float4 *Sn = T->dev.snaps + nv * it;
+        HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
+        D.x = Sn;
+        for (int c = 0; c < T->n_colors; ++c)
+            HIP_TRY(launch_solve(D, K, T->color_off[c], T->color_off[c + 1], true, false, T->cfg, s));
+    }
+    // reverse sweep
+    HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
+    for (int it = p->n_iters; it >= 1; --it) {
+        const float4 *Sn = T->dev.snaps + nv * it, *Sp = Sn - nv;
+        for (int c = T->n_colors - 1; c >= 0; --c)
+            HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T->color_off[c], T->color_off[c + 1], g_E,
+                                         T->cfg, s));
+    }
+    HIP_TRY(launch_bwd_final(D, v_t, v_prev, gx_in, gv_in, gvp_in, K, s));
+    return VBD_OK;
+}
+
+vbd_status vbd_get_launch_config(vbd_topology T, vbd_launch_config *c)
+{
+    if (!T || !c) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    c->lanes_per_vertex = T->cfg.lanes;
+    c->block_size = T->cfg.block;
+    c->xcd_remap = T->cfg.xcd_remap;
+    c->blocks_per_cu = T->cfg.blocks_per_cu;
+    return VBD_OK;
+}
+
+vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
+{
+    if (!T || !c) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    const int L = c->lanes_per_vertex;
+    if (L != 4 && L != 8 && L != 16 && L != 32) return fail(VBD_E_INVALID_ARG, "lanes_per_vertex must be 4, 8, 16 or 32");
+    if (c->block_size < 64 || c->block_size > 1024 || c->block_size % 64)
+        return fail(VBD_E_INVALID_ARG, "block_size must be a multiple of 64 in [64, 1024]");
+    if (c->blocks_per_cu < 0) return fail(VBD_E_INVALID_ARG, "blocks_per_cu < 0");
+    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu};
+    if (T->have_graph) {
+        (void)hipGraphExecDestroy(T->gexec);
+        (void)hipGraphDestroy(T->graph);
+        T->gexec = nullptr; T->graph = nullptr; T->have_graph = false;
+    }
+    return VBD_OK;
+}
+
+vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x, const float *v,
+                        const float *vp, const float *E, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if ((st = validate_params(*T, p))) return st;
+    const bool persistent = p->launch_mode >= VBD_LAUNCH_PERSISTENT;
+    const auto key = std::make_tuple(T->arch, log2_bucket(T->nv), log2_bucket(T->nt),
+                                     log2_bucket(T->ns), persistent ? 1 : 0, T->n_colors);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            T->cfg = it->second;
+            return VBD_OK;
+        }
+    }
+    const StepConsts K = make_consts(*T, p);
+    hipStream_t s = (hipStream_t)stream;
+    const bool tets = T->nt > 0, springs = T->ns > 0;
+    std::vector<LaunchCfg> cands;
+    for (int L : {4, 8, 16})
+        for (int B : {128, 256, 512})
+            for (int rm : {0, 1}) {
+                if (persistent)
+                    for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc});
+                else
+                    cands.push_back(LaunchCfg{L, B, rm, 0});
+            }
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    const int sweeps = std::max(1, std::min(p->n_iters, 8));
+    float best = 1e30f;
+    LaunchCfg best_cfg = T->cfg;
+    for (const LaunchCfg &cf : cands) {
+        HIP_TRY(launch_material(T->dev, E, K, s));
+        HIP_TRY(launch_predict(T->dev, x, v, vp, K, true, s));
+        HIP_TRY(hipEventRecord(a, s));
+        if (persistent) {
+            hipError_t e = launch_persistent(T->dev, K, sweeps, tets, springs, cf, T->n_cu, true, s, nullptr);
+            if (e != hipSuccess) { (void)hipGetLastError(); continue; }
+        } else {
+            for (int it = 0; it < sweeps; ++it)
+                for (int c = 0; c < T->n_colors; ++c)
+                    HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], tets, springs, cf, s));
+        }
+        HIP_TRY(hipEventRecord(b, s));
+        HIP_TRY(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, a, b));
+        if (persistent) {
+            // a configuration whose blocks were not all resident trips the
+            // barrier guard: discard it and clear the flag
+            uint32_t f[2] = {0, 0};
+            HIP_TRY(hipMemcpy(f, T->dev.flags, sizeof(f), hipMemcpyDeviceToHost));
+            if (f[1] != 0) {
+                HIP_TRY(launch_zero_u32(T->dev.flags + 1, 5, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                continue;
+            }
+        }
+        if (ms < best) { best = ms; best_cfg = cf; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    T->cfg = best_cfg;
+    if (T->have_graph) {
+        (void)hipGraphExecDestroy(T->gexec);
+        (void)hipGraphDestroy(T->graph);
+        T->gexec = nullptr; T->graph = nullptr; T->have_graph = false;
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best_cfg;
+    return VBD_OK;
+}
+
+vbd_status vbd_profile_enable(vbd_topology T, int32_t enable)
+{
+    if (!T) return fail(VBD_E_INVALID_ARG, "NULL topology");
+    T->profiling = enable != 0;
+    return VBD_OK;
+}
+
+vbd_status vbd_profile_read(vbd_topology T, vbd_profile_stats *out, int32_t reset)
+{
+    if (!T || !out) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    for (auto &e : T->events) {
+        HIP_TRY(hipEventSynchronize(e.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+        T->acc.n_launches += 1;
+        T->acc.total_ms += ms;
+        T->acc.total_bytes += e.bytes;
+        T->acc.n_vertex_updates += e.updates;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    T->events.clear();
+    *out = T->acc;
+    if (reset) T->acc = vbd_profile_stats{};
+    return VBD_OK;
+}
+
+vbd_status vbd_check(vbd_topology T, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(f, T->dev.flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (f[1] != 0) {
+        HIP_TRY(launch_zero_u32(T->dev.flags + 1, 1, s));
+        HIP_TRY(launch_zero_u32(T->dev.flags + 3, 3, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return fail(VBD_E_DEVICE,
+                    "persistent kernel barrier timed out: arrivals seen %u of target %u, grid %u blocks "
+                    "(%d CUs)", f[3], f[4], f[5], T->n_cu);
+    }
+    return VBD_OK;
+}
+
+vbd_status vbd_probe_copy(void *dst, const void *src, size_t n_bytes, void *stream)
+{
+    if (!dst || !src || n_bytes % 16) return fail(VBD_E_INVALID_ARG, "bad copy arguments");
+    if (n_bytes / 16 > (size_t)INT32_MAX) return fail(VBD_E_INVALID_ARG, "copy too large");
+    HIP_TRY(launch_copy4((float4 *)dst, (const float4 *)src, (int)(n_bytes / 16), (hipStream_t)stream));
+    return VBD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the host orchestration (vbd_host.cpp) and
+// the gfx950 kernels (vbd_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace vbd {
+
+// 64-byte tet record, color-sorted vertex ids.
+//   ids = the 4 vertex slots (permuted ids)
+//   b0  = {B00, B01, B02, B10}, b1 = {B11, B12, B20, B21},
+//   b2  = {B22, V*mu, V*lambda, V}
+// B = inverse rest edge matrix (row l = gradient of the shape function of
+// slot l+1).  V*mu and V*lambda are rewritten from the per-tet Young's
+// modulus at the start of every step.
+struct __align__(16) TetRec {
+    int4 ids;
+    float4 b0, b1, b2;
+};
+static_assert(sizeof(TetRec) == 64, "tet record must be 64 bytes");
+
+constexpr int kMaxObstacles = 8;
+
+// Per-step constants passed by value to every kernel.
+struct StepConsts {
+    float h, inv_h;
+    float gx, gy, gz, gnorm;       // external acceleration and its norm
+    int init_mode;
+    float det_eps_rel;
+    float kc, delta;               // penalty stiffness and contact distance
+    float kd_over_h;               // Rayleigh damping k_d / h
+    float fric_mu, fric_hev;       // friction coefficient and h * eps_v
+    float cheb_rho;
+    float alpha;                   // 1 + mu/lambda (depends on nu only)
+    float k_mu, k_lam;             // mu / E and lambda / E
+    float spring_k;
+    int spring_psd;
+    int n_spheres, n_planes;
+    float4 spheres[kMaxObstacles]; // cx, cy, cz, R
+    float4 planes[kMaxObstacles];  // unit normal, offset
+};
+
+// Device-side view of a bound workspace.
+struct DevTopo {
+    TetRec *rec;
+    const int *tet_row, *tet_ent;      // CSR over free permuted vertices
+    const int *spr_row;
+    const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
+    const int *perm;                   // permuted slot -> original id
+    const float *mass;                 // permuted
+    const int *color_off;              // [n_colors + 1]
+    float4 *x, *xt, *y;                // current iterate, x^t, inertia target (w = m/h^2)
+    float4 *prev1, *prev2;             // Chebyshev history
+    unsigned char *collided;           // sticky contact flag within a step
+    unsigned *flags;                   // [0] barrier counter, [1] abort flag, [2] skip count
+    float4 *snaps;                     // backward: (n_iters + 1) iterates
+    float4 *xbar, *ybar, *xtbar, *vbar;
+    int n_verts, n_tets, n_free, n_colors;
+};
+
+struct LaunchCfg {
+    int lanes;        // lanes per vertex
+    int block;        // threads per block
+    int xcd_remap;
+    int blocks_per_cu;
+};
+
+// ---- kernel launchers (vbd_kernels.hip) ----
+hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K,
+                           hipStream_t s);
+hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,
+                          const StepConsts &K, bool reset_flags, hipStream_t s);
+hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end,
+                        bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s);
+hipError_t launch_finalize(const DevTopo &T, float *x, float *v, float *vp,
+                           const StepConsts &K, hipStream_t s);
+// Persistent kernel over all iterations and colors.  grid = 0 -> occupancy
+// limited.  cooperative: launch through hipLaunchCooperativeKernel.
+hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters, bool tets,
+                             bool springs, const LaunchCfg &cfg, int n_cu, bool cooperative,
+                             hipStream_t s, int *grid_out);
+hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s);
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s);
+
+// backward
+hipError_t launch_bwd_init(const DevTopo &T, const float *gx_out, const float *gv_out,
+                           const float *gvp_out, const StepConsts &K, hipStream_t s);
+hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const float4 *Sn,
+                                const float4 *Sp, int v_begin, int v_end, float *g_tet_E,
+                                const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev,
+                            float *gx_in, float *gv_in, float *gvp_in, const StepConsts &K,
+                            hipStream_t s);
+
+}  // namespace vbd

@@ -1,0 +1,795 @@
+// gfx950 kernels of the VBD hot path.
+//
+// Vertex Block Descent (Chen, Liu, Yang, Yuksel, ACM TOG 2024).  A color
+// phase updates every free vertex of one color in parallel (Sec. 3.9).  One
+// vertex is handled by a group of L lanes of a wave64: the lanes stride over
+// the vertex's incident elements (color-sorted CSR), each accumulating the
+// element force and 3x3 Hessian block, then the group reduces the 9 values
+// with DPP row operations, adds inertia / damping / contact / friction terms
+// and solves the 3x3 system analytically (Sec. 3.2).
+#include "vbd_internal.h"
+
+namespace vbd {
+
+// ---------------------------------------------------------------- helpers --
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator*(float3 a, float s) { return make_float3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float3 operator-(float3 a) { return make_float3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b)
+{
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.x, a.y, a.z); }
+__device__ __forceinline__ float3 ld3(const float *p, int i)
+{
+    return make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+__device__ __forceinline__ void st3(float *p, int i, float3 v)
+{
+    p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over aligned groups of L lanes (L = 4, 8, 16, 32, 64); every lane of
+// the group receives the total.  Must be called with the whole wave active.
+template <int L>
+__device__ __forceinline__ float group_sum(float v)
+{
+    v += dpp_mov<0xB1>(v);              // quad_perm [1,0,3,2]  (xor 1)
+    v += dpp_mov<0x4E>(v);              // quad_perm [2,3,0,1]  (xor 2)
+    if (L >= 8) v += dpp_mov<0x141>(v); // row_half_mirror      (lane i <-> 7-i)
+    if (L >= 16) v += dpp_mov<0x140>(v);// row_mirror           (lane i <-> 15-i)
+    if (L >= 32) v += __shfl_xor(v, 16);
+    if (L >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
+// blockIdx -> logical block: each of the 8 XCDs (which receive blocks
+// round-robin) gets a contiguous range of logical blocks.
+__device__ __forceinline__ int xcd_block(int b, int nb, int remap)
+{
+    if (!remap) return b;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// --------------------------------------------------------- element terms --
+// Stable Neo-Hookean tet without the log term (Sec. 5):
+//   Psi = mu/2 (|F|^2 - 3) + lam/2 (J - alpha)^2, alpha = 1 + mu/lam.
+// For the vertex in slot k with shape gradient m_k:
+//   dE/dx_k = V (mu F m_k + lam (J - alpha) c_k),  c_k = cof(F) m_k,
+//   d2E/dx_k2 = V (mu |m_k|^2 I + lam c_k c_k^T)   (J is affine in x_k).
+struct TetLocal {
+    float3 f0, f1, f2;   // columns of F
+    float3 c0, c1, c2;   // columns of cof(F)
+    float J;
+    float3 r0, r1, r2;   // rows of Dm^{-1} = shape gradients of slots 1..3
+};
+
+__device__ __forceinline__ void tet_local(const TetRec &r, float4 q0, float4 q1, float4 q2,
+                                          float4 q3, TetLocal &L)
+{
+    const float3 e1 = xyz(q1) - xyz(q0), e2 = xyz(q2) - xyz(q0), e3 = xyz(q3) - xyz(q0);
+    L.r0 = make_float3(r.b0.x, r.b0.y, r.b0.z);
+    L.r1 = make_float3(r.b0.w, r.b1.x, r.b1.y);
+    L.r2 = make_float3(r.b1.z, r.b1.w, r.b2.x);
+    L.f0 = e1 * L.r0.x + e2 * L.r1.x + e3 * L.r2.x;
+    L.f1 = e1 * L.r0.y + e2 * L.r1.y + e3 * L.r2.y;
+    L.f2 = e1 * L.r0.z + e2 * L.r1.z + e3 * L.r2.z;
+    L.c0 = cross3(L.f1, L.f2);
+    L.c1 = cross3(L.f2, L.f0);
+    L.c2 = cross3(L.f0, L.f1);
+    L.J = dot3(L.f0, L.c0);
+}
+
+__device__ __forceinline__ float3 sel3(bool c, float3 a, float3 b)
+{
+    return make_float3(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z);
+}
+
+// slot 0 -> m_0 = -(r0 + r1 + r2), slot 1..3 -> r0..r2; written as two
+// levels of per-component selects so that no private array is formed.
+__device__ __forceinline__ float3 shape_grad(const TetLocal &L, int k)
+{
+    const float3 m0 = -(L.r0 + L.r1 + L.r2);
+    const bool b0 = (k & 1) != 0, b1 = (k & 2) != 0;
+    return sel3(b1, sel3(b0, L.r2, L.r1), sel3(b0, L.r0, m0));
+}
+
+__device__ __forceinline__ float3 Fmul(const TetLocal &L, float3 m)
+{
+    return L.f0 * m.x + L.f1 * m.y + L.f2 * m.z;
+}
+__device__ __forceinline__ float3 Cmul(const TetLocal &L, float3 m)
+{
+    return L.c0 * m.x + L.c1 * m.y + L.c2 * m.z;
+}
+
+struct Acc {
+    float fx, fy, fz, hxx, hxy, hxz, hyy, hyz, hzz;
+};
+
+__device__ __forceinline__ void acc_zero(Acc &a)
+{
+    a.fx = a.fy = a.fz = a.hxx = a.hxy = a.hxz = a.hyy = a.hyz = a.hzz = 0.f;
+}
+
+__device__ __forceinline__ void tet_contrib(const DevTopo &T, const float4 *X, int ent, float alpha,
+                                            Acc &a)
+{
+    const int t = ent >> 2, k = ent & 3;
+    const TetRec r = T.rec[t];
+    const float4 q0 = X[r.ids.x], q1 = X[r.ids.y], q2 = X[r.ids.z], q3 = X[r.ids.w];
+    TetLocal L;
+    tet_local(r, q0, q1, q2, q3, L);
+    const float3 mk = shape_grad(L, k);
+    const float3 Fm = Fmul(L, mk), cm = Cmul(L, mk);
+    const float Vmu = r.b2.y, Vlam = r.b2.z;
+    const float s = Vlam * (L.J - alpha);
+    a.fx -= Vmu * Fm.x + s * cm.x;
+    a.fy -= Vmu * Fm.y + s * cm.y;
+    a.fz -= Vmu * Fm.z + s * cm.z;
+    const float d = Vmu * dot3(mk, mk);
+    a.hxx += d + Vlam * cm.x * cm.x;
+    a.hxy += Vlam * cm.x * cm.y;
+    a.hxz += Vlam * cm.x * cm.z;
+    a.hyy += d + Vlam * cm.y * cm.y;
+    a.hyz += Vlam * cm.y * cm.z;
+    a.hzz += d + Vlam * cm.z * cm.z;
+}
+
+// Linear spring E = k/2 (l - L)^2: dE/dx_i = k (l - L) u,
+// d2E/dx_i2 = k (1 - L/l) I + k (L/l) u u^T, unprojected (Sec. 3.2) unless
+// the transverse clamp is requested.
+__device__ __forceinline__ void spring_contrib(const float4 *X, float3 xi, int2 se, float k, int psd,
+                                               Acc &a)
+{
+    const float3 xj = xyz(X[se.x]);
+    const float L = __int_as_float(se.y);
+    const float3 d = xi - xj;
+    const float l = sqrtf(dot3(d, d));
+    const float inv_l = 1.0f / l;
+    const float3 u = d * inv_l;
+    const float g = k * (l - L);
+    a.fx -= g * u.x; a.fy -= g * u.y; a.fz -= g * u.z;
+    float ci = k * (1.0f - L * inv_l);
+    const float cu = k - ci;                 // k L / l
+    if (psd && ci < 0.f) ci = 0.f;           // transverse stiffness clamped (option)
+    a.hxx += ci + cu * u.x * u.x;
+    a.hxy += cu * u.x * u.y;
+    a.hxz += cu * u.x * u.z;
+    a.hyy += ci + cu * u.y * u.y;
+    a.hyz += cu * u.y * u.z;
+    a.hzz += ci + cu * u.z * u.z;
+}
+
+template <int L>
+__device__ __forceinline__ void acc_reduce(Acc &a)
+{
+    a.fx = group_sum<L>(a.fx); a.fy = group_sum<L>(a.fy); a.fz = group_sum<L>(a.fz);
+    a.hxx = group_sum<L>(a.hxx); a.hxy = group_sum<L>(a.hxy); a.hxz = group_sum<L>(a.hxz);
+    a.hyy = group_sum<L>(a.hyy); a.hyz = group_sum<L>(a.hyz); a.hzz = group_sum<L>(a.hzz);
+}
+
+// Analytic 3x3 solve with the determinant skip of Sec. 3.2:
+// skip iff |det H| <= eps_rel * ||H||_F^3.  Returns false when skipped.
+__device__ __forceinline__ bool solve_sym3(const Acc &a, float eps_rel, float3 &dx)
+{
+    const float A00 = a.hyy * a.hzz - a.hyz * a.hyz;
+    const float A01 = a.hxz * a.hyz - a.hxy * a.hzz;
+    const float A02 = a.hxy * a.hyz - a.hxz * a.hyy;
+    const float A11 = a.hxx * a.hzz - a.hxz * a.hxz;
+    const float A12 = a.hxy * a.hxz - a.hxx * a.hyz;
+    const float A22 = a.hxx * a.hyy - a.hxy * a.hxy;
+    const float det = a.hxx * A00 + a.hxy * A01 + a.hxz * A02;
+    const float fro = sqrtf(a.hxx * a.hxx + a.hyy * a.hyy + a.hzz * a.hzz +
+                            2.f * (a.hxy * a.hxy + a.hxz * a.hxz + a.hyz * a.hyz));
+    if (!(fabsf(det) > eps_rel * fro * fro * fro)) return false;
+    const float inv = 1.0f / det;
+    dx.x = (A00 * a.fx + A01 * a.fy + A02 * a.fz) * inv;
+    dx.y = (A01 * a.fx + A11 * a.fy + A12 * a.fz) * inv;
+    dx.z = (A02 * a.fx + A12 * a.fy + A22 * a.fz) * inv;
+    return true;
+}
+
+// Inertia (Eq. VBDForce/VBDHessian), Rayleigh damping on the summed element
+// Hessian (Eq. VBDForceWithDamping/VBDHessianWithDamping), penalty contact
+// against analytic obstacles with a fixed normal (Eq. collisionEnergy) and
+// IPC-style friction with the approximate Hessian (Eq. IPC_friction).
+__device__ __forceinline__ bool vertex_terms(const DevTopo &T, const StepConsts &K, int p,
+                                             float3 xi, Acc &a)
+{
+    const float4 yv = T.y[p];
+    const float w = yv.w;   // m / h^2
+    bool contact = false;
+    float3 xt = make_float3(0.f, 0.f, 0.f);
+    const bool need_xt = (K.kd_over_h != 0.f) || (K.fric_mu > 0.f);
+    if (need_xt) xt = xyz(T.xt[p]);
+    if (K.kd_over_h != 0.f) {
+        const float3 d = xi - xt;
+        const float c = K.kd_over_h;
+        a.fx -= c * (a.hxx * d.x + a.hxy * d.y + a.hxz * d.z);
+        a.fy -= c * (a.hxy * d.x + a.hyy * d.y + a.hyz * d.z);
+        a.fz -= c * (a.hxz * d.x + a.hyz * d.y + a.hzz * d.z);
+        a.hxx *= 1.f + c; a.hxy *= 1.f + c; a.hxz *= 1.f + c;
+        a.hyy *= 1.f + c; a.hyz *= 1.f + c; a.hzz *= 1.f + c;
+    }
+    a.fx -= w * (xi.x - yv.x);
+    a.fy -= w * (xi.y - yv.y);
+    a.fz -= w * (xi.z - yv.z);
+    a.hxx += w; a.hyy += w; a.hzz += w;
+    const int nobs = K.n_spheres + K.n_planes;
+    for (int o = 0; o < nobs; ++o) {
+        float3 n;
+        float pen;
+        if (o < K.n_spheres) {
+            const float4 s = K.spheres[o];
+            const float3 r = xi - make_float3(s.x, s.y, s.z);
+            const float dist = sqrtf(dot3(r, r));
+            n = r * (1.0f / dist);
+            pen = s.w + K.delta - dist;
+        } else {
+            const float4 pl = K.planes[o - K.n_spheres];
+            n = make_float3(pl.x, pl.y, pl.z);
+            pen = K.delta - (dot3(n, xi) - pl.w);
+        }
+        if (!(pen > 0.f)) continue;
+        contact = true;
+        const float kp = K.kc * pen;
+        a.fx += kp * n.x; a.fy += kp * n.y; a.fz += kp * n.z;
+        a.hxx += K.kc * n.x * n.x; a.hxy += K.kc * n.x * n.y; a.hxz += K.kc * n.x * n.z;
+        a.hyy += K.kc * n.y * n.y; a.hyz += K.kc * n.y * n.z; a.hzz += K.kc * n.z * n.z;
+        if (K.fric_mu > 0.f) {
+            const float3 dx = xi - xt;
+            const float dn = dot3(dx, n);
+            const float3 u = dx - n * dn;
+            const float un = sqrtf(dot3(u, u));
+            const float hev = K.fric_hev;
+            const float f1u = (un < hev) ? (2.0f / hev - un / (hev * hev)) : (1.0f / un);
+            const float s = K.fric_mu * kp * f1u;
+            a.fx -= s * u.x; a.fy -= s * u.y; a.fz -= s * u.z;
+            a.hxx += s * (1.f - n.x * n.x); a.hxy -= s * n.x * n.y; a.hxz -= s * n.x * n.z;
+            a.hyy += s * (1.f - n.y * n.y); a.hyz -= s * n.y * n.z; a.hzz += s * (1.f - n.z * n.z);
+        }
+    }
+    return contact;
+}
+
+// One vertex update by a group of L lanes.  All lanes of the wave must call
+// this (inactive groups pass active = false) because of the DPP reduction.
+template <int L, bool TETS, bool SPRINGS>
+__device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
+                                             int lane, bool active)
+{
+    Acc a;
+    acc_zero(a);
+    float4 xi4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) {
+        xi4 = T.x[p];
+        if (TETS) {
+            const int e1 = T.tet_row[p + 1];
+            for (int e = T.tet_row[p] + lane; e < e1; e += L) tet_contrib(T, T.x, T.tet_ent[e], K.alpha, a);
+        }
+        if (SPRINGS) {
+            const int e1 = T.spr_row[p + 1];
+            for (int e = T.spr_row[p] + lane; e < e1; e += L)
+                spring_contrib(T.x, xyz(xi4), T.spr_ent[e], K.spring_k, K.spring_psd, a);
+        }
+    }
+    acc_reduce<L>(a);
+    if (!active) return;
+    const float3 xi = xyz(xi4);
+    const bool contact = vertex_terms(T, K, p, xi, a);
+    float3 dx;
+    const bool ok = solve_sym3(a, K.det_eps_rel, dx);
+    if (lane == 0) {
+        if (ok) T.x[p] = make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w);
+        else atomicAdd(&T.flags[2], 1u);
+        if (contact) T.collided[p] = 1;
+    }
+}
+
+// ----------------------------------------------------------------- kernels --
+__global__ void k_material(TetRec *rec, const float *E, int n, float k_mu, float k_lam)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float4 b2 = rec[t].b2;
+    const float VE = b2.w * E[t];
+    b2.y = VE * k_mu;
+    b2.z = VE * k_lam;
+    rec[t].b2 = b2;
+}
+
+// y = x^t + h v^t + h^2 a_ext (Eq. inertia) and the initial guess (Sec. 3.7).
+__global__ void k_predict(DevTopo T, const float *x, const float *v, const float *vp,
+                          StepConsts K, int reset_flags, int cheb)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0 && reset_flags) T.flags[0] = 0u;
+    if (p >= T.n_verts) return;
+    const int o = T.perm[p];
+    const float3 xt = ld3(x, o), vt = ld3(v, o);
+    const float h = K.h;
+    const float3 g = make_float3(K.gx, K.gy, K.gz);
+    const float w = T.mass[p] * K.inv_h * K.inv_h;
+    const float3 y = xt + vt * h + g * (h * h);
+    T.xt[p] = make_float4(xt.x, xt.y, xt.z, 0.f);
+    T.y[p] = make_float4(y.x, y.y, y.z, w);
+    float3 x0 = xt;
+    if (p < T.n_free) {
+        switch (K.init_mode) {
+        case 0: break;
+        case 1: x0 = xt + vt * h; break;
+        case 2: x0 = y; break;
+        default: {
+            float at = 0.f;
+            if (K.gnorm > 0.f) {
+                const float3 vpt = ld3(vp, o);
+                at = dot3((vt - vpt) * K.inv_h, g) / K.gnorm;
+            }
+            float atil;
+            if (K.gnorm == 0.f) atil = 0.f;
+            else if (at > K.gnorm) atil = 1.f;
+            else if (at < 0.f) atil = 0.f;
+            else atil = at / K.gnorm;
+            x0 = xt + vt * h + g * (h * h * atil);
+        }
+        }
+    }
+    const float4 x04 = make_float4(x0.x, x0.y, x0.z, 0.f);
+    T.x[p] = x04;
+    T.collided[p] = 0;
+    if (cheb) { T.prev1[p] = x04; T.prev2[p] = x04; }
+}
+
+template <int L, bool TETS, bool SPRINGS>
+__global__ void k_solve(DevTopo T, StepConsts K, int v_begin, int v_end, int remap)
+{
+    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int gid = b * blockDim.x + threadIdx.x;
+    const int p = v_begin + gid / L;
+    solve_vertex<L, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end);
+}
+
+__device__ __forceinline__ float cheb_omega(int it, float rho)
+{
+    // Eq. accelerator: omega_1 = 1, omega_2 = 2/(2 - rho^2),
+    // omega_n = 4/(4 - rho^2 omega_{n-1})
+    float om = 1.f;
+    for (int n = 2; n <= it; ++n) om = (n == 2) ? 2.f / (2.f - rho * rho) : 4.f / (4.f - rho * rho * om);
+    return om;
+}
+
+__device__ __forceinline__ void cheb_vertex(const DevTopo &T, int p, float om)
+{
+    const float4 xb = T.x[p], p2 = T.prev2[p];
+    float4 xn = xb;
+    if (!T.collided[p]) {
+        xn.x = om * (xb.x - p2.x) + p2.x;
+        xn.y = om * (xb.y - p2.y) + p2.y;
+        xn.z = om * (xb.z - p2.z) + p2.z;
+    }
+    T.prev2[p] = T.prev1[p];
+    T.prev1[p] = xn;
+    T.x[p] = xn;
+}
+
+__global__ void k_cheb(DevTopo T, float rho, int it)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_free) return;
+    cheb_vertex(T, p, cheb_omega(it, rho));
+}
+
+// v^{t+1} = (x^{t+1} - x^t)/h (Eq. velocity_update); the state's previous
+// velocity becomes v^t; results go back in the original vertex order.
+__global__ void k_finalize(DevTopo T, float *x, float *v, float *vp, float h)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_verts) return;
+    const int o = T.perm[p];
+    const float3 xn = xyz(T.x[p]), xt = xyz(T.xt[p]);
+    const float3 vold = ld3(v, o);
+    st3(vp, o, vold);
+    st3(v, o, (xn - xt) * (1.0f / h));
+    st3(x, o, xn);
+}
+
+// Device-wide barrier for the persistent kernel.  flags[0] counts arrivals
+// (reset to 0 by k_predict before the launch); barrier number k completes
+// when it reaches k * nblocks.  The wait is bounded: after kSpinLimit polls
+// the block raises flags[1] and every block leaves at its next barrier, so
+// the kernel always terminates.  Returns true when the kernel must stop.
+constexpr long kSpinLimit = 1L << 20;
+
+__device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned target)
+{
+    __shared__ int s_abort;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int abort = 0;
+        // release this block's writes (all waves passed the barrier above),
+        // arrive, then poll with plain agent-scope loads; one acquire fence
+        // after the wait makes the other blocks' writes visible to the CU
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&flags[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                abort = 1;
+                break;
+            }
+            if (++spins > kSpinLimit) {
+                // record what the waiting block saw, for vbd_check's message
+                const unsigned seen = __hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&flags[3], seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&flags[4], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&flags[5], gridDim.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&flags[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                abort = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_abort = abort;
+    }
+    __syncthreads();
+    return s_abort != 0;
+}
+
+template <int L, bool TETS, bool SPRINGS>
+__global__ void k_persistent(DevTopo T, StepConsts K, int n_iters, int remap)
+{
+    const int nb = gridDim.x;
+    const int b = xcd_block(blockIdx.x, nb, remap);
+    const int G = blockDim.x / L;   // vertex groups per block
+    const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+    unsigned nbar = 0;
+    for (int it = 1; it <= n_iters; ++it) {
+        for (int c = 0; c < T.n_colors; ++c) {
+            const int vb = T.color_off[c], ve = T.color_off[c + 1];
+            // contiguous chunk of the color per logical block
+            const int n = ve - vb;
+            const int chunk = (n + nb - 1) / nb;
+            const int cb = vb + b * chunk;
+            const int cend = min(cb + chunk, ve);
+            for (int base = cb; base < cb + chunk; base += G) {
+                const int p = base + g;
+                solve_vertex<L, TETS, SPRINGS>(T, K, p, lane, p < cend);
+            }
+            ++nbar;
+            if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
+        }
+        if (K.cheb_rho > 0.f) {
+            const float om = cheb_omega(it, K.cheb_rho);
+            for (int p = b * blockDim.x + threadIdx.x; p < T.n_free; p += nb * blockDim.x)
+                cheb_vertex(T, p, om);
+            ++nbar;
+            if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
+        }
+    }
+}
+
+__global__ void k_copy4(float4 *dst, const float4 *src, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_zero_u32(unsigned *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- adjoint --
+__global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const float *gvp, float h)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_verts) return;
+    const int o = T.perm[p];
+    const float3 a = ld3(gx, o), b = ld3(gv, o), c = ld3(gvp, o);
+    const float ih = 1.0f / h;
+    T.xbar[p] = make_float4(a.x + b.x * ih, a.y + b.y * ih, a.z + b.z * ih, 0.f);
+    T.xtbar[p] = make_float4(-b.x * ih, -b.y * ih, -b.z * ih, 0.f);
+    T.vbar[p] = make_float4(c.x, c.y, c.z, 0.f);
+    T.ybar[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Reverse of one color phase.  The update x_i' = argmin G_i (exact for
+// these tets, G_i quadratic in x_i) satisfies grad_i G_i(x_i'; x_nbr, y_i, E)
+// = 0, so with w = H_i^{-1} xbar_i:
+//   xbar_i <- 0,  ybar_i += (m/h^2) w,  xbar_j -= K_ij^T w  (K = d2E/dx_i dx_j),
+//   Ebar_t -= w . (dE_t/dx_i) / E_t,
+// all at the state right after the update: vertices of colors <= c from
+// iteration n (Sn), the others from iteration n-1 (Sp).
+//   K_kq^T w = V [mu (m_k.m_q) w + lam c_q (c_k.w) + lam (J - alpha) (u x w)],
+//   u = F (m_k x m_q)   (d2J/dx_k dx_q w' = w' x u).
+template <int L>
+__global__ void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const float4 *Sp,
+                                int v_begin, int v_end, float *gE, int remap)
+{
+    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int gid = b * blockDim.x + threadIdx.x;
+    const int p = v_begin + gid / L;
+    const int lane = threadIdx.x & (L - 1);
+    const bool active = p < v_end;
+    const int c_end = v_end;   // permuted slots < c_end have color <= c
+    Acc a;
+    acc_zero(a);
+    int e0 = 0, e1 = 0;
+    if (active) {
+        e0 = T.tet_row[p];
+        e1 = T.tet_row[p + 1];
+        for (int e = e0 + lane; e < e1; e += L) {
+            const int ent = T.tet_ent[e];
+            const int t = ent >> 2, k = ent & 3;
+            const TetRec r = T.rec[t];
+            const float4 q0 = (r.ids.x < c_end ? Sn : Sp)[r.ids.x];
+            const float4 q1 = (r.ids.y < c_end ? Sn : Sp)[r.ids.y];
+            const float4 q2 = (r.ids.z < c_end ? Sn : Sp)[r.ids.z];
+            const float4 q3 = (r.ids.w < c_end ? Sn : Sp)[r.ids.w];
+            TetLocal Lc;
+            tet_local(r, q0, q1, q2, q3, Lc);
+            const float3 mk = shape_grad(Lc, k);
+            const float3 cm = Cmul(Lc, mk);
+            const float Vmu = r.b2.y, Vlam = r.b2.z;
+            const float d = Vmu * dot3(mk, mk);
+            a.hxx += d + Vlam * cm.x * cm.x; a.hxy += Vlam * cm.x * cm.y; a.hxz += Vlam * cm.x * cm.z;
+            a.hyy += d + Vlam * cm.y * cm.y; a.hyz += Vlam * cm.y * cm.z; a.hzz += d + Vlam * cm.z * cm.z;
+        }
+    }
+    acc_reduce<L>(a);
+    if (!active) return;
+    const float wm = T.y[p].w;
+    a.hxx += wm; a.hyy += wm; a.hzz += wm;
+    const float4 xb4 = T.xbar[p];
+    a.fx = xb4.x; a.fy = xb4.y; a.fz = xb4.z;
+    float3 w;
+    if (!solve_sym3(a, K.det_eps_rel, w)) return;   // skipped update: xbar passes through
+    if (lane == 0) {
+        T.xbar[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 yb = T.ybar[p];
+        yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
+        T.ybar[p] = yb;
+    }
+    for (int e = e0 + lane; e < e1; e += L) {
+        const int ent = T.tet_ent[e];
+        const int t = ent >> 2, k = ent & 3;
+        const TetRec r = T.rec[t];
+        const int ids[4] = {r.ids.x, r.ids.y, r.ids.z, r.ids.w};
+        const float4 q0 = (ids[0] < c_end ? Sn : Sp)[ids[0]];
+        const float4 q1 = (ids[1] < c_end ? Sn : Sp)[ids[1]];
+        const float4 q2 = (ids[2] < c_end ? Sn : Sp)[ids[2]];
+        const float4 q3 = (ids[3] < c_end ? Sn : Sp)[ids[3]];
+        TetLocal Lc;
+        tet_local(r, q0, q1, q2, q3, Lc);
+        const float3 mk = shape_grad(Lc, k);
+        const float3 ck = Cmul(Lc, mk);
+        const float cw = dot3(ck, w);
+        const float Vmu = r.b2.y, Vlam = r.b2.z;
+        const float s = Vlam * (Lc.J - K.alpha);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q == k) continue;
+            const float3 mq = shape_grad(Lc, q);
+            const float3 cq = Cmul(Lc, mq);
+            const float3 u = Fmul(Lc, cross3(mk, mq));
+            const float3 uw = cross3(u, w);
+            const float mm = Vmu * dot3(mk, mq);
+            float4 *dst = T.xbar + ids[q];
+            atomicAdd(&dst->x, -(mm * w.x + Vlam * cw * cq.x + s * uw.x));
+            atomicAdd(&dst->y, -(mm * w.y + Vlam * cw * cq.y + s * uw.y));
+            atomicAdd(&dst->z, -(mm * w.z + Vlam * cw * cq.z + s * uw.z));
+        }
+        const float3 Fm = Fmul(Lc, mk);
+        const float V = r.b2.w;
+        gE[t] -= V * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
+    }
+}
+
+// Adjoint of the initial guess (Sec. 3.7) and of y, written in original order.
+__global__ void k_bwd_final(DevTopo T, const float *v_t, const float *v_prev, float *gx_in,
+                            float *gv_in, float *gvp_in, StepConsts K)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_verts) return;
+    const int o = T.perm[p];
+    const float3 xb = xyz(T.xbar[p]);
+    float3 gx = xyz(T.xtbar[p]) + xb;
+    float3 gv = xyz(T.vbar[p]);
+    float3 gvp = make_float3(0.f, 0.f, 0.f);
+    if (p < T.n_free) {
+        const float h = K.h;
+        if (K.init_mode != 0) gv = gv + xb * h;
+        if (K.init_mode == 3 && K.gnorm > 0.f) {
+            const float3 g = make_float3(K.gx, K.gy, K.gz);
+            const float at = dot3((ld3(v_t, o) - ld3(v_prev, o)) * K.inv_h, g) / K.gnorm;
+            if (at > 0.f && at < K.gnorm) {
+                const float s = h * h * dot3(g, xb) / K.gnorm;
+                const float3 dd = g * (s / (K.gnorm * h));
+                gv = gv + dd;
+                gvp = gvp - dd;
+            }
+        }
+        const float3 yb = xyz(T.ybar[p]);
+        gx = gx + yb;
+        gv = gv + yb * h;
+    }
+    st3(gx_in, o, gx);
+    st3(gv_in, o, gv);
+    st3(gvp_in, o, gvp);
+}
+
+// -------------------------------------------------------------- launchers --
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K, hipStream_t s)
+{
+    if (T.n_tets == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_material, dim3(cdiv(T.n_tets, 256)), dim3(256), 0, s, T.rec, tet_E,
+                       T.n_tets, K.k_mu, K.k_lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,
+                          const StepConsts &K, bool reset_flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_predict, dim3(cdiv(T.n_verts > 0 ? T.n_verts : 1, 256)), dim3(256), 0, s,
+                       T, x, v, vp, K, reset_flags ? 1 : 0, K.cheb_rho > 0.f ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int L>
+static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
+                                 bool springs, const LaunchCfg &cfg, hipStream_t s)
+{
+    const int grid = cdiv((long)(ve - vb) * L, cfg.block);
+    if (tets && springs)
+        hipLaunchKernelGGL((k_solve<L, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+    else if (tets)
+        hipLaunchKernelGGL((k_solve<L, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+    else if (springs)
+        hipLaunchKernelGGL((k_solve<L, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+    else
+        hipLaunchKernelGGL((k_solve<L, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
+                        bool springs, const LaunchCfg &cfg, hipStream_t s)
+{
+    if (ve <= vb) return hipSuccess;
+    switch (cfg.lanes) {
+    case 4: return solve_dispatch<4>(T, K, vb, ve, tets, springs, cfg, s);
+    case 8: return solve_dispatch<8>(T, K, vb, ve, tets, springs, cfg, s);
+    case 16: return solve_dispatch<16>(T, K, vb, ve, tets, springs, cfg, s);
+    case 32: return solve_dispatch<32>(T, K, vb, ve, tets, springs, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s)
+{
+    if (T.n_free == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cheb, dim3(cdiv(T.n_free, 256)), dim3(256), 0, s, T, K.cheb_rho, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevTopo &T, float *x, float *v, float *vp, const StepConsts &K,
+                           hipStream_t s)
+{
+    if (T.n_verts == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T, x, v, vp, K.h);
+    return hipGetLastError();
+}
+
+template <int L, bool TE, bool SP>
+static hipError_t persistent_go(const DevTopo &T, const StepConsts &K, int n_iters,
+                                const LaunchCfg &cfg, int n_cu, bool coop, hipStream_t s,
+                                int *grid_out)
+{
+    auto fn = k_persistent<L, TE, SP>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, cfg.block, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu <= 0) return hipErrorInvalidConfiguration;
+    // The occupancy query does not see every residency limit (measured on
+    // gfx950: this kernel's 87 SGPRs allow 7 waves per SIMD where the query
+    // assumes 8), so the persistent grid uses at most 3/4 of what it reports.
+    per_cu = per_cu * 3 / 4;
+    if (per_cu < 1) per_cu = 1;
+    if (cfg.blocks_per_cu > 0 && cfg.blocks_per_cu < per_cu) per_cu = cfg.blocks_per_cu;
+    const int grid = per_cu * n_cu;
+    if (grid_out) *grid_out = grid;
+    DevTopo Tc = T;
+    StepConsts Kc = K;
+    int it = n_iters, rm = cfg.xcd_remap;
+    if (coop) {
+        void *args[] = {(void *)&Tc, (void *)&Kc, (void *)&it, (void *)&rm};
+        return hipLaunchCooperativeKernel((const void *)fn, dim3(grid), dim3(cfg.block), args, 0, s);
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.block), 0, s, Tc, Kc, it, rm);
+    return hipGetLastError();
+}
+
+template <int L>
+static hipError_t persistent_kinds(const DevTopo &T, const StepConsts &K, int n_iters, bool tets,
+                                   bool springs, const LaunchCfg &cfg, int n_cu, bool coop,
+                                   hipStream_t s, int *grid_out)
+{
+    if (tets && springs) return persistent_go<L, true, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (tets) return persistent_go<L, true, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (springs) return persistent_go<L, false, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    return persistent_go<L, false, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+}
+
+hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters, bool tets,
+                             bool springs, const LaunchCfg &cfg, int n_cu, bool coop,
+                             hipStream_t s, int *grid_out)
+{
+    switch (cfg.lanes) {
+    case 4: return persistent_kinds<4>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 8: return persistent_kinds<8>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 16: return persistent_kinds<16>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 32: return persistent_kinds<32>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int grid = cdiv(n, 256);
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_copy4, dim3(grid), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_init(const DevTopo &T, const float *gx, const float *gv, const float *gvp,
+                           const StepConsts &K, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bwd_init, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T, gx, gv, gvp, K.h);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const float4 *Sn,
+                                const float4 *Sp, int vb, int ve, float *gE, const LaunchCfg &cfg,
+                                hipStream_t s)
+{
+    if (ve <= vb) return hipSuccess;
+    const int grid = cdiv((long)(ve - vb) * cfg.lanes, cfg.block);
+    switch (cfg.lanes) {
+    case 4: hipLaunchKernelGGL(k_adjoint_color<4>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
+    case 8: hipLaunchKernelGGL(k_adjoint_color<8>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
+    case 16: hipLaunchKernelGGL(k_adjoint_color<16>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
+    case 32: hipLaunchKernelGGL(k_adjoint_color<32>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev, float *gx_in,
+                            float *gv_in, float *gvp_in, const StepConsts &K, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bwd_final, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T, v_t, v_prev,
+                       gx_in, gv_in, gvp_in, K);
+    return hipGetLastError();
+}
+
+}  // namespace vbd

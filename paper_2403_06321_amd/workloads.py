@@ -55,6 +55,7 @@ class StepParams:
     cheb_rho: float = 0.0                  # Chebyshev spectral radius (0 = off)
     friction_mu: float = 0.0
     friction_eps_v: float = 1e-2
+    spring_psd: bool = False               # clamp transverse spring stiffness at 0
 
 
 @dataclasses.dataclass
@@ -208,21 +209,28 @@ def config_large_cube(frames: int = 60) -> Workload:
                     name="tet cube 65^3")
 
 
-def config_cloth(n: int = 1024, frames: int = 120) -> Workload:
+def config_cloth(n: int = 1024, frames: int = 120, spacing: float = 1e-3,
+                 mass: float = 1e-4) -> Workload:
     """Mass-spring cloth (n x n, 1 mm spacing) over a sphere and a ground plane."""
-    spacing = 1e-3
     rest, springs = cloth_grid(n, spacing, 0.62)
     nv = rest.shape[0]
     pinned = np.zeros(nv, np.uint8)
     pinned[0] = 1
     pinned[n - 1] = 1
-    p = StepParams(n_iters=50, contact_k=1e5, contact_thickness=1e-3,
+    p = StepParams(n_iters=50, contact_k=1e5, contact_thickness=1e-3, spring_psd=True,
                    spheres=np.array([[0.0, 0.0, 0.3, 0.3]]),
                    planes=np.array([[0.0, 0.0, 1.0, 0.0]]))
     return Workload(name=f"cloth {n}^2", rest=rest, tets=np.zeros((0, 4), np.int32),
                     pinned=pinned, x0=rest.copy(), v0=np.zeros((nv, 3)),
                     tet_E=np.zeros(0), springs=springs, spring_k=1e3,
-                    mass=np.full(nv, 1e-4), params=p, frames=frames)
+                    mass=np.full(nv, mass), params=p, frames=frames)
+
+
+def config_cloth_coarse(n: int = 64, frames: int = 60) -> Workload:
+    """The cloth of config_cloth over the same 1.023 m square with n x n
+    vertices: spacing 1.023/(n-1) m and the same total mass."""
+    spacing = 1.023 / (n - 1)
+    return config_cloth(n, frames, spacing=spacing, mass=1e-4 * (1024.0 / n) ** 2)
 
 
 def config_batch(n_meshes: int = 512, seed: int = 3, lo: int = 4, hi: int = 33,

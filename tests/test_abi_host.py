@@ -1,0 +1,168 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every symbol declared in include/vbd.h; topology preprocessing (coloring,
+permutation, incidence CSR) is bit-exact against the oracle and brute force;
+FP64 rest data and masses agree with the oracle; bad inputs give the
+documented error codes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_06321_amd import _native as N
+from paper_2403_06321_amd import workloads as W
+from paper_2403_06321_amd.api import Topology
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "vbd.h")).read()
+    declared = set(re.findall(r"\b(vbd_[a-z_]+)\s*\(", header))
+    assert declared == set(N.EXPORTS)
+    lib = N.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("n", [3, 5, 11])
+def test_coloring_matches_oracle_bit_exact(n):
+    w = W.tet_cube(n, n)
+    t = Topology.from_workload(w, bind=False)
+    m = O.Model.from_workload(w)
+    assert t.n_colors == m.n_colors
+    assert np.array_equal(t.query(N.Q_COLORS), m.colors)
+
+
+def test_cloth_coloring_matches_oracle():
+    w = W.config_cloth(32)
+    t = Topology.from_workload(w, bind=False)
+    m = O.Model.from_workload(w)
+    assert np.array_equal(t.query(N.Q_COLORS), m.colors)
+    assert t.n_colors == 7
+
+
+def test_batch_coloring_equals_per_mesh_coloring():
+    w = W.config_batch(n_meshes=6, lo=3, hi=6)
+    t = Topology.from_workload(w, bind=False)
+    colors = t.query(N.Q_COLORS)
+    vo, to = w.offsets()
+    for k in range(w.n_meshes):
+        sub = W.subset_meshes(w, [k])
+        m = O.Model.from_workload(sub)
+        assert np.array_equal(colors[vo[k]:vo[k + 1]], m.colors)
+
+
+def _expected_layout(w, colors):
+    nv = w.n_verts
+    pinned = w.pinned.astype(bool)
+    free = np.flatnonzero(~pinned)
+    perm = np.concatenate([free[np.lexsort((free, colors[free]))], np.flatnonzero(pinned)])
+    iperm = np.empty(nv, np.int64); iperm[perm] = np.arange(nv)
+    rows, ents = [0], []
+    for v in perm[:len(free)]:
+        inc = [(t << 2) | int(np.flatnonzero(w.tets[t] == v)[0])
+               for t in np.flatnonzero((w.tets == v).any(1))]
+        ents.extend(sorted(inc))
+        rows.append(len(ents))
+    return perm, np.array(rows), np.array(ents)
+
+
+def test_permutation_and_csr_bit_exact():
+    w = W.tet_cube(4, 1)
+    t = Topology.from_workload(w, bind=False)
+    colors = O.Model.from_workload(w).colors
+    perm, rows, ents = _expected_layout(w, colors)
+    assert np.array_equal(t.query(N.Q_PERM), perm)
+    assert np.array_equal(t.query(N.Q_TET_ROWS), rows)
+    assert np.array_equal(t.query(N.Q_TET_ENTRIES), ents)
+    co = t.query(N.Q_COLOR_OFFSETS)
+    free_colors = colors[perm[:co[-1]]]
+    assert np.array_equal(np.searchsorted(free_colors, np.arange(t.n_colors + 1)), co)
+
+
+def test_spring_csr():
+    w = W.config_cloth(8)
+    t = Topology.from_workload(w, bind=False)
+    perm = t.query(N.Q_PERM)
+    rows = t.query(N.Q_SPRING_ROWS)
+    nbrs = t.query(N.Q_SPRING_NBRS)
+    for s, v in enumerate(perm[:len(rows) - 1]):
+        exp = [int(b if a == v else a) for a, b in w.springs if a == v or b == v]
+        assert nbrs[rows[s]:rows[s + 1]].tolist() == exp
+
+
+def test_rest_data_and_masses_match_oracle():
+    w = W.config_large_cube() if os.environ.get("VBD_BIG_HOST_TESTS") else W.tet_cube(9, 2)
+    t = Topology.from_workload(w, bind=False)
+    m = O.Model.from_workload(w)
+    assert np.allclose(t.query(N.Q_MASS), m.mass, rtol=1e-13, atol=0)
+    assert np.allclose(t.query(N.Q_VOLUME), m.vol, rtol=1e-13, atol=0)
+    assert np.allclose(t.query(N.Q_DMINV).reshape(-1, 9), m.Dminv, rtol=0, atol=1e-11)
+
+
+def _status(fn):
+    try:
+        fn()
+    except N.VBDError as e:
+        return e.status
+    return 0
+
+
+def test_error_codes():
+    rest, tets = W.cube_lattice(2, 2, 2)
+    bad = tets.copy(); bad[0, 0] = 99
+    assert _status(lambda: Topology(rest, bad, bind=False)) == -2          # out of range
+    rep = tets.copy(); rep[0, 1] = rep[0, 0]
+    assert _status(lambda: Topology(rest, rep, bind=False)) == -2          # repeated vertex
+    flat = rest.copy(); flat[:, 2] = 0.0
+    assert _status(lambda: Topology(flat, tets, bind=False)) == -2         # degenerate rest tet
+    assert _status(lambda: Topology(rest, tets, nu=0.5, bind=False)) == -1  # bad Poisson ratio
+    sp = np.array([[0, 0]], np.int32)
+    assert _status(lambda: Topology(rest, None, springs=sp, mass=np.ones(8), bind=False)) == -2
+    assert _status(lambda: Topology(rest, None, springs=np.array([[0, 1]]), spring_rest=[0.0],
+                                    mass=np.ones(8), bind=False)) == -2
+
+
+def test_step_before_color_and_bind():
+    L = N.lib()
+    rest, tets = W.cube_lattice(2, 2, 2)
+    rest = np.ascontiguousarray(rest); tets = np.ascontiguousarray(tets)
+    desc = N.MeshDesc(8, tets.shape[0], 0, 1, None, None, tets.ctypes.data, None, rest.ctypes.data,
+                      None, 0.0, None, 1000.0, 0.3, None)
+    h = C.c_void_p()
+    assert L.vbd_build_topology(C.byref(desc), C.byref(h)) == 0
+    ps, _ = __import__("paper_2403_06321_amd.api", fromlist=["params_struct"]).params_struct(W.StepParams())
+    assert L.vbd_step(h, C.byref(ps), None, None, None, None, None) == -3   # not colored
+    sz = C.c_size_t()
+    assert L.vbd_workspace_size(h, 0, C.byref(sz)) == -3
+    assert L.vbd_color(h, None, None) == 0
+    assert L.vbd_step(h, C.byref(ps), None, None, None, None, None) == -4   # no workspace
+    assert L.vbd_workspace_size(h, 0, C.byref(sz)) == 0 and sz.value > 0
+    assert b"vbd_bind_workspace" in L.vbd_last_error()
+    assert L.vbd_topology_destroy(h) == 0
+
+
+def test_batched_offsets_validated():
+    w = W.config_batch(n_meshes=3, lo=3, hi=4)
+    vo = w.vert_offsets.copy(); vo[-1] += 1
+    assert _status(lambda: Topology(w.rest, w.tets, vert_offsets=vo, tet_offsets=w.tet_offsets,
+                                    bind=False)) == -1
+    tets = w.tets.copy(); tets[0, 0] = w.vert_offsets[1]   # crosses into mesh 1
+    assert _status(lambda: Topology(w.rest, tets, vert_offsets=w.vert_offsets,
+                                    tet_offsets=w.tet_offsets, bind=False)) == -2
+
+
+def test_phase_bytes_model():
+    w = W.tet_cube(4, 0)
+    t = Topology.from_workload(w, bind=False)
+    pb = t.query(N.Q_PHASE_BYTES)
+    rows = t.query(N.Q_TET_ROWS)
+    co = t.query(N.Q_COLOR_OFFSETS)
+    for c in range(t.n_colors):
+        pairs = rows[co[c + 1]] - rows[co[c]]
+        nvc = co[c + 1] - co[c]
+        assert pb[c] >= 68 * pairs + 52 * nvc
+        assert pb[c] <= 68 * pairs + 52 * nvc + 16 * w.n_verts

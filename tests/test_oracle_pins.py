@@ -502,3 +502,22 @@ def test_skip_rule_on_singular_hessian():
     x, _, _, st = O.step(m, p, rest, np.zeros((2, 3)), np.zeros((2, 3)), np.zeros(0))
     assert st["n_skips"] == 2 and st["n_updates"] == 2
     assert np.array_equal(x, rest)
+
+
+def test_spring_psd_clamp_by_hand():
+    """Optional clamp of the spring Hessian: for a compressed spring the
+    transverse stiffness k(1 - L/l) < 0 is replaced by 0 (the exact PSD
+    projection of a spring block, whose eigenvalues are k and k(1 - L/l))."""
+    w = W.single_particle_chain(2, length=0.1, k=100.0, m=0.01)
+    m = O.Model.from_workload(w)
+    x0 = np.array([[0, 0, 0], [0.01, 0.005, -0.06]])      # l < L: compressed
+    v0 = np.zeros((2, 3))
+    h, k, L, mass = 1 / 60, 100.0, 0.1, 0.01
+    y = x0[1] + h * h * np.array(W.GRAVITY)
+    d = x0[1] - x0[0]; l = np.linalg.norm(d); u = d / l
+    f = -mass / h ** 2 * (x0[1] - y) - k * (l - L) * u
+    for psd, trans in ((False, k * (1 - L / l)), (True, 0.0)):
+        p = P(n_iters=1, init_mode=W.INIT_PREV, spring_psd=psd)
+        x, _, _, _ = O.step(m, p, x0, v0, v0, np.zeros(0))
+        H = mass / h ** 2 * np.eye(3) + k * np.outer(u, u) + trans * (np.eye(3) - np.outer(u, u))
+        assert np.allclose(x[1], x0[1] + np.linalg.solve(H, f), atol=1e-14)
