@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--profile-only", default="",
-                    help="run only one workload for a profiler: cube|batch|adjoint|cloth|copy")
+                    help="run only one workload for a profiler: cube|copy")
+    ap.add_argument("--lanes", type=int, default=8, help="--profile-only: lanes per vertex")
+    ap.add_argument("--block", type=int, default=128, help="--profile-only: block size")
+    ap.add_argument("--remap", type=int, default=1, help="--profile-only: XCD remap")
     return ap.parse_args()
 
 
@@ -158,6 +161,8 @@ def main():
     topo = Topology.from_workload(w)
     log(f"[bench] topology built in {time.perf_counter() - t0:.1f} s, {topo.n_colors} colors")
     if args.profile_only == "cube":
+        topo.launch_config = dict(lanes_per_vertex=args.lanes, block_size=args.block,
+                                  xcd_remap=args.remap)
         secs, upd = time_frames(topo, w, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
         print(json.dumps({"profile": "cube", "ms_per_frame": secs / args.steps * 1e3}))
         return

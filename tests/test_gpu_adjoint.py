@@ -32,6 +32,7 @@ def gpu_grad(w, frames=None):
     loss.backward()
     torch.cuda.synchronize()
     topo.check()
+    gpu_grad.last_x = xT.detach().double().cpu().numpy()
     return (float(loss), E.grad.double().cpu().numpy(), v0.grad.double().cpu().numpy(),
             x0.grad.double().cpu().numpy())
 
@@ -102,6 +103,10 @@ def test_adjoint_full_size_full_depth_vs_stored_oracle():
     ref = np.load(GOLDEN)
     w = W.config_differentiable()
     lg, gE, gv, gx = gpu_grad(w)
+    xo = ref["x_final"].astype(np.float64)
+    err = np.linalg.norm(gpu_grad.last_x - xo, axis=1).max() / np.linalg.norm(xo.max(0) - xo.min(0))
+    say(f"33^3 after 30 frames: bbox-relative position error {err:.2e}")
+    assert err <= 1e-5
     say(f"loss gpu {lg:.9e} oracle {float(ref['loss']):.9e}")
     assert lg == pytest.approx(float(ref["loss"]), rel=1e-4)
     compare("33^3 dL/dE", gE, ref["g_E"].astype(np.float64))
