@@ -208,7 +208,7 @@ def main():
                    "free_vertices": int((w.pinned == 0).sum()), "iterations": w.params.n_iters},
         "roofline": {"bound": "hbm", "achieved": roof["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": roof["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_solve<tets> (one color phase)",
+                     "traffic": traffic, "kernel": "k_solve<tets> (one color phase per launch)",
                      "avg_launch_us": roof["avg_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": roof["avg_bytes"]},
     }

@@ -118,7 +118,11 @@ enum {
     VBD_Q_MASS = 8,         /* double[n_verts] lumped or given masses (original order) */
     VBD_Q_DMINV = 9,        /* double[n_tets][9] */
     VBD_Q_VOLUME = 10,      /* double[n_tets] */
-    VBD_Q_PHASE_BYTES = 11  /* double[n_colors]: algorithmic HBM bytes of one color solve */
+    VBD_Q_PHASE_BYTES = 11, /* double[n_colors]: algorithmic HBM bytes of one color solve */
+    VBD_Q_TET_ORDER = 12,   /* int32[n_tets]: stored tet position -> caller's tet id
+                               (tets grouped by the colors of their vertices) */
+    VBD_Q_REST_FRAME = 13   /* double[n_tets][6]: upper triangle of R^{-1}, D_m = Q R with
+                               Q a proper rotation (caller's tet order) */
 };
 vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
 vbd_status vbd_topology_destroy(vbd_topology topo);
@@ -183,9 +187,10 @@ vbd_status vbd_step_backward(vbd_topology topo, const vbd_step_params *params,
 /* Kernel launch configuration of the color solve. */
 typedef struct {
     int32_t lanes_per_vertex;   /* 4, 8, 16 or 32 lanes of a wave64 per vertex */
-    int32_t block_size;         /* 64..1024, multiple of 64 */
+    int32_t block_size;         /* 64..512, multiple of 64 */
     int32_t xcd_remap;          /* 1: give each XCD a contiguous range of blocks */
     int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */
+    int32_t tet_unroll;         /* 1..3 tet entries per lane loaded together */
 } vbd_launch_config;
 vbd_status vbd_get_launch_config(vbd_topology topo, vbd_launch_config *cfg);
 vbd_status vbd_set_launch_config(vbd_topology topo, const vbd_launch_config *cfg);
@@ -199,10 +204,11 @@ vbd_status vbd_set_launch_config(vbd_topology topo, const vbd_launch_config *cfg
 vbd_status vbd_autotune(vbd_topology topo, const vbd_step_params *params, const float *x,
                         const float *v, const float *v_prev, const float *tet_E, void *stream);
 
-/* Per-launch timing of the hot kernel (hipEvents on the launch stream).
- * When enabled, vbd_step records an event pair around every color-solve
- * launch (or around the persistent kernel).  vbd_profile_read synchronizes
- * and reports totals since the last reset. */
+/* Timing of the hot kernel (hipEvents on the launch stream).  When enabled,
+ * vbd_step runs its plain launch sequence and records one event pair around
+ * the step's back-to-back color-solve launches (or around the persistent
+ * kernel); total_ms / n_launches is the average launch duration.
+ * vbd_profile_read synchronizes and reports totals since the last reset. */
 typedef struct {
     int64_t n_launches;        /* timed hot-kernel launches */
     double total_ms;           /* summed event time of those launches */

@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "VBD_OK", -1: "VBD_E_INVALID_ARG", -2: "VBD_E_TOPOLOGY", -3: 
 LAUNCH_PLAIN, LAUNCH_GRAPH, LAUNCH_PERSISTENT, LAUNCH_PERSISTENT_GRAPH = 0, 1, 2, 3
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
- Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES) = range(12)
+ Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME) = range(14)
 
 # every symbol include/vbd.h declares
 EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_workspace_size", "vbd_bind_workspace",
@@ -43,7 +43,7 @@ class StepParamsC(C.Structure):
 
 class LaunchConfig(C.Structure):
     _fields_ = [("lanes_per_vertex", C.c_int32), ("block_size", C.c_int32),
-                ("xcd_remap", C.c_int32), ("blocks_per_cu", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("blocks_per_cu", C.c_int32), ("tet_unroll", C.c_int32)]
 
 
 class ProfileStats(C.Structure):

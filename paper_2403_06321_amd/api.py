@@ -126,7 +126,9 @@ class Topology:
                 N.Q_TET_ENTRIES: (np.int32, c["tet_entries"]), N.Q_SPRING_ROWS: (np.int32, n_free + 1),
                 N.Q_SPRING_NBRS: (np.int32, c["spring_entries"]), N.Q_MASS: (np.float64, c["n_verts"]),
                 N.Q_DMINV: (np.float64, 9 * c["n_tets"]), N.Q_VOLUME: (np.float64, c["n_tets"]),
-                N.Q_PHASE_BYTES: (np.float64, c["n_colors"])}[what]
+                N.Q_PHASE_BYTES: (np.float64, c["n_colors"]),
+                N.Q_TET_ORDER: (np.int32, c["n_tets"]),
+                N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"])}[what]
         out = np.zeros(spec[1], spec[0])
         N.check(N.lib().vbd_topology_query(self._h, what, _np_ptr(out), out.nbytes))
         return out
@@ -170,14 +172,14 @@ class Topology:
         c = N.LaunchConfig()
         N.check(N.lib().vbd_get_launch_config(self._h, C.byref(c)))
         return dict(lanes_per_vertex=c.lanes_per_vertex, block_size=c.block_size,
-                    xcd_remap=c.xcd_remap, blocks_per_cu=c.blocks_per_cu)
+                    xcd_remap=c.xcd_remap, blocks_per_cu=c.blocks_per_cu, tet_unroll=c.tet_unroll)
 
     @launch_config.setter
     def launch_config(self, cfg):
         cur = self.launch_config
         cur.update(cfg)
         c = N.LaunchConfig(cur["lanes_per_vertex"], cur["block_size"], cur["xcd_remap"],
-                           cur["blocks_per_cu"])
+                           cur["blocks_per_cu"], cur["tet_unroll"])
         N.check(N.lib().vbd_set_launch_config(self._h, C.byref(c)))
 
     def profile_enable(self, on: bool = True):

@@ -46,7 +46,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec, tet_row, tet_ent, spr_row, spr_ent, perm, mass, color_off;
+    size_t rec, vol, tet_perm, tet_row, tet_ent, spr_row, spr_ent, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar;
     size_t total;
@@ -65,8 +65,9 @@ struct GraphKey {
 
 struct ProfileEvent {
     hipEvent_t a, b;
-    double bytes;
-    int64_t updates;
+    double bytes;       // algorithmic bytes of the launches inside [a, b]
+    int64_t updates;    // vertex updates inside [a, b]
+    int64_t launches;   // hot-kernel launches inside [a, b]
 };
 
 }  // namespace
@@ -84,6 +85,7 @@ struct vbd_topology_s {
     int n_colors = 0, n_free = 0;
     std::vector<int32_t> colors, perm, iperm, color_off;
     std::vector<int32_t> tet_row, tet_ent, spr_row, spr_nbr_orig;
+    std::vector<int32_t> tet_order, tet_rank;   // stored position <-> caller's tet id
     std::vector<float> spr_len;
     std::vector<double> phase_bytes;
     std::vector<int64_t> phase_updates;
@@ -95,7 +97,7 @@ struct vbd_topology_s {
     DevTopo dev{};
     int n_cu = 0;
     std::string arch;
-    LaunchCfg cfg{8, 256, 1, 0};
+    LaunchCfg cfg{8, 128, 1, 0, 2};
     // graph cache
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -125,6 +127,8 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes ? bytes : 1); return o; };
     const size_t nv = (size_t)T.nv;
     L.rec = take(sizeof(TetRec) * (size_t)T.nt);
+    L.vol = take(sizeof(float) * (size_t)T.nt);
+    L.tet_perm = take(sizeof(int32_t) * (size_t)T.nt);
     L.tet_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
     L.tet_ent = take(sizeof(int32_t) * T.tet_ent.size());
     L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
@@ -157,6 +161,8 @@ void set_dev_pointers(vbd_topology_s &T)
     const Layout &L = T.lay;
     DevTopo &D = T.dev;
     D.rec = (TetRec *)(b + L.rec);
+    D.vol = (const float *)(b + L.vol);
+    D.tet_perm = (const int *)(b + L.tet_perm);
     D.tet_row = (const int *)(b + L.tet_row);
     D.tet_ent = (const int *)(b + L.tet_ent);
     D.spr_row = (const int *)(b + L.spr_row);
@@ -282,6 +288,36 @@ void greedy_color(vbd_topology_s &T)
     T.n_colors = nc;
 }
 
+// S = R^{-1} for the rest edge matrix D_m = [X1-X0, X2-X0, X3-X0] = Q R,
+// Gram-Schmidt with Q a proper rotation (R's last diagonal entry takes the
+// sign of det D_m).  S is upper triangular: {S00, S01, S02, S11, S12, S22}.
+void rest_frame_inverse(const std::vector<double> &X, const int32_t *q, double S[6])
+{
+    double d[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) d[c][r] = X[3 * (size_t)q[c + 1] + r] - X[3 * (size_t)q[0] + r];
+    auto dotp = [](const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    double q1[3], q2[3], u[3];
+    const double r11 = std::sqrt(dotp(d[0], d[0]));
+    for (int r = 0; r < 3; ++r) q1[r] = d[0][r] / r11;
+    const double r12 = dotp(q1, d[1]);
+    for (int r = 0; r < 3; ++r) u[r] = d[1][r] - r12 * q1[r];
+    const double r22 = std::sqrt(dotp(u, u));
+    for (int r = 0; r < 3; ++r) q2[r] = u[r] / r22;
+    const double r13 = dotp(q1, d[2]), r23 = dotp(q2, d[2]);
+    for (int r = 0; r < 3; ++r) u[r] = d[2][r] - r13 * q1[r] - r23 * q2[r];
+    // third axis q3 = q1 x q2 keeps Q proper; r33 = q3 . d3 carries det's sign
+    const double q3[3] = {q1[1] * q2[2] - q1[2] * q2[1], q1[2] * q2[0] - q1[0] * q2[2],
+                          q1[0] * q2[1] - q1[1] * q2[0]};
+    const double r33 = dotp(q3, d[2]);
+    S[0] = 1.0 / r11;
+    S[1] = -r12 / (r11 * r22);
+    S[2] = (r12 * r23 - r13 * r22) / (r11 * r22 * r33);
+    S[3] = 1.0 / r22;
+    S[4] = -r23 / (r22 * r33);
+    S[5] = 1.0 / r33;
+}
+
 void build_csr(vbd_topology_s &T)
 {
     const int nv = T.nv;
@@ -339,7 +375,28 @@ void build_csr(vbd_topology_s &T)
                 spos[s]++;
             }
         }
-    // algorithmic bytes of one color solve: 64 B tet record + 4 B CSR entry per
+    // stored tet order: grouped by the sorted colors of the tet's 4 vertices
+    // (then by tet id), so tets sharing a cache line are read in the same
+    // color phases
+    {
+        std::vector<std::pair<uint64_t, int32_t>> key(T.nt);
+        for (int t = 0; t < T.nt; ++t) {
+            int c[4];
+            for (int k = 0; k < 4; ++k) c[k] = T.colors[T.tets[4 * (size_t)t + k]];
+            std::sort(c, c + 4);
+            uint64_t kk = 0;
+            for (int k = 0; k < 4; ++k) kk = (kk << 16) | (uint64_t)(c[k] & 0xffff);
+            key[t] = {kk, t};
+        }
+        std::sort(key.begin(), key.end());
+        T.tet_order.assign(T.nt, 0);
+        T.tet_rank.assign(T.nt, 0);
+        for (int i = 0; i < T.nt; ++i) {
+            T.tet_order[i] = key[i].second;
+            T.tet_rank[key[i].second] = i;
+        }
+    }
+    // algorithmic bytes of one color solve: 48 B tet record + 4 B CSR entry per
     // tet pair, 8 B per spring entry, 4 B row offset and 48 B own state
     // (x read, y read, x write) per vertex, 16 B per distinct neighbour position.
     T.phase_bytes.assign(T.n_colors, 0.0);
@@ -351,7 +408,7 @@ void build_csr(vbd_topology_s &T)
         for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
             const int pairs = T.tet_row[s + 1] - T.tet_row[s];
             const int sp = T.spr_row[s + 1] - T.spr_row[s];
-            bytes += 68.0 * pairs + 8.0 * sp + 4.0 + 48.0;
+            bytes += (double)(sizeof(TetRec) + 4) * pairs + 8.0 * sp + 4.0 + 48.0;
             for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
                 const int t = T.tet_ent[e] >> 2;
                 for (int k = 0; k < 4; ++k) {
@@ -404,25 +461,33 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
             for (int c = 0; c < T.n_colors; ++c) { bytes += T.phase_bytes[c]; upd += T.phase_updates[c]; }
             ev.bytes = bytes * p->n_iters;
             ev.updates = upd * p->n_iters;
+            ev.launches = 1;
             T.events.push_back(ev);
         }
     } else {
+        // profiling brackets the whole sequence of color-solve launches of the
+        // step with one event pair (no per-launch event overhead)
+        ProfileEvent ev{};
+        if (prof) {
+            vbd_status st = prof_begin(T, s, ev);
+            if (st) return st;
+        }
+        int64_t launches = 0;
         for (int it = 1; it <= p->n_iters; ++it) {
             for (int c = 0; c < T.n_colors; ++c) {
-                ProfileEvent ev{};
-                if (prof) {
-                    vbd_status st = prof_begin(T, s, ev);
-                    if (st) return st;
-                }
                 HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], tets, springs, T.cfg, s));
-                if (prof) {
-                    HIP_TRY(hipEventRecord(ev.b, s));
-                    ev.bytes = T.phase_bytes[c];
-                    ev.updates = T.phase_updates[c];
-                    T.events.push_back(ev);
+                if (T.color_off[c + 1] > T.color_off[c]) {
+                    ++launches;
+                    ev.bytes += T.phase_bytes[c];
+                    ev.updates += T.phase_updates[c];
                 }
             }
             if (p->cheb_rho > 0.f) HIP_TRY(launch_cheb(T.dev, K, it, s));
+        }
+        if (prof) {
+            HIP_TRY(hipEventRecord(ev.b, s));
+            ev.launches = launches;
+            T.events.push_back(ev);
         }
     }
     HIP_TRY(launch_finalize(T.dev, x, v, vp, K, s));
@@ -634,13 +699,21 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     set_dev_pointers(*T);
     // host staging of every static array
     std::vector<TetRec> rec(T->nt);
-    for (int t = 0; t < T->nt; ++t) {
+    std::vector<float> volf(T->nt);
+    for (int i = 0; i < T->nt; ++i) {
+        const int t = T->tet_order[i];
         const int32_t *q = &T->tets[4 * (size_t)t];
-        const double *B = &T->Dminv[9 * (size_t)t];
-        rec[t].ids = make_int4(T->iperm[q[0]], T->iperm[q[1]], T->iperm[q[2]], T->iperm[q[3]]);
-        rec[t].b0 = make_float4((float)B[0], (float)B[1], (float)B[2], (float)B[3]);
-        rec[t].b1 = make_float4((float)B[4], (float)B[5], (float)B[6], (float)B[7]);
-        rec[t].b2 = make_float4((float)B[8], 0.f, 0.f, (float)T->vol[t]);
+        double S[6];
+        rest_frame_inverse(T->rest, q, S);
+        rec[i].ids = make_int4(T->iperm[q[0]], T->iperm[q[1]], T->iperm[q[2]], T->iperm[q[3]]);
+        rec[i].a = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
+        rec[i].b = make_float4((float)S[4], (float)S[5], 0.f, 0.f);
+        volf[i] = (float)T->vol[t];
+    }
+    std::vector<int32_t> tet_ent_dev(T->tet_ent.size());
+    for (size_t e = 0; e < tet_ent_dev.size(); ++e) {
+        const int32_t v = T->tet_ent[e];
+        tet_ent_dev[e] = (T->tet_rank[v >> 2] << 2) | (v & 3);
     }
     std::vector<int2> spr(T->spr_nbr_orig.size());
     for (size_t e = 0; e < spr.size(); ++e) {
@@ -656,8 +729,10 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         return hipMemcpyAsync(T->ws + off, src, n, hipMemcpyHostToDevice, s);
     };
     HIP_TRY(up(T->lay.rec, rec.data(), sizeof(TetRec) * rec.size()));
+    HIP_TRY(up(T->lay.vol, volf.data(), 4 * volf.size()));
+    HIP_TRY(up(T->lay.tet_perm, T->tet_order.data(), 4 * T->tet_order.size()));
     HIP_TRY(up(T->lay.tet_row, T->tet_row.data(), 4 * T->tet_row.size()));
-    HIP_TRY(up(T->lay.tet_ent, T->tet_ent.data(), 4 * T->tet_ent.size()));
+    HIP_TRY(up(T->lay.tet_ent, tet_ent_dev.data(), 4 * tet_ent_dev.size()));
     HIP_TRY(up(T->lay.spr_row, T->spr_row.data(), 4 * T->spr_row.size()));
     HIP_TRY(up(T->lay.spr_ent, spr.data(), sizeof(int2) * spr.size()));
     HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));
@@ -700,6 +775,12 @@ vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t by
     case VBD_Q_SPRING_ROWS: return give(T->spr_row.data(), 4 * T->spr_row.size());
     case VBD_Q_SPRING_NBRS: return give(T->spr_nbr_orig.data(), 4 * T->spr_nbr_orig.size());
     case VBD_Q_PHASE_BYTES: return give(T->phase_bytes.data(), 8 * T->phase_bytes.size());
+    case VBD_Q_TET_ORDER: return give(T->tet_order.data(), 4 * T->tet_order.size());
+    case VBD_Q_REST_FRAME: {
+        std::vector<double> S(6 * (size_t)T->nt);
+        for (int t = 0; t < T->nt; ++t) rest_frame_inverse(T->rest, &T->tets[4 * (size_t)t], &S[6 * (size_t)t]);
+        return give(S.data(), 8 * S.size());
+    }
     default: return fail(VBD_E_INVALID_ARG, "unknown query %d", what);
     }
 }
@@ -814,6 +895,7 @@ vbd_status vbd_get_launch_config(vbd_topology T, vbd_launch_config *c)
     c->block_size = T->cfg.block;
     c->xcd_remap = T->cfg.xcd_remap;
     c->blocks_per_cu = T->cfg.blocks_per_cu;
+    c->tet_unroll = T->cfg.unroll;
     return VBD_OK;
 }
 
@@ -822,10 +904,11 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
     if (!T || !c) return fail(VBD_E_INVALID_ARG, "NULL argument");
     const int L = c->lanes_per_vertex;
     if (L != 4 && L != 8 && L != 16 && L != 32) return fail(VBD_E_INVALID_ARG, "lanes_per_vertex must be 4, 8, 16 or 32");
-    if (c->block_size < 64 || c->block_size > 1024 || c->block_size % 64)
-        return fail(VBD_E_INVALID_ARG, "block_size must be a multiple of 64 in [64, 1024]");
+    if (c->block_size < 64 || c->block_size > 512 || c->block_size % 64)
+        return fail(VBD_E_INVALID_ARG, "block_size must be a multiple of 64 in [64, 512]");
     if (c->blocks_per_cu < 0) return fail(VBD_E_INVALID_ARG, "blocks_per_cu < 0");
-    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu};
+    if (c->tet_unroll < 1 || c->tet_unroll > 3) return fail(VBD_E_INVALID_ARG, "tet_unroll must be 1, 2 or 3");
+    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu, c->tet_unroll};
     if (T->have_graph) {
         (void)hipGraphExecDestroy(T->gexec);
         (void)hipGraphDestroy(T->graph);
@@ -856,13 +939,16 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     const bool tets = T->nt > 0, springs = T->ns > 0;
     std::vector<LaunchCfg> cands;
     for (int L : {4, 8, 16})
-        for (int B : {128, 256, 512})
-            for (int rm : {0, 1}) {
-                if (persistent)
-                    for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc});
-                else
-                    cands.push_back(LaunchCfg{L, B, rm, 0});
-            }
+        for (int U : {1, 2, 3}) {
+            if (!tets && U > 1) continue;
+            for (int B : {64, 128, 256, 512})
+                for (int rm : {0, 1}) {
+                    if (persistent)
+                        for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc, U});
+                    else
+                        cands.push_back(LaunchCfg{L, B, rm, 0, U});
+                }
+        }
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
@@ -925,7 +1011,7 @@ vbd_status vbd_profile_read(vbd_topology T, vbd_profile_stats *out, int32_t rese
         HIP_TRY(hipEventSynchronize(e.b));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
-        T->acc.n_launches += 1;
+        T->acc.n_launches += e.launches;
         T->acc.total_ms += ms;
         T->acc.total_bytes += e.bytes;
         T->acc.n_vertex_updates += e.updates;

@@ -7,18 +7,23 @@
 
 namespace vbd {
 
-// 64-byte tet record, color-sorted vertex ids.
-//   ids = the 4 vertex slots (permuted ids)
-//   b0  = {B00, B01, B02, B10}, b1 = {B11, B12, B20, B21},
-//   b2  = {B22, V*mu, V*lambda, V}
-// B = inverse rest edge matrix (row l = gradient of the shape function of
-// slot l+1).  V*mu and V*lambda are rewritten from the per-tet Young's
-// modulus at the start of every step.
+// 48-byte tet record.
+//   ids = the 4 vertex slots (permuted vertex ids)
+//   a   = {S00, S01, S02, S11}, b = {S12, S22, V*mu, V*lambda}
+// S = R^{-1}, the inverse of the triangular factor of the rest edge matrix
+// D_m = Q R (Q a proper rotation).  The stable Neo-Hookean energy depends on
+// F only through F^T F and det F, both unchanged by F -> F Q, so
+// F' = D_s R^{-1} = F Q gives the same energy, forces and Hessians; row l of
+// S is the shape-function gradient of slot l+1 in that rotated frame.
+// V*mu and V*lambda are rewritten from the per-tet Young's modulus at the
+// start of every step.  Records are stored in tet_perm order (tets grouped by
+// the colors of their four vertices, so a cache line only holds tets that
+// are touched in the same color phases).
 struct __align__(16) TetRec {
     int4 ids;
-    float4 b0, b1, b2;
+    float4 a, b;
 };
-static_assert(sizeof(TetRec) == 64, "tet record must be 64 bytes");
+static_assert(sizeof(TetRec) == 48, "tet record must be 48 bytes");
 
 constexpr int kMaxObstacles = 8;
 
@@ -43,8 +48,10 @@ struct StepConsts {
 
 // Device-side view of a bound workspace.
 struct DevTopo {
-    TetRec *rec;
-    const int *tet_row, *tet_ent;      // CSR over free permuted vertices
+    TetRec *rec;                       // [n_tets] in tet_perm order
+    const float *vol;                  // [n_tets] rest volume, tet_perm order
+    const int *tet_perm;               // stored tet -> caller's tet index
+    const int *tet_row, *tet_ent;      // CSR over free permuted vertices: (stored tet << 2) | slot
     const int *spr_row;
     const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
     const int *perm;                   // permuted slot -> original id
@@ -61,9 +68,10 @@ struct DevTopo {
 
 struct LaunchCfg {
     int lanes;        // lanes per vertex
-    int block;        // threads per block
+    int block;        // threads per block (<= 512)
     int xcd_remap;
     int blocks_per_cu;
+    int unroll;       // tet entries per lane whose loads are issued together (1..3)
 };
 
 // ---- kernel launchers (vbd_kernels.hip) ----

@@ -67,22 +67,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int remap)
 //   dE/dx_k = V (mu F m_k + lam (J - alpha) c_k),  c_k = cof(F) m_k,
 //   d2E/dx_k2 = V (mu |m_k|^2 I + lam c_k c_k^T)   (J is affine in x_k).
 struct TetLocal {
-    float3 f0, f1, f2;   // columns of F
+    float3 f0, f1, f2;   // columns of F (rotated rest frame, see TetRec)
     float3 c0, c1, c2;   // columns of cof(F)
     float J;
-    float3 r0, r1, r2;   // rows of Dm^{-1} = shape gradients of slots 1..3
+    float3 r0, r1, r2;   // rows of S = shape gradients of slots 1..3
 };
 
 __device__ __forceinline__ void tet_local(const TetRec &r, float4 q0, float4 q1, float4 q2,
                                           float4 q3, TetLocal &L)
 {
     const float3 e1 = xyz(q1) - xyz(q0), e2 = xyz(q2) - xyz(q0), e3 = xyz(q3) - xyz(q0);
-    L.r0 = make_float3(r.b0.x, r.b0.y, r.b0.z);
-    L.r1 = make_float3(r.b0.w, r.b1.x, r.b1.y);
-    L.r2 = make_float3(r.b1.z, r.b1.w, r.b2.x);
-    L.f0 = e1 * L.r0.x + e2 * L.r1.x + e3 * L.r2.x;
-    L.f1 = e1 * L.r0.y + e2 * L.r1.y + e3 * L.r2.y;
-    L.f2 = e1 * L.r0.z + e2 * L.r1.z + e3 * L.r2.z;
+    // S is upper triangular: F = [e1 e2 e3] S
+    L.r0 = make_float3(r.a.x, r.a.y, r.a.z);
+    L.r1 = make_float3(0.f, r.a.w, r.b.x);
+    L.r2 = make_float3(0.f, 0.f, r.b.y);
+    L.f0 = e1 * r.a.x;
+    L.f1 = e1 * r.a.y + e2 * r.a.w;
+    L.f2 = e1 * r.a.z + e2 * r.b.x + e3 * r.b.y;
     L.c0 = cross3(L.f1, L.f2);
     L.c1 = cross3(L.f2, L.f0);
     L.c2 = cross3(L.f0, L.f1);
@@ -121,17 +122,14 @@ __device__ __forceinline__ void acc_zero(Acc &a)
     a.fx = a.fy = a.fz = a.hxx = a.hxy = a.hxz = a.hyy = a.hyz = a.hzz = 0.f;
 }
 
-__device__ __forceinline__ void tet_contrib(const DevTopo &T, const float4 *X, int ent, float alpha,
-                                            Acc &a)
+__device__ __forceinline__ void tet_accumulate(const TetRec &r, int k, float4 q0, float4 q1,
+                                               float4 q2, float4 q3, float alpha, Acc &a)
 {
-    const int t = ent >> 2, k = ent & 3;
-    const TetRec r = T.rec[t];
-    const float4 q0 = X[r.ids.x], q1 = X[r.ids.y], q2 = X[r.ids.z], q3 = X[r.ids.w];
     TetLocal L;
     tet_local(r, q0, q1, q2, q3, L);
     const float3 mk = shape_grad(L, k);
     const float3 Fm = Fmul(L, mk), cm = Cmul(L, mk);
-    const float Vmu = r.b2.y, Vlam = r.b2.z;
+    const float Vmu = r.b.z, Vlam = r.b.w;
     const float s = Vlam * (L.J - alpha);
     a.fx -= Vmu * Fm.x + s * cm.x;
     a.fy -= Vmu * Fm.y + s * cm.y;
@@ -143,6 +141,38 @@ __device__ __forceinline__ void tet_contrib(const DevTopo &T, const float4 *X, i
     a.hyy += d + Vlam * cm.y * cm.y;
     a.hyz += Vlam * cm.y * cm.z;
     a.hzz += d + Vlam * cm.z * cm.z;
+}
+
+// Tet terms of one vertex: the lanes of the group take entries e0 + lane,
+// e0 + lane + L, ...; each lane issues the loads of KU entries level by level
+// (CSR entries, then records, then positions) so that a vertex costs three
+// dependent memory round trips per KU*L entries instead of three per entry.
+template <int L, int KU>
+__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, int e0, int e1,
+                                          int lane, float alpha, Acc &a)
+{
+    for (int base = e0 + lane; base < e1; base += L * KU) {
+        int ent[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j) {
+            const int e = base + j * L;
+            ent[j] = (e < e1) ? T.tet_ent[e] : -1;
+        }
+        TetRec r[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j] >= 0) r[j] = T.rec[ent[j] >> 2];
+        float4 q[KU][4];
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j] >= 0) {
+                q[j][0] = X[r[j].ids.x]; q[j][1] = X[r[j].ids.y];
+                q[j][2] = X[r[j].ids.z]; q[j][3] = X[r[j].ids.w];
+            }
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j] >= 0) tet_accumulate(r[j], ent[j] & 3, q[j][0], q[j][1], q[j][2], q[j][3], alpha, a);
+    }
 }
 
 // Linear spring E = k/2 (l - L)^2: dE/dx_i = k (l - L) u,
@@ -264,7 +294,7 @@ __device__ __forceinline__ bool vertex_terms(const DevTopo &T, const StepConsts 
 
 // One vertex update by a group of L lanes.  All lanes of the wave must call
 // this (inactive groups pass active = false) because of the DPP reduction.
-template <int L, bool TETS, bool SPRINGS>
+template <int L, int KU, bool TETS, bool SPRINGS>
 __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
                                              int lane, bool active)
 {
@@ -273,10 +303,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     float4 xi4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) {
         xi4 = T.x[p];
-        if (TETS) {
-            const int e1 = T.tet_row[p + 1];
-            for (int e = T.tet_row[p] + lane; e < e1; e += L) tet_contrib(T, T.x, T.tet_ent[e], K.alpha, a);
-        }
+        if (TETS) tet_terms<L, KU>(T, T.x, T.tet_row[p], T.tet_row[p + 1], lane, K.alpha, a);
         if (SPRINGS) {
             const int e1 = T.spr_row[p + 1];
             for (int e = T.spr_row[p] + lane; e < e1; e += L)
@@ -297,15 +324,16 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
 }
 
 // ----------------------------------------------------------------- kernels --
-__global__ void k_material(TetRec *rec, const float *E, int n, float k_mu, float k_lam)
+__global__ void k_material(TetRec *rec, const float *vol, const int *tet_perm, const float *E,
+                           int n, float k_mu, float k_lam)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    float4 b2 = rec[t].b2;
-    const float VE = b2.w * E[t];
-    b2.y = VE * k_mu;
-    b2.z = VE * k_lam;
-    rec[t].b2 = b2;
+    float4 b = rec[t].b;
+    const float VE = vol[t] * E[tet_perm[t]];
+    b.z = VE * k_mu;
+    b.w = VE * k_lam;
+    rec[t].b = b;
 }
 
 // y = x^t + h v^t + h^2 a_ext (Eq. inertia) and the initial guess (Sec. 3.7).
@@ -350,13 +378,16 @@ __global__ void k_predict(DevTopo T, const float *x, const float *v, const float
     if (cheb) { T.prev1[p] = x04; T.prev2[p] = x04; }
 }
 
-template <int L, bool TETS, bool SPRINGS>
-__global__ void k_solve(DevTopo T, StepConsts K, int v_begin, int v_end, int remap)
+constexpr int kMaxBlock = 512;
+
+template <int L, int KU, bool TETS, bool SPRINGS>
+__global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, int v_begin,
+                                                     int v_end, int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end);
+    solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end);
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -446,8 +477,9 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned target)
     return s_abort != 0;
 }
 
-template <int L, bool TETS, bool SPRINGS>
-__global__ void k_persistent(DevTopo T, StepConsts K, int n_iters, int remap)
+template <int L, int KU, bool TETS, bool SPRINGS>
+__global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts K, int n_iters,
+                                                          int remap)
 {
     const int nb = gridDim.x;
     const int b = xcd_block(blockIdx.x, nb, remap);
@@ -464,7 +496,7 @@ __global__ void k_persistent(DevTopo T, StepConsts K, int n_iters, int remap)
             const int cend = min(cb + chunk, ve);
             for (int base = cb; base < cb + chunk; base += G) {
                 const int p = base + g;
-                solve_vertex<L, TETS, SPRINGS>(T, K, p, lane, p < cend);
+                solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, lane, p < cend);
             }
             ++nbar;
             if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
@@ -514,7 +546,7 @@ __global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const fl
 //   K_kq^T w = V [mu (m_k.m_q) w + lam c_q (c_k.w) + lam (J - alpha) (u x w)],
 //   u = F (m_k x m_q)   (d2J/dx_k dx_q w' = w' x u).
 template <int L>
-__global__ void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const float4 *Sp,
+__global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const float4 *Sp,
                                 int v_begin, int v_end, float *gE, int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
@@ -541,7 +573,7 @@ __global__ void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const
             tet_local(r, q0, q1, q2, q3, Lc);
             const float3 mk = shape_grad(Lc, k);
             const float3 cm = Cmul(Lc, mk);
-            const float Vmu = r.b2.y, Vlam = r.b2.z;
+            const float Vmu = r.b.z, Vlam = r.b.w;
             const float d = Vmu * dot3(mk, mk);
             a.hxx += d + Vlam * cm.x * cm.x; a.hxy += Vlam * cm.x * cm.y; a.hxz += Vlam * cm.x * cm.z;
             a.hyy += d + Vlam * cm.y * cm.y; a.hyz += Vlam * cm.y * cm.z; a.hzz += d + Vlam * cm.z * cm.z;
@@ -575,7 +607,7 @@ __global__ void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const
         const float3 mk = shape_grad(Lc, k);
         const float3 ck = Cmul(Lc, mk);
         const float cw = dot3(ck, w);
-        const float Vmu = r.b2.y, Vlam = r.b2.z;
+        const float Vmu = r.b.z, Vlam = r.b.w;
         const float s = Vlam * (Lc.J - K.alpha);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -591,8 +623,8 @@ __global__ void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const
             atomicAdd(&dst->z, -(mm * w.z + Vlam * cw * cq.z + s * uw.z));
         }
         const float3 Fm = Fmul(Lc, mk);
-        const float V = r.b2.w;
-        gE[t] -= V * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
+        const float V = T.vol[t];
+        gE[T.tet_perm[t]] -= V * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
     }
 }
 
@@ -635,8 +667,8 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K, hipStream_t s)
 {
     if (T.n_tets == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_material, dim3(cdiv(T.n_tets, 256)), dim3(256), 0, s, T.rec, tet_E,
-                       T.n_tets, K.k_mu, K.k_lam);
+    hipLaunchKernelGGL(k_material, dim3(cdiv(T.n_tets, 256)), dim3(256), 0, s, T.rec, T.vol,
+                       T.tet_perm, tet_E, T.n_tets, K.k_mu, K.k_lam);
     return hipGetLastError();
 }
 
@@ -648,31 +680,44 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
     return hipGetLastError();
 }
 
-template <int L>
+template <int L, int KU>
 static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
                                  bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
     if (tets && springs)
-        hipLaunchKernelGGL((k_solve<L, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve<L, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve<L, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve<L, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
     return hipGetLastError();
+}
+
+template <int L>
+static hipError_t solve_unroll(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
+                               bool springs, const LaunchCfg &cfg, hipStream_t s)
+{
+    switch (cfg.unroll) {
+    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, tets, springs, cfg, s);
+    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, tets, springs, cfg, s);
+    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, tets, springs, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
                         bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
+    if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
-    case 4: return solve_dispatch<4>(T, K, vb, ve, tets, springs, cfg, s);
-    case 8: return solve_dispatch<8>(T, K, vb, ve, tets, springs, cfg, s);
-    case 16: return solve_dispatch<16>(T, K, vb, ve, tets, springs, cfg, s);
-    case 32: return solve_dispatch<32>(T, K, vb, ve, tets, springs, cfg, s);
+    case 4: return solve_unroll<4>(T, K, vb, ve, tets, springs, cfg, s);
+    case 8: return solve_unroll<8>(T, K, vb, ve, tets, springs, cfg, s);
+    case 16: return solve_unroll<16>(T, K, vb, ve, tets, springs, cfg, s);
+    case 32: return solve_unroll<32>(T, K, vb, ve, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -692,12 +737,12 @@ hipError_t launch_finalize(const DevTopo &T, float *x, float *v, float *vp, cons
     return hipGetLastError();
 }
 
-template <int L, bool TE, bool SP>
+template <int L, int KU, bool TE, bool SP>
 static hipError_t persistent_go(const DevTopo &T, const StepConsts &K, int n_iters,
                                 const LaunchCfg &cfg, int n_cu, bool coop, hipStream_t s,
                                 int *grid_out)
 {
-    auto fn = k_persistent<L, TE, SP>;
+    auto fn = k_persistent<L, KU, TE, SP>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, cfg.block, 0);
     if (e != hipSuccess) return e;
@@ -721,26 +766,40 @@ static hipError_t persistent_go(const DevTopo &T, const StepConsts &K, int n_ite
     return hipGetLastError();
 }
 
-template <int L>
+template <int L, int KU>
 static hipError_t persistent_kinds(const DevTopo &T, const StepConsts &K, int n_iters, bool tets,
                                    bool springs, const LaunchCfg &cfg, int n_cu, bool coop,
                                    hipStream_t s, int *grid_out)
 {
-    if (tets && springs) return persistent_go<L, true, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
-    if (tets) return persistent_go<L, true, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
-    if (springs) return persistent_go<L, false, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
-    return persistent_go<L, false, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (tets && springs) return persistent_go<L, KU, true, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (tets) return persistent_go<L, KU, true, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (springs) return persistent_go<L, 1, false, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    return persistent_go<L, 1, false, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+}
+
+template <int L>
+static hipError_t persistent_unroll(const DevTopo &T, const StepConsts &K, int n_iters, bool tets,
+                                    bool springs, const LaunchCfg &cfg, int n_cu, bool coop,
+                                    hipStream_t s, int *grid_out)
+{
+    switch (cfg.unroll) {
+    case 1: return persistent_kinds<L, 1>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 2: return persistent_kinds<L, 2>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 3: return persistent_kinds<L, 3>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters, bool tets,
                              bool springs, const LaunchCfg &cfg, int n_cu, bool coop,
                              hipStream_t s, int *grid_out)
 {
+    if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
-    case 4: return persistent_kinds<4>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
-    case 8: return persistent_kinds<8>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
-    case 16: return persistent_kinds<16>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
-    case 32: return persistent_kinds<32>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 4: return persistent_unroll<4>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 8: return persistent_unroll<8>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 16: return persistent_unroll<16>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
+    case 32: return persistent_unroll<32>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
     default: return hipErrorInvalidValue;
     }
 }

@@ -164,5 +164,36 @@ def test_phase_bytes_model():
     for c in range(t.n_colors):
         pairs = rows[co[c + 1]] - rows[co[c]]
         nvc = co[c + 1] - co[c]
-        assert pb[c] >= 68 * pairs + 52 * nvc
-        assert pb[c] <= 68 * pairs + 52 * nvc + 16 * w.n_verts
+        assert pb[c] >= 52 * pairs + 52 * nvc
+        assert pb[c] <= 52 * pairs + 52 * nvc + 16 * w.n_verts
+
+
+def test_tet_order_groups_tets_by_vertex_colors():
+    w = W.tet_cube(7, 2)
+    t = Topology.from_workload(w, bind=False)
+    order = t.query(N.Q_TET_ORDER)
+    assert np.array_equal(np.sort(order), np.arange(w.n_tets))
+    colors = t.query(N.Q_COLORS)
+    keys = [tuple(sorted(colors[w.tets[o]])) for o in order]
+    assert keys == sorted(keys)
+
+
+def test_rest_frame_preserves_deformation_invariants():
+    """F' = D_s R^{-1} = F Q (Q a proper rotation) must keep F F^T, tr(F^T F)
+    and det F of F = D_s D_m^{-1}: the invariants the energy depends on."""
+    w = W.tet_cube(4, 3)
+    t = Topology.from_workload(w, bind=False)
+    S6 = t.query(N.Q_REST_FRAME).reshape(-1, 6)
+    Dminv = t.query(N.Q_DMINV).reshape(-1, 3, 3)
+    rng = np.random.default_rng(0)
+    x = w.rest + rng.normal(scale=0.02, size=w.rest.shape)
+    for k in rng.choice(w.n_tets, 50, replace=False):
+        S = np.array([[S6[k, 0], S6[k, 1], S6[k, 2]], [0, S6[k, 3], S6[k, 4]], [0, 0, S6[k, 5]]])
+        q = w.tets[k]
+        Ds = (x[q[1:]] - x[q[0]]).T
+        F, Fp = Ds @ Dminv[k], Ds @ S
+        assert np.allclose(Fp @ Fp.T, F @ F.T, rtol=1e-12, atol=1e-12)
+        assert np.trace(Fp.T @ Fp) == pytest.approx(np.trace(F.T @ F), rel=1e-12)
+        Q = np.linalg.solve(F, Fp)
+        assert np.allclose(Q.T @ Q, np.eye(3), atol=1e-10)
+        assert np.linalg.det(Fp) == pytest.approx(np.linalg.det(F), rel=1e-12)
