@@ -90,8 +90,9 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *desc, vbd_topology *out);
 /* Greedy vertex coloring (Sec. 3.9): no force element (tet, spring) may use
  * two vertices of one color; first-fit in ascending vertex id.  Then builds
  * the color-sorted vertex permutation (free vertices by (color, id), pinned
- * vertices last by id) and the incidence CSR of every free vertex.  Host,
- * synchronous.  colors_out: host [n_verts] or NULL. */
+ * vertices last by id), the tet incidence CSR of every vertex slot and the
+ * spring incidence CSR of every free slot.  Host, synchronous.
+ * colors_out: host [n_verts] or NULL. */
 vbd_status vbd_color(vbd_topology topo, int32_t *n_colors_out, int32_t *colors_out);
 
 /* Device bytes the workspace needs.  max_backward_iters: largest n_iters that
@@ -111,7 +112,7 @@ enum {
     VBD_Q_COLORS = 1,       /* int32[n_verts] */
     VBD_Q_PERM = 2,         /* int32[n_verts]: permuted slot -> original id */
     VBD_Q_COLOR_OFFSETS = 3,/* int32[n_colors+1] over the free permuted slots */
-    VBD_Q_TET_ROWS = 4,     /* int32[n_free+1] */
+    VBD_Q_TET_ROWS = 4,     /* int32[n_verts+1] over permuted slots (free slots first) */
     VBD_Q_TET_ENTRIES = 5,  /* int32[entries]: (tet << 2) | slot, ascending tet */
     VBD_Q_SPRING_ROWS = 6,  /* int32[n_free+1] */
     VBD_Q_SPRING_NBRS = 7,  /* int32[entries]: original id of the other end */

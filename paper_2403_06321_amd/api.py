@@ -122,7 +122,7 @@ class Topology:
         c = self.counts()
         n_free = c["n_free"]
         spec = {N.Q_COLORS: (np.int32, c["n_verts"]), N.Q_PERM: (np.int32, c["n_verts"]),
-                N.Q_COLOR_OFFSETS: (np.int32, c["n_colors"] + 1), N.Q_TET_ROWS: (np.int32, n_free + 1),
+                N.Q_COLOR_OFFSETS: (np.int32, c["n_colors"] + 1), N.Q_TET_ROWS: (np.int32, c["n_verts"] + 1),
                 N.Q_TET_ENTRIES: (np.int32, c["tet_entries"]), N.Q_SPRING_ROWS: (np.int32, n_free + 1),
                 N.Q_SPRING_NBRS: (np.int32, c["spring_entries"]), N.Q_MASS: (np.float64, c["n_verts"]),
                 N.Q_DMINV: (np.float64, 9 * c["n_tets"]), N.Q_VOLUME: (np.float64, c["n_tets"]),

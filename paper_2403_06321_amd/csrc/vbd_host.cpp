@@ -48,7 +48,7 @@ inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t rec, vol, tet_perm, tet_row, tet_ent, spr_row, spr_ent, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
-    size_t snaps, xbar, ybar, xtbar, vbar;
+    size_t snaps, xbar, ybar, xtbar, vbar, contrib;
     size_t total;
     int max_bwd_iters;
 };
@@ -129,7 +129,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.rec = take(sizeof(TetRec) * (size_t)T.nt);
     L.vol = take(sizeof(float) * (size_t)T.nt);
     L.tet_perm = take(sizeof(int32_t) * (size_t)T.nt);
-    L.tet_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
+    L.tet_row = take(sizeof(int32_t) * (size_t)(T.nv + 1));
     L.tet_ent = take(sizeof(int32_t) * T.tet_ent.size());
     L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
     L.spr_ent = take(sizeof(int2) * T.spr_nbr_orig.size());
@@ -150,6 +150,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.ybar = take(sizeof(float4) * nv);
         L.xtbar = take(sizeof(float4) * nv);
         L.vbar = take(sizeof(float4) * nv);
+        L.contrib = take(sizeof(float4) * 4 * (size_t)T.nt);
     }
     L.total = off;
     return L;
@@ -182,6 +183,7 @@ void set_dev_pointers(vbd_topology_s &T)
     D.ybar = L.max_bwd_iters > 0 ? (float4 *)(b + L.ybar) : nullptr;
     D.xtbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xtbar) : nullptr;
     D.vbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.vbar) : nullptr;
+    D.contrib = L.max_bwd_iters > 0 ? (float4 *)(b + L.contrib) : nullptr;
     D.n_verts = T.nv;
     D.n_tets = T.nt;
     D.n_free = T.n_free;
@@ -338,21 +340,20 @@ void build_csr(vbd_topology_s &T)
         T.perm[slot] = v;
         T.iperm[v] = slot;
     }
-    // tet incidence of free vertices, ascending tet id
-    std::vector<int32_t> deg(n_free + 1, 0);
+    // tet incidence of every vertex slot (free ones first), ascending tet id;
+    // the solve kernels only visit the free slots, the adjoint's final fold
+    // visits all of them
+    std::vector<int32_t> deg(nv + 1, 0);
     for (int t = 0; t < T.nt; ++t)
-        for (int k = 0; k < 4; ++k) {
-            const int s = T.iperm[T.tets[4 * (size_t)t + k]];
-            if (s < n_free) deg[s + 1]++;
-        }
-    T.tet_row.assign(n_free + 1, 0);
-    for (int s = 0; s < n_free; ++s) T.tet_row[s + 1] = T.tet_row[s] + deg[s + 1];
-    T.tet_ent.assign((size_t)T.tet_row[n_free], 0);
+        for (int k = 0; k < 4; ++k) deg[T.iperm[T.tets[4 * (size_t)t + k]] + 1]++;
+    T.tet_row.assign(nv + 1, 0);
+    for (int s = 0; s < nv; ++s) T.tet_row[s + 1] = T.tet_row[s] + deg[s + 1];
+    T.tet_ent.assign((size_t)T.tet_row[nv], 0);
     std::vector<int32_t> pos(T.tet_row.begin(), T.tet_row.end() - 1);
     for (int t = 0; t < T.nt; ++t)
         for (int k = 0; k < 4; ++k) {
             const int s = T.iperm[T.tets[4 * (size_t)t + k]];
-            if (s < n_free) T.tet_ent[pos[s]++] = (t << 2) | k;
+            T.tet_ent[pos[s]++] = (t << 2) | k;
         }
     // spring incidence, ascending spring id
     std::vector<int32_t> sdeg(n_free + 1, 0);
@@ -878,12 +879,14 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
     }
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
+    if (T->nt > 0) HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 16 * T->nt, s));
     for (int it = p->n_iters; it >= 1; --it) {
         const float4 *Sn = T->dev.snaps + nv * it, *Sp = Sn - nv;
         for (int c = T->n_colors - 1; c >= 0; --c)
             HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T->color_off[c], T->color_off[c + 1], g_E,
                                          T->cfg, s));
     }
+    HIP_TRY(launch_bwd_fold(D, s));
     HIP_TRY(launch_bwd_final(D, v_t, v_prev, gx_in, gv_in, gvp_in, K, s));
     return VBD_OK;
 }

@@ -51,7 +51,7 @@ struct DevTopo {
     TetRec *rec;                       // [n_tets] in tet_perm order
     const float *vol;                  // [n_tets] rest volume, tet_perm order
     const int *tet_perm;               // stored tet -> caller's tet index
-    const int *tet_row, *tet_ent;      // CSR over free permuted vertices: (stored tet << 2) | slot
+    const int *tet_row, *tet_ent;      // CSR over all permuted vertices: (stored tet << 2) | slot
     const int *spr_row;
     const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
     const int *perm;                   // permuted slot -> original id
@@ -63,6 +63,7 @@ struct DevTopo {
     unsigned *flags;                   // [0] barrier counter, [1] abort flag, [2] skip count
     float4 *snaps;                     // backward: (n_iters + 1) iterates
     float4 *xbar, *ybar, *xtbar, *vbar;
+    float4 *contrib;                   // backward: [n_tets][4] pending neighbour adjoints
     int n_verts, n_tets, n_free, n_colors;
 };
 
@@ -98,6 +99,7 @@ hipError_t launch_bwd_init(const DevTopo &T, const float *gx_out, const float *g
 hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const float4 *Sn,
                                 const float4 *Sp, int v_begin, int v_end, float *g_tet_E,
                                 const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s);
 hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev,
                             float *gx_in, float *gv_in, float *gvp_in, const StepConsts &K,
                             hipStream_t s);

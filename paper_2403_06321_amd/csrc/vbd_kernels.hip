@@ -511,9 +511,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
     }
 }
 
+// Streaming copy: each thread keeps four independent 16-B loads in flight.
 __global__ void k_copy4(float4 *dst, const float4 *src, int n)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+    const int stride = gridDim.x * blockDim.x;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_zero_u32(unsigned *p, int n)
@@ -545,9 +555,16 @@ __global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const fl
 // iteration n (Sn), the others from iteration n-1 (Sp).
 //   K_kq^T w = V [mu (m_k.m_q) w + lam c_q (c_k.w) + lam (J - alpha) (u x w)],
 //   u = F (m_k x m_q)   (d2J/dx_k dx_q w' = w' x u).
+// Neighbour adjoints go to per-(tet, slot) cells instead of the neighbours
+// themselves: in a color phase a tet has at most one vertex of that color, so
+// its cells are written by one thread only (no atomics, deterministic).  A
+// vertex folds (reads and clears) its own cells when its color is processed,
+// and k_bwd_fold folds what is left at the end of the sweep.
 template <int L>
-__global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K, const float4 *Sn, const float4 *Sp,
-                                int v_begin, int v_end, float *gE, int remap)
+__global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K,
+                                                             const float4 *Sn, const float4 *Sp,
+                                                             int v_begin, int v_end, float *gE,
+                                                             int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
@@ -577,6 +594,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             const float d = Vmu * dot3(mk, mk);
             a.hxx += d + Vlam * cm.x * cm.x; a.hxy += Vlam * cm.x * cm.y; a.hxz += Vlam * cm.x * cm.z;
             a.hyy += d + Vlam * cm.y * cm.y; a.hyz += Vlam * cm.y * cm.z; a.hzz += d + Vlam * cm.z * cm.z;
+            float4 *cell = T.contrib + 4 * (size_t)t + k;
+            const float4 g = *cell;
+            a.fx += g.x; a.fy += g.y; a.fz += g.z;
+            *cell = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
     acc_reduce<L>(a);
@@ -584,9 +605,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
     const float wm = T.y[p].w;
     a.hxx += wm; a.hyy += wm; a.hzz += wm;
     const float4 xb4 = T.xbar[p];
-    a.fx = xb4.x; a.fy = xb4.y; a.fz = xb4.z;
+    a.fx += xb4.x; a.fy += xb4.y; a.fz += xb4.z;
     float3 w;
-    if (!solve_sym3(a, K.det_eps_rel, w)) return;   // skipped update: xbar passes through
+    if (!solve_sym3(a, K.det_eps_rel, w)) {
+        // skipped update: the adjoint passes through (with the folded cells)
+        if (lane == 0) T.xbar[p] = make_float4(a.fx, a.fy, a.fz, 0.f);
+        return;
+    }
     if (lane == 0) {
         T.xbar[p] = make_float4(0.f, 0.f, 0.f, 0.f);
         float4 yb = T.ybar[p];
@@ -617,15 +642,32 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             const float3 u = Fmul(Lc, cross3(mk, mq));
             const float3 uw = cross3(u, w);
             const float mm = Vmu * dot3(mk, mq);
-            float4 *dst = T.xbar + ids[q];
-            atomicAdd(&dst->x, -(mm * w.x + Vlam * cw * cq.x + s * uw.x));
-            atomicAdd(&dst->y, -(mm * w.y + Vlam * cw * cq.y + s * uw.y));
-            atomicAdd(&dst->z, -(mm * w.z + Vlam * cw * cq.z + s * uw.z));
+            float4 *cell = T.contrib + 4 * (size_t)t + q;
+            float4 g = *cell;
+            g.x -= mm * w.x + Vlam * cw * cq.x + s * uw.x;
+            g.y -= mm * w.y + Vlam * cw * cq.y + s * uw.y;
+            g.z -= mm * w.z + Vlam * cw * cq.z + s * uw.z;
+            *cell = g;
         }
         const float3 Fm = Fmul(Lc, mk);
         const float V = T.vol[t];
         gE[T.tet_perm[t]] -= V * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
     }
+}
+
+// End of the reverse sweep: every vertex (pinned ones included) folds the
+// cells of its incident tets into its adjoint.
+__global__ void k_bwd_fold(DevTopo T)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_verts) return;
+    float4 xb = T.xbar[p];
+    for (int e = T.tet_row[p]; e < T.tet_row[p + 1]; ++e) {
+        const int ent = T.tet_ent[e];
+        const float4 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
+        xb.x += g.x; xb.y += g.y; xb.z += g.z;
+    }
+    T.xbar[p] = xb;
 }
 
 // Adjoint of the initial guess (Sec. 3.7) and of y, written in original order.
@@ -808,7 +850,7 @@ hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     int grid = cdiv(n, 256);
-    if (grid > 8192) grid = 8192;
+    if (grid > 4096) grid = 4096;
     hipLaunchKernelGGL(k_copy4, dim3(grid), dim3(256), 0, s, dst, src, n);
     return hipGetLastError();
 }
@@ -840,6 +882,12 @@ hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const flo
     case 32: hipLaunchKernelGGL(k_adjoint_color<32>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bwd_fold, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T);
     return hipGetLastError();
 }
 

@@ -62,7 +62,7 @@ def _expected_layout(w, colors):
     perm = np.concatenate([free[np.lexsort((free, colors[free]))], np.flatnonzero(pinned)])
     iperm = np.empty(nv, np.int64); iperm[perm] = np.arange(nv)
     rows, ents = [0], []
-    for v in perm[:len(free)]:
+    for v in perm:
         inc = [(t << 2) | int(np.flatnonzero(w.tets[t] == v)[0])
                for t in np.flatnonzero((w.tets == v).any(1))]
         ents.extend(sorted(inc))
