@@ -322,6 +322,10 @@ def extras(dev, W, Topology):
     res["cloth_persistent_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
     secs, upd = time_frames(tc, wc, MODES["graph"], 10, 3, dev)
     res["cloth_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
+    roof = kernel_roofline(tc, wc, dev, frames=2)
+    res["cloth_solve_kernel"] = dict(avg_launch_us=roof["avg_ms"] * 1e3,
+                                     achieved_gbs=roof["achieved_gbs"],
+                                     frac=roof["achieved_gbs"] / HBM_PEAK_GBS)
     log(f"[bench] cloth {res['cloth_persistent_graph']['updates_per_s']:.3e} / "
         f"{res['cloth_graph']['updates_per_s']:.3e} v-upd/s")
     return res
