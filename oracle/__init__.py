@@ -49,6 +49,12 @@ def lib():
         L.oracle_step_backward.argtypes = [p] * 13
         L.oracle_step_backward.restype = i32
         L.oracle_set_threads.argtypes = [i32]
+        L.oracle_surface.argtypes = [i32, p, p, p]
+        L.oracle_surface.restype = i32
+        L.oracle_closest_point_triangle.argtypes = [p, p, p, p, p, p]
+        L.oracle_detect_contacts.argtypes = [p, p, p, p]
+        L.oracle_winding_number.argtypes = [p, C.c_int32, p, p]
+        L.oracle_winding_number.restype = C.c_double
         _lib = L
     return _lib
 
@@ -62,7 +68,8 @@ class _Model(C.Structure):
                 ("n_colors", C.c_int32), ("tets", C.c_void_p), ("springs", C.c_void_p),
                 ("Dminv", C.c_void_p), ("vol", C.c_void_p), ("spring_rest", C.c_void_p),
                 ("mass", C.c_void_p), ("pinned", C.c_void_p), ("colors", C.c_void_p),
-                ("nu", C.c_double), ("spring_k", C.c_double)]
+                ("nu", C.c_double), ("spring_k", C.c_double),
+                ("n_surf_tris", C.c_int32), ("surf_tris", C.c_void_p), ("vert_mesh", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -73,7 +80,8 @@ class _Params(C.Structure):
                 ("n_planes", C.c_int32), ("planes", C.c_void_p),
                 ("kd", C.c_double), ("cheb_rho", C.c_double),
                 ("friction_mu", C.c_double), ("friction_eps_v", C.c_double),
-                ("spring_psd", C.c_int32)]
+                ("spring_psd", C.c_int32), ("mesh_contacts", C.c_int32),
+                ("collision_radius", C.c_double), ("n_col", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -151,11 +159,26 @@ def spring_derivs(xa, xb, L, k):
     return g, H
 
 
+def surface(tets, rest):
+    tets = np.ascontiguousarray(tets, np.int32)
+    out = np.zeros((4 * tets.shape[0], 3), np.int32)
+    n = lib().oracle_surface(tets.shape[0], _ptr(tets), _ptr(np.ascontiguousarray(rest, np.float64)),
+                             _ptr(out))
+    return out[:n].copy()
+
+
+def closest_point_triangle(p, a, b, c):
+    arr = [np.ascontiguousarray(v, np.float64) for v in (p, a, b, c)]
+    q = np.zeros(3); bary = np.zeros(3)
+    lib().oracle_closest_point_triangle(*[_ptr(v) for v in arr], _ptr(q), _ptr(bary))
+    return q, bary
+
+
 class Model:
     """Oracle-side model: rest data, masses and coloring computed by the oracle."""
 
     def __init__(self, rest, tets, pinned, *, density=1000.0, nu=0.3, springs=None,
-                 spring_rest_len=None, spring_k=0.0, mass=None):
+                 spring_rest_len=None, spring_k=0.0, mass=None, vert_offsets=None):
         self.rest = np.ascontiguousarray(rest, np.float64)
         self.n_verts = self.rest.shape[0]
         self.tets = np.ascontiguousarray(tets, np.int32).reshape(-1, 4)
@@ -178,15 +201,23 @@ class Model:
         else:
             self.spring_rest = np.zeros(0)
         self.colors, self.n_colors = color_greedy(self.n_verts, self.tets, self.springs)
+        self.surf_tris = (surface(self.tets, self.rest) if self.tets.shape[0]
+                          else np.zeros((0, 3), np.int32))
+        self.vert_mesh = np.zeros(self.n_verts, np.int32)
+        if vert_offsets is not None:
+            for k in range(len(vert_offsets) - 1):
+                self.vert_mesh[int(vert_offsets[k]):int(vert_offsets[k + 1])] = k
         self._s = _Model(self.n_verts, self.tets.shape[0], self.springs.shape[0], self.n_colors,
                          _ptr(self.tets), _ptr(self.springs), _ptr(self.Dminv), _ptr(self.vol),
                          _ptr(self.spring_rest), _ptr(self.mass), _ptr(self.pinned),
-                         _ptr(self.colors), self.nu, self.spring_k)
+                         _ptr(self.colors), self.nu, self.spring_k, self.surf_tris.shape[0],
+                         _ptr(self.surf_tris), _ptr(self.vert_mesh))
 
     @classmethod
     def from_workload(cls, w):
         return cls(w.rest, w.tets, w.pinned, density=w.density, nu=w.nu, springs=w.springs,
-                   spring_rest_len=w.spring_rest, spring_k=w.spring_k, mass=w.mass)
+                   spring_rest_len=w.spring_rest, spring_k=w.spring_k, mass=w.mass,
+                   vert_offsets=w.vert_offsets)
 
     def set_colors(self, colors):
         """Replace the coloring (tests of coloring-dependent behaviour)."""
@@ -203,7 +234,9 @@ def _params(p):
                 int(p.init_mode), float(p.det_eps_rel), float(p.contact_k),
                 float(p.contact_thickness), 0 if sph is None else sph.shape[0], _ptr(sph),
                 0 if pl is None else pl.shape[0], _ptr(pl), float(p.kd), float(p.cheb_rho),
-                float(p.friction_mu), float(p.friction_eps_v), int(bool(getattr(p, "spring_psd", False))))
+                float(p.friction_mu), float(p.friction_eps_v), int(bool(getattr(p, "spring_psd", False))),
+                int(bool(getattr(p, "mesh_contacts", False))), float(getattr(p, "collision_radius", 0.0)),
+                int(getattr(p, "n_col", 0)))
     return s, (sph, pl)
 
 
@@ -240,6 +273,20 @@ def step_cs(model: Model, params, x, v, vprev, tet_E):
     if r != 0:
         raise ValueError(f"oracle_step_cs failed ({r})")
     return x, v, vp
+
+
+def detect_contacts(model: Model, params, x):
+    x = np.ascontiguousarray(x, np.float64)
+    out = np.zeros(model.n_verts, np.int32)
+    ps, keep = _params(params)
+    lib().oracle_detect_contacts(C.byref(model._s), C.byref(ps), _ptr(x), _ptr(out))
+    return out
+
+
+def winding_number(model: Model, mesh, p, x):
+    x = np.ascontiguousarray(x, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    return lib().oracle_winding_number(C.byref(model._s), int(mesh), _ptr(p), _ptr(x))
 
 
 def predict(model: Model, params, x, v):

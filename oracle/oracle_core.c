@@ -280,15 +280,207 @@ static void inc_free(Inc *ic)
 }
 
 /* ---------------------------------------------------------------------------
+ * Mesh-mesh vertex-triangle contacts (Sec. 3.5).  Closest point on a triangle:
+ * the projection onto its plane if that lies inside, otherwise the nearest
+ * of the three edge projections (each clamped to its segment).  Region
+ * decisions use real parts.
+ * ------------------------------------------------------------------------- */
+static void closest_point_R(const R p[3], const R a[3], const R b[3], const R c[3], R q[3],
+                            R bary[3])
+{
+    R ab[3], ac[3], n[3];
+    for (int k = 0; k < 3; ++k) { ab[k] = b[k] - a[k]; ac[k] = c[k] - a[k]; }
+    n[0] = ab[1] * ac[2] - ab[2] * ac[1];
+    n[1] = ab[2] * ac[0] - ab[0] * ac[2];
+    n[2] = ab[0] * ac[1] - ab[1] * ac[0];
+    R nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    R t = ((p[0] - a[0]) * n[0] + (p[1] - a[1]) * n[1] + (p[2] - a[2]) * n[2]) / nn;
+    R q0[3] = {p[0] - t * n[0], p[1] - t * n[1], p[2] - t * n[2]};
+    /* barycentric weights by signed sub-triangle areas */
+    const R *V[3] = {a, b, c};
+    R w[3];
+    for (int k = 0; k < 3; ++k) {
+        const R *u = V[(k + 1) % 3], *v = V[(k + 2) % 3];
+        R e1[3] = {u[0] - q0[0], u[1] - q0[1], u[2] - q0[2]};
+        R e2[3] = {v[0] - q0[0], v[1] - q0[1], v[2] - q0[2]};
+        R cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        w[k] = (cr[0] * n[0] + cr[1] * n[1] + cr[2] * n[2]) / nn;
+    }
+    if (RE(w[0]) >= 0.0 && RE(w[1]) >= 0.0 && RE(w[2]) >= 0.0) {
+        for (int k = 0; k < 3; ++k) { q[k] = q0[k]; bary[k] = w[k]; }
+        return;
+    }
+    double best = -1.0;
+    for (int e = 0; e < 3; ++e) {
+        const int i0 = e, i1 = (e + 1) % 3;
+        const R *u = V[i0], *v = V[i1];
+        R d[3] = {v[0] - u[0], v[1] - u[1], v[2] - u[2]};
+        R sn = ((p[0] - u[0]) * d[0] + (p[1] - u[1]) * d[1] + (p[2] - u[2]) * d[2]) /
+               (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (RE(sn) < 0.0) sn = 0.0;
+        if (RE(sn) > 1.0) sn = 1.0;
+        R c0[3] = {u[0] + sn * d[0], u[1] + sn * d[1], u[2] + sn * d[2]};
+        double dd = 0.0;
+        for (int k = 0; k < 3; ++k) dd += RE(p[k] - c0[k]) * RE(p[k] - c0[k]);
+        if (best < 0.0 || dd < best) {
+            best = dd;
+            for (int k = 0; k < 3; ++k) { q[k] = c0[k]; bary[k] = 0.0; }
+            bary[i0] = 1.0 - sn;
+            bary[i1] = sn;
+        }
+    }
+}
+
+static void tri_normal_R(const R a[3], const R b[3], const R c[3], R n[3])
+{
+    R ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, ac[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    n[0] = ab[1] * ac[2] - ab[2] * ac[1];
+    n[1] = ab[2] * ac[0] - ab[0] * ac[2];
+    n[2] = ab[0] * ac[1] - ab[1] * ac[0];
+    R l = RSQRT(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int k = 0; k < 3; ++k) n[k] /= l;
+}
+
+typedef struct {
+    int32_t *tri;          /* [n_verts] contact triangle of a surface vertex or -1 */
+    int32_t *crow, *cent;  /* corner incidence: vertices whose contact triangle uses v */
+} Contacts;
+
+/* detection: for each surface vertex, the closest surface triangle of another
+ * mesh within collision_radius whose outward side is closer than delta */
+/* generalized winding number of the closed surface of mesh `mesh` at p:
+ * sum of the signed solid angles of its triangles over 4 pi (Van Oosterom and
+ * Strackee's formula for the solid angle of a triangle); 1 inside, 0 outside
+ * for outward-oriented triangles. */
+static double winding_number(const oracle_model *M, int mesh, const double p[3], const R *x)
+{
+    double w = 0.0;
+    for (int t = 0; t < M->n_surf_tris; ++t) {
+        const int32_t *T = M->surf_tris + 3 * t;
+        if ((M->vert_mesh ? M->vert_mesh[T[0]] : 0) != mesh) continue;
+        double a[3], b[3], c[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = RE(x[3 * T[0] + k]) - p[k];
+            b[k] = RE(x[3 * T[1] + k]) - p[k];
+            c[k] = RE(x[3 * T[2] + k]) - p[k];
+        }
+        const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        const double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        const double lc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        const double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                           a[2] * (b[0] * c[1] - b[1] * c[0]);
+        const double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+        const double ac = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+        const double bc = b[0] * c[0] + b[1] * c[1] + b[2] * c[2];
+        w += 2.0 * atan2(det, la * lb * lc + ab * lc + ac * lb + bc * la);
+    }
+    return w / (4.0 * 3.14159265358979323846);
+}
+
+/* discrete detection (Sec. 3.5): for each surface vertex, the closest surface
+ * triangle of any other mesh within collision_radius (ties: lower index); the
+ * pair is a contact when the vertex has penetrated that mesh (winding number
+ * above 1/2) or lies closer than the contact thickness to its surface. */
+static void detect_R(const oracle_model *M, const oracle_params *P, const R *x, int32_t *tri_out)
+{
+    const int nv = M->n_verts;
+    uint8_t *on_surf = (uint8_t *)calloc((size_t)nv + 1, 1);
+    for (int t = 0; t < M->n_surf_tris; ++t)
+        for (int k = 0; k < 3; ++k) on_surf[M->surf_tris[3 * t + k]] = 1;
+    for (int v = 0; v < nv; ++v) {
+        tri_out[v] = -1;
+        if (!on_surf[v]) continue;
+        const int mv = M->vert_mesh ? M->vert_mesh[v] : 0;
+        double best = 0.0;
+        int bt = -1;
+        for (int t = 0; t < M->n_surf_tris; ++t) {
+            const int32_t *T = M->surf_tris + 3 * t;
+            if ((M->vert_mesh ? M->vert_mesh[T[0]] : 0) == mv) continue;
+            R q[3], bary[3];
+            closest_point_R(x + 3 * v, x + 3 * T[0], x + 3 * T[1], x + 3 * T[2], q, bary);
+            double dist = 0.0;
+            for (int k = 0; k < 3; ++k) dist += RE(x[3 * v + k] - q[k]) * RE(x[3 * v + k] - q[k]);
+            dist = sqrt(dist);
+            if (!(dist < P->collision_radius)) continue;
+            if (bt < 0 || dist < best) { best = dist; bt = t; }
+        }
+        if (bt < 0) continue;
+        const double p[3] = {RE(x[3 * v]), RE(x[3 * v + 1]), RE(x[3 * v + 2])};
+        const int mb = M->vert_mesh ? M->vert_mesh[M->surf_tris[3 * bt]] : 0;
+        if (best < P->contact_thickness || winding_number(M, mb, p, x) > 0.5) tri_out[v] = bt;
+    }
+    free(on_surf);
+}
+
+static void contacts_index(const oracle_model *M, Contacts *C)
+{
+    const int nv = M->n_verts;
+    free(C->crow); free(C->cent);
+    C->crow = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int v = 0; v < nv; ++v)
+        if (C->tri[v] >= 0)
+            for (int k = 0; k < 3; ++k) C->crow[M->surf_tris[3 * C->tri[v] + k] + 1]++;
+    for (int v = 0; v < nv; ++v) C->crow[v + 1] += C->crow[v];
+    C->cent = (int32_t *)malloc(sizeof(int32_t) * ((size_t)C->crow[nv] + 1));
+    int32_t *fill = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int v = 0; v < nv; ++v)
+        if (C->tri[v] >= 0)
+            for (int k = 0; k < 3; ++k) {
+                const int c = M->surf_tris[3 * C->tri[v] + k];
+                C->cent[C->crow[c] + fill[c]++] = v;
+            }
+    free(fill);
+}
+
+/* one vertex-triangle element seen from vertex `role` (-1: the colliding
+ * vertex a, 0..2: that corner of the triangle).  E = 1/2 k_c d^2 with
+ * d = delta - (x_a - x_b).n, x_b = closest point, n and the barycentric
+ * weights held fixed (Sec. 3.5); IPC-style friction with the relative
+ * displacement (x_a - x_a^t) - sum_k beta_k (x_k - x_k^t) (Sec. 3.6). */
+static int vt_contact(const oracle_params *P, const R xa[3], const R *xc[3], const R xat[3],
+                      const R *xct[3], int role, R f[3], R H[3][3])
+{
+    R q[3], bary[3], n[3];
+    closest_point_R(xa, xc[0], xc[1], xc[2], q, bary);
+    tri_normal_R(xc[0], xc[1], xc[2], n);
+    R d = P->contact_thickness - ((xa[0] - q[0]) * n[0] + (xa[1] - q[1]) * n[1] + (xa[2] - q[2]) * n[2]);
+    if (!(RE(d) > 0.0)) return 0;
+    /* dd/dx_a = -n, dd/dx_j = beta_j n */
+    R g = (role < 0) ? -1.0 : bary[role];
+    for (int a = 0; a < 3; ++a) {
+        f[a] -= P->contact_k * d * g * n[a];
+        for (int b = 0; b < 3; ++b) H[a][b] += P->contact_k * g * g * n[a] * n[b];
+    }
+    if (P->friction_mu > 0.0) {
+        R dx[3];
+        for (int a = 0; a < 3; ++a)
+            dx[a] = (xa[a] - xat[a]) - (bary[0] * (xc[0][a] - xct[0][a]) + bary[1] * (xc[1][a] - xct[1][a]) +
+                                        bary[2] * (xc[2][a] - xct[2][a]));
+        R dn = dx[0] * n[0] + dx[1] * n[1] + dx[2] * n[2];
+        R u[3] = {dx[0] - dn * n[0], dx[1] - dn * n[1], dx[2] - dn * n[2]};
+        R un = RSQRT(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double hev = P->h * P->friction_eps_v;
+        R f1u = (RE(un) < hev) ? (2.0 / hev - un / (hev * hev)) : (1.0 / un);
+        R s = P->friction_mu * P->contact_k * d * f1u;
+        /* d(dx)/dx_role = -g I  (a: +I) */
+        for (int a = 0; a < 3; ++a) {
+            f[a] += s * g * u[a];
+            for (int b = 0; b < 3; ++b) H[a][b] += s * g * g * ((a == b ? 1.0 : 0.0) - n[a] * n[b]);
+        }
+    }
+    return 1;
+}
+
+/* ---------------------------------------------------------------------------
  * Local system of vertex i (Eq. VBDForce / VBDHessian, damping Eq.
  * VBDForceWithDamping / VBDHessianWithDamping on material elements,
  * penalty contact Eq. collisionEnergy with the normal held fixed, IPC-style
  * friction Eq. IPC_friction with the approximate Hessian).
  * xi_over: optional replacement of x_i (used to evaluate after an update).
  * ------------------------------------------------------------------------- */
-static void local_system(const oracle_model *M, const oracle_params *P, const Inc *ic, int i,
-                         const R *x, const R *xi_over, const R *y, const R *xt, const R *E,
-                         R f[3], R H[3][3], int *in_contact)
+static void local_system(const oracle_model *M, const oracle_params *P, const Inc *ic,
+                         const Contacts *CT, int i, const R *x, const R *xi_over, const R *y,
+                         const R *xt, const R *E, R f[3], R H[3][3], int *in_contact)
 {
     const double h = P->h;
     const double mh2 = M->mass[i] / (h * h);
@@ -346,6 +538,27 @@ static void local_system(const oracle_model *M, const oracle_params *P, const In
             }
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) H[a][b] += kdh * Hb[a][b];
+        }
+    }
+    /* mesh-mesh vertex-triangle contacts, at the current iterate */
+    if (CT) {
+        if (CT->tri[i] >= 0) {
+            const int32_t *T = M->surf_tris + 3 * CT->tri[i];
+            const R *xc[3] = {x + 3 * T[0], x + 3 * T[1], x + 3 * T[2]};
+            const R *xct[3] = {xt + 3 * T[0], xt + 3 * T[1], xt + 3 * T[2]};
+            if (vt_contact(P, xi, xc, xt + 3 * i, xct, -1, f, H)) *in_contact = 1;
+        }
+        for (int e = CT->crow[i]; e < CT->crow[i + 1]; ++e) {
+            const int a = CT->cent[e];
+            const int32_t *T = M->surf_tris + 3 * CT->tri[a];
+            int role = 0;
+            while (T[role] != i) ++role;
+            const R *xc[3], *xct[3];
+            for (int k = 0; k < 3; ++k) {
+                xc[k] = (k == role) ? xi : x + 3 * T[k];
+                xct[k] = xt + 3 * T[k];
+            }
+            if (vt_contact(P, x + 3 * a, xc, xt + 3 * a, xct, role, f, H)) *in_contact = 1;
         }
     }
     /* contacts against analytic spheres and planes, at the current iterate */
@@ -603,8 +816,21 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
     }
     int64_t n_upd = 0, n_skip = 0, n_con = 0;
     double max_lg = 0.0, omega = 1.0;
+    Contacts CTs = {NULL, NULL, NULL};
+    const Contacts *CT = NULL;
+    if (P->mesh_contacts && M->n_surf_tris > 0) {
+        /* discrete detection at x^t (Sec. 3.5, Alg. 1) */
+        CTs.tri = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nv + 1));
+        detect_R(M, P, xt, CTs.tri);
+        contacts_index(M, &CTs);
+        CT = &CTs;
+    }
 
     for (int it = 1; it <= P->n_iters; ++it) {
+        if (CT && P->n_col > 0 && it > 1 && (it - 1) % P->n_col == 0) {
+            detect_R(M, P, x, CTs.tri);        /* re-detection every n_col iterations */
+            contacts_index(M, &CTs);
+        }
         for (int c = 0; c < C; ++c) {
             const int cb = crow[c], ce = crow[c + 1];
 #ifdef _OPENMP
@@ -615,7 +841,7 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
                 if (M->pinned[i]) continue;
                 R f[3], H[3][3], dx[3];
                 int con = 0;
-                local_system(M, P, &inc, i, x, NULL, y, xt, E, f, H, &con);
+                local_system(M, P, &inc, CT, i, x, NULL, y, xt, E, f, H, &con);
                 if (con) { collided[i] = 1; n_con++; }
                 R det = solve3((const R(*)[3])H, f, dx);
                 n_upd++;
@@ -628,7 +854,7 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
                 if (track_local_grad) {
                     R f2[3], H2[3][3];
                     int con2 = 0;
-                    local_system(M, P, &inc, i, x, xnew + 3 * i, y, xt, E, f2, H2, &con2);
+                    local_system(M, P, &inc, CT, i, x, xnew + 3 * i, y, xt, E, f2, H2, &con2);
                     double gmax = 0;
                     for (int a = 0; a < 3; ++a) gmax = fmax(gmax, fabs(RE(f2[a])));
                     if (gmax > max_lg) max_lg = gmax;
@@ -669,6 +895,7 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
     }
     free(xt); free(y); free(xnew); free(pr1); free(pr2); free(collided);
     free(crow); free(clist);
+    free(CTs.tri); free(CTs.crow); free(CTs.cent);
     inc_free(&inc);
     return 0;
 }
@@ -741,6 +968,23 @@ double oracle_energy_G(const oracle_model *M, const oracle_params *P, const doub
     return energy_G_impl(M, P, x, y, tet_E, grad, hess);
 }
 
+void oracle_closest_point_triangle(const double p[3], const double a[3], const double b[3],
+                                   const double c[3], double q[3], double bary[3])
+{
+    closest_point_R(p, a, b, c, q, bary);
+}
+
+void oracle_detect_contacts(const oracle_model *M, const oracle_params *P, const double *x,
+                            int32_t *tri_of_vertex)
+{
+    detect_R(M, P, x, tri_of_vertex);
+}
+
+double oracle_winding_number(const oracle_model *M, int32_t mesh, const double p[3], const double *x)
+{
+    return winding_number(M, mesh, p, x);
+}
+
 /* d2J/dx_k dx_l: (M_kl)_ac = sum_b,e (m_k)_b (m_l)_e dcof_ab/dF_ce,
  * with dcof_ab/dF_ce = sum_df eps_acd eps_bef F_df. */
 static void d2J_kl(const double F[3][3], const double m[4][3], int k, int l, double Mk[3][3])
@@ -779,7 +1023,7 @@ int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, cons
 {
     if (check_args(M, P)) return -1;
     if (M->n_springs > 0 || P->n_spheres > 0 || P->n_planes > 0 || P->kd != 0.0 ||
-        P->cheb_rho > 0.0)
+        P->cheb_rho > 0.0 || P->mesh_contacts)
         return -2;
     const int nv = M->n_verts, C = M->n_colors, N = P->n_iters;
     const size_t n3 = 3 * (size_t)nv;
@@ -811,7 +1055,7 @@ int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, cons
                 if (M->colors[i] != c || M->pinned[i]) continue;
                 double f[3], H[3][3], dx[3];
                 int con = 0;
-                local_system(M, P, &inc, i, x, NULL, y, x_t, E, f, H, &con);
+                local_system(M, P, &inc, NULL, i, x, NULL, y, x_t, E, f, H, &con);
                 double det = solve3((const double(*)[3])H, f, dx);
                 for (int a = 0; a < 3; ++a)
                     xnew[3 * i + a] = skip_solve((const double(*)[3])H, det, P->det_eps_rel)
@@ -846,7 +1090,7 @@ int32_t oracle_step_backward(const oracle_model *M, const oracle_params *P, cons
                 if (M->colors[i] != c || M->pinned[i]) continue;
                 double f[3], H[3][3], D[3], w[3];
                 int con = 0;
-                local_system(M, P, &inc, i, cur, NULL, y, x_t, E, f, H, &con);
+                local_system(M, P, &inc, NULL, i, cur, NULL, y, x_t, E, f, H, &con);
                 double det = solve3((const double(*)[3])H, f, D);
                 if (skip_solve((const double(*)[3])H, det, P->det_eps_rel)) continue;
                 double g[3] = {xb[3 * i], xb[3 * i + 1], xb[3 * i + 2]};

@@ -125,3 +125,56 @@ void oracle_set_threads(int32_t n)
     (void)n;
 #endif
 }
+
+typedef struct { int32_t key[3]; int32_t v[3]; int32_t opp; } Face;
+
+static int face_cmp(const void *p, const void *q)
+{
+    const Face *a = (const Face *)p, *b = (const Face *)q;
+    for (int k = 0; k < 3; ++k)
+        if (a->key[k] != b->key[k]) return a->key[k] < b->key[k] ? -1 : 1;
+    return 0;
+}
+
+/* Faces used by exactly one tet, with the normal (b-a) x (c-a) pointing away
+ * from the tet's fourth vertex; ordered by their sorted vertex ids. */
+int32_t oracle_surface(int32_t n_tets, const int32_t *tets, const double *rest, int32_t *tris_out)
+{
+    Face *F = (Face *)malloc(sizeof(Face) * (4 * (size_t)n_tets + 1));
+    size_t nf = 0;
+    for (int t = 0; t < n_tets; ++t)
+        for (int o = 0; o < 4; ++o) {
+            Face f;
+            int k = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != o) f.v[k++] = tets[4 * t + j];
+            f.opp = tets[4 * t + o];
+            int a = f.v[0], b = f.v[1], c = f.v[2], tmp;
+            if (a > b) { tmp = a; a = b; b = tmp; }
+            if (b > c) { tmp = b; b = c; c = tmp; }
+            if (a > b) { tmp = a; a = b; b = tmp; }
+            f.key[0] = a; f.key[1] = b; f.key[2] = c;
+            F[nf++] = f;
+        }
+    qsort(F, nf, sizeof(Face), face_cmp);
+    int32_t n_out = 0;
+    for (size_t i = 0; i < nf;) {
+        size_t j = i + 1;
+        while (j < nf && face_cmp(&F[i], &F[j]) == 0) ++j;
+        if (j - i == 1) {
+            const double *A = rest + 3 * F[i].v[0], *B = rest + 3 * F[i].v[1], *Cc = rest + 3 * F[i].v[2];
+            const double *D = rest + 3 * F[i].opp;
+            double ab[3], ac[3], ad[3];
+            for (int k = 0; k < 3; ++k) { ab[k] = B[k] - A[k]; ac[k] = Cc[k] - A[k]; ad[k] = D[k] - A[k]; }
+            double n[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2], ab[0] * ac[1] - ab[1] * ac[0]};
+            int32_t *o = tris_out + 3 * n_out;
+            o[0] = F[i].v[0];
+            if (n[0] * ad[0] + n[1] * ad[1] + n[2] * ad[2] > 0.0) { o[1] = F[i].v[2]; o[2] = F[i].v[1]; }
+            else { o[1] = F[i].v[1]; o[2] = F[i].v[2]; }
+            ++n_out;
+        }
+        i = j;
+    }
+    free(F);
+    return n_out;
+}

@@ -34,6 +34,9 @@ typedef struct {
     const int32_t *colors;      /* [n_verts] */
     double nu;                  /* Poisson ratio (tets) */
     double spring_k;            /* spring stiffness */
+    int32_t n_surf_tris;        /* surface triangles for mesh-mesh contacts (0 = none) */
+    const int32_t *surf_tris;   /* [n_surf_tris*3], outward oriented */
+    const int32_t *vert_mesh;   /* [n_verts] mesh id of each vertex, or NULL (one mesh) */
 } oracle_model;
 
 typedef struct {
@@ -49,6 +52,9 @@ typedef struct {
     double cheb_rho;           /* Chebyshev spectral radius (Sec. 3.8), 0 = off */
     double friction_mu, friction_eps_v;        /* Sec. 3.6 */
     int32_t spring_psd;        /* 1: clamp the transverse spring stiffness at 0 */
+    int32_t mesh_contacts;     /* 1: vertex-triangle contacts between different meshes */
+    double collision_radius;   /* detection radius for mesh-mesh contacts */
+    int32_t n_col;             /* re-detect every n_col iterations (0 = only at x^t) */
 } oracle_params;
 
 typedef struct {
@@ -72,6 +78,22 @@ void oracle_lumped_mass(int32_t n_verts, int32_t n_tets, const int32_t *tets,
                         const double *vol, double density, double *mass);
 void oracle_spring_rest(int32_t n_springs, const int32_t *springs, const double *rest,
                         double *L);
+
+/* Surface triangles of a tet mesh (faces used by exactly one tet), oriented
+ * so the normal points away from the tet's fourth vertex.  tris_out needs
+ * room for 4*n_tets triangles; returns the number written. */
+int32_t oracle_surface(int32_t n_tets, const int32_t *tets, const double *rest, int32_t *tris_out);
+/* Closest point q on triangle (a, b, c) to p and its barycentric weights. */
+void oracle_closest_point_triangle(const double p[3], const double a[3], const double b[3],
+                                   const double c[3], double q[3], double bary[3]);
+/* Mesh-mesh contact detection used by the step: for each surface vertex the
+ * closest surface triangle of another mesh within collision_radius, kept when
+ * the vertex is inside that mesh or closer than the contact thickness to its
+ * surface (-1 if none). */
+void oracle_detect_contacts(const oracle_model *M, const oracle_params *P, const double *x,
+                            int32_t *tri_of_vertex);
+/* Generalized winding number of mesh `mesh`'s surface at p (positions x). */
+double oracle_winding_number(const oracle_model *M, int32_t mesh, const double p[3], const double *x);
 
 /* ---- element energies and derivatives (real) ------------------------------ */
 void   oracle_lame(double E, double nu, double *mu, double *lam);

@@ -56,6 +56,9 @@ class StepParams:
     friction_mu: float = 0.0
     friction_eps_v: float = 1e-2
     spring_psd: bool = False               # clamp transverse spring stiffness at 0
+    mesh_contacts: bool = False            # vertex-triangle contacts between meshes
+    collision_radius: float = 0.0          # detection radius for mesh contacts
+    n_col: int = 0                         # re-detect every n_col iterations (0: only at x^t)
 
 
 @dataclasses.dataclass

@@ -1,0 +1,170 @@
+"""Pins of the oracle's mesh-mesh vertex-triangle contacts (Sec. 3.5, 3.9)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_06321_amd import workloads as W
+
+
+def P(**kw):
+    return dataclasses.replace(W.StepParams(), **kw)
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+def test_surface_is_closed_and_encloses_the_volume(n):
+    """Divergence theorem: V = 1/3 sum_T (c_T . n_T) A_T, sum_T n_T A_T = 0."""
+    rest, tets = W.cube_lattice(n, n, n)
+    tris = O.surface(tets, rest)
+    assert tris.shape[0] == 2 * 6 * (n - 1) ** 2
+    a, b, c = rest[tris[:, 0]], rest[tris[:, 1]], rest[tris[:, 2]]
+    nA = 0.5 * np.cross(b - a, c - a)              # area-weighted outward normals
+    cen = (a + b + c) / 3.0
+    assert np.abs(nA.sum(0)).max() < 1e-12
+    vol = (cen * nA).sum() / 3.0
+    assert vol == pytest.approx((n - 1) ** 3 * W.EDGE ** 3, rel=1e-12)
+    # every edge of a closed surface is shared by exactly two triangles
+    edges = np.sort(np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]]), axis=1)
+    _, counts = np.unique(edges, axis=0, return_counts=True)
+    assert np.all(counts == 2)
+
+
+def test_closest_point_matches_dense_sampling():
+    rng = np.random.default_rng(0)
+    s = np.linspace(0.0, 1.0, 401)
+    u, v = np.meshgrid(s, s)
+    keep = (u + v) <= 1.0
+    u, v = u[keep], v[keep]
+    for _ in range(40):
+        a, b, c = rng.normal(size=(3, 3))
+        p = rng.normal(size=3) * 2.0
+        q, bary = O.closest_point_triangle(p, a, b, c)
+        assert np.allclose(bary.sum(), 1.0) and np.all(bary >= -1e-12)
+        assert np.allclose(q, bary[0] * a + bary[1] * b + bary[2] * c)
+        pts = a + u[:, None] * (b - a) + v[:, None] * (c - a)
+        dmin = np.linalg.norm(pts - p, axis=1).min()
+        d = np.linalg.norm(q - p)
+        assert d <= dmin + 1e-12
+        assert d >= dmin - 5e-3 * np.linalg.norm(np.cross(b - a, c - a)) ** 0.5
+
+
+def _two_blocks(dx=0.033, dy=0.041, gap=-0.003, n=4, pin_lower=True, E=1e5):
+    """Lower block (mesh 0) and an upper block (mesh 1) whose bottom face lies
+    `gap` above the lower block's top face, shifted by (dx, dy)."""
+    r0, t0 = W.cube_lattice(n, n, n)
+    r1, t1 = W.cube_lattice(n, n, n)
+    top = r0[:, 2].max()
+    r1 = r1 + np.array([dx, dy, top + gap])
+    rest = np.concatenate([r0, r1])
+    tets = np.concatenate([t0, t1 + r0.shape[0]]).astype(np.int32)
+    pinned = np.zeros(rest.shape[0], np.uint8)
+    if pin_lower:
+        pinned[:r0.shape[0]] = 1
+    vo = np.array([0, r0.shape[0], rest.shape[0]])
+    return rest, tets, pinned, vo, np.full(tets.shape[0], E)
+
+
+def _box(x):
+    return x.min(0), x.max(0)
+
+
+def _box_distance(p, lo, hi):
+    """Distance from p to the boundary of the box [lo, hi] and whether p is inside."""
+    inside = np.all((p > lo) & (p < hi), axis=-1)
+    out = np.linalg.norm(np.maximum(np.maximum(lo - p, p - hi), 0.0), axis=-1)
+    depth = np.minimum(p - lo, hi - p).min(-1)
+    return np.where(inside, depth, out), inside
+
+
+def test_winding_number_is_one_inside_and_zero_outside():
+    rest, tets, pinned, vo, E = _two_blocks()
+    m = O.Model(rest, tets, pinned, vert_offsets=vo)
+    rng = np.random.default_rng(2)
+    # a rigid motion changes nothing
+    A = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    A *= np.sign(np.linalg.det(A))
+    x = rest @ A.T + np.array([0.3, -0.2, 0.1])
+    for mesh in (0, 1):
+        lo, hi = _box(rest[vo[mesh]:vo[mesh + 1]])
+        pts = rng.uniform(lo - 0.1, hi + 0.1, size=(200, 3))
+        d, inside = _box_distance(pts, lo, hi)
+        keep = d > 1e-6
+        for q, ins in zip(pts[keep], inside[keep]):
+            w = O.winding_number(m, mesh, q @ A.T + np.array([0.3, -0.2, 0.1]), x)
+            assert w == pytest.approx(1.0 if ins else 0.0, abs=1e-9)
+
+
+def test_detection_matches_brute_force_on_boxes():
+    """Both blocks are axis-aligned boxes at rest, so penetration and distance
+    to the other block have closed forms: the detected set is exactly the
+    surface vertices inside the other box or closer than the thickness."""
+    rest, tets, pinned, vo, E = _two_blocks()
+    m = O.Model(rest, tets, pinned, vert_offsets=vo)
+    delta = 1e-3
+    p = P(mesh_contacts=True, collision_radius=0.05, contact_thickness=delta)
+    tri = O.detect_contacts(m, p, rest)
+    surf = m.surf_tris
+    on_surf = np.zeros(rest.shape[0], bool); on_surf[surf.ravel()] = True
+    boxes = [_box(rest[vo[k]:vo[k + 1]]) for k in (0, 1)]
+    for v in range(rest.shape[0]):
+        other = 1 - m.vert_mesh[v]
+        d, inside = _box_distance(rest[v], *boxes[other])
+        expect = on_surf[v] and (inside or d < delta)
+        assert (tri[v] >= 0) == expect, v
+        if expect:
+            T = surf[tri[v]]
+            assert np.all(m.vert_mesh[T] == other)
+            q, _ = O.closest_point_triangle(rest[v], *rest[T])
+            assert np.linalg.norm(q - rest[v]) == pytest.approx(d, abs=1e-12)
+    hit = np.flatnonzero(tri >= 0)
+    assert set(m.vert_mesh[hit]) == {0, 1}
+
+
+def test_vertex_on_triangle_interior_equals_plane_contact():
+    """A free vertex pressing into the interior of a pinned mesh's top face
+    behaves exactly like the analytic plane through that face (same penalty,
+    same friction): the upper block hovers 1 cm above the lower one and only
+    one of its bottom vertices, dipped 2 mm into the lower block, is free."""
+    rest, tets, pinned, vo, E = _two_blocks(gap=0.01)
+    pinned[:] = 1
+    upper = np.arange(vo[1], vo[2])
+    bottom = upper[np.abs(rest[upper, 2] - rest[upper, 2].min()) < 1e-9]
+    v = bottom[len(bottom) // 2]
+    pinned[v] = 0
+    top = rest[:vo[1], 2].max()
+    x0 = rest.copy()
+    x0[v, 2] = top - 0.002
+    m = O.Model(rest, tets, pinned, vert_offsets=vo)
+    for mu in (0.0, 0.4):
+        base = dict(n_iters=5, contact_k=1e4, contact_thickness=1e-3, init_mode=W.INIT_PREV,
+                    friction_mu=mu, friction_eps_v=1e-2)
+        pm = P(mesh_contacts=True, collision_radius=0.05, **base)
+        pp = P(planes=np.array([[0.0, 0.0, 1.0, top]]), **base)
+        tri = O.detect_contacts(m, pm, x0)
+        assert np.flatnonzero(tri >= 0).tolist() == [v]
+        vel = np.zeros_like(rest); vel[v] = [0.05, -0.02, -0.1]
+        xm, vm, _, stm = O.step(m, pm, x0, vel, vel, E)
+        xp, vp, _, stp = O.step(m, pp, x0, vel, vel, E)
+        assert stm["n_contacts"] > 0 and stm["n_contacts"] == stp["n_contacts"]
+        assert np.allclose(xm, xp, rtol=0, atol=1e-13)
+        assert xm[v, 2] > x0[v, 2]
+
+
+def test_contact_forces_conserve_momentum_at_convergence():
+    """Two free blocks in contact, no gravity, no pins: the converged implicit
+    Euler step conserves linear momentum (contact gradients sum to zero over
+    the four vertices of an element)."""
+    rest, tets, pinned, vo, E = _two_blocks(gap=-0.002, pin_lower=False)
+    m = O.Model(rest, tets, pinned, vert_offsets=vo)
+    p = P(n_iters=3000, gravity=(0.0, 0.0, 0.0), mesh_contacts=True, collision_radius=0.05,
+          contact_k=1e4, contact_thickness=1e-3)
+    v0 = np.zeros_like(rest)
+    v0[vo[1]:] = [0.0, 0.0, -0.3]
+    x, v, _, st = O.step(m, p, rest, v0, v0, E)
+    assert st["n_contacts"] > 0
+    P0 = (m.mass[:, None] * v0).sum(0)
+    P1 = (m.mass[:, None] * v).sum(0)
+    assert np.abs(P1 - P0).max() <= 1e-8 * np.abs(m.mass[:, None] * v0).sum()
+    # the contact pushed the blocks apart relative to free flight
+    assert v[vo[1]:, 2].mean() > -0.3
