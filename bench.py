@@ -315,6 +315,24 @@ def extras(dev, W, Topology):
                           workload="33^3 cube, 30 frames x 20 iterations, loss on final centroid")
     log(f"[bench] adjoint fwd+bwd {ms:.1f} ms, forward {ms_fwd:.1f} ms")
     del td
+    # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, graph launches
+    ws = W.config_block_stack(cols=8, levels=4, n=9)
+    ts = Topology.from_workload(ws)
+    secs, upd = time_frames(ts, ws, MODES["graph"], 10, 2, dev)
+    xs = state(ws, dev)[0]
+    ts.detect_contacts(xs, ws.params)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(10):
+        tri = ts.detect_contacts(xs, ws.params)
+    b.record(); torch.cuda.synchronize()
+    res["block_stack_contacts_graph"] = dict(
+        updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100,
+        detection_ms=a.elapsed_time(b) / 10, contacts_at_rest=int((tri >= 0).sum().item()),
+        workload=f"{ws.name}: {ws.n_verts} vertices, {ws.n_tets} tets, {ws.params.n_iters} iterations")
+    log(f"[bench] block stack {res['block_stack_contacts_graph']['updates_per_s']:.3e} v-upd/s, "
+        f"detection {res['block_stack_contacts_graph']['detection_ms']:.3f} ms")
+    del ts
     # cloth
     wc = W.config_cloth()
     tc = Topology.from_workload(wc)

@@ -122,8 +122,13 @@ enum {
     VBD_Q_PHASE_BYTES = 11, /* double[n_colors]: algorithmic HBM bytes of one color solve */
     VBD_Q_TET_ORDER = 12,   /* int32[n_tets]: stored tet position -> caller's tet id
                                (tets grouped by the colors of their vertices) */
-    VBD_Q_REST_FRAME = 13   /* double[n_tets][6]: upper triangle of R^{-1}, D_m = Q R with
+    VBD_Q_REST_FRAME = 13,  /* double[n_tets][6]: upper triangle of R^{-1}, D_m = Q R with
                                Q a proper rotation (caller's tet order) */
+    VBD_Q_SURFACE = 14,     /* int32[n_surf_tris][3]: surface triangles (faces of exactly
+                               one tet; extracted when n_meshes > 1), original vertex ids,
+                               ordered so (b - a) x (c - a) points out of the mesh;
+                               sorted by their ascending vertex-id triples */
+    VBD_Q_SURFACE_COUNTS = 15 /* int64[2]: n_surf_tris, n_surf_verts */
 };
 vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
 vbd_status vbd_topology_destroy(vbd_topology topo);
@@ -150,6 +155,19 @@ typedef struct {
                                       1: transverse stiffness k(1 - L/l) clamped at 0,
                                       the exact PSD projection of a spring block */
     int32_t launch_mode;           /* VBD_LAUNCH_* */
+    /* Mesh-mesh vertex-triangle contacts (Sec. 3.5, 3.9), between different
+     * meshes of a batched topology (no self-contact).  Detection at x^t: each
+     * surface vertex takes the closest surface triangle of another mesh within
+     * collision_radius; the pair is a contact element when the vertex is inside
+     * that mesh or closer than contact_thickness to its surface.  Detection is
+     * repeated on the current iterate before iterations 1 + k n_col (n_col > 0;
+     * 0 = only at x^t).  Elements use the penalty energy with the closest point
+     * recomputed at every evaluation and the triangle normal held fixed; same-
+     * color updates read the positions from before the color (x_new buffer).
+     * Needs launch_mode PLAIN or GRAPH (else VBD_E_UNSUPPORTED). */
+    int32_t mesh_contacts;         /* 1 = on */
+    float collision_radius;        /* > 0 when mesh_contacts is on */
+    int32_t n_col;                 /* >= 0 */
 } vbd_step_params;
 
 /* One implicit-Euler time step of every mesh (Alg. 1):
@@ -184,6 +202,16 @@ vbd_status vbd_step_backward(vbd_topology topo, const vbd_step_params *params,
                              const float *tet_E, const float *gx_out, const float *gv_out,
                              const float *gvp_out, float *gx_in, float *gv_in, float *gvp_in,
                              float *g_tet_E, void *stream);
+
+/* Runs the mesh-mesh contact detection that vbd_step does at x^t (params:
+ * mesh_contacts must be 1; collision_radius and contact_thickness are used) on
+ * the positions x (device float [n_verts][3], original order) and writes, for
+ * every vertex, the index of its contact triangle in VBD_Q_SURFACE order or -1
+ * (tri_out: device int32 [n_verts], original order).  Uses the library's
+ * internal state buffers (a following vbd_step is unaffected).  Errors:
+ * VBD_E_NOT_COLORED, VBD_E_NO_WORKSPACE, VBD_E_INVALID_ARG, VBD_E_HIP. */
+vbd_status vbd_detect_contacts(vbd_topology topo, const vbd_step_params *params, const float *x,
+                               int32_t *tri_out, void *stream);
 
 /* Kernel launch configuration of the color solve. */
 typedef struct {

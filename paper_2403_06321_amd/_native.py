@@ -14,14 +14,15 @@ STATUS_NAMES = {0: "VBD_OK", -1: "VBD_E_INVALID_ARG", -2: "VBD_E_TOPOLOGY", -3: 
 LAUNCH_PLAIN, LAUNCH_GRAPH, LAUNCH_PERSISTENT, LAUNCH_PERSISTENT_GRAPH = 0, 1, 2, 3
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
- Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME) = range(14)
+ Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME, Q_SURFACE,
+ Q_SURFACE_COUNTS) = range(16)
 
 # every symbol include/vbd.h declares
 EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_workspace_size", "vbd_bind_workspace",
            "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_backward",
            "vbd_get_launch_config", "vbd_set_launch_config", "vbd_autotune",
            "vbd_profile_enable", "vbd_profile_read", "vbd_check", "vbd_probe_copy",
-           "vbd_last_error"]
+           "vbd_detect_contacts", "vbd_last_error"]
 
 
 class MeshDesc(C.Structure):
@@ -38,7 +39,8 @@ class StepParamsC(C.Structure):
                 ("contact_thickness", C.c_float), ("n_spheres", C.c_int32), ("spheres", C.c_void_p),
                 ("n_planes", C.c_int32), ("planes", C.c_void_p), ("kd", C.c_float),
                 ("cheb_rho", C.c_float), ("friction_mu", C.c_float), ("friction_eps_v", C.c_float),
-                ("spring_psd", C.c_int32), ("launch_mode", C.c_int32)]
+                ("spring_psd", C.c_int32), ("launch_mode", C.c_int32),
+                ("mesh_contacts", C.c_int32), ("collision_radius", C.c_float), ("n_col", C.c_int32)]
 
 
 class LaunchConfig(C.Structure):
@@ -85,6 +87,7 @@ def lib():
     L.vbd_profile_read.argtypes = [p, C.POINTER(ProfileStats), i32]
     L.vbd_check.argtypes = [p, p]
     L.vbd_probe_copy.argtypes = [p, p, sz, p]
+    L.vbd_detect_contacts.argtypes = [p, C.POINTER(StepParamsC), p, p, p]
     L.vbd_last_error.argtypes = []
     L.vbd_last_error.restype = C.c_char_p
     for name in EXPORTS:

@@ -37,7 +37,9 @@ def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN):
                       float(p.contact_thickness), 0 if sph is None else sph.shape[0], _np_ptr(sph),
                       0 if pl is None else pl.shape[0], _np_ptr(pl), float(p.kd), float(p.cheb_rho),
                       float(p.friction_mu), float(p.friction_eps_v),
-                      int(bool(getattr(p, "spring_psd", False))), int(launch_mode))
+                      int(bool(getattr(p, "spring_psd", False))), int(launch_mode),
+                      int(bool(getattr(p, "mesh_contacts", False))),
+                      float(getattr(p, "collision_radius", 0.0)), int(getattr(p, "n_col", 0)))
     return s, (sph, pl)
 
 
@@ -128,12 +130,29 @@ class Topology:
                 N.Q_DMINV: (np.float64, 9 * c["n_tets"]), N.Q_VOLUME: (np.float64, c["n_tets"]),
                 N.Q_PHASE_BYTES: (np.float64, c["n_colors"]),
                 N.Q_TET_ORDER: (np.int32, c["n_tets"]),
-                N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"])}[what]
+                N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"]),
+                N.Q_SURFACE_COUNTS: (np.int64, 2)}
+        if what == N.Q_SURFACE:
+            n_tri = int(self.query(N.Q_SURFACE_COUNTS)[0])
+            out = np.zeros((n_tri, 3), np.int32)
+            N.check(N.lib().vbd_topology_query(self._h, what, _np_ptr(out), out.nbytes))
+            return out
+        spec = spec[what]
         out = np.zeros(spec[1], spec[0])
         N.check(N.lib().vbd_topology_query(self._h, what, _np_ptr(out), out.nbytes))
         return out
 
     # ----------------------------------------------------------- compute --
+    def detect_contacts(self, x, params: StepParams, stream=None):
+        """Mesh-mesh contact detection on positions x (device float32 [n_verts, 3]):
+        int32 [n_verts] contact triangle (index into the Q_SURFACE rows) or -1."""
+        _check_state(x, self.n_verts, "x")
+        out = torch.empty(self.n_verts, dtype=torch.int32, device=x.device)
+        ps, keep = params_struct(params)
+        N.check(N.lib().vbd_detect_contacts(self._h, C.byref(ps), _t_ptr(x), _t_ptr(out),
+                                            _stream_handle(stream)))
+        return out
+
     def step(self, x, v, v_prev, tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
              stream=None):
         """One time step in place on (x, v, v_prev): device float32 [n_verts, 3]."""

@@ -1,0 +1,371 @@
+// gfx950 kernels of the mesh-mesh contact detection (Sec. 3.5).
+//
+// Discrete detection on a set of positions X (x^t at the start of a step,
+// the current iterate when it is repeated): every surface vertex takes the
+// closest surface triangle of another mesh within the collision radius, and
+// the pair becomes a contact element when the vertex lies inside that mesh
+// or closer than the contact thickness to its surface.
+//
+// Broad phase: triangle centroids binned into a hashed uniform grid whose
+// cell size s = r + R_max (R_max = largest centroid-to-corner distance of any
+// surface triangle at X).  A point within r of a triangle is within
+// r + R_max of its centroid, so the 27 cells around the vertex's cell hold
+// every candidate.  Buckets are built by counting, an exclusive scan and a
+// fill; the query keeps the minimum of (distance, triangle index), which does
+// not depend on the order inside a bucket.
+//
+// Inside test: the sign of (p - q).N with N the angle-weighted pseudonormal of
+// the closest feature (face normal, sum of the two face normals of an edge,
+// angle-weighted vertex normal), exact for closed, consistently oriented
+// surfaces (Baerentzen and Aanaes, IEEE TVCG 11(3), 2005).
+//
+// The corner incidence (for each vertex, the colliding vertices whose
+// contact triangle has it as a corner) is built the same way and each row is
+// sorted, so the solve visits the elements in a fixed order.
+#include "vbd_device.h"
+
+namespace vbd {
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------- scan --
+// Exclusive scan of n unsigned values into out[0..n], out[n] = total.  Three
+// launches: per-block scans of kScanTile values with the block totals in tmp,
+// one block scanning tmp, then the block offsets added.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+// In-place exclusive scan of the kScanTile values in lds; returns the total.
+__device__ unsigned block_scan_tile(unsigned *lds, unsigned *sums)
+{
+    const int tid = threadIdx.x;
+    unsigned run = 0;
+    unsigned v[kScanPer];
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = lds[tid * kScanPer + j];
+        run += v[j];
+    }
+    sums[tid] = run;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread sums
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const unsigned add = tid >= off ? sums[tid - off] : 0u;
+        __syncthreads();
+        sums[tid] += add;
+        __syncthreads();
+    }
+    const unsigned total = sums[kScanThreads - 1];
+    unsigned acc = sums[tid] - run;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        lds[tid * kScanPer + j] = acc;
+        acc += v[j];
+    }
+    __syncthreads();
+    return total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const unsigned *in, unsigned *out,
+                                                             unsigned *tmp, int n)
+{
+    __shared__ unsigned lds[kScanTile];
+    __shared__ unsigned sums[kScanThreads];
+    const long base = (long)blockIdx.x * kScanTile;
+    for (int j = threadIdx.x; j < kScanTile; j += kScanThreads)
+        lds[j] = (base + j < n) ? in[base + j] : 0u;
+    __syncthreads();
+    const unsigned total = block_scan_tile(lds, sums);
+    for (int j = threadIdx.x; j < kScanTile; j += kScanThreads)
+        if (base + j < n) out[base + j] = lds[j];
+    if (threadIdx.x == 0) tmp[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the nb block totals (in tiles, with a carry);
+// out[n] receives the grand total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(unsigned *tmp, int nb, unsigned *out,
+                                                              int n)
+{
+    __shared__ unsigned lds[kScanTile];
+    __shared__ unsigned sums[kScanThreads];
+    unsigned carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kScanTile) {
+        for (int j = threadIdx.x; j < kScanTile; j += kScanThreads)
+            lds[j] = (b0 + j < nb) ? tmp[b0 + j] : 0u;
+        __syncthreads();
+        const unsigned total = block_scan_tile(lds, sums);
+        for (int j = threadIdx.x; j < kScanTile; j += kScanThreads)
+            if (b0 + j < nb) tmp[b0 + j] = lds[j] + carry;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(unsigned *out, const unsigned *tmp, int n)
+{
+    const long base = (long)blockIdx.x * kScanTile;
+    const unsigned add = tmp[blockIdx.x];
+    for (int j = threadIdx.x; j < kScanTile; j += kScanThreads)
+        if (base + j < n) out[base + j] += add;
+}
+
+static hipError_t scan_exclusive(const unsigned *in, unsigned *out, unsigned *tmp, int n,
+                                 hipStream_t s)
+{
+    const int nb = cdiv(n > 0 ? n : 1, kScanTile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanThreads), 0, s, in, out, tmp, n);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, out, n);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, s, out, tmp, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- fill --
+__global__ void k_fill_u32(unsigned *p, int n, unsigned v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static hipError_t fill_u32(unsigned *p, int n, unsigned v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ grid helpers --
+__device__ __forceinline__ int cell_coord(float v, float inv_s)
+{
+    // clamped so that far-away points still map to valid (if shared) cells
+    const float c = floorf(v * inv_s);
+    return (int)fminf(fmaxf(c, -1048576.f), 1048576.f);
+}
+
+__device__ __forceinline__ unsigned cell_hash(int i, int j, int k, int mask)
+{
+    const unsigned h = ((unsigned)i * 73856093u) ^ ((unsigned)j * 19349663u) ^ ((unsigned)k * 83492791u);
+    return h & (unsigned)mask;
+}
+
+__device__ __forceinline__ float grid_cell_size(const DevSurf &S, const StepConsts &K)
+{
+    const float s = K.col_radius + __uint_as_float(S.gparam[0]);
+    return s > 0.f ? s : 1.f;
+}
+
+// ---------------------------------------------------------------- kernels --
+// Unit normals and the largest centroid-to-corner distance.
+__global__ void k_tri_prep(DevSurf S, const float4 *X)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S.n_tri) return;
+    const int4 tr = S.tri[t];
+    const float3 a = xyz(X[tr.x]), b = xyz(X[tr.y]), c = xyz(X[tr.z]);
+    const float3 n = cross3(b - a, c - a);
+    const float l = sqrtf(dot3(n, n));
+    const float3 u = l > 0.f ? n * (1.0f / l) : make_float3(0.f, 0.f, 0.f);
+    S.tnorm[t] = make_float4(u.x, u.y, u.z, 0.f);
+    const float3 g = (a + b + c) * (1.0f / 3.0f);
+    const float3 da = a - g, db = b - g, dc = c - g;
+    const float R = sqrtf(fmaxf(dot3(da, da), fmaxf(dot3(db, db), dot3(dc, dc))));
+    // non-negative floats order like their bit patterns
+    atomicMax(&S.gparam[0], __float_as_uint(R));
+}
+
+// Angle-weighted pseudonormal of every surface vertex.
+__global__ void k_vert_normals(DevSurf S, const float4 *X)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= S.n_sv) return;
+    const int slot = S.svert[v].x;
+    const float3 xv = xyz(X[slot]);
+    float3 acc = make_float3(0.f, 0.f, 0.f);
+    for (int e = S.sv_row[v]; e < S.sv_row[v + 1]; ++e) {
+        const int t = S.sv_tri[e];
+        const int4 tr = S.tri[t];
+        int o1, o2;
+        if (tr.x == slot) { o1 = tr.y; o2 = tr.z; }
+        else if (tr.y == slot) { o1 = tr.z; o2 = tr.x; }
+        else { o1 = tr.x; o2 = tr.y; }
+        const float3 e1 = xyz(X[o1]) - xv, e2 = xyz(X[o2]) - xv;
+        const float3 cr = cross3(e1, e2);
+        const float ang = atan2f(sqrtf(dot3(cr, cr)), dot3(e1, e2));
+        acc = acc + xyz(S.tnorm[t]) * ang;
+    }
+    S.vnorm[v] = make_float4(acc.x, acc.y, acc.z, 0.f);
+}
+
+__global__ void k_grid_count(DevSurf S, const float4 *X, StepConsts K)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S.n_tri) return;
+    const int4 tr = S.tri[t];
+    const float3 g = (xyz(X[tr.x]) + xyz(X[tr.y]) + xyz(X[tr.z])) * (1.0f / 3.0f);
+    const float inv_s = 1.0f / grid_cell_size(S, K);
+    const unsigned h = cell_hash(cell_coord(g.x, inv_s), cell_coord(g.y, inv_s), cell_coord(g.z, inv_s), S.hmask);
+    atomicAdd(&S.hcount[h], 1u);
+}
+
+__global__ void k_grid_fill(DevSurf S, const float4 *X, StepConsts K)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S.n_tri) return;
+    const int4 tr = S.tri[t];
+    const float3 g = (xyz(X[tr.x]) + xyz(X[tr.y]) + xyz(X[tr.z])) * (1.0f / 3.0f);
+    const float inv_s = 1.0f / grid_cell_size(S, K);
+    const unsigned h = cell_hash(cell_coord(g.x, inv_s), cell_coord(g.y, inv_s), cell_coord(g.z, inv_s), S.hmask);
+    const unsigned pos = S.hstart[h] + atomicAdd(&S.hcount[h], 1u);
+    S.hitems[pos] = t;
+}
+
+// Pseudonormal of the closest feature of triangle t.
+__device__ __forceinline__ float3 feature_normal(const DevSurf &S, int t, int feature)
+{
+    const float3 nt = xyz(S.tnorm[t]);
+    if (feature == 0) return nt;
+    const int4 tr = S.tri[t];
+    if (feature <= 3) {
+        const int slot = feature == 1 ? tr.x : (feature == 2 ? tr.y : tr.z);
+        const int v = S.svidx[slot];
+        return xyz(S.vnorm[v]);
+    }
+    const int4 adj = S.tadj[t];
+    const int o = feature == 4 ? adj.x : (feature == 5 ? adj.y : adj.z);
+    return o >= 0 ? nt + xyz(S.tnorm[o]) : nt;
+}
+
+__global__ void k_detect(DevSurf S, const float4 *X, StepConsts K)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= S.n_sv) return;
+    const int2 sv = S.svert[v];
+    const float3 p = xyz(X[sv.x]);
+    const float inv_s = 1.0f / grid_cell_size(S, K);
+    const int ci = cell_coord(p.x, inv_s), cj = cell_coord(p.y, inv_s), ck = cell_coord(p.z, inv_s);
+    float best_d2 = K.col_radius * K.col_radius;
+    int best = -1;
+    ClosestPt bcp{};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const unsigned h = cell_hash(ci + dx, cj + dy, ck + dz, S.hmask);
+                const unsigned e1 = S.hstart[h + 1];
+                for (unsigned e = S.hstart[h]; e < e1; ++e) {
+                    const int t = S.hitems[e];
+                    const int4 tr = S.tri[t];
+                    if (tr.w == sv.y) continue;
+                    const ClosestPt cp = closest_on_triangle(p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]));
+                    const float3 d = p - cp.q;
+                    const float d2 = dot3(d, d);
+                    if (d2 < best_d2 || (d2 == best_d2 && best >= 0 && t < best)) {
+                        best_d2 = d2;
+                        best = t;
+                        bcp = cp;
+                    }
+                }
+            }
+    int hit = -1;
+    if (best >= 0) {
+        const bool inside = dot3(p - bcp.q, feature_normal(S, best, bcp.feature)) < 0.f;
+        if (sqrtf(best_d2) < K.delta || inside) hit = best;
+    }
+    S.ctri[sv.x] = hit;
+    if (hit >= 0) {
+        const int4 tr = S.tri[hit];
+        atomicAdd(&S.ccount[tr.x], 1u);
+        atomicAdd(&S.ccount[tr.y], 1u);
+        atomicAdd(&S.ccount[tr.z], 1u);
+    }
+}
+
+__global__ void k_corner_fill(DevSurf S)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= S.n_sv) return;
+    const int slot = S.svert[v].x;
+    const int t = S.ctri[slot];
+    if (t < 0) return;
+    const int4 tr = S.tri[t];
+    const int c[3] = {tr.x, tr.y, tr.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const unsigned pos = S.crow[c[k]] + atomicAdd(&S.ccount[c[k]], 1u);
+        S.cent[pos] = slot;
+    }
+}
+
+// Insertion sort of every corner row (rows are short: a handful of entries).
+__global__ void k_corner_sort(DevSurf S, int n_verts)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_verts) return;
+    const int b = (int)S.crow[p], e = (int)S.crow[p + 1];
+    for (int i = b + 1; i < e; ++i) {
+        const int key = S.cent[i];
+        int j = i - 1;
+        while (j >= b && S.cent[j] > key) {
+            S.cent[j + 1] = S.cent[j];
+            --j;
+        }
+        S.cent[j + 1] = key;
+    }
+}
+
+__global__ void k_load_x(DevTopo T, const float *x)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_verts) return;
+    const float3 v = ld3(x, T.perm[p]);
+    T.x[p] = make_float4(v.x, v.y, v.z, 0.f);
+}
+
+__global__ void k_store_ctri(DevTopo T, DevSurf S, int *out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= T.n_verts) return;
+    out[T.perm[p]] = S.ctri ? S.ctri[p] : -1;
+}
+
+// -------------------------------------------------------------- launchers --
+hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X, const StepConsts &K,
+                         hipStream_t s)
+{
+    if (S.n_tri == 0 || S.n_sv == 0) return hipSuccess;
+    const int H = S.hmask + 1;
+    hipError_t e;
+    if ((e = fill_u32(S.gparam, 4, 0u, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.hcount, H, 0u, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.ccount, T.n_verts, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tri_prep, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X);
+    hipLaunchKernelGGL(k_vert_normals, dim3(cdiv(S.n_sv, 256)), dim3(256), 0, s, S, X);
+    hipLaunchKernelGGL(k_grid_count, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X, K);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive(S.hcount, S.hstart, S.scan_tmp, H, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.hcount, H, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grid_fill, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X, K);
+    hipLaunchKernelGGL(k_detect, dim3(cdiv(S.n_sv, 128)), dim3(128), 0, s, S, X, K);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive(S.ccount, S.crow, S.scan_tmp, T.n_verts, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.ccount, T.n_verts, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_corner_fill, dim3(cdiv(S.n_sv, 256)), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_corner_sort, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, S, T.n_verts);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_x(const DevTopo &T, const float *x, hipStream_t s)
+{
+    if (T.n_verts == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_load_x, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_ctri(const DevTopo &T, const DevSurf &S, int *out, hipStream_t s)
+{
+    if (T.n_verts == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_store_ctri, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T, S, out);
+    return hipGetLastError();
+}
+
+}  // namespace vbd

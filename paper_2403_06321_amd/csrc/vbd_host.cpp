@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -49,6 +50,10 @@ struct Layout {
     size_t rec, vol, tet_perm, tet_row, tet_ent, spr_row, spr_ent, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib;
+    // mesh-mesh contacts (only when the topology has a surface)
+    size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam;
+    size_t s_hcount, s_hstart, s_scan, s_hitems, s_ctri, s_ccount, s_crow, s_cent, s_xnew;
+    int hsize;
     size_t total;
     int max_bwd_iters;
 };
@@ -89,6 +94,13 @@ struct vbd_topology_s {
     std::vector<float> spr_len;
     std::vector<double> phase_bytes;
     std::vector<int64_t> phase_updates;
+    // surface (extracted by vbd_color when there is more than one mesh)
+    std::vector<int32_t> surf;          // [n_tri][3] original ids, outward
+    std::vector<int32_t> surf_adj;      // [n_tri][3] triangle across edge k or -1
+    std::vector<int32_t> vert_mesh;     // [nv]
+    std::vector<int32_t> sv_slot;       // surface vertices as permuted slots, ascending
+    std::vector<int32_t> sv_row, sv_tri;
+    DevSurf surf_dev{};
     // device
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -152,6 +164,31 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.vbar = take(sizeof(float4) * nv);
         L.contrib = take(sizeof(float4) * 4 * (size_t)T.nt);
     }
+    const size_t ntri = T.surf.size() / 3, nsv = T.sv_slot.size();
+    if (ntri > 0) {
+        int H = 1024;
+        while ((size_t)H < 2 * ntri) H <<= 1;
+        L.hsize = H;
+        L.s_tri = take(sizeof(int4) * ntri);
+        L.s_tadj = take(sizeof(int4) * ntri);
+        L.s_svert = take(sizeof(int2) * nsv);
+        L.s_svidx = take(sizeof(int32_t) * nv);
+        L.s_sv_row = take(sizeof(int32_t) * (nsv + 1));
+        L.s_sv_tri = take(sizeof(int32_t) * T.sv_tri.size());
+        L.s_tnorm = take(sizeof(float4) * ntri);
+        L.s_vnorm = take(sizeof(float4) * nsv);
+        L.s_gparam = take(sizeof(uint32_t) * 4);
+        L.s_hcount = take(sizeof(uint32_t) * (size_t)H);
+        L.s_hstart = take(sizeof(uint32_t) * ((size_t)H + 1));
+        const size_t big = std::max<size_t>((size_t)H, nv + 1);
+        L.s_scan = take(sizeof(uint32_t) * (big / 2048 + 2));
+        L.s_hitems = take(sizeof(int32_t) * ntri);
+        L.s_ctri = take(sizeof(int32_t) * nv);
+        L.s_ccount = take(sizeof(uint32_t) * nv);
+        L.s_crow = take(sizeof(uint32_t) * (nv + 1));
+        L.s_cent = take(sizeof(int32_t) * 3 * nsv);
+        L.s_xnew = take(sizeof(float4) * nv);
+    }
     L.total = off;
     return L;
 }
@@ -188,6 +225,31 @@ void set_dev_pointers(vbd_topology_s &T)
     D.n_tets = T.nt;
     D.n_free = T.n_free;
     D.n_colors = T.n_colors;
+    DevSurf &S = T.surf_dev;
+    S = DevSurf{};
+    S.n_tri = (int)(T.surf.size() / 3);
+    S.n_sv = (int)T.sv_slot.size();
+    if (S.n_tri > 0) {
+        S.tri = (const int4 *)(b + L.s_tri);
+        S.tadj = (const int4 *)(b + L.s_tadj);
+        S.svert = (const int2 *)(b + L.s_svert);
+        S.svidx = (const int *)(b + L.s_svidx);
+        S.sv_row = (const int *)(b + L.s_sv_row);
+        S.sv_tri = (const int *)(b + L.s_sv_tri);
+        S.tnorm = (float4 *)(b + L.s_tnorm);
+        S.vnorm = (float4 *)(b + L.s_vnorm);
+        S.gparam = (unsigned *)(b + L.s_gparam);
+        S.hcount = (unsigned *)(b + L.s_hcount);
+        S.hstart = (unsigned *)(b + L.s_hstart);
+        S.scan_tmp = (unsigned *)(b + L.s_scan);
+        S.hitems = (int *)(b + L.s_hitems);
+        S.ctri = (int *)(b + L.s_ctri);
+        S.ccount = (unsigned *)(b + L.s_ccount);
+        S.crow = (unsigned *)(b + L.s_crow);
+        S.cent = (int *)(b + L.s_cent);
+        S.xnew = (float4 *)(b + L.s_xnew);
+        S.hmask = L.hsize - 1;
+    }
 }
 
 // ------------------------------------------------------------- validation --
@@ -208,6 +270,13 @@ vbd_status validate_params(const vbd_topology_s &T, const vbd_step_params *p)
         return fail(VBD_E_INVALID_ARG, "kd, friction_mu, contact_k must be >= 0");
     if (p->friction_mu > 0.f && !(p->friction_eps_v > 0.f))
         return fail(VBD_E_INVALID_ARG, "friction_eps_v must be > 0");
+    if (p->mesh_contacts) {
+        if (!(p->collision_radius > 0.f) || !std::isfinite(p->collision_radius))
+            return fail(VBD_E_INVALID_ARG, "collision_radius must be > 0 with mesh_contacts");
+        if (p->n_col < 0) return fail(VBD_E_INVALID_ARG, "n_col must be >= 0");
+        if (p->launch_mode == VBD_LAUNCH_PERSISTENT || p->launch_mode == VBD_LAUNCH_PERSISTENT_GRAPH)
+            return fail(VBD_E_UNSUPPORTED, "mesh contacts need launch_mode PLAIN or GRAPH");
+    }
     (void)T;
     return VBD_OK;
 }
@@ -246,6 +315,7 @@ StepConsts make_consts(const vbd_topology_s &T, const vbd_step_params *p)
         const float s = n > 0.f ? 1.0f / n : 0.f;
         K.planes[i] = make_float4(q[0] * s, q[1] * s, q[2] * s, q[3] * s);
     }
+    K.col_radius = p->mesh_contacts ? p->collision_radius : 0.f;
     return K;
 }
 
@@ -427,6 +497,92 @@ void build_csr(vbd_topology_s &T)
     }
 }
 
+// ----------------------------------------------------------------- surface --
+// Faces used by exactly one tet, oriented so (b - a) x (c - a) points away
+// from the tet's fourth vertex (out of the mesh), sorted by their ascending
+// vertex-id triples; the triangle across each edge; the surface vertices (as
+// permuted slots) with their incident triangles.  Only for batched
+// topologies (mesh-mesh contacts are between different meshes).
+void build_surface(vbd_topology_s &T)
+{
+    T.surf.clear(); T.surf_adj.clear(); T.sv_slot.clear(); T.sv_row.clear(); T.sv_tri.clear();
+    T.vert_mesh.assign(T.nv, 0);
+    for (int m = 0; m < T.n_meshes; ++m)
+        for (int64_t v = T.vert_off[m]; v < T.vert_off[m + 1]; ++v) T.vert_mesh[v] = m;
+    if (T.n_meshes < 2 || T.nt == 0) return;
+    struct Face { std::array<int32_t, 3> key; int32_t t, opp; };
+    std::vector<Face> f;
+    f.reserve(4 * (size_t)T.nt);
+    for (int t = 0; t < T.nt; ++t)
+        for (int o = 0; o < 4; ++o) {
+            Face x{};
+            int k = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != o) x.key[k++] = T.tets[4 * (size_t)t + j];
+            std::sort(x.key.begin(), x.key.end());
+            x.t = t;
+            x.opp = o;
+            f.push_back(x);
+        }
+    std::sort(f.begin(), f.end(), [](const Face &a, const Face &b) { return a.key < b.key; });
+    auto P = [&](int v, int r) { return T.rest[3 * (size_t)v + r]; };
+    for (size_t i = 0; i < f.size();) {
+        size_t j = i + 1;
+        while (j < f.size() && f[j].key == f[i].key) ++j;
+        if (j - i == 1) {
+            const int32_t *q = &T.tets[4 * (size_t)f[i].t];
+            int v[3], k = 0;
+            for (int a = 0; a < 4; ++a)
+                if (a != f[i].opp) v[k++] = q[a];
+            const int d = q[f[i].opp];
+            double e1[3], e2[3], e3[3];
+            for (int r = 0; r < 3; ++r) {
+                e1[r] = P(v[1], r) - P(v[0], r);
+                e2[r] = P(v[2], r) - P(v[0], r);
+                e3[r] = P(d, r) - P(v[0], r);
+            }
+            const double n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2],
+                         n2 = e1[0] * e2[1] - e1[1] * e2[0];
+            if (n0 * e3[0] + n1 * e3[1] + n2 * e3[2] > 0.0) std::swap(v[1], v[2]);
+            T.surf.insert(T.surf.end(), {v[0], v[1], v[2]});
+        }
+        i = j;
+    }
+    const int ntri = (int)(T.surf.size() / 3);
+    // edge adjacency: (min, max, triangle, edge) sorted by the undirected edge
+    std::vector<std::array<int32_t, 4>> ed;
+    ed.reserve(3 * (size_t)ntri);
+    for (int t = 0; t < ntri; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const int a = T.surf[3 * (size_t)t + k], b = T.surf[3 * (size_t)t + (k + 1) % 3];
+            ed.push_back({std::min(a, b), std::max(a, b), t, k});
+        }
+    std::sort(ed.begin(), ed.end());
+    T.surf_adj.assign(3 * (size_t)ntri, -1);
+    for (size_t i = 0; i < ed.size();) {
+        size_t j = i + 1;
+        while (j < ed.size() && ed[j][0] == ed[i][0] && ed[j][1] == ed[i][1]) ++j;
+        if (j - i == 2) {
+            T.surf_adj[3 * (size_t)ed[i][2] + ed[i][3]] = ed[i + 1][2];
+            T.surf_adj[3 * (size_t)ed[i + 1][2] + ed[i + 1][3]] = ed[i][2];
+        }
+        i = j;
+    }
+    // surface vertices as ascending permuted slots, with incident triangles
+    std::vector<int32_t> idx(T.nv, -1);
+    for (int32_t v : T.surf) idx[T.iperm[v]] = 0;
+    for (int sl = 0; sl < T.nv; ++sl)
+        if (idx[sl] == 0) { idx[sl] = (int32_t)T.sv_slot.size(); T.sv_slot.push_back(sl); }
+    const int nsv = (int)T.sv_slot.size();
+    T.sv_row.assign(nsv + 1, 0);
+    for (int32_t v : T.surf) T.sv_row[idx[T.iperm[v]] + 1]++;
+    for (int i = 0; i < nsv; ++i) T.sv_row[i + 1] += T.sv_row[i];
+    T.sv_tri.assign((size_t)T.sv_row[nsv], 0);
+    std::vector<int32_t> pos(T.sv_row.begin(), T.sv_row.end() - 1);
+    for (int t = 0; t < ntri; ++t)
+        for (int k = 0; k < 3; ++k) T.sv_tri[pos[idx[T.iperm[T.surf[3 * (size_t)t + k]]]]++] = t;
+}
+
 // --------------------------------------------------------------- profiling --
 vbd_status prof_begin(vbd_topology_s &T, hipStream_t s, ProfileEvent &ev)
 {
@@ -474,9 +630,17 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
             if (st) return st;
         }
         int64_t launches = 0;
+        const bool mc = p->mesh_contacts && T.surf_dev.n_tri > 0;
+        if (mc) HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.xt, K, s));
         for (int it = 1; it <= p->n_iters; ++it) {
+            if (mc && p->n_col > 0 && it > 1 && (it - 1) % p->n_col == 0)
+                HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.x, K, s));
             for (int c = 0; c < T.n_colors; ++c) {
-                HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], tets, springs, T.cfg, s));
+                if (mc)
+                    HIP_TRY(launch_solve_contacts(T.dev, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
+                                                  tets, springs, T.cfg, s));
+                else
+                    HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], tets, springs, T.cfg, s));
                 if (T.color_off[c + 1] > T.color_off[c]) {
                     ++launches;
                     ev.bytes += T.phase_bytes[c];
@@ -511,6 +675,7 @@ GraphKey make_key(const vbd_step_params *p, const void *x, const void *v, const 
     push(&p->kd, 4); push(&p->cheb_rho, 4); push(&p->friction_mu, 4); push(&p->friction_eps_v, 4);
     push(&p->spring_psd, 4);
     push(&p->launch_mode, 4);
+    push(&p->mesh_contacts, 4); push(&p->collision_radius, 4); push(&p->n_col, 4);
     return k;
 }
 
@@ -654,6 +819,7 @@ vbd_status vbd_color(vbd_topology T, int32_t *n_colors_out, int32_t *colors_out)
     if (!T->colored) {
         greedy_color(*T);
         build_csr(*T);
+        build_surface(*T);
         T->colored = true;
     }
     if (n_colors_out) *n_colors_out = T->n_colors;
@@ -739,6 +905,30 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));
     HIP_TRY(up(T->lay.mass, massp.data(), 4 * massp.size()));
     HIP_TRY(up(T->lay.color_off, T->color_off.data(), 4 * T->color_off.size()));
+    const int ntri = (int)(T->surf.size() / 3), nsv = (int)T->sv_slot.size();
+    std::vector<int4> stri(ntri), sadj(ntri);
+    std::vector<int2> svert(nsv);
+    std::vector<int32_t> svidx(T->nv, -1), ctri(T->nv, -1);
+    if (ntri > 0) {
+        for (int t = 0; t < ntri; ++t) {
+            const int32_t *q = &T->surf[3 * (size_t)t];
+            stri[t] = make_int4(T->iperm[q[0]], T->iperm[q[1]], T->iperm[q[2]], T->vert_mesh[q[0]]);
+            const int32_t *a = &T->surf_adj[3 * (size_t)t];
+            sadj[t] = make_int4(a[0], a[1], a[2], -1);
+        }
+        for (int i = 0; i < nsv; ++i) {
+            svert[i] = make_int2(T->sv_slot[i], T->vert_mesh[T->perm[T->sv_slot[i]]]);
+            svidx[T->sv_slot[i]] = i;
+        }
+        HIP_TRY(up(T->lay.s_tri, stri.data(), sizeof(int4) * stri.size()));
+        HIP_TRY(up(T->lay.s_tadj, sadj.data(), sizeof(int4) * sadj.size()));
+        HIP_TRY(up(T->lay.s_svert, svert.data(), sizeof(int2) * svert.size()));
+        HIP_TRY(up(T->lay.s_svidx, svidx.data(), 4 * svidx.size()));
+        HIP_TRY(up(T->lay.s_sv_row, T->sv_row.data(), 4 * T->sv_row.size()));
+        HIP_TRY(up(T->lay.s_sv_tri, T->sv_tri.data(), 4 * T->sv_tri.size()));
+        HIP_TRY(up(T->lay.s_ctri, ctri.data(), 4 * ctri.size()));
+        HIP_TRY(launch_zero_u32((unsigned *)(T->ws + T->lay.s_crow), T->nv + 1, s));
+    }
     HIP_TRY(launch_zero_u32(T->dev.flags, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
     T->bound = true;
@@ -777,6 +967,11 @@ vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t by
     case VBD_Q_SPRING_NBRS: return give(T->spr_nbr_orig.data(), 4 * T->spr_nbr_orig.size());
     case VBD_Q_PHASE_BYTES: return give(T->phase_bytes.data(), 8 * T->phase_bytes.size());
     case VBD_Q_TET_ORDER: return give(T->tet_order.data(), 4 * T->tet_order.size());
+    case VBD_Q_SURFACE: return give(T->surf.data(), 4 * T->surf.size());
+    case VBD_Q_SURFACE_COUNTS: {
+        int64_t c[2] = {(int64_t)(T->surf.size() / 3), (int64_t)T->sv_slot.size()};
+        return give(c, sizeof(c));
+    }
     case VBD_Q_REST_FRAME: {
         std::vector<double> S(6 * (size_t)T->nt);
         for (int t = 0; t < T->nt; ++t) rest_frame_inverse(T->rest, &T->tets[4 * (size_t)t], &S[6 * (size_t)t]);
@@ -853,7 +1048,7 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
     if (st) return st;
     if ((st = validate_params(*T, p))) return st;
     if (T->ns > 0 || p->n_spheres > 0 || p->n_planes > 0 || p->kd != 0.f || p->cheb_rho > 0.f ||
-        p->friction_mu > 0.f)
+        p->friction_mu > 0.f || p->mesh_contacts)
         return fail(VBD_E_UNSUPPORTED, "backward supports tets, inertia and pins only");
     if (p->n_iters > T->lay.max_bwd_iters)
         return fail(VBD_E_NO_WORKSPACE, "workspace holds %d backward iterations, need %d",
@@ -888,6 +1083,23 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
     }
     HIP_TRY(launch_bwd_fold(D, s));
     HIP_TRY(launch_bwd_final(D, v_t, v_prev, gx_in, gv_in, gvp_in, K, s));
+    return VBD_OK;
+}
+
+vbd_status vbd_detect_contacts(vbd_topology T, const vbd_step_params *p, const float *x,
+                               int32_t *tri_out, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if ((st = validate_params(*T, p))) return st;
+    if (!p->mesh_contacts) return fail(VBD_E_INVALID_ARG, "params->mesh_contacts must be 1");
+    if (T->nv > 0 && (!x || !tri_out)) return fail(VBD_E_INVALID_ARG, "NULL device pointer");
+    if (T->nv == 0) return VBD_OK;
+    const StepConsts K = make_consts(*T, p);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_load_x(T->dev, x, s));
+    HIP_TRY(launch_detect(T->dev, T->surf_dev, T->dev.x, K, s));
+    HIP_TRY(launch_store_ctri(T->dev, T->surf_dev, tri_out, s));
     return VBD_OK;
 }
 

@@ -44,6 +44,7 @@ struct StepConsts {
     int n_spheres, n_planes;
     float4 spheres[kMaxObstacles]; // cx, cy, cz, R
     float4 planes[kMaxObstacles];  // unit normal, offset
+    float col_radius;              // mesh-mesh detection radius
 };
 
 // Device-side view of a bound workspace.
@@ -67,6 +68,30 @@ struct DevTopo {
     int n_verts, n_tets, n_free, n_colors;
 };
 
+// Surface of a batched topology and the mesh-mesh contact state (present
+// when the topology has more than one mesh).
+struct DevSurf {
+    const int4 *tri;       // [n_tri] {a, b, c, mesh}, permuted ids, (b-a)x(c-a) outward
+    const int4 *tadj;      // [n_tri] triangle across edge (a,b), (b,c), (c,a) or -1
+    const int2 *svert;     // [n_sv] {permuted slot, mesh}
+    const int *svidx;      // [n_verts] permuted slot -> surface vertex index or -1
+    const int *sv_row;     // [n_sv + 1] incident surface triangles of a surface vertex
+    const int *sv_tri;
+    float4 *tnorm;         // [n_tri] unit normal
+    float4 *vnorm;         // [n_sv] angle-weighted pseudonormal
+    unsigned *gparam;      // [4] {max centroid radius bits, ...}
+    unsigned *hcount;      // [H] bucket sizes, then fill cursors
+    unsigned *hstart;      // [H + 1]
+    unsigned *scan_tmp;    // [n_scan_blocks + 1]
+    int *hitems;           // [n_tri]
+    int *ctri;             // [n_verts] contact triangle of a permuted slot or -1
+    unsigned *ccount;      // [n_verts] corner entries per slot, then fill cursors
+    unsigned *crow;        // [n_verts + 1]
+    int *cent;             // [3 n_sv] colliding vertex of each corner entry
+    float4 *xnew;          // [n_verts] updates of the current color
+    int n_tri, n_sv, hmask;
+};
+
 struct LaunchCfg {
     int lanes;        // lanes per vertex
     int block;        // threads per block (<= 512)
@@ -82,6 +107,18 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
                           const StepConsts &K, bool reset_flags, hipStream_t s);
 hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end,
                         bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
+// Color solve with mesh-mesh contact elements: writes S.xnew, then
+// copies the color's range back into T.x.
+hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K,
+                                 int v_begin, int v_end, bool tets, bool springs,
+                                 const LaunchCfg &cfg, hipStream_t s);
+// Detection on the permuted positions X (T.xt or T.x) into S.ctri and the
+// corner CSR (S.crow, S.cent).
+hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X,
+                         const StepConsts &K, hipStream_t s);
+// x (original order) -> T.x, and S.ctri -> tri_out (original order, or -1).
+hipError_t launch_load_x(const DevTopo &T, const float *x, hipStream_t s);
+hipError_t launch_store_ctri(const DevTopo &T, const DevSurf &S, int *tri_out, hipStream_t s);
 hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s);
 hipError_t launch_finalize(const DevTopo &T, float *x, float *v, float *vp,
                            const StepConsts &K, hipStream_t s);

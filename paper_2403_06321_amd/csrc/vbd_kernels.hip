@@ -7,29 +7,9 @@
 // element force and 3x3 Hessian block, then the group reduces the 9 values
 // with DPP row operations, adds inertia / damping / contact / friction terms
 // and solves the 3x3 system analytically (Sec. 3.2).
-#include "vbd_internal.h"
+#include "vbd_device.h"
 
 namespace vbd {
-
-// ---------------------------------------------------------------- helpers --
-__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
-__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
-__device__ __forceinline__ float3 operator*(float3 a, float s) { return make_float3(a.x * s, a.y * s, a.z * s); }
-__device__ __forceinline__ float3 operator-(float3 a) { return make_float3(-a.x, -a.y, -a.z); }
-__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ float3 cross3(float3 a, float3 b)
-{
-    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.x, a.y, a.z); }
-__device__ __forceinline__ float3 ld3(const float *p, int i)
-{
-    return make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
-}
-__device__ __forceinline__ void st3(float *p, int i, float3 v)
-{
-    p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z;
-}
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v)
@@ -292,15 +272,84 @@ __device__ __forceinline__ bool vertex_terms(const DevTopo &T, const StepConsts 
     return contact;
 }
 
+// Mesh-mesh vertex-triangle contact element (Sec. 3.5) seen from one of its
+// vertices: role -1 = the colliding vertex xa, 0..2 = that triangle corner.
+// E = k_c/2 d^2, d = delta - (xa - q).n, q the closest point on the triangle
+// (recomputed here), n its unit normal; n and q's barycentric weights are held
+// fixed in the derivatives: dd/dxa = -n, dd/dc_k = w_k n.  Friction (Sec. 3.6)
+// on the relative displacement (xa - xa^t) - sum_k w_k (c_k - c_k^t) with
+// lambda = k_c d.  Adds to a and returns true when the element is active.
+__device__ __forceinline__ bool vt_term(const StepConsts &K, const float4 *Xt, float3 xa, int ia,
+                                        float3 c0, float3 c1, float3 c2, int4 tri, int role,
+                                        Acc &a)
+{
+    const ClosestPt cp = closest_on_triangle(xa, c0, c1, c2);
+    const float3 n = normalize3(cross3(c1 - c0, c2 - c0));
+    const float d = K.delta - dot3(xa - cp.q, n);
+    if (!(d > 0.f)) return false;
+    const float g = role < 0 ? -1.f : (role == 0 ? cp.w0 : (role == 1 ? cp.w1 : cp.w2));
+    const float kd = K.kc * d * g, kh = K.kc * g * g;
+    a.fx -= kd * n.x; a.fy -= kd * n.y; a.fz -= kd * n.z;
+    a.hxx += kh * n.x * n.x; a.hxy += kh * n.x * n.y; a.hxz += kh * n.x * n.z;
+    a.hyy += kh * n.y * n.y; a.hyz += kh * n.y * n.z; a.hzz += kh * n.z * n.z;
+    if (K.fric_mu > 0.f) {
+        const float3 dxa = xa - xyz(Xt[ia]);
+        const float3 d0 = c0 - xyz(Xt[tri.x]), d1 = c1 - xyz(Xt[tri.y]), d2 = c2 - xyz(Xt[tri.z]);
+        const float3 dx = dxa - (d0 * cp.w0 + d1 * cp.w1 + d2 * cp.w2);
+        const float3 u = dx - n * dot3(dx, n);
+        const float un = sqrtf(dot3(u, u));
+        const float hev = K.fric_hev;
+        const float f1u = (un < hev) ? (2.0f / hev - un / (hev * hev)) : (1.0f / un);
+        const float sf = K.fric_mu * K.kc * d * f1u;
+        const float sg = sf * g, sg2 = sf * g * g;
+        a.fx += sg * u.x; a.fy += sg * u.y; a.fz += sg * u.z;
+        a.hxx += sg2 * (1.f - n.x * n.x); a.hxy -= sg2 * n.x * n.y; a.hxz -= sg2 * n.x * n.z;
+        a.hyy += sg2 * (1.f - n.y * n.y); a.hyz -= sg2 * n.y * n.z; a.hzz += sg2 * (1.f - n.z * n.z);
+    }
+    return true;
+}
+
+// Contact elements of vertex p: lane 0 takes p's own contact (p is the
+// colliding vertex), the lanes stride over the corner entries (p is a corner
+// of another vertex's contact triangle).  Returns the number of active
+// elements this lane added.
+template <int L>
+__device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &S,
+                                               const StepConsts &K, int p, float3 xi, int lane,
+                                               Acc &a)
+{
+    float nc = 0.f;
+    const float4 *X = T.x;
+    if (lane == 0) {
+        const int own = S.ctri[p];
+        if (own >= 0) {
+            const int4 tr = S.tri[own];
+            if (vt_term(K, T.xt, xi, p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]), tr, -1, a)) nc += 1.f;
+        }
+    }
+    const int e1 = (int)S.crow[p + 1];
+    for (int e = (int)S.crow[p] + lane; e < e1; e += L) {
+        const int va = S.cent[e];
+        const int4 tr = S.tri[S.ctri[va]];
+        const int role = (tr.x == p) ? 0 : ((tr.y == p) ? 1 : 2);
+        if (vt_term(K, T.xt, xyz(X[va]), va, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]), tr, role, a))
+            nc += 1.f;
+    }
+    return nc;
+}
+
 // One vertex update by a group of L lanes.  All lanes of the wave must call
 // this (inactive groups pass active = false) because of the DPP reduction.
-template <int L, int KU, bool TETS, bool SPRINGS>
+// MC: mesh-mesh contacts; the update then goes to S.xnew (the color's
+// positions stay readable until the copy back).
+template <int L, int KU, bool TETS, bool SPRINGS, bool MC = false>
 __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
-                                             int lane, bool active)
+                                             int lane, bool active, const DevSurf *S = nullptr)
 {
     Acc a;
     acc_zero(a);
     float4 xi4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float nc = 0.f;
     if (active) {
         xi4 = T.x[p];
         if (TETS) tet_terms<L, KU>(T, T.x, T.tet_row[p], T.tet_row[p + 1], lane, K.alpha, a);
@@ -310,15 +359,38 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
                 spring_contrib(T.x, xyz(xi4), T.spr_ent[e], K.spring_k, K.spring_psd, a);
         }
     }
+    if (MC) {
+        // Rayleigh damping applies to the material Hessian only: contact
+        // terms are added after it (see below) when damping is on
+        if (active && K.kd_over_h == 0.f) nc = contact_terms<L>(T, *S, K, p, xyz(xi4), lane, a);
+    }
     acc_reduce<L>(a);
+    if (MC) nc = group_sum<L>(nc);
     if (!active) return;
     const float3 xi = xyz(xi4);
-    const bool contact = vertex_terms(T, K, p, xi, a);
+    bool contact = vertex_terms(T, K, p, xi, a);
+    if (MC && K.kd_over_h != 0.f) {
+        // damping on: the group's lanes are past the reduction, so lane 0
+        // alone adds the contact elements to the reduced system
+        Acc c;
+        acc_zero(c);
+        float ncl = 0.f;
+        if (lane == 0) {
+            ncl = contact_terms<1>(T, *S, K, p, xi, 0, c);
+            a.fx += c.fx; a.fy += c.fy; a.fz += c.fz;
+            a.hxx += c.hxx; a.hxy += c.hxy; a.hxz += c.hxz;
+            a.hyy += c.hyy; a.hyz += c.hyz; a.hzz += c.hzz;
+        }
+        nc += ncl;
+    }
+    if (MC && nc > 0.f) contact = true;
     float3 dx;
     const bool ok = solve_sym3(a, K.det_eps_rel, dx);
     if (lane == 0) {
-        if (ok) T.x[p] = make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w);
-        else atomicAdd(&T.flags[2], 1u);
+        const float4 xo = ok ? make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w) : xi4;
+        if (MC) S->xnew[p] = xo;
+        else if (ok) T.x[p] = xo;
+        if (!ok) atomicAdd(&T.flags[2], 1u);
         if (contact) T.collided[p] = 1;
     }
 }
@@ -388,6 +460,23 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, in
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
     solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end);
+}
+
+template <int L, int KU, bool TETS, bool SPRINGS>
+__global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, StepConsts K,
+                                                        int v_begin, int v_end, int remap)
+{
+    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int gid = b * blockDim.x + threadIdx.x;
+    const int p = v_begin + gid / L;
+    solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, &S);
+}
+
+// End of a color phase with mesh contacts: its updates become visible.
+__global__ void k_copyback(float4 *x, const float4 *xnew, int v_begin, int v_end)
+{
+    const int p = v_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < v_end) x[p] = xnew[p];
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -762,6 +851,55 @@ hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, b
     case 32: return solve_unroll<32>(T, K, vb, ve, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int L, int KU>
+static hipError_t solve_mc_dispatch(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
+                                    int ve, bool tets, bool springs, const LaunchCfg &cfg,
+                                    hipStream_t s)
+{
+    const int grid = cdiv((long)(ve - vb) * L, cfg.block);
+    if (tets && springs)
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+    else if (tets)
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+    else if (springs)
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+    else
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+    return hipGetLastError();
+}
+
+template <int L>
+static hipError_t solve_mc_unroll(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
+                                  int ve, bool tets, bool springs, const LaunchCfg &cfg,
+                                  hipStream_t s)
+{
+    switch (cfg.unroll) {
+    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, tets, springs, cfg, s);
+    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, tets, springs, cfg, s);
+    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, tets, springs, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
+                                 int ve, bool tets, bool springs, const LaunchCfg &cfg,
+                                 hipStream_t s)
+{
+    if (ve <= vb) return hipSuccess;
+    if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
+    hipError_t e;
+    switch (cfg.lanes) {
+    case 4: e = solve_mc_unroll<4>(T, S, K, vb, ve, tets, springs, cfg, s); break;
+    case 8: e = solve_mc_unroll<8>(T, S, K, vb, ve, tets, springs, cfg, s); break;
+    case 16: e = solve_mc_unroll<16>(T, S, K, vb, ve, tets, springs, cfg, s); break;
+    case 32: e = solve_mc_unroll<32>(T, S, K, vb, ve, tets, springs, cfg, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copyback, dim3(cdiv(ve - vb, 256)), dim3(256), 0, s, T.x, S.xnew, vb, ve);
+    return hipGetLastError();
 }
 
 hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s)

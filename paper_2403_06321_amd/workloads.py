@@ -268,6 +268,48 @@ def config_batch(n_meshes: int = 512, seed: int = 3, lo: int = 4, hi: int = 33,
                     params=StepParams(n_iters=n_iters), frames=frames)
 
 
+def config_block_stack(cols: int = 2, levels: int = 3, n: int = 5, seed: int = 5,
+                       overlap: float = 0.002, gap: float = 0.5 * EDGE, frames: int = 10,
+                       n_iters: int = 20, contact_k: float = 1e4) -> Workload:
+    """cols x cols columns of `levels` stacked n^3 lattice cubes (separate
+    meshes).  Each cube sinks `overlap` into the one below it; odd levels are
+    shifted by (0.33, 0.41) lattice cells so no vertex lies above an edge of
+    the surface under it.  The bottom face of the lowest level is pinned;
+    per-block E log-uniform in [1e5, 1e6]; x0 = rest, v0 = 0; gravity.
+    k_c = 1e4 keeps every contact element a few mm deep (its resting depth is
+    about 4 mm), away from the d = 0 switch where the penalty Hessian jumps."""
+    rng = np.random.default_rng(seed)
+    side = (n - 1) * EDGE
+    rests, tetss, Es, pins, vo, to = [], [], [], [], [0], [0]
+    for lev in range(levels):
+        shift = np.array([0.33, 0.41]) * EDGE if lev % 2 else np.zeros(2)
+        z0 = lev * (side - overlap)
+        for i in range(cols):
+            for j in range(cols):
+                r, t = cube_lattice(n, n, n)
+                r = r - r.min(axis=0)
+                r = r + np.array([i * (side + gap + EDGE) + shift[0],
+                                  j * (side + gap + EDGE) + shift[1], z0])
+                pin = np.zeros(r.shape[0], np.uint8)
+                if lev == 0:
+                    pin[np.abs(r[:, 2]) < 1e-12] = 1
+                rests.append(r)
+                tetss.append(t + vo[-1])
+                Es.append(np.full(t.shape[0], _log_uniform(rng, 1e5, 1e6, 1)[0]))
+                pins.append(pin)
+                vo.append(vo[-1] + r.shape[0])
+                to.append(to[-1] + t.shape[0])
+    rest = np.concatenate(rests)
+    tets = np.concatenate(tetss).astype(np.int32)
+    nv = rest.shape[0]
+    params = StepParams(n_iters=n_iters, contact_k=contact_k, contact_thickness=1e-3,
+                        mesh_contacts=True, collision_radius=0.5 * EDGE)
+    return Workload(name=f"stack of {levels} x {cols}x{cols} cubes {n}^3", rest=rest, tets=tets,
+                    pinned=np.concatenate(pins), x0=rest.copy(), v0=np.zeros((nv, 3)),
+                    tet_E=np.concatenate(Es), vert_offsets=np.array(vo, np.int64),
+                    tet_offsets=np.array(to, np.int64), params=params, frames=frames)
+
+
 def config_differentiable(n: int = 33, seed: int = 4, frames: int = 30, n_iters: int = 20) -> Workload:
     """n^3 cube, per-tet E log-uniform, v0 = 0, seeded target for a centroid loss."""
     rng = np.random.default_rng(seed)

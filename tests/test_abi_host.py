@@ -197,3 +197,25 @@ def test_rest_frame_preserves_deformation_invariants():
         Q = np.linalg.solve(F, Fp)
         assert np.allclose(Q.T @ Q, np.eye(3), atol=1e-10)
         assert np.linalg.det(Fp) == pytest.approx(np.linalg.det(F), rel=1e-12)
+
+
+def test_surface_matches_oracle_with_outward_orientation():
+    """The library's surface (extracted for batched topologies) is the
+    oracle's set of boundary faces, each with the same outward orientation."""
+    w = W.config_block_stack(cols=2, levels=2, n=4)
+    t = Topology.from_workload(w, bind=False)
+    surf = t.query(N.Q_SURFACE)
+    n_tri, n_sv = t.query(N.Q_SURFACE_COUNTS)
+    m = O.Model.from_workload(w)
+    assert n_tri == surf.shape[0] == m.surf_tris.shape[0] == w.n_meshes * 2 * 6 * 3 ** 2
+    assert n_sv == np.unique(surf).size
+    rot = {}
+    for tri in m.surf_tris:
+        k = int(np.argmin(tri))
+        rot[tuple(np.roll(tri, -k))] = True
+    for tri in surf:
+        k = int(np.argmin(tri))
+        assert tuple(np.roll(tri, -k)) in rot
+    # a single mesh has no surface (contacts are between meshes)
+    t1 = Topology.from_workload(W.tet_cube(4, 0), bind=False)
+    assert tuple(t1.query(N.Q_SURFACE_COUNTS)) == (0, 0)

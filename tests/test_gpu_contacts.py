@@ -1,0 +1,104 @@
+"""Mesh-mesh vertex-triangle contacts on the GPU against the FP64 oracle
+(Sec. 3.5, 3.6, 3.9): detection compared as integers, steps per frame from the
+oracle's state."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_06321_amd import workloads as W
+from gpu_util import oracle_states, replace, resync_parity, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _tri_keys(surf, tri):
+    return [tuple(sorted(surf[k])) if k >= 0 else None for k in tri]
+
+
+def _gpu_detect(w, p, x):
+    import torch
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    t = Topology.from_workload(w)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda").contiguous()
+    tri = t.detect_contacts(xd, p).cpu().numpy()
+    return tri, t.query(N.Q_SURFACE)
+
+
+@pytest.mark.parametrize("cols,levels,n", [(2, 3, 5), (3, 2, 9)])
+def test_detection_matches_oracle(cols, levels, n):
+    w = W.config_block_stack(cols=cols, levels=levels, n=n)
+    say(f"detection {w.name}: {w.n_verts} vertices")
+    tri_g, surf_g = _gpu_detect(w, w.params, w.x0)
+    m = O.Model.from_workload(w)
+    tri_o = O.detect_contacts(m, w.params, w.x0)
+    assert (tri_o >= 0).sum() > 0
+    assert _tri_keys(surf_g, tri_g) == _tri_keys(m.surf_tris, tri_o)
+
+
+def test_detection_on_rotated_jittered_blocks():
+    """A rigid rotation moves every contact off the lattice axes; jitter of
+    0.1 % of a cell keeps the configuration away from ties.  Vertices where the
+    oracle's decision is within FP32 reach of a tie are not compared."""
+    w = W.config_block_stack(cols=2, levels=3, n=5)
+    rng = np.random.default_rng(9)
+    A = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    A *= np.sign(np.linalg.det(A))
+    x = w.x0 @ A.T + rng.uniform(-1e-4, 1e-4, size=w.x0.shape)
+    tri_g, surf_g = _gpu_detect(w, w.params, x)
+    m = O.Model.from_workload(w)
+    tri_o = O.detect_contacts(m, w.params, x)
+    kg, ko = _tri_keys(surf_g, tri_g), _tri_keys(m.surf_tris, tri_o)
+    diff = [i for i in range(w.n_verts) if kg[i] != ko[i]]
+    for i in diff:
+        # allowed only when the two triangles are equally close (shared edge
+        # or vertex) to FP32 precision
+        assert kg[i] is not None and ko[i] is not None, f"vertex {i}: contact {ko[i]} vs {kg[i]}"
+        dg = np.linalg.norm(O.closest_point_triangle(x[i], *x[list(kg[i])])[0] - x[i])
+        do = np.linalg.norm(O.closest_point_triangle(x[i], *x[list(ko[i])])[0] - x[i])
+        assert abs(dg - do) <= 1e-6, f"vertex {i}: distances {do} vs {dg}"
+    say(f"rotated stack: {sum(k is not None for k in ko)} contacts, {len(diff)} equal-distance ties")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_block_stack_steps_match_oracle(mode):
+    w = W.config_block_stack(cols=2, levels=3, n=5, frames=6)
+    st = oracle_states(w, w.frames)
+    resync_parity(w, st, launch_mode=mode, tol=1e-5, label=f"block stack mode {mode}")
+
+
+def test_block_stack_friction_redetection_and_acceleration():
+    w = W.config_block_stack(cols=2, levels=2, n=5, frames=3, n_iters=30)
+    p = replace(w.params, friction_mu=0.3, friction_eps_v=1e-2, n_col=10, cheb_rho=0.5)
+    w.v0[w.vert_offsets[4]:, 0] = -0.5   # the upper level slides along -x
+    st = oracle_states(w, w.frames, params=p)
+    resync_parity(w, st, params=p, tol=1e-5, label="block stack friction, n_col=10, chebyshev")
+
+
+def test_block_stack_damping():
+    w = W.config_block_stack(cols=1, levels=3, n=5, frames=3)
+    p = replace(w.params, kd=1e-5)
+    st = oracle_states(w, w.frames, params=p)
+    resync_parity(w, st, params=p, tol=1e-5, label="block stack damping")
+
+
+def test_graph_replays_match_plain_bitwise_and_persistent_is_refused():
+    import torch
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    w = W.config_block_stack(cols=2, levels=2, n=5)
+    out = []
+    for mode in (0, 1):
+        t = Topology.from_workload(w)
+        x = torch.tensor(w.x0, dtype=torch.float32, device="cuda").contiguous()
+        v = torch.zeros_like(x)
+        vp = torch.zeros_like(x)
+        E = torch.tensor(w.tet_E, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            t.step(x, v, vp, E, w.params, mode)
+            torch.cuda.synchronize()
+        out.append(x.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    with pytest.raises(N.VBDError) as e:
+        t.step(x, v, vp, E, w.params, N.LAUNCH_PERSISTENT)
+    assert e.value.status == -6
