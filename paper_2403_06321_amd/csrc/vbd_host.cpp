@@ -142,7 +142,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.vol = take(sizeof(float) * (size_t)T.nt);
     L.tet_perm = take(sizeof(int32_t) * (size_t)T.nt);
     L.tet_row = take(sizeof(int32_t) * (size_t)(T.nv + 1));
-    L.tet_ent = take(sizeof(int32_t) * T.tet_ent.size());
+    L.tet_ent = take(sizeof(PairEnt) * T.tet_ent.size());
     L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
     L.spr_ent = take(sizeof(int2) * T.spr_nbr_orig.size());
     L.perm = take(sizeof(int32_t) * nv);
@@ -202,7 +202,7 @@ void set_dev_pointers(vbd_topology_s &T)
     D.vol = (const float *)(b + L.vol);
     D.tet_perm = (const int *)(b + L.tet_perm);
     D.tet_row = (const int *)(b + L.tet_row);
-    D.tet_ent = (const int *)(b + L.tet_ent);
+    D.tet_ent = (const PairEnt *)(b + L.tet_ent);
     D.spr_row = (const int *)(b + L.spr_row);
     D.spr_ent = (const int2 *)(b + L.spr_ent);
     D.perm = (const int *)(b + L.perm);
@@ -467,9 +467,10 @@ void build_csr(vbd_topology_s &T)
             T.tet_rank[key[i].second] = i;
         }
     }
-    // algorithmic bytes of one color solve: 48 B tet record + 4 B CSR entry per
-    // tet pair, 8 B per spring entry, 4 B row offset and 48 B own state
-    // (x read, y read, x write) per vertex, 16 B per distinct neighbour position.
+    // algorithmic bytes of one color solve: 32 B tet record + 16 B incidence
+    // entry per tet pair, 8 B per spring entry, 4 B row offset and 48 B own
+    // state (x read, y read, x write) per vertex, 16 B per distinct neighbour
+    // position.
     T.phase_bytes.assign(T.n_colors, 0.0);
     T.phase_updates.assign(T.n_colors, 0);
     std::vector<int32_t> stamp(nv, -1);
@@ -479,7 +480,7 @@ void build_csr(vbd_topology_s &T)
         for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
             const int pairs = T.tet_row[s + 1] - T.tet_row[s];
             const int sp = T.spr_row[s + 1] - T.spr_row[s];
-            bytes += (double)(sizeof(TetRec) + 4) * pairs + 8.0 * sp + 4.0 + 48.0;
+            bytes += (double)(sizeof(TetRec) + sizeof(PairEnt)) * pairs + 8.0 * sp + 4.0 + 48.0;
             for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
                 const int t = T.tet_ent[e] >> 2;
                 for (int k = 0; k < 4; ++k) {
@@ -872,15 +873,19 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         const int32_t *q = &T->tets[4 * (size_t)t];
         double S[6];
         rest_frame_inverse(T->rest, q, S);
-        rec[i].ids = make_int4(T->iperm[q[0]], T->iperm[q[1]], T->iperm[q[2]], T->iperm[q[3]]);
         rec[i].a = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
         rec[i].b = make_float4((float)S[4], (float)S[5], 0.f, 0.f);
         volf[i] = (float)T->vol[t];
     }
-    std::vector<int32_t> tet_ent_dev(T->tet_ent.size());
+    std::vector<PairEnt> tet_ent_dev(T->tet_ent.size());
     for (size_t e = 0; e < tet_ent_dev.size(); ++e) {
         const int32_t v = T->tet_ent[e];
-        tet_ent_dev[e] = (T->tet_rank[v >> 2] << 2) | (v & 3);
+        const int t = v >> 2, k = v & 3;
+        const int32_t *q = &T->tets[4 * (size_t)t];
+        int o[3], n = 0;
+        for (int j = 0; j < 4; ++j)
+            if (j != k) o[n++] = T->iperm[q[j]];
+        tet_ent_dev[e] = make_int4((T->tet_rank[t] << 2) | k, o[0], o[1], o[2]);
     }
     std::vector<int2> spr(T->spr_nbr_orig.size());
     for (size_t e = 0; e < spr.size(); ++e) {
@@ -899,7 +904,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(up(T->lay.vol, volf.data(), 4 * volf.size()));
     HIP_TRY(up(T->lay.tet_perm, T->tet_order.data(), 4 * T->tet_order.size()));
     HIP_TRY(up(T->lay.tet_row, T->tet_row.data(), 4 * T->tet_row.size()));
-    HIP_TRY(up(T->lay.tet_ent, tet_ent_dev.data(), 4 * tet_ent_dev.size()));
+    HIP_TRY(up(T->lay.tet_ent, tet_ent_dev.data(), sizeof(PairEnt) * tet_ent_dev.size()));
     HIP_TRY(up(T->lay.spr_row, T->spr_row.data(), 4 * T->spr_row.size()));
     HIP_TRY(up(T->lay.spr_ent, spr.data(), sizeof(int2) * spr.size()));
     HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));

@@ -7,9 +7,7 @@
 
 namespace vbd {
 
-// 48-byte tet record.
-//   ids = the 4 vertex slots (permuted vertex ids)
-//   a   = {S00, S01, S02, S11}, b = {S12, S22, V*mu, V*lambda}
+// 32-byte tet record: a = {S00, S01, S02, S11}, b = {S12, S22, V*mu, V*lambda}.
 // S = R^{-1}, the inverse of the triangular factor of the rest edge matrix
 // D_m = Q R (Q a proper rotation).  The stable Neo-Hookean energy depends on
 // F only through F^T F and det F, both unchanged by F -> F Q, so
@@ -20,10 +18,16 @@ namespace vbd {
 // the colors of their four vertices, so a cache line only holds tets that
 // are touched in the same color phases).
 struct __align__(16) TetRec {
-    int4 ids;
     float4 a, b;
 };
-static_assert(sizeof(TetRec) == 48, "tet record must be 48 bytes");
+static_assert(sizeof(TetRec) == 32, "tet record must be 32 bytes");
+
+// Incidence entry of a (vertex, tet) pair, 16 bytes:
+//   x = (stored tet << 2) | slot of the vertex in the tet,
+//   y, z, w = permuted ids of the tet's other three vertices in slot order.
+// The record and the three neighbour positions depend only on this entry,
+// so their loads are issued together.
+using PairEnt = int4;
 
 constexpr int kMaxObstacles = 8;
 
@@ -52,7 +56,8 @@ struct DevTopo {
     TetRec *rec;                       // [n_tets] in tet_perm order
     const float *vol;                  // [n_tets] rest volume, tet_perm order
     const int *tet_perm;               // stored tet -> caller's tet index
-    const int *tet_row, *tet_ent;      // CSR over all permuted vertices: (stored tet << 2) | slot
+    const int *tet_row;                // CSR over all permuted vertices
+    const PairEnt *tet_ent;            // (tet, slot, other vertices) per entry
     const int *spr_row;
     const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
     const int *perm;                   // permuted slot -> original id

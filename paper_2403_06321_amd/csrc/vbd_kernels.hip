@@ -123,35 +123,51 @@ __device__ __forceinline__ void tet_accumulate(const TetRec &r, int k, float4 q0
     a.hzz += d + Vlam * cm.z * cm.z;
 }
 
+// Positions of a tet's four slots from the vertex's own position (slot k)
+// and the other three in slot order (a, b, c): slot s < k -> others[s],
+// s == k -> own, s > k -> others[s - 1].
+__device__ __forceinline__ void slot_positions(int k, float4 own, float4 a, float4 b, float4 c,
+                                               float4 &q0, float4 &q1, float4 &q2, float4 &q3)
+{
+    q0 = k == 0 ? own : a;
+    q1 = k < 1 ? a : (k == 1 ? own : b);
+    q2 = k < 2 ? b : (k == 2 ? own : c);
+    q3 = k < 3 ? c : own;
+}
+
 // Tet terms of one vertex: the lanes of the group take entries e0 + lane,
 // e0 + lane + L, ...; each lane issues the loads of KU entries level by level
-// (CSR entries, then records, then positions) so that a vertex costs three
-// dependent memory round trips per KU*L entries instead of three per entry.
+// (incidence entries, then records and neighbour positions together) so that
+// a vertex costs two dependent memory round trips per KU*L entries.
 template <int L, int KU>
-__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, int e0, int e1,
-                                          int lane, float alpha, Acc &a)
+__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own, int e0,
+                                          int e1, int lane, float alpha, Acc &a)
 {
     for (int base = e0 + lane; base < e1; base += L * KU) {
-        int ent[KU];
+        PairEnt ent[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j) {
             const int e = base + j * L;
-            ent[j] = (e < e1) ? T.tet_ent[e] : -1;
+            ent[j] = (e < e1) ? T.tet_ent[e] : make_int4(-1, 0, 0, 0);
         }
         TetRec r[KU];
+        float4 qa[KU], qb[KU], qc[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (ent[j] >= 0) r[j] = T.rec[ent[j] >> 2];
-        float4 q[KU][4];
-#pragma unroll
-        for (int j = 0; j < KU; ++j)
-            if (ent[j] >= 0) {
-                q[j][0] = X[r[j].ids.x]; q[j][1] = X[r[j].ids.y];
-                q[j][2] = X[r[j].ids.z]; q[j][3] = X[r[j].ids.w];
+            if (ent[j].x >= 0) {
+                r[j] = T.rec[ent[j].x >> 2];
+                qa[j] = X[ent[j].y];
+                qb[j] = X[ent[j].z];
+                qc[j] = X[ent[j].w];
             }
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (ent[j] >= 0) tet_accumulate(r[j], ent[j] & 3, q[j][0], q[j][1], q[j][2], q[j][3], alpha, a);
+            if (ent[j].x >= 0) {
+                const int k = ent[j].x & 3;
+                float4 q0, q1, q2, q3;
+                slot_positions(k, own, qa[j], qb[j], qc[j], q0, q1, q2, q3);
+                tet_accumulate(r[j], k, q0, q1, q2, q3, alpha, a);
+            }
     }
 }
 
@@ -352,7 +368,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     float nc = 0.f;
     if (active) {
         xi4 = T.x[p];
-        if (TETS) tet_terms<L, KU>(T, T.x, T.tet_row[p], T.tet_row[p + 1], lane, K.alpha, a);
+        if (TETS) tet_terms<L, KU>(T, T.x, xi4, T.tet_row[p], T.tet_row[p + 1], lane, K.alpha, a);
         if (SPRINGS) {
             const int e1 = T.spr_row[p + 1];
             for (int e = T.spr_row[p] + lane; e < e1; e += L)
@@ -667,14 +683,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
     if (active) {
         e0 = T.tet_row[p];
         e1 = T.tet_row[p + 1];
+        const float4 own = Sn[p];
         for (int e = e0 + lane; e < e1; e += L) {
-            const int ent = T.tet_ent[e];
-            const int t = ent >> 2, k = ent & 3;
+            const PairEnt ent = T.tet_ent[e];
+            const int t = ent.x >> 2, k = ent.x & 3;
             const TetRec r = T.rec[t];
-            const float4 q0 = (r.ids.x < c_end ? Sn : Sp)[r.ids.x];
-            const float4 q1 = (r.ids.y < c_end ? Sn : Sp)[r.ids.y];
-            const float4 q2 = (r.ids.z < c_end ? Sn : Sp)[r.ids.z];
-            const float4 q3 = (r.ids.w < c_end ? Sn : Sp)[r.ids.w];
+            float4 q0, q1, q2, q3;
+            slot_positions(k, own, (ent.y < c_end ? Sn : Sp)[ent.y], (ent.z < c_end ? Sn : Sp)[ent.z],
+                           (ent.w < c_end ? Sn : Sp)[ent.w], q0, q1, q2, q3);
             TetLocal Lc;
             tet_local(r, q0, q1, q2, q3, Lc);
             const float3 mk = shape_grad(Lc, k);
@@ -707,15 +723,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
         T.ybar[p] = yb;
     }
+    const float4 own = Sn[p];
     for (int e = e0 + lane; e < e1; e += L) {
-        const int ent = T.tet_ent[e];
-        const int t = ent >> 2, k = ent & 3;
+        const PairEnt ent = T.tet_ent[e];
+        const int t = ent.x >> 2, k = ent.x & 3;
         const TetRec r = T.rec[t];
-        const int ids[4] = {r.ids.x, r.ids.y, r.ids.z, r.ids.w};
-        const float4 q0 = (ids[0] < c_end ? Sn : Sp)[ids[0]];
-        const float4 q1 = (ids[1] < c_end ? Sn : Sp)[ids[1]];
-        const float4 q2 = (ids[2] < c_end ? Sn : Sp)[ids[2]];
-        const float4 q3 = (ids[3] < c_end ? Sn : Sp)[ids[3]];
+        float4 q0, q1, q2, q3;
+        slot_positions(k, own, (ent.y < c_end ? Sn : Sp)[ent.y], (ent.z < c_end ? Sn : Sp)[ent.z],
+                       (ent.w < c_end ? Sn : Sp)[ent.w], q0, q1, q2, q3);
         TetLocal Lc;
         tet_local(r, q0, q1, q2, q3, Lc);
         const float3 mk = shape_grad(Lc, k);
@@ -752,7 +767,7 @@ __global__ void k_bwd_fold(DevTopo T)
     if (p >= T.n_verts) return;
     float4 xb = T.xbar[p];
     for (int e = T.tet_row[p]; e < T.tet_row[p + 1]; ++e) {
-        const int ent = T.tet_ent[e];
+        const int ent = T.tet_ent[e].x;
         const float4 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
         xb.x += g.x; xb.y += g.y; xb.z += g.z;
     }
