@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--profile-only", default="",
-                    help="run only one workload for a profiler: cube|copy")
+                    help="run only one workload for a profiler: cube|copy|stack")
     ap.add_argument("--lanes", type=int, default=8, help="--profile-only: lanes per vertex")
     ap.add_argument("--block", type=int, default=128, help="--profile-only: block size")
     ap.add_argument("--remap", type=int, default=1, help="--profile-only: XCD remap")
@@ -153,6 +153,14 @@ def main():
             probe_copy(dst, src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": 2 * 4 * n}))
+        return
+
+    if args.profile_only == "stack":
+        # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, plain launches
+        ws = W.config_block_stack(cols=8, levels=4, n=9)
+        ts = Topology.from_workload(ws)
+        secs, upd = time_frames(ts, ws, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
+        print(json.dumps({"profile": "stack", "ms_per_frame": secs / args.steps * 1e3}))
         return
 
     # ---------------------------------------------------------- headline ----

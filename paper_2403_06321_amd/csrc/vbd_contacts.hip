@@ -12,7 +12,9 @@
 // r + R_max of its centroid, so the 27 cells around the vertex's cell hold
 // every candidate.  Buckets are built by counting, an exclusive scan and a
 // fill; the query keeps the minimum of (distance, triangle index), which does
-// not depend on the order inside a bucket.
+// not depend on the order inside a bucket.  Bucket items carry the
+// triangle's mesh (same-mesh candidates are skipped without further loads)
+// and a bounding sphere rejects triangles that cannot beat the best so far.
 //
 // Inside test: the sign of (p - q).N with N the angle-weighted pseudonormal of
 // the closest feature (face normal, sum of the two face normals of an edge,
@@ -156,22 +158,28 @@ __device__ __forceinline__ float grid_cell_size(const DevSurf &S, const StepCons
 }
 
 // ---------------------------------------------------------------- kernels --
-// Unit normals and the largest centroid-to-corner distance.
-__global__ void k_tri_prep(DevSurf S, const float4 *X)
+// Unit normals, bounding spheres and the largest centroid-to-corner
+// distance (reduced over the wave, then one atomic per wave).
+__global__ __launch_bounds__(256) void k_tri_prep(DevSurf S, const float4 *X)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= S.n_tri) return;
-    const int4 tr = S.tri[t];
-    const float3 a = xyz(X[tr.x]), b = xyz(X[tr.y]), c = xyz(X[tr.z]);
-    const float3 n = cross3(b - a, c - a);
-    const float l = sqrtf(dot3(n, n));
-    const float3 u = l > 0.f ? n * (1.0f / l) : make_float3(0.f, 0.f, 0.f);
-    S.tnorm[t] = make_float4(u.x, u.y, u.z, 0.f);
-    const float3 g = (a + b + c) * (1.0f / 3.0f);
-    const float3 da = a - g, db = b - g, dc = c - g;
-    const float R = sqrtf(fmaxf(dot3(da, da), fmaxf(dot3(db, db), dot3(dc, dc))));
+    float R = 0.f;
+    if (t < S.n_tri) {
+        const int4 tr = S.tri[t];
+        const float3 a = xyz(X[tr.x]), b = xyz(X[tr.y]), c = xyz(X[tr.z]);
+        const float3 n = cross3(b - a, c - a);
+        const float l = sqrtf(dot3(n, n));
+        const float3 u = l > 0.f ? n * (1.0f / l) : make_float3(0.f, 0.f, 0.f);
+        S.tnorm[t] = make_float4(u.x, u.y, u.z, 0.f);
+        const float3 g = (a + b + c) * (1.0f / 3.0f);
+        const float3 da = a - g, db = b - g, dc = c - g;
+        R = sqrtf(fmaxf(dot3(da, da), fmaxf(dot3(db, db), dot3(dc, dc))));
+        S.tsph[t] = make_float4(g.x, g.y, g.z, R);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) R = fmaxf(R, __shfl_xor(R, off, 64));
     // non-negative floats order like their bit patterns
-    atomicMax(&S.gparam[0], __float_as_uint(R));
+    if ((threadIdx.x & 63) == 0) atomicMax(&S.gparam[0], __float_as_uint(R));
 }
 
 // Angle-weighted pseudonormal of every surface vertex.
@@ -217,7 +225,7 @@ __global__ void k_grid_fill(DevSurf S, const float4 *X, StepConsts K)
     const float inv_s = 1.0f / grid_cell_size(S, K);
     const unsigned h = cell_hash(cell_coord(g.x, inv_s), cell_coord(g.y, inv_s), cell_coord(g.z, inv_s), S.hmask);
     const unsigned pos = S.hstart[h] + atomicAdd(&S.hcount[h], 1u);
-    S.hitems[pos] = t;
+    S.hitems[pos] = make_int2(t, tr.w);
 }
 
 // Pseudonormal of the closest feature of triangle t.
@@ -236,39 +244,66 @@ __device__ __forceinline__ float3 feature_normal(const DevSurf &S, int t, int fe
     return o >= 0 ? nt + xyz(S.tnorm[o]) : nt;
 }
 
-__global__ void k_detect(DevSurf S, const float4 *X, StepConsts K)
+// One surface vertex per group of kDetLanes lanes: lane l < 27 scans the
+// bucket of neighbouring cell l, then the group reduces the (distance^2,
+// triangle) minimum with shuffles; the group's first lane decides the contact.
+constexpr int kDetLanes = 32;
+
+__global__ __launch_bounds__(256) void k_detect(DevSurf S, const float4 *X, StepConsts K)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= S.n_sv) return;
-    const int2 sv = S.svert[v];
-    const float3 p = xyz(X[sv.x]);
-    const float inv_s = 1.0f / grid_cell_size(S, K);
-    const int ci = cell_coord(p.x, inv_s), cj = cell_coord(p.y, inv_s), ck = cell_coord(p.z, inv_s);
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = gid / kDetLanes, lane = threadIdx.x & (kDetLanes - 1);
+    const bool active = v < S.n_sv;
+    int2 sv = make_int2(0, -1);
+    float3 p = make_float3(0.f, 0.f, 0.f);
     float best_d2 = K.col_radius * K.col_radius;
     int best = -1;
-    ClosestPt bcp{};
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const unsigned h = cell_hash(ci + dx, cj + dy, ck + dz, S.hmask);
-                const unsigned e1 = S.hstart[h + 1];
-                for (unsigned e = S.hstart[h]; e < e1; ++e) {
-                    const int t = S.hitems[e];
-                    const int4 tr = S.tri[t];
-                    if (tr.w == sv.y) continue;
-                    const ClosestPt cp = closest_on_triangle(p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]));
-                    const float3 d = p - cp.q;
-                    const float d2 = dot3(d, d);
-                    if (d2 < best_d2 || (d2 == best_d2 && best >= 0 && t < best)) {
-                        best_d2 = d2;
-                        best = t;
-                        bcp = cp;
-                    }
-                }
+    if (active) {
+        sv = S.svert[v];
+        p = xyz(X[sv.x]);
+    }
+    if (active && lane < 27) {
+        const float inv_s = 1.0f / grid_cell_size(S, K);
+        const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+        const unsigned h = cell_hash(cell_coord(p.x, inv_s) + dx, cell_coord(p.y, inv_s) + dy,
+                                     cell_coord(p.z, inv_s) + dz, S.hmask);
+        const unsigned e1 = S.hstart[h + 1];
+        for (unsigned e = S.hstart[h]; e < e1; ++e) {
+            const int2 item = S.hitems[e];
+            if (item.y == sv.y) continue;              // own mesh
+            const int t = item.x;
+            // every point of the triangle lies within R of its centroid; the
+            // margin keeps rounding of the bound from deciding a tie
+            const float4 sph = S.tsph[t];
+            const float3 dc = p - make_float3(sph.x, sph.y, sph.z);
+            const float lb = sqrtf(dot3(dc, dc)) - sph.w;
+            if (lb > 0.f && lb * lb > 1.001f * best_d2) continue;
+            const int4 tr = S.tri[t];
+            const ClosestPt cp = closest_on_triangle(p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]));
+            const float3 d = p - cp.q;
+            const float d2 = dot3(d, d);
+            if (d2 < best_d2 || (d2 == best_d2 && best >= 0 && t < best)) {
+                best_d2 = d2;
+                best = t;
             }
+        }
+    }
+    // lexicographic minimum of (d2, t) over the group (t = -1: none found)
+#pragma unroll
+    for (int off = kDetLanes / 2; off > 0; off >>= 1) {
+        const float od2 = __shfl_xor(best_d2, off, kDetLanes);
+        const int ot = __shfl_xor(best, off, kDetLanes);
+        if (ot >= 0 && (best < 0 || od2 < best_d2 || (od2 == best_d2 && ot < best))) {
+            best_d2 = od2;
+            best = ot;
+        }
+    }
+    if (!active || lane != 0) return;
     int hit = -1;
     if (best >= 0) {
-        const bool inside = dot3(p - bcp.q, feature_normal(S, best, bcp.feature)) < 0.f;
+        const int4 tr = S.tri[best];
+        const ClosestPt cp = closest_on_triangle(p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]));
+        const bool inside = dot3(p - cp.q, feature_normal(S, best, cp.feature)) < 0.f;
         if (sqrtf(best_d2) < K.delta || inside) hit = best;
     }
     S.ctri[sv.x] = hit;
@@ -345,7 +380,7 @@ hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X, co
     if ((e = scan_exclusive(S.hcount, S.hstart, S.scan_tmp, H, s)) != hipSuccess) return e;
     if ((e = fill_u32(S.hcount, H, 0u, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_grid_fill, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X, K);
-    hipLaunchKernelGGL(k_detect, dim3(cdiv(S.n_sv, 128)), dim3(128), 0, s, S, X, K);
+    hipLaunchKernelGGL(k_detect, dim3(cdiv((long)S.n_sv * kDetLanes, 256)), dim3(256), 0, s, S, X, K);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive(S.ccount, S.crow, S.scan_tmp, T.n_verts, s)) != hipSuccess) return e;
     if ((e = fill_u32(S.ccount, T.n_verts, 0u, s)) != hipSuccess) return e;

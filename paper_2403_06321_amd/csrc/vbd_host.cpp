@@ -52,7 +52,7 @@ struct Layout {
     size_t snaps, xbar, ybar, xtbar, vbar, contrib;
     // mesh-mesh contacts (only when the topology has a surface)
     size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam;
-    size_t s_hcount, s_hstart, s_scan, s_hitems, s_ctri, s_ccount, s_crow, s_cent, s_xnew;
+    size_t s_hcount, s_hstart, s_scan, s_hitems, s_tsph, s_ctri, s_ccount, s_crow, s_cent, s_xsnap;
     int hsize;
     size_t total;
     int max_bwd_iters;
@@ -182,12 +182,13 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.s_hstart = take(sizeof(uint32_t) * ((size_t)H + 1));
         const size_t big = std::max<size_t>((size_t)H, nv + 1);
         L.s_scan = take(sizeof(uint32_t) * (big / 2048 + 2));
-        L.s_hitems = take(sizeof(int32_t) * ntri);
+        L.s_hitems = take(sizeof(int2) * ntri);
+        L.s_tsph = take(sizeof(float4) * ntri);
         L.s_ctri = take(sizeof(int32_t) * nv);
         L.s_ccount = take(sizeof(uint32_t) * nv);
         L.s_crow = take(sizeof(uint32_t) * (nv + 1));
         L.s_cent = take(sizeof(int32_t) * 3 * nsv);
-        L.s_xnew = take(sizeof(float4) * nv);
+        L.s_xsnap = take(sizeof(float4) * nv);
     }
     L.total = off;
     return L;
@@ -242,12 +243,13 @@ void set_dev_pointers(vbd_topology_s &T)
         S.hcount = (unsigned *)(b + L.s_hcount);
         S.hstart = (unsigned *)(b + L.s_hstart);
         S.scan_tmp = (unsigned *)(b + L.s_scan);
-        S.hitems = (int *)(b + L.s_hitems);
+        S.hitems = (int2 *)(b + L.s_hitems);
+        S.tsph = (float4 *)(b + L.s_tsph);
         S.ctri = (int *)(b + L.s_ctri);
         S.ccount = (unsigned *)(b + L.s_ccount);
         S.crow = (unsigned *)(b + L.s_crow);
         S.cent = (int *)(b + L.s_cent);
-        S.xnew = (float4 *)(b + L.s_xnew);
+        S.xsnap = (float4 *)(b + L.s_xsnap);
         S.hmask = L.hsize - 1;
     }
 }
@@ -632,15 +634,25 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
         }
         int64_t launches = 0;
         const bool mc = p->mesh_contacts && T.surf_dev.n_tri > 0;
-        if (mc) HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.xt, K, s));
+        // mesh contacts: the snapshot starts equal to the initial guess; each
+        // phase refreshes the snapshot of the color solved before it
+        int pend_b = 0, pend_e = 0;
+        if (mc) {
+            HIP_TRY(launch_copy4(T.surf_dev.xsnap, T.dev.x, T.nv, s));
+            HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.xt, K, s));
+        }
         for (int it = 1; it <= p->n_iters; ++it) {
             if (mc && p->n_col > 0 && it > 1 && (it - 1) % p->n_col == 0)
                 HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.x, K, s));
             for (int c = 0; c < T.n_colors; ++c) {
-                if (mc)
-                    HIP_TRY(launch_solve_contacts(T.dev, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
-                                                  tets, springs, T.cfg, s));
-                else
+                if (mc) {
+                    if (T.color_off[c + 1] > T.color_off[c]) {
+                        HIP_TRY(launch_solve_contacts(T.dev, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
+                                                      pend_b, pend_e, tets, springs, T.cfg, s));
+                        pend_b = T.color_off[c];
+                        pend_e = T.color_off[c + 1];
+                    }
+                } else
                     HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], tets, springs, T.cfg, s));
                 if (T.color_off[c + 1] > T.color_off[c]) {
                     ++launches;
@@ -648,7 +660,10 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
                     ev.updates += T.phase_updates[c];
                 }
             }
-            if (p->cheb_rho > 0.f) HIP_TRY(launch_cheb(T.dev, K, it, s));
+            if (p->cheb_rho > 0.f) {
+                HIP_TRY(launch_cheb(T.dev, K, it, s, mc ? T.surf_dev.xsnap : nullptr));
+                pend_b = pend_e = 0;
+            }
         }
         if (prof) {
             HIP_TRY(hipEventRecord(ev.b, s));

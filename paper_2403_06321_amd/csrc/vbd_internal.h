@@ -88,12 +88,14 @@ struct DevSurf {
     unsigned *hcount;      // [H] bucket sizes, then fill cursors
     unsigned *hstart;      // [H + 1]
     unsigned *scan_tmp;    // [n_scan_blocks + 1]
-    int *hitems;           // [n_tri]
+    int2 *hitems;          // [n_tri] {triangle, its mesh} grouped by bucket
+    float4 *tsph;          // [n_tri] centroid and centroid-to-corner radius
     int *ctri;             // [n_verts] contact triangle of a permuted slot or -1
     unsigned *ccount;      // [n_verts] corner entries per slot, then fill cursors
     unsigned *crow;        // [n_verts + 1]
     int *cent;             // [3 n_sv] colliding vertex of each corner entry
-    float4 *xnew;          // [n_verts] updates of the current color
+    float4 *xsnap;         // [n_verts] positions of each color as of the start of its
+                           // phase (read for same-color contact partners)
     int n_tri, n_sv, hmask;
 };
 
@@ -112,11 +114,13 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
                           const StepConsts &K, bool reset_flags, hipStream_t s);
 hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end,
                         bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
-// Color solve with mesh-mesh contact elements: writes S.xnew, then
-// copies the color's range back into T.x.
+// Color solve with mesh-mesh contact elements.  Updates T.x in place; contact
+// partners of the same color are read from S.xsnap (their positions before
+// the phase).  [prev_begin, prev_end): the previously solved color, whose
+// snapshot the kernel refreshes from T.x.
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K,
-                                 int v_begin, int v_end, bool tets, bool springs,
-                                 const LaunchCfg &cfg, hipStream_t s);
+                                 int v_begin, int v_end, int prev_begin, int prev_end,
+                                 bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
 // Detection on the permuted positions X (T.xt or T.x) into S.ctri and the
 // corner CSR (S.crow, S.cent).
 hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X,
@@ -124,7 +128,9 @@ hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X,
 // x (original order) -> T.x, and S.ctri -> tri_out (original order, or -1).
 hipError_t launch_load_x(const DevTopo &T, const float *x, hipStream_t s);
 hipError_t launch_store_ctri(const DevTopo &T, const DevSurf &S, int *tri_out, hipStream_t s);
-hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s);
+// snap: when not null, also receives the accelerated positions.
+hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s,
+                       float4 *snap = nullptr);
 hipError_t launch_finalize(const DevTopo &T, float *x, float *v, float *vp,
                            const StepConsts &K, hipStream_t s);
 // Persistent kernel over all iterations and colors.  grid = 0 -> occupancy

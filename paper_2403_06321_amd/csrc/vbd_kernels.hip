@@ -325,22 +325,31 @@ __device__ __forceinline__ bool vt_term(const StepConsts &K, const float4 *Xt, f
     return true;
 }
 
+// Position of a contact partner q during the phase over slots [vb, ve).
+__device__ __forceinline__ float3 phase_pos(const float4 *X, const float4 *Xs, int q, int vb, int ve)
+{
+    return xyz((q >= vb && q < ve) ? Xs[q] : X[q]);
+}
+
 // Contact elements of vertex p: lane 0 takes p's own contact (p is the
 // colliding vertex), the lanes stride over the corner entries (p is a corner
-// of another vertex's contact triangle).  Returns the number of active
-// elements this lane added.
+// of another vertex's contact triangle).  Partners of p's color (slots in
+// [vb, ve)) are read at their positions from before the phase, the others
+// at their latest.  Returns the number of active elements this lane added.
 template <int L>
 __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &S,
                                                const StepConsts &K, int p, float3 xi, int lane,
-                                               Acc &a)
+                                               int vb, int ve, Acc &a)
 {
     float nc = 0.f;
-    const float4 *X = T.x;
+    const float4 *X = T.x, *Xs = S.xsnap;
     if (lane == 0) {
         const int own = S.ctri[p];
         if (own >= 0) {
             const int4 tr = S.tri[own];
-            if (vt_term(K, T.xt, xi, p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]), tr, -1, a)) nc += 1.f;
+            if (vt_term(K, T.xt, xi, p, phase_pos(X, Xs, tr.x, vb, ve), phase_pos(X, Xs, tr.y, vb, ve),
+                        phase_pos(X, Xs, tr.z, vb, ve), tr, -1, a))
+                nc += 1.f;
         }
     }
     const int e1 = (int)S.crow[p + 1];
@@ -348,19 +357,21 @@ __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &
         const int va = S.cent[e];
         const int4 tr = S.tri[S.ctri[va]];
         const int role = (tr.x == p) ? 0 : ((tr.y == p) ? 1 : 2);
-        if (vt_term(K, T.xt, xyz(X[va]), va, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]), tr, role, a))
-            nc += 1.f;
+        const float3 c0 = role == 0 ? xi : phase_pos(X, Xs, tr.x, vb, ve);
+        const float3 c1 = role == 1 ? xi : phase_pos(X, Xs, tr.y, vb, ve);
+        const float3 c2 = role == 2 ? xi : phase_pos(X, Xs, tr.z, vb, ve);
+        if (vt_term(K, T.xt, phase_pos(X, Xs, va, vb, ve), va, c0, c1, c2, tr, role, a)) nc += 1.f;
     }
     return nc;
 }
 
 // One vertex update by a group of L lanes.  All lanes of the wave must call
 // this (inactive groups pass active = false) because of the DPP reduction.
-// MC: mesh-mesh contacts; the update then goes to S.xnew (the color's
-// positions stay readable until the copy back).
+// MC: mesh-mesh contacts of a phase over slots [vb, ve).
 template <int L, int KU, bool TETS, bool SPRINGS, bool MC = false>
 __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
-                                             int lane, bool active, const DevSurf *S = nullptr)
+                                             int lane, bool active, const DevSurf *S = nullptr,
+                                             int vb = 0, int ve = 0)
 {
     Acc a;
     acc_zero(a);
@@ -378,7 +389,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     if (MC) {
         // Rayleigh damping applies to the material Hessian only: contact
         // terms are added after it (see below) when damping is on
-        if (active && K.kd_over_h == 0.f) nc = contact_terms<L>(T, *S, K, p, xyz(xi4), lane, a);
+        if (active && K.kd_over_h == 0.f) nc = contact_terms<L>(T, *S, K, p, xyz(xi4), lane, vb, ve, a);
     }
     acc_reduce<L>(a);
     if (MC) nc = group_sum<L>(nc);
@@ -392,7 +403,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
         acc_zero(c);
         float ncl = 0.f;
         if (lane == 0) {
-            ncl = contact_terms<1>(T, *S, K, p, xi, 0, c);
+            ncl = contact_terms<1>(T, *S, K, p, xi, 0, vb, ve, c);
             a.fx += c.fx; a.fy += c.fy; a.fz += c.fz;
             a.hxx += c.hxx; a.hxy += c.hxy; a.hxz += c.hxz;
             a.hyy += c.hyy; a.hyz += c.hyz; a.hzz += c.hzz;
@@ -403,10 +414,8 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     float3 dx;
     const bool ok = solve_sym3(a, K.det_eps_rel, dx);
     if (lane == 0) {
-        const float4 xo = ok ? make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w) : xi4;
-        if (MC) S->xnew[p] = xo;
-        else if (ok) T.x[p] = xo;
-        if (!ok) atomicAdd(&T.flags[2], 1u);
+        if (ok) T.x[p] = make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w);
+        else atomicAdd(&T.flags[2], 1u);
         if (contact) T.collided[p] = 1;
     }
 }
@@ -478,21 +487,22 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, in
     solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end);
 }
 
+// Color phase with mesh contacts.  The previously solved color's snapshot is
+// refreshed here: during this phase neither its positions change nor its
+// snapshot is read.
 template <int L, int KU, bool TETS, bool SPRINGS>
 __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, StepConsts K,
-                                                        int v_begin, int v_end, int remap)
+                                                        int v_begin, int v_end, int prev_begin,
+                                                        int prev_end, int remap)
 {
+    for (int q = prev_begin + blockIdx.x * blockDim.x + threadIdx.x; q < prev_end;
+         q += gridDim.x * blockDim.x)
+        S.xsnap[q] = T.x[q];
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, &S);
-}
-
-// End of a color phase with mesh contacts: its updates become visible.
-__global__ void k_copyback(float4 *x, const float4 *xnew, int v_begin, int v_end)
-{
-    const int p = v_begin + blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < v_end) x[p] = xnew[p];
+    solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, &S,
+                                             v_begin, v_end);
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -518,11 +528,12 @@ __device__ __forceinline__ void cheb_vertex(const DevTopo &T, int p, float om)
     T.x[p] = xn;
 }
 
-__global__ void k_cheb(DevTopo T, float rho, int it)
+__global__ void k_cheb(DevTopo T, float rho, int it, float4 *snap)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= T.n_free) return;
     cheb_vertex(T, p, cheb_omega(it, rho));
+    if (snap) snap[p] = T.x[p];
 }
 
 // v^{t+1} = (x^{t+1} - x^t)/h (Eq. velocity_update); the state's previous
@@ -870,57 +881,53 @@ hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, b
 
 template <int L, int KU>
 static hipError_t solve_mc_dispatch(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                    int ve, bool tets, bool springs, const LaunchCfg &cfg,
-                                    hipStream_t s)
+                                    int ve, int pb, int pe, bool tets, bool springs,
+                                    const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
     if (tets && springs)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
     return hipGetLastError();
 }
 
 template <int L>
 static hipError_t solve_mc_unroll(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                  int ve, bool tets, bool springs, const LaunchCfg &cfg,
-                                  hipStream_t s)
+                                  int ve, int pb, int pe, bool tets, bool springs,
+                                  const LaunchCfg &cfg, hipStream_t s)
 {
     switch (cfg.unroll) {
-    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, tets, springs, cfg, s);
-    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, tets, springs, cfg, s);
-    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, tets, springs, cfg, s);
+    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                 int ve, bool tets, bool springs, const LaunchCfg &cfg,
-                                 hipStream_t s)
+                                 int ve, int pb, int pe, bool tets, bool springs,
+                                 const LaunchCfg &cfg, hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
-    hipError_t e;
     switch (cfg.lanes) {
-    case 4: e = solve_mc_unroll<4>(T, S, K, vb, ve, tets, springs, cfg, s); break;
-    case 8: e = solve_mc_unroll<8>(T, S, K, vb, ve, tets, springs, cfg, s); break;
-    case 16: e = solve_mc_unroll<16>(T, S, K, vb, ve, tets, springs, cfg, s); break;
-    case 32: e = solve_mc_unroll<32>(T, S, K, vb, ve, tets, springs, cfg, s); break;
+    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copyback, dim3(cdiv(ve - vb, 256)), dim3(256), 0, s, T.x, S.xnew, vb, ve);
-    return hipGetLastError();
 }
 
-hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s)
+hipError_t launch_cheb(const DevTopo &T, const StepConsts &K, int iter, hipStream_t s, float4 *snap)
 {
     if (T.n_free == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cheb, dim3(cdiv(T.n_free, 256)), dim3(256), 0, s, T, K.cheb_rho, iter);
+    hipLaunchKernelGGL(k_cheb, dim3(cdiv(T.n_free, 256)), dim3(256), 0, s, T, K.cheb_rho, iter, snap);
     return hipGetLastError();
 }
 
