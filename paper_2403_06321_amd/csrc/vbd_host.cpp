@@ -47,7 +47,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec, vol, tet_perm, tet_row, tet_ent, spr_row, spr_ent, perm, mass, color_off;
+    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, ell_info, spr_row, spr_ent, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib;
     // mesh-mesh contacts (only when the topology has a surface)
@@ -91,6 +91,8 @@ struct vbd_topology_s {
     std::vector<int32_t> colors, perm, iperm, color_off;
     std::vector<int32_t> tet_row, tet_ent, spr_row, spr_nbr_orig;
     std::vector<int32_t> tet_order, tet_rank;   // stored position <-> caller's tet id
+    std::vector<int2> ell_info;                 // per color {first entry, padded degree}
+    size_t ell_total = 0;
     std::vector<float> spr_len;
     std::vector<double> phase_bytes;
     std::vector<int64_t> phase_updates;
@@ -143,6 +145,8 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.tet_perm = take(sizeof(int32_t) * (size_t)T.nt);
     L.tet_row = take(sizeof(int32_t) * (size_t)(T.nv + 1));
     L.tet_ent = take(sizeof(PairEnt) * T.tet_ent.size());
+    L.ell = take(sizeof(PairEnt) * T.ell_total);
+    L.ell_info = take(sizeof(int2) * (size_t)T.n_colors);
     L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
     L.spr_ent = take(sizeof(int2) * T.spr_nbr_orig.size());
     L.perm = take(sizeof(int32_t) * nv);
@@ -204,6 +208,8 @@ void set_dev_pointers(vbd_topology_s &T)
     D.tet_perm = (const int *)(b + L.tet_perm);
     D.tet_row = (const int *)(b + L.tet_row);
     D.tet_ent = (const PairEnt *)(b + L.tet_ent);
+    D.ell = (const PairEnt *)(b + L.ell);
+    D.ell_info = (const int2 *)(b + L.ell_info);
     D.spr_row = (const int *)(b + L.spr_row);
     D.spr_ent = (const int2 *)(b + L.spr_ent);
     D.perm = (const int *)(b + L.perm);
@@ -448,6 +454,16 @@ void build_csr(vbd_topology_s &T)
                 spos[s]++;
             }
         }
+    // color-solve incidence: each color padded to its largest tet count
+    T.ell_info.assign(T.n_colors, make_int2(0, 0));
+    T.ell_total = 0;
+    for (int c = 0; c < T.n_colors; ++c) {
+        int dmax = 0;
+        for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s)
+            dmax = std::max(dmax, T.tet_row[s + 1] - T.tet_row[s]);
+        T.ell_info[c] = make_int2((int)T.ell_total, dmax);
+        T.ell_total += (size_t)dmax * (size_t)(T.color_off[c + 1] - T.color_off[c]);
+    }
     // stored tet order: grouped by the sorted colors of the tet's 4 vertices
     // (then by tet id), so tets sharing a cache line are read in the same
     // color phases
@@ -470,9 +486,8 @@ void build_csr(vbd_topology_s &T)
         }
     }
     // algorithmic bytes of one color solve: 32 B tet record + 16 B incidence
-    // entry per tet pair, 8 B per spring entry, 4 B row offset and 48 B own
-    // state (x read, y read, x write) per vertex, 16 B per distinct neighbour
-    // position.
+    // entry per tet pair, 8 B per spring entry, 48 B own state per vertex
+    // (x read, y read, x write), 16 B per distinct neighbour position.
     T.phase_bytes.assign(T.n_colors, 0.0);
     T.phase_updates.assign(T.n_colors, 0);
     std::vector<int32_t> stamp(nv, -1);
@@ -482,7 +497,7 @@ void build_csr(vbd_topology_s &T)
         for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
             const int pairs = T.tet_row[s + 1] - T.tet_row[s];
             const int sp = T.spr_row[s + 1] - T.spr_row[s];
-            bytes += (double)(sizeof(TetRec) + sizeof(PairEnt)) * pairs + 8.0 * sp + 4.0 + 48.0;
+            bytes += (double)(sizeof(TetRec) + sizeof(PairEnt)) * pairs + 8.0 * sp + 48.0;
             for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
                 const int t = T.tet_ent[e] >> 2;
                 for (int k = 0; k < 4; ++k) {
@@ -648,12 +663,12 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
                 if (mc) {
                     if (T.color_off[c + 1] > T.color_off[c]) {
                         HIP_TRY(launch_solve_contacts(T.dev, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
-                                                      pend_b, pend_e, tets, springs, T.cfg, s));
+                                                      T.ell_info[c], pend_b, pend_e, tets, springs, T.cfg, s));
                         pend_b = T.color_off[c];
                         pend_e = T.color_off[c + 1];
                     }
                 } else
-                    HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], tets, springs, T.cfg, s));
+                    HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], T.ell_info[c], tets, springs, T.cfg, s));
                 if (T.color_off[c + 1] > T.color_off[c]) {
                     ++launches;
                     ev.bytes += T.phase_bytes[c];
@@ -857,6 +872,8 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     if (!T || !dev_ptr) return fail(VBD_E_INVALID_ARG, "NULL argument");
     if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color first");
     if ((uintptr_t)dev_ptr % kAlign) return fail(VBD_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (T->ell_total > (size_t)INT32_MAX)
+        return fail(VBD_E_INVALID_ARG, "topology too large: %zu padded incidence entries", T->ell_total);
     // the largest backward iteration count that fits
     Layout L0 = make_layout(*T, 0);
     if (bytes < L0.total) return fail(VBD_E_NO_WORKSPACE, "workspace too small: %zu < %zu", bytes, L0.total);
@@ -920,6 +937,19 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(up(T->lay.tet_perm, T->tet_order.data(), 4 * T->tet_order.size()));
     HIP_TRY(up(T->lay.tet_row, T->tet_row.data(), 4 * T->tet_row.size()));
     HIP_TRY(up(T->lay.tet_ent, tet_ent_dev.data(), sizeof(PairEnt) * tet_ent_dev.size()));
+    {
+        std::vector<PairEnt> ell(T->ell_total, make_int4(-1, 0, 0, 0));
+        for (int c = 0; c < T->n_colors; ++c) {
+            const int2 info = T->ell_info[c];
+            for (int sl = T->color_off[c]; sl < T->color_off[c + 1]; ++sl) {
+                const size_t base = (size_t)info.x + (size_t)(sl - T->color_off[c]) * (size_t)info.y;
+                for (int e = T->tet_row[sl]; e < T->tet_row[sl + 1]; ++e)
+                    ell[base + (size_t)(e - T->tet_row[sl])] = tet_ent_dev[e];
+            }
+        }
+        HIP_TRY(up(T->lay.ell, ell.data(), sizeof(PairEnt) * ell.size()));
+        HIP_TRY(up(T->lay.ell_info, T->ell_info.data(), sizeof(int2) * T->ell_info.size()));
+    }
     HIP_TRY(up(T->lay.spr_row, T->spr_row.data(), 4 * T->spr_row.size()));
     HIP_TRY(up(T->lay.spr_ent, spr.data(), sizeof(int2) * spr.size()));
     HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));
@@ -1090,7 +1120,7 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
         HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
         D.x = Sn;
         for (int c = 0; c < T->n_colors; ++c)
-            HIP_TRY(launch_solve(D, K, T->color_off[c], T->color_off[c + 1], true, false, T->cfg, s));
+            HIP_TRY(launch_solve(D, K, T->color_off[c], T->color_off[c + 1], T->ell_info[c], true, false, T->cfg, s));
     }
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
@@ -1200,7 +1230,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
         } else {
             for (int it = 0; it < sweeps; ++it)
                 for (int c = 0; c < T->n_colors; ++c)
-                    HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], tets, springs, cf, s));
+                    HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], T->ell_info[c], tets, springs, cf, s));
         }
         HIP_TRY(hipEventRecord(b, s));
         HIP_TRY(hipEventSynchronize(b));

@@ -56,8 +56,14 @@ struct DevTopo {
     TetRec *rec;                       // [n_tets] in tet_perm order
     const float *vol;                  // [n_tets] rest volume, tet_perm order
     const int *tet_perm;               // stored tet -> caller's tet index
-    const int *tet_row;                // CSR over all permuted vertices
+    const int *tet_row;                // CSR over all permuted vertices (adjoint)
     const PairEnt *tet_ent;            // (tet, slot, other vertices) per entry
+    // Color-solve incidence, per color c: every free vertex of the color owns
+    // ell_info[c].y consecutive entries starting at ell_info[c].x +
+    // (slot - color_off[c]) * ell_info[c].y, padded with x = -1, so the entry
+    // addresses follow from the slot alone.
+    const PairEnt *ell;
+    const int2 *ell_info;              // [n_colors] {first entry, padded degree}
     const int *spr_row;
     const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
     const int *perm;                   // permuted slot -> original id
@@ -112,14 +118,15 @@ hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConst
                            hipStream_t s);
 hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,
                           const StepConsts &K, bool reset_flags, hipStream_t s);
-hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end,
+// ell: {first entry, padded degree} of the color (DevTopo::ell_info).
+hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end, int2 ell,
                         bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
 // Color solve with mesh-mesh contact elements.  Updates T.x in place; contact
 // partners of the same color are read from S.xsnap (their positions before
 // the phase).  [prev_begin, prev_end): the previously solved color, whose
 // snapshot the kernel refreshes from T.x.
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K,
-                                 int v_begin, int v_end, int prev_begin, int prev_end,
+                                 int v_begin, int v_end, int2 ell, int prev_begin, int prev_end,
                                  bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
 // Detection on the permuted positions X (T.xt or T.x) into S.ctri and the
 // corner CSR (S.crow, S.cent).

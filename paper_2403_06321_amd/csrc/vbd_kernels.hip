@@ -135,20 +135,21 @@ __device__ __forceinline__ void slot_positions(int k, float4 own, float4 a, floa
     q3 = k < 3 ? c : own;
 }
 
-// Tet terms of one vertex: the lanes of the group take entries e0 + lane,
-// e0 + lane + L, ...; each lane issues the loads of KU entries level by level
-// (incidence entries, then records and neighbour positions together) so that
-// a vertex costs two dependent memory round trips per KU*L entries.
+// Tet terms of one vertex from its D consecutive incidence entries at E:
+// the lanes of the group take entries lane, lane + L, ...; each lane issues
+// the loads of KU entries level by level (incidence entries, then records and
+// neighbour positions together).  The entry addresses depend on the slot
+// only, so the first level is issued with the vertex's own state.
 template <int L, int KU>
-__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own, int e0,
-                                          int e1, int lane, float alpha, Acc &a)
+__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own,
+                                          const PairEnt *E, int D, int lane, float alpha, Acc &a)
 {
-    for (int base = e0 + lane; base < e1; base += L * KU) {
+    for (int base = lane; base < D; base += L * KU) {
         PairEnt ent[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j) {
             const int e = base + j * L;
-            ent[j] = (e < e1) ? T.tet_ent[e] : make_int4(-1, 0, 0, 0);
+            ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
         TetRec r[KU];
         float4 qa[KU], qb[KU], qc[KU];
@@ -230,9 +231,8 @@ __device__ __forceinline__ bool solve_sym3(const Acc &a, float eps_rel, float3 &
 // against analytic obstacles with a fixed normal (Eq. collisionEnergy) and
 // IPC-style friction with the approximate Hessian (Eq. IPC_friction).
 __device__ __forceinline__ bool vertex_terms(const DevTopo &T, const StepConsts &K, int p,
-                                             float3 xi, Acc &a)
+                                             float3 xi, float4 yv, Acc &a)
 {
-    const float4 yv = T.y[p];
     const float w = yv.w;   // m / h^2
     bool contact = false;
     float3 xt = make_float3(0.f, 0.f, 0.f);
@@ -367,19 +367,23 @@ __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &
 
 // One vertex update by a group of L lanes.  All lanes of the wave must call
 // this (inactive groups pass active = false) because of the DPP reduction.
-// MC: mesh-mesh contacts of a phase over slots [vb, ve).
+// The phase covers slots [vb, ve) of one color with incidence layout ell.
+// MC: mesh-mesh contacts.
 template <int L, int KU, bool TETS, bool SPRINGS, bool MC = false>
 __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
-                                             int lane, bool active, const DevSurf *S = nullptr,
-                                             int vb = 0, int ve = 0)
+                                             int lane, bool active, int vb, int ve, int2 ell,
+                                             const DevSurf *S = nullptr)
 {
     Acc a;
     acc_zero(a);
-    float4 xi4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 xi4 = make_float4(0.f, 0.f, 0.f, 0.f), yv = xi4;
     float nc = 0.f;
     if (active) {
         xi4 = T.x[p];
-        if (TETS) tet_terms<L, KU>(T, T.x, xi4, T.tet_row[p], T.tet_row[p + 1], lane, K.alpha, a);
+        yv = T.y[p];
+        if (TETS)
+            tet_terms<L, KU>(T, T.x, xi4, T.ell + ell.x + (size_t)(p - vb) * ell.y, ell.y, lane,
+                             K.alpha, a);
         if (SPRINGS) {
             const int e1 = T.spr_row[p + 1];
             for (int e = T.spr_row[p] + lane; e < e1; e += L)
@@ -395,7 +399,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     if (MC) nc = group_sum<L>(nc);
     if (!active) return;
     const float3 xi = xyz(xi4);
-    bool contact = vertex_terms(T, K, p, xi, a);
+    bool contact = vertex_terms(T, K, p, xi, yv, a);
     if (MC && K.kd_over_h != 0.f) {
         // damping on: the group's lanes are past the reduction, so lane 0
         // alone adds the contact elements to the reduced system
@@ -479,12 +483,12 @@ constexpr int kMaxBlock = 512;
 
 template <int L, int KU, bool TETS, bool SPRINGS>
 __global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, int v_begin,
-                                                     int v_end, int remap)
+                                                     int v_end, int2 ell, int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end);
+    solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin, v_end, ell);
 }
 
 // Color phase with mesh contacts.  The previously solved color's snapshot is
@@ -492,8 +496,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, in
 // snapshot is read.
 template <int L, int KU, bool TETS, bool SPRINGS>
 __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, StepConsts K,
-                                                        int v_begin, int v_end, int prev_begin,
-                                                        int prev_end, int remap)
+                                                        int v_begin, int v_end, int2 ell,
+                                                        int prev_begin, int prev_end, int remap)
 {
     for (int q = prev_begin + blockIdx.x * blockDim.x + threadIdx.x; q < prev_end;
          q += gridDim.x * blockDim.x)
@@ -501,8 +505,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, St
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, &S,
-                                             v_begin, v_end);
+    solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin,
+                                             v_end, ell, &S);
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -605,6 +609,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
     for (int it = 1; it <= n_iters; ++it) {
         for (int c = 0; c < T.n_colors; ++c) {
             const int vb = T.color_off[c], ve = T.color_off[c + 1];
+            const int2 ell = T.ell_info[c];
             // contiguous chunk of the color per logical block
             const int n = ve - vb;
             const int chunk = (n + nb - 1) / nb;
@@ -612,7 +617,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
             const int cend = min(cb + chunk, ve);
             for (int base = cb; base < cb + chunk; base += G) {
                 const int p = base + g;
-                solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, lane, p < cend);
+                solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, lane, p < cend, vb, ve, ell);
             }
             ++nbar;
             if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
@@ -838,88 +843,88 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
 }
 
 template <int L, int KU>
-static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
-                                 bool springs, const LaunchCfg &cfg, hipStream_t s)
+static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, int2 ell,
+                                 bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
     if (tets && springs)
-        hipLaunchKernelGGL((k_solve<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
     return hipGetLastError();
 }
 
 template <int L>
-static hipError_t solve_unroll(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
-                               bool springs, const LaunchCfg &cfg, hipStream_t s)
+static hipError_t solve_unroll(const DevTopo &T, const StepConsts &K, int vb, int ve, int2 ell,
+                               bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     switch (cfg.unroll) {
-    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, tets, springs, cfg, s);
-    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, tets, springs, cfg, s);
-    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, tets, springs, cfg, s);
+    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, ell, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, bool tets,
+hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, int2 ell, bool tets,
                         bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
-    case 4: return solve_unroll<4>(T, K, vb, ve, tets, springs, cfg, s);
-    case 8: return solve_unroll<8>(T, K, vb, ve, tets, springs, cfg, s);
-    case 16: return solve_unroll<16>(T, K, vb, ve, tets, springs, cfg, s);
-    case 32: return solve_unroll<32>(T, K, vb, ve, tets, springs, cfg, s);
+    case 4: return solve_unroll<4>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 8: return solve_unroll<8>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 16: return solve_unroll<16>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 32: return solve_unroll<32>(T, K, vb, ve, ell, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int L, int KU>
 static hipError_t solve_mc_dispatch(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                    int ve, int pb, int pe, bool tets, bool springs,
+                                    int ve, int2 ell, int pb, int pe, bool tets, bool springs,
                                     const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
     if (tets && springs)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
     return hipGetLastError();
 }
 
 template <int L>
 static hipError_t solve_mc_unroll(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                  int ve, int pb, int pe, bool tets, bool springs,
+                                  int ve, int2 ell, int pb, int pe, bool tets, bool springs,
                                   const LaunchCfg &cfg, hipStream_t s)
 {
     switch (cfg.unroll) {
-    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
-    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
-    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                 int ve, int pb, int pe, bool tets, bool springs,
+                                 int ve, int2 ell, int pb, int pe, bool tets, bool springs,
                                  const LaunchCfg &cfg, hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
-    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
-    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
-    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
-    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, pb, pe, tets, springs, cfg, s);
+    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
