@@ -158,10 +158,12 @@ __device__ __forceinline__ float grid_cell_size(const DevSurf &S, const StepCons
 }
 
 // ---------------------------------------------------------------- kernels --
-// Unit normals, bounding spheres and the largest centroid-to-corner
-// distance (reduced over the wave, then one atomic per wave).
+// Unit normals, bounding spheres, and per block the largest centroid-to-
+// corner distance (gmax[block]; k_max_radius reduces them, which avoids
+// serialising every block on one atomic).
 __global__ __launch_bounds__(256) void k_tri_prep(DevSurf S, const float4 *X)
 {
+    __shared__ float wmax[4];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     float R = 0.f;
     if (t < S.n_tri) {
@@ -178,8 +180,23 @@ __global__ __launch_bounds__(256) void k_tri_prep(DevSurf S, const float4 *X)
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) R = fmaxf(R, __shfl_xor(R, off, 64));
-    // non-negative floats order like their bit patterns
-    if ((threadIdx.x & 63) == 0) atomicMax(&S.gparam[0], __float_as_uint(R));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = R;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        S.gmax[blockIdx.x] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+}
+
+// One block: gparam[0] = float bits of the largest triangle radius.
+__global__ __launch_bounds__(256) void k_max_radius(DevSurf S, int nb)
+{
+    __shared__ float wmax[4];
+    float R = 0.f;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) R = fmaxf(R, S.gmax[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) R = fmaxf(R, __shfl_xor(R, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = R;
+    __syncthreads();
+    if (threadIdx.x == 0) S.gparam[0] = __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
 }
 
 // Angle-weighted pseudonormal of every surface vertex.
@@ -370,10 +387,11 @@ hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X, co
     if (S.n_tri == 0 || S.n_sv == 0) return hipSuccess;
     const int H = S.hmask + 1;
     hipError_t e;
-    if ((e = fill_u32(S.gparam, 4, 0u, s)) != hipSuccess) return e;
     if ((e = fill_u32(S.hcount, H, 0u, s)) != hipSuccess) return e;
     if ((e = fill_u32(S.ccount, T.n_verts, 0u, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tri_prep, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X);
+    const int nb_tri = cdiv(S.n_tri, 256);
+    hipLaunchKernelGGL(k_tri_prep, dim3(nb_tri), dim3(256), 0, s, S, X);
+    hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(256), 0, s, S, nb_tri);
     hipLaunchKernelGGL(k_vert_normals, dim3(cdiv(S.n_sv, 256)), dim3(256), 0, s, S, X);
     hipLaunchKernelGGL(k_grid_count, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X, K);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -51,7 +51,7 @@ struct Layout {
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib;
     // mesh-mesh contacts (only when the topology has a surface)
-    size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam;
+    size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam, s_gmax;
     size_t s_hcount, s_hstart, s_scan, s_hitems, s_tsph, s_ctri, s_ccount, s_crow, s_cent, s_xsnap;
     int hsize;
     size_t total;
@@ -182,6 +182,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.s_tnorm = take(sizeof(float4) * ntri);
         L.s_vnorm = take(sizeof(float4) * nsv);
         L.s_gparam = take(sizeof(uint32_t) * 4);
+        L.s_gmax = take(sizeof(float) * (ntri / 256 + 1));
         L.s_hcount = take(sizeof(uint32_t) * (size_t)H);
         L.s_hstart = take(sizeof(uint32_t) * ((size_t)H + 1));
         const size_t big = std::max<size_t>((size_t)H, nv + 1);
@@ -246,6 +247,7 @@ void set_dev_pointers(vbd_topology_s &T)
         S.tnorm = (float4 *)(b + L.s_tnorm);
         S.vnorm = (float4 *)(b + L.s_vnorm);
         S.gparam = (unsigned *)(b + L.s_gparam);
+        S.gmax = (float *)(b + L.s_gmax);
         S.hcount = (unsigned *)(b + L.s_hcount);
         S.hstart = (unsigned *)(b + L.s_hstart);
         S.scan_tmp = (unsigned *)(b + L.s_scan);

@@ -91,6 +91,7 @@ struct DevSurf {
     float4 *tnorm;         // [n_tri] unit normal
     float4 *vnorm;         // [n_sv] angle-weighted pseudonormal
     unsigned *gparam;      // [4] {max centroid radius bits, ...}
+    float *gmax;           // [ceil(n_tri / 256)] per-block maximum radius
     unsigned *hcount;      // [H] bucket sizes, then fill cursors
     unsigned *hstart;      // [H + 1]
     unsigned *scan_tmp;    // [n_scan_blocks + 1]
