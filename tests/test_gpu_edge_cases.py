@@ -1,0 +1,110 @@
+"""Edge cases of the GPU step against the FP64 oracle: empty and fully pinned
+topologies, the smallest mesh, a ragged batch (a single tet, isolated
+vertices, lattices of different shapes) and the determinant skip of Sec. 3.2
+taken by every vertex."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_06321_amd import workloads as W
+from gpu_util import assert_parity, gpu_rollout, oracle_rollout, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_empty_topology_step_is_a_no_op():
+    import torch
+    from paper_2403_06321_amd.api import Topology
+    t = Topology(np.zeros((0, 3)), np.zeros((0, 4), np.int32))
+    x = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    E = torch.zeros(0, dtype=torch.float32, device="cuda")
+    for mode in (0, 1, 2, 3):
+        t.step(x, x.clone(), x.clone(), E, W.StepParams(), mode)
+    torch.cuda.synchronize()
+    t.check()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_fully_pinned_mesh_stays_put(mode):
+    import torch
+    from paper_2403_06321_amd.api import Topology
+    w = W.tet_cube(4, 0)
+    w.pinned[:] = 1
+    t = Topology.from_workload(w)
+    x = torch.tensor(w.x0, dtype=torch.float32, device="cuda").contiguous()
+    v = torch.ones_like(x)
+    vp = torch.zeros_like(x)
+    E = torch.tensor(w.tet_E, dtype=torch.float32, device="cuda")
+    x0 = x.clone()
+    t.step(x, v, vp, E, w.params, mode)
+    torch.cuda.synchronize()
+    assert torch.equal(x, x0)
+    assert torch.count_nonzero(v).item() == 0
+    assert torch.equal(vp, torch.ones_like(x))
+
+
+def _single_tet():
+    rest = np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0], [0.0, 0.1, 0.0], [0.0, 0.0, 0.1]])
+    x0 = rest + np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0], [0.0, -0.005, 0.0], [0.0, 0.0, 0.02]])
+    return W.Workload(name="single tet", rest=rest, tets=np.array([[0, 1, 2, 3]], np.int32),
+                      pinned=np.array([1, 0, 0, 0], np.uint8), x0=x0, v0=np.zeros((4, 3)),
+                      tet_E=np.array([1e5]), params=W.StepParams(n_iters=30), frames=5)
+
+
+def test_single_tet_matches_oracle():
+    w = _single_tet()
+    xo, _ = oracle_rollout(w, w.frames)
+    for mode in (0, 3):
+        xg, _, _ = gpu_rollout(w, w.frames, launch_mode=mode)
+        assert_parity(w, xg, xo, label=f"single tet mode {mode}")
+
+
+def test_ragged_batch_matches_oracle():
+    """A single tet, five isolated vertices (inertia only), a 2x3x4 and a 5x2x3
+    lattice in one batch; masses given explicitly (isolated vertices have no
+    tets to lump from)."""
+    parts = []
+    st = _single_tet()
+    parts.append((st.rest, st.tets, st.pinned, st.x0))
+    iso = np.array([[1.0, 0.0, 0.0], [1.1, 0.0, 0.0], [1.2, 0.1, 0.0], [1.0, 0.3, 0.2], [1.4, 0.0, 0.1]])
+    parts.append((iso, np.zeros((0, 4), np.int32), np.zeros(5, np.uint8), iso.copy()))
+    rng = np.random.default_rng(12)
+    for dims, shift in (((2, 3, 4), 2.0), ((5, 2, 3), 3.0)):
+        r, t = W.cube_lattice(*dims)
+        r = r - r.min(0) + np.array([shift, 0.0, 0.0])
+        pin = (r[:, 2] == 0.0).astype(np.uint8)
+        x0 = r + rng.uniform(-1e-3, 1e-3, r.shape) * (pin[:, None] == 0)
+        parts.append((r, t, pin, x0))
+    rests, tets, pins, x0s, vo, to = [], [], [], [], [0], [0]
+    for r, t, pin, x0 in parts:
+        rests.append(r); tets.append(t + vo[-1]); pins.append(pin); x0s.append(x0)
+        vo.append(vo[-1] + r.shape[0]); to.append(to[-1] + t.shape[0])
+    rest = np.concatenate(rests)
+    tet = np.concatenate(tets).astype(np.int32)
+    vol = O.tet_rest(tet, rest)[1] if tet.shape[0] else np.zeros(0)
+    mass = O.lumped_mass(rest.shape[0], tet, vol, W.DENSITY)
+    mass[vo[1]:vo[2]] = rng.uniform(0.1, 1.0, 5)
+    w = W.Workload(name="ragged batch", rest=rest, tets=tet, pinned=np.concatenate(pins),
+                   x0=np.concatenate(x0s), v0=rng.normal(scale=0.1, size=rest.shape),
+                   tet_E=rng.uniform(1e4, 1e6, tet.shape[0]), mass=mass,
+                   vert_offsets=np.array(vo, np.int64), tet_offsets=np.array(to, np.int64),
+                   params=W.StepParams(n_iters=25), frames=4)
+    xo, _ = oracle_rollout(w, w.frames)
+    for mode in (0, 1, 3):
+        xg, _, _ = gpu_rollout(w, w.frames, launch_mode=mode)
+        assert_parity(w, xg, xo, label=f"ragged batch mode {mode}")
+
+
+def test_determinant_skip_everywhere():
+    """det_eps_rel so large that every local solve is skipped: each vertex
+    keeps its initial guess (adaptive), on both sides."""
+    w = W.tet_cube(5, 3, frames=2)
+    p = dataclasses.replace(w.params, det_eps_rel=1e30)
+    m = O.Model.from_workload(w)
+    xo, vo_, _, st = O.step(m, p, w.x0, w.v0, w.v0, w.tet_E)
+    assert st["n_skips"] == st["n_updates"] > 0
+    xg, _, _ = gpu_rollout(w, 1, params=p)
+    say(f"skip-all: max |x_gpu - x_oracle| = {np.abs(xg[0] - xo).max():.2e}")
+    assert np.allclose(xg[0], xo, rtol=0, atol=1e-6)
