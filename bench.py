@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--profile-only", default="",
-                    help="run only one workload for a profiler: cube|copy|stack")
+                    help="run only one workload for a profiler: cube|copy|stack|adjoint")
     ap.add_argument("--lanes", type=int, default=8, help="--profile-only: lanes per vertex")
     ap.add_argument("--block", type=int, default=128, help="--profile-only: block size")
     ap.add_argument("--remap", type=int, default=1, help="--profile-only: XCD remap")
@@ -161,6 +161,21 @@ def main():
         ts = Topology.from_workload(ws)
         secs, upd = time_frames(ts, ws, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
         print(json.dumps({"profile": "stack", "ms_per_frame": secs / args.steps * 1e3}))
+        return
+
+    if args.profile_only == "adjoint":
+        # forward + backward through the 33^3 differentiable workload
+        from paper_2403_06321_amd.api import Rollout
+        wd = W.config_differentiable()
+        td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
+        x0, v0, _, E = state(wd, dev)
+        v0.requires_grad_(True); E.requires_grad_(True)
+        target = torch.tensor(wd.target, dtype=torch.float32, device=dev)
+        for _ in range(args.steps):
+            xT, _ = Rollout.apply(x0, v0, E, td, wd.params, wd.frames)
+            ((xT.mean(0) - target) ** 2).sum().backward()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "adjoint"}))
         return
 
     # ---------------------------------------------------------- headline ----

@@ -196,7 +196,11 @@ vbd_status vbd_step(vbd_topology topo, const vbd_step_params *params, float *x, 
  * device float [n_verts][3].  Outputs gx_in, gv_in, gvp_in: adjoints of
  * (x^t, v^t, v^{t-1}) (overwritten); g_tet_E: device float [n_tets],
  * ACCUMULATED (+=).  The workspace must have been sized with
- * max_backward_iters >= params->n_iters. */
+ * max_backward_iters >= params->n_iters.  launch_mode GRAPH or
+ * PERSISTENT_GRAPH: the launch sequence is captured into a hipGraph and
+ * replayed while the pointers, parameters and stream stay the same (callers
+ * that keep their buffers fixed pay the launch cost once); PLAIN or
+ * PERSISTENT: plain launches. */
 vbd_status vbd_step_backward(vbd_topology topo, const vbd_step_params *params,
                              const float *x_t, const float *v_t, const float *v_prev,
                              const float *tet_E, const float *gx_out, const float *gv_out,

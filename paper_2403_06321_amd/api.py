@@ -167,12 +167,13 @@ class Topology:
                                  _t_ptr(tet_E) if self.n_tets else None, _stream_handle(stream)))
 
     def step_backward(self, x_t, v_t, v_prev, tet_E, gx_out, gv_out, gvp_out, gx_in, gv_in,
-                      gvp_in, g_tet_E, params: StepParams, stream=None):
+                      gvp_in, g_tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
+                      stream=None):
         for t, name in ((x_t, "x_t"), (v_t, "v_t"), (v_prev, "v_prev"), (gx_out, "gx_out"),
                         (gv_out, "gv_out"), (gvp_out, "gvp_out"), (gx_in, "gx_in"),
                         (gv_in, "gv_in"), (gvp_in, "gvp_in")):
             _check_state(t, self.n_verts, name)
-        ps, keep = params_struct(params, N.LAUNCH_PLAIN)
+        ps, keep = params_struct(params, launch_mode)
         N.check(N.lib().vbd_step_backward(self._h, C.byref(ps), _t_ptr(x_t), _t_ptr(v_t),
                                           _t_ptr(v_prev), _t_ptr(tet_E), _t_ptr(gx_out),
                                           _t_ptr(gv_out), _t_ptr(gvp_out), _t_ptr(gx_in),
@@ -233,7 +234,8 @@ class Rollout(torch.autograd.Function):
     each frame's iterates and runs the hand-written adjoint kernels.
 
     apply(x0, v0, tet_E, topo, params, frames) -> (x_T, v_T); the state
-    before frame 0 has v^{-1} = v^0.
+    before frame 0 has v^{-1} = v^0.  Both directions work on fixed buffers
+    so that one captured hipGraph per direction is replayed for every frame.
     """
 
     @staticmethod
@@ -245,7 +247,7 @@ class Rollout(torch.autograd.Function):
         states = []
         for _ in range(frames):
             states.append((x.clone(), v.clone(), vp.clone()))
-            topo.step(x, v, vp, E, params)
+            topo.step(x, v, vp, E, params, N.LAUNCH_GRAPH)
         ctx.topo, ctx.params, ctx.states = topo, params, states
         ctx.save_for_backward(E)
         return x, v
@@ -255,12 +257,16 @@ class Rollout(torch.autograd.Function):
         (E,) = ctx.saved_tensors
         topo, params = ctx.topo, ctx.params
         ref = ctx.states[0][0]
-        gx = torch.zeros_like(ref) if gx is None else gx.contiguous().float()
-        gv = torch.zeros_like(ref) if gv is None else gv.contiguous().float()
-        gvp = torch.zeros_like(ref)
+        g_out = [torch.zeros_like(ref) if g is None else g.contiguous().float().clone()
+                 for g in (gx, gv)] + [torch.zeros_like(ref)]
+        g_in = [torch.empty_like(ref) for _ in range(3)]
+        stage = [torch.empty_like(ref) for _ in range(3)]
         gE = torch.zeros_like(E)
-        for (xt, vt, vpt) in reversed(ctx.states):
-            gx_in, gv_in, gvp_in = torch.empty_like(ref), torch.empty_like(ref), torch.empty_like(ref)
-            topo.step_backward(xt, vt, vpt, E, gx, gv, gvp, gx_in, gv_in, gvp_in, gE, params)
-            gx, gv, gvp = gx_in, gv_in, gvp_in
-        return gx, gv + gvp, gE, None, None, None
+        for state in reversed(ctx.states):
+            for dst, src in zip(stage, state):
+                dst.copy_(src)
+            topo.step_backward(*stage, E, *g_out, *g_in, gE, params, N.LAUNCH_GRAPH)
+            for dst, src in zip(g_out, g_in):
+                dst.copy_(src)
+        gx0, gv0, gvp0 = g_out
+        return gx0, gv0 + gvp0, gE, None, None, None

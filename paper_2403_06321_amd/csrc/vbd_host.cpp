@@ -49,7 +49,7 @@ inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t rec, vol, tet_perm, tet_row, tet_ent, ell, ell_info, spr_row, spr_ent, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
-    size_t snaps, xbar, ybar, xtbar, vbar, contrib;
+    size_t snaps, xbar, ybar, xtbar, vbar, contrib, ebar;
     // mesh-mesh contacts (only when the topology has a surface)
     size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam, s_gmax;
     size_t s_hcount, s_hstart, s_scan, s_hitems, s_tsph, s_ctri, s_ccount, s_crow, s_cent, s_xsnap;
@@ -59,12 +59,29 @@ struct Layout {
 };
 
 struct GraphKey {
-    const void *x, *v, *vp, *E;
+    std::vector<const void *> ptrs;
     void *stream;
     std::vector<uint32_t> params;
     bool operator==(const GraphKey &o) const
     {
-        return x == o.x && v == o.v && vp == o.vp && E == o.E && stream == o.stream && params == o.params;
+        return ptrs == o.ptrs && stream == o.stream && params == o.params;
+    }
+};
+
+// One captured launch sequence, replayed while its key (device pointers,
+// parameters, stream) is unchanged.
+struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphKey key{};
+    bool have = false;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        have = false;
     }
 };
 
@@ -112,20 +129,17 @@ struct vbd_topology_s {
     int n_cu = 0;
     std::string arch;
     LaunchCfg cfg{8, 128, 1, 0, 2};
-    // graph cache
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // graph caches of vbd_step and vbd_step_backward
     hipStream_t cap_stream = nullptr;   // library-owned stream used only for capture
-    GraphKey gkey{};
-    bool have_graph = false;
+    GraphCache fwd_graph, bwd_graph;
     // profiling
     bool profiling = false;
     std::vector<ProfileEvent> events;
     vbd_profile_stats acc{};
     ~vbd_topology_s()
     {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
+        fwd_graph.reset();
+        bwd_graph.reset();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (auto &e : events) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     }
@@ -167,6 +181,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.xtbar = take(sizeof(float4) * nv);
         L.vbar = take(sizeof(float4) * nv);
         L.contrib = take(sizeof(float4) * 4 * (size_t)T.nt);
+        L.ebar = take(sizeof(float) * (size_t)T.nt);
     }
     const size_t ntri = T.surf.size() / 3, nsv = T.sv_slot.size();
     if (ntri > 0) {
@@ -229,6 +244,7 @@ void set_dev_pointers(vbd_topology_s &T)
     D.xtbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xtbar) : nullptr;
     D.vbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.vbar) : nullptr;
     D.contrib = L.max_bwd_iters > 0 ? (float4 *)(b + L.contrib) : nullptr;
+    D.ebar = L.max_bwd_iters > 0 ? (float *)(b + L.ebar) : nullptr;
     D.n_verts = T.nv;
     D.n_tets = T.nt;
     D.n_free = T.n_free;
@@ -692,11 +708,11 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
     return VBD_OK;
 }
 
-GraphKey make_key(const vbd_step_params *p, const void *x, const void *v, const void *vp,
-                  const void *E, void *stream)
+GraphKey make_key(const vbd_step_params *p, std::vector<const void *> ptrs, void *stream)
 {
     GraphKey k;
-    k.x = x; k.v = v; k.vp = vp; k.E = E; k.stream = stream;
+    k.ptrs = std::move(ptrs);
+    k.stream = stream;
     auto push = [&](const void *src, size_t n) {
         const uint32_t *w = (const uint32_t *)src;
         for (size_t i = 0; i < n / 4; ++i) k.params.push_back(w[i]);
@@ -710,6 +726,71 @@ GraphKey make_key(const vbd_step_params *p, const void *x, const void *v, const 
     push(&p->launch_mode, 4);
     push(&p->mesh_contacts, 4); push(&p->collision_radius, 4); push(&p->n_col, 4);
     return k;
+}
+
+// Replays C's graph when its key matches, else captures `enqueue` on the
+// library-owned capture stream (the caller's may be the null stream, which
+// cannot be captured) and replays that; the graph is launched on `s`.
+template <class F>
+vbd_status run_graph(vbd_topology_s &T, GraphCache &C, GraphKey key, hipStream_t s, F enqueue)
+{
+    if (!C.have || !(key == C.key)) {
+        C.reset();
+        if (!T.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&T.cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(T.cap_stream, hipStreamCaptureModeThreadLocal));
+        vbd_status cs = enqueue(T.cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(T.cap_stream, &g);
+        if (cs != VBD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ce != hipSuccess) return fail(VBD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+        HIP_TRY(hipGraphInstantiate(&C.exec, g, nullptr, nullptr, 0));
+        C.graph = g;
+        C.key = std::move(key);
+        C.have = true;
+    }
+    HIP_TRY(hipGraphLaunch(C.exec, s));
+    return VBD_OK;
+}
+
+// Backward of one step: forward recompute with an iterate snapshot per
+// iteration, then the reverse color sweeps, the fold of the pending cells and
+// the adjoints of the initial guess and of y.
+vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
+                            const float *x_t, const float *v_t, const float *v_prev, const float *E,
+                            const float *gx_out, const float *gv_out, const float *gvp_out,
+                            float *gx_in, float *gv_in, float *gvp_in, float *g_E, hipStream_t s)
+{
+    const size_t nv = (size_t)T.nv;
+    // forward recompute, snapshot n = iterate after iteration n
+    DevTopo D = T.dev;
+    D.x = D.snaps;
+    HIP_TRY(launch_material(D, E, K, s));
+    HIP_TRY(launch_predict(D, x_t, v_t, v_prev, K, false, s));
+    for (int it = 1; it <= p->n_iters; ++it) {
+        float4 *Sn = T.dev.snaps + nv * it;
+        HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
+        D.x = Sn;
+        for (int c = 0; c < T.n_colors; ++c)
+            HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], T.ell_info[c], true, false, T.cfg, s));
+    }
+    // reverse sweep
+    HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
+    if (T.nt > 0) {
+        HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 16 * T.nt, s));
+        HIP_TRY(launch_zero_u32((unsigned *)D.ebar, T.nt, s));
+    }
+    for (int it = p->n_iters; it >= 1; --it) {
+        const float4 *Sn = T.dev.snaps + nv * it, *Sp = Sn - nv;
+        for (int c = T.n_colors - 1; c >= 0; --c)
+            HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T.color_off[c], T.color_off[c + 1], T.ell_info[c],
+                                         T.cfg, s));
+    }
+    HIP_TRY(launch_bwd_fold(D, s));
+    HIP_TRY(launch_bwd_final(D, v_t, v_prev, gx_in, gv_in, gvp_in, g_E, K, s));
+    return VBD_OK;
 }
 
 // autotune cache: (arch, log2 size buckets, kinds, persistent) -> config
@@ -984,11 +1065,8 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(launch_zero_u32(T->dev.flags, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
     T->bound = true;
-    if (T->have_graph) {
-        (void)hipGraphExecDestroy(T->gexec);
-        (void)hipGraphDestroy(T->graph);
-        T->gexec = nullptr; T->graph = nullptr; T->have_graph = false;
-    }
+    T->fwd_graph.reset();
+    T->bwd_graph.reset();
     return VBD_OK;
 }
 
@@ -1063,32 +1141,9 @@ vbd_status vbd_step(vbd_topology T, const vbd_step_params *p, float *x, float *v
     if (mode == VBD_LAUNCH_PLAIN || mode == VBD_LAUNCH_PERSISTENT || T->profiling)
         return enqueue_step(*T, p, K, x, v, vp, E, s, persistent, false);
     // graph modes: capture once per (pointers, parameters, stream), replay after
-    GraphKey key = make_key(p, x, v, vp, E, stream);
-    if (!T->have_graph || !(key == T->gkey)) {
-        if (T->have_graph) {
-            (void)hipGraphExecDestroy(T->gexec);
-            (void)hipGraphDestroy(T->graph);
-            T->have_graph = false;
-        }
-        // capture on a library-owned stream (the caller's may be the null
-        // stream, which cannot be captured); the graph is launched on `s`
-        if (!T->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&T->cap_stream, hipStreamNonBlocking));
-        HIP_TRY(hipStreamBeginCapture(T->cap_stream, hipStreamCaptureModeThreadLocal));
-        vbd_status cs = enqueue_step(*T, p, K, x, v, vp, E, T->cap_stream, persistent, true);
-        hipGraph_t g = nullptr;
-        hipError_t ce = hipStreamEndCapture(T->cap_stream, &g);
-        if (cs != VBD_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return cs;
-        }
-        if (ce != hipSuccess) return fail(VBD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
-        HIP_TRY(hipGraphInstantiate(&T->gexec, g, nullptr, nullptr, 0));
-        T->graph = g;
-        T->gkey = key;
-        T->have_graph = true;
-    }
-    HIP_TRY(hipGraphLaunch(T->gexec, s));
-    return VBD_OK;
+    return run_graph(*T, T->fwd_graph, make_key(p, {x, v, vp, E}, stream), s, [&](hipStream_t cs) {
+        return enqueue_step(*T, p, K, x, v, vp, E, cs, persistent, true);
+    });
 }
 
 vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const float *x_t,
@@ -1111,31 +1166,16 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
         return fail(VBD_E_INVALID_ARG, "NULL array");
     const StepConsts K = make_consts(*T, p);
     hipStream_t s = (hipStream_t)stream;
-    const size_t nv = (size_t)T->nv;
-    // forward recompute, snapshot n = iterate after iteration n
-    DevTopo D = T->dev;
-    D.x = D.snaps;
-    HIP_TRY(launch_material(D, E, K, s));
-    HIP_TRY(launch_predict(D, x_t, v_t, v_prev, K, false, s));
-    for (int it = 1; it <= p->n_iters; ++it) {
-        float4 *Sn = T->dev.snaps + nv * it;
-        HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
-        D.x = Sn;
-        for (int c = 0; c < T->n_colors; ++c)
-            HIP_TRY(launch_solve(D, K, T->color_off[c], T->color_off[c + 1], T->ell_info[c], true, false, T->cfg, s));
-    }
-    // reverse sweep
-    HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
-    if (T->nt > 0) HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 16 * T->nt, s));
-    for (int it = p->n_iters; it >= 1; --it) {
-        const float4 *Sn = T->dev.snaps + nv * it, *Sp = Sn - nv;
-        for (int c = T->n_colors - 1; c >= 0; --c)
-            HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T->color_off[c], T->color_off[c + 1], g_E,
-                                         T->cfg, s));
-    }
-    HIP_TRY(launch_bwd_fold(D, s));
-    HIP_TRY(launch_bwd_final(D, v_t, v_prev, gx_in, gv_in, gvp_in, K, s));
-    return VBD_OK;
+    auto enqueue = [&](hipStream_t q) {
+        return enqueue_backward(*T, p, K, x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in,
+                                gvp_in, g_E, q);
+    };
+    if (p->launch_mode == VBD_LAUNCH_PLAIN || p->launch_mode == VBD_LAUNCH_PERSISTENT || T->profiling)
+        return enqueue(s);
+    return run_graph(*T, T->bwd_graph,
+                     make_key(p, {x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in, gvp_in, g_E},
+                              stream),
+                     s, enqueue);
 }
 
 vbd_status vbd_detect_contacts(vbd_topology T, const vbd_step_params *p, const float *x,
@@ -1176,11 +1216,8 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
     if (c->blocks_per_cu < 0) return fail(VBD_E_INVALID_ARG, "blocks_per_cu < 0");
     if (c->tet_unroll < 1 || c->tet_unroll > 3) return fail(VBD_E_INVALID_ARG, "tet_unroll must be 1, 2 or 3");
     T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu, c->tet_unroll};
-    if (T->have_graph) {
-        (void)hipGraphExecDestroy(T->gexec);
-        (void)hipGraphDestroy(T->graph);
-        T->gexec = nullptr; T->graph = nullptr; T->have_graph = false;
-    }
+    T->fwd_graph.reset();
+    T->bwd_graph.reset();
     return VBD_OK;
 }
 
@@ -1254,11 +1291,8 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     T->cfg = best_cfg;
-    if (T->have_graph) {
-        (void)hipGraphExecDestroy(T->gexec);
-        (void)hipGraphDestroy(T->graph);
-        T->gexec = nullptr; T->graph = nullptr; T->have_graph = false;
-    }
+    T->fwd_graph.reset();
+    T->bwd_graph.reset();
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = best_cfg;
     return VBD_OK;

@@ -76,6 +76,7 @@ struct DevTopo {
     float4 *snaps;                     // backward: (n_iters + 1) iterates
     float4 *xbar, *ybar, *xtbar, *vbar;
     float4 *contrib;                   // backward: [n_tets][4] pending neighbour adjoints
+    float *ebar;                       // backward: [n_tets] Ebar of this step, stored order
     int n_verts, n_tets, n_free, n_colors;
 };
 
@@ -153,11 +154,12 @@ hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s);
 hipError_t launch_bwd_init(const DevTopo &T, const float *gx_out, const float *gv_out,
                            const float *gvp_out, const StepConsts &K, hipStream_t s);
 hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const float4 *Sn,
-                                const float4 *Sp, int v_begin, int v_end, float *g_tet_E,
+                                const float4 *Sp, int v_begin, int v_end, int2 ell,
                                 const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s);
+// Also adds T.ebar into g_tet_E (caller's tet order).
 hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev,
-                            float *gx_in, float *gv_in, float *gvp_in, const StepConsts &K,
-                            hipStream_t s);
+                            float *gx_in, float *gv_in, float *gvp_in, float *g_tet_E,
+                            const StepConsts &K, hipStream_t s);
 
 }  // namespace vbd

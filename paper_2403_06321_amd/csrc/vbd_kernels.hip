@@ -681,10 +681,21 @@ __global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const fl
 // its cells are written by one thread only (no atomics, deterministic).  A
 // vertex folds (reads and clears) its own cells when its color is processed,
 // and k_bwd_fold folds what is left at the end of the sweep.
-template <int L>
+// Position of a neighbour q in the state right after the update of the
+// phase's vertex: colors <= c (slots < c_end) from iteration n, the others
+// from iteration n - 1.
+__device__ __forceinline__ float4 adj_pos(const float4 *Sn, const float4 *Sp, int q, int c_end)
+{
+    return (q < c_end ? Sn : Sp)[q];
+}
+
+// The entries come from the same per-color padded incidence as the forward
+// solve; each lane handles KU entries at a time with their loads issued
+// together (records, neighbour positions and contribution cells).
+template <int L, int KU>
 __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K,
                                                              const float4 *Sn, const float4 *Sp,
-                                                             int v_begin, int v_end, float *gE,
+                                                             int v_begin, int v_end, int2 ell,
                                                              int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
@@ -693,39 +704,57 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
     const int lane = threadIdx.x & (L - 1);
     const bool active = p < v_end;
     const int c_end = v_end;   // permuted slots < c_end have color <= c
+    const int D = active ? ell.y : 0;
+    const PairEnt *E = T.ell + ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
     Acc a;
     acc_zero(a);
-    int e0 = 0, e1 = 0;
+    float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
+    float wm = 0.f;
     if (active) {
-        e0 = T.tet_row[p];
-        e1 = T.tet_row[p + 1];
-        const float4 own = Sn[p];
-        for (int e = e0 + lane; e < e1; e += L) {
-            const PairEnt ent = T.tet_ent[e];
-            const int t = ent.x >> 2, k = ent.x & 3;
-            const TetRec r = T.rec[t];
-            float4 q0, q1, q2, q3;
-            slot_positions(k, own, (ent.y < c_end ? Sn : Sp)[ent.y], (ent.z < c_end ? Sn : Sp)[ent.z],
-                           (ent.w < c_end ? Sn : Sp)[ent.w], q0, q1, q2, q3);
-            TetLocal Lc;
-            tet_local(r, q0, q1, q2, q3, Lc);
-            const float3 mk = shape_grad(Lc, k);
-            const float3 cm = Cmul(Lc, mk);
-            const float Vmu = r.b.z, Vlam = r.b.w;
-            const float d = Vmu * dot3(mk, mk);
-            a.hxx += d + Vlam * cm.x * cm.x; a.hxy += Vlam * cm.x * cm.y; a.hxz += Vlam * cm.x * cm.z;
-            a.hyy += d + Vlam * cm.y * cm.y; a.hyz += Vlam * cm.y * cm.z; a.hzz += d + Vlam * cm.z * cm.z;
-            float4 *cell = T.contrib + 4 * (size_t)t + k;
-            const float4 g = *cell;
-            a.fx += g.x; a.fy += g.y; a.fz += g.z;
-            *cell = make_float4(0.f, 0.f, 0.f, 0.f);
+        own = Sn[p];
+        xb4 = T.xbar[p];
+        wm = T.y[p].w;
+    }
+    // pass 1: H_i at the post-update state, and this vertex's pending cells
+    for (int base = lane; base < D; base += L * KU) {
+        PairEnt ent[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j) {
+            const int e = base + j * L;
+            ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
+        TetRec r[KU];
+        float4 qa[KU], qb[KU], qc[KU], g[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j].x >= 0) {
+                r[j] = T.rec[ent[j].x >> 2];
+                qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
+                qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
+                qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
+                g[j] = T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)];
+            }
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j].x >= 0) {
+                const int t = ent[j].x >> 2, k = ent[j].x & 3;
+                float4 q0, q1, q2, q3;
+                slot_positions(k, own, qa[j], qb[j], qc[j], q0, q1, q2, q3);
+                TetLocal Lc;
+                tet_local(r[j], q0, q1, q2, q3, Lc);
+                const float3 mk = shape_grad(Lc, k);
+                const float3 cm = Cmul(Lc, mk);
+                const float Vmu = r[j].b.z, Vlam = r[j].b.w;
+                const float d = Vmu * dot3(mk, mk);
+                a.hxx += d + Vlam * cm.x * cm.x; a.hxy += Vlam * cm.x * cm.y; a.hxz += Vlam * cm.x * cm.z;
+                a.hyy += d + Vlam * cm.y * cm.y; a.hyz += Vlam * cm.y * cm.z; a.hzz += d + Vlam * cm.z * cm.z;
+                a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
+                T.contrib[4 * (size_t)t + k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
     }
     acc_reduce<L>(a);
     if (!active) return;
-    const float wm = T.y[p].w;
     a.hxx += wm; a.hyy += wm; a.hzz += wm;
-    const float4 xb4 = T.xbar[p];
     a.fx += xb4.x; a.fy += xb4.y; a.fz += xb4.z;
     float3 w;
     if (!solve_sym3(a, K.det_eps_rel, w)) {
@@ -739,39 +768,68 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
         T.ybar[p] = yb;
     }
-    const float4 own = Sn[p];
-    for (int e = e0 + lane; e < e1; e += L) {
-        const PairEnt ent = T.tet_ent[e];
-        const int t = ent.x >> 2, k = ent.x & 3;
-        const TetRec r = T.rec[t];
-        float4 q0, q1, q2, q3;
-        slot_positions(k, own, (ent.y < c_end ? Sn : Sp)[ent.y], (ent.z < c_end ? Sn : Sp)[ent.z],
-                       (ent.w < c_end ? Sn : Sp)[ent.w], q0, q1, q2, q3);
-        TetLocal Lc;
-        tet_local(r, q0, q1, q2, q3, Lc);
-        const float3 mk = shape_grad(Lc, k);
-        const float3 ck = Cmul(Lc, mk);
-        const float cw = dot3(ck, w);
-        const float Vmu = r.b.z, Vlam = r.b.w;
-        const float s = Vlam * (Lc.J - K.alpha);
+    // pass 2: -K_kq^T w into the cells of the other three slots, and Ebar
+    // (in stored tet order; k_bwd_final scatters it to the caller's order).
+    // All loads of KU entries, their cells included, are issued before the
+    // stores, which would otherwise order every cell's read after the
+    // previous cell's write.
+    for (int base = lane; base < D; base += L * KU) {
+        PairEnt ent[KU];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q == k) continue;
-            const float3 mq = shape_grad(Lc, q);
-            const float3 cq = Cmul(Lc, mq);
-            const float3 u = Fmul(Lc, cross3(mk, mq));
-            const float3 uw = cross3(u, w);
-            const float mm = Vmu * dot3(mk, mq);
-            float4 *cell = T.contrib + 4 * (size_t)t + q;
-            float4 g = *cell;
-            g.x -= mm * w.x + Vlam * cw * cq.x + s * uw.x;
-            g.y -= mm * w.y + Vlam * cw * cq.y + s * uw.y;
-            g.z -= mm * w.z + Vlam * cw * cq.z + s * uw.z;
-            *cell = g;
+        for (int j = 0; j < KU; ++j) {
+            const int e = base + j * L;
+            ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
-        const float3 Fm = Fmul(Lc, mk);
-        const float V = T.vol[t];
-        gE[T.tet_perm[t]] -= V * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
+        TetRec r[KU];
+        float4 qa[KU], qb[KU], qc[KU], c0[KU], c1[KU], c2[KU];
+        float vol[KU], eb[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j].x >= 0) {
+                const int t = ent[j].x >> 2, k = ent[j].x & 3;
+                r[j] = T.rec[t];
+                qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
+                qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
+                qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
+                vol[j] = T.vol[t];
+                eb[j] = T.ebar[t];
+                // the cells of the other slots in ascending slot order
+                const float4 *cell = T.contrib + 4 * (size_t)t;
+                c0[j] = cell[k == 0 ? 1 : 0];
+                c1[j] = cell[k <= 1 ? 2 : 1];
+                c2[j] = cell[k <= 2 ? 3 : 2];
+            }
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ent[j].x >= 0) {
+                const int t = ent[j].x >> 2, k = ent[j].x & 3;
+                float4 q0, q1, q2, q3;
+                slot_positions(k, own, qa[j], qb[j], qc[j], q0, q1, q2, q3);
+                TetLocal Lc;
+                tet_local(r[j], q0, q1, q2, q3, Lc);
+                const float3 mk = shape_grad(Lc, k);
+                const float3 ck = Cmul(Lc, mk);
+                const float cw = dot3(ck, w);
+                const float Vmu = r[j].b.z, Vlam = r[j].b.w;
+                const float s = Vlam * (Lc.J - K.alpha);
+                float4 *cell = T.contrib + 4 * (size_t)t;
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    const int q = o + (o >= k ? 1 : 0);
+                    const float3 mq = shape_grad(Lc, q);
+                    const float3 cq = Cmul(Lc, mq);
+                    const float3 u = Fmul(Lc, cross3(mk, mq));
+                    const float3 uw = cross3(u, w);
+                    const float mm = Vmu * dot3(mk, mq);
+                    float4 gq = o == 0 ? c0[j] : (o == 1 ? c1[j] : c2[j]);
+                    gq.x -= mm * w.x + Vlam * cw * cq.x + s * uw.x;
+                    gq.y -= mm * w.y + Vlam * cw * cq.y + s * uw.y;
+                    gq.z -= mm * w.z + Vlam * cw * cq.z + s * uw.z;
+                    cell[q] = gq;
+                }
+                const float3 Fm = Fmul(Lc, mk);
+                T.ebar[t] = eb[j] - vol[j] * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
+            }
     }
 }
 
@@ -792,9 +850,11 @@ __global__ void k_bwd_fold(DevTopo T)
 
 // Adjoint of the initial guess (Sec. 3.7) and of y, written in original order.
 __global__ void k_bwd_final(DevTopo T, const float *v_t, const float *v_prev, float *gx_in,
-                            float *gv_in, float *gvp_in, StepConsts K)
+                            float *gv_in, float *gvp_in, float *gE, StepConsts K)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // Ebar, accumulated in stored tet order, added into the caller's order
+    for (int t = p; t < T.n_tets; t += gridDim.x * blockDim.x) gE[T.tet_perm[t]] += T.ebar[t];
     if (p >= T.n_verts) return;
     const int o = T.perm[p];
     const float3 xb = xyz(T.xbar[p]);
@@ -1034,17 +1094,29 @@ hipError_t launch_bwd_init(const DevTopo &T, const float *gx, const float *gv, c
     return hipGetLastError();
 }
 
+template <int L>
+static void adjoint_go(const DevTopo &T, const StepConsts &K, const float4 *Sn, const float4 *Sp,
+                       int vb, int ve, int2 ell, const LaunchCfg &cfg, hipStream_t s)
+{
+    const int grid = cdiv((long)(ve - vb) * L, cfg.block);
+    if (cfg.unroll >= 2)
+        hipLaunchKernelGGL((k_adjoint_color<L, 2>), dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, ell, cfg.xcd_remap);
+    else
+        hipLaunchKernelGGL((k_adjoint_color<L, 1>), dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, ell, cfg.xcd_remap);
+}
+
 hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const float4 *Sn,
-                                const float4 *Sp, int vb, int ve, float *gE, const LaunchCfg &cfg,
+                                const float4 *Sp, int vb, int ve, int2 ell, const LaunchCfg &cfg,
                                 hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
-    const int grid = cdiv((long)(ve - vb) * cfg.lanes, cfg.block);
+    // at least 16 lanes per vertex: a phase has few vertices on small meshes
+    // and the reverse work per vertex is about three times the forward's
     switch (cfg.lanes) {
-    case 4: hipLaunchKernelGGL(k_adjoint_color<4>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
-    case 8: hipLaunchKernelGGL(k_adjoint_color<8>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
-    case 16: hipLaunchKernelGGL(k_adjoint_color<16>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
-    case 32: hipLaunchKernelGGL(k_adjoint_color<32>, dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, gE, cfg.xcd_remap); break;
+    case 4:
+    case 8:
+    case 16: adjoint_go<16>(T, K, Sn, Sp, vb, ve, ell, cfg, s); break;
+    case 32: adjoint_go<32>(T, K, Sn, Sp, vb, ve, ell, cfg, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1057,10 +1129,10 @@ hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s)
 }
 
 hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev, float *gx_in,
-                            float *gv_in, float *gvp_in, const StepConsts &K, hipStream_t s)
+                            float *gv_in, float *gvp_in, float *gE, const StepConsts &K, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bwd_final, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T, v_t, v_prev,
-                       gx_in, gv_in, gvp_in, K);
+                       gx_in, gv_in, gvp_in, gE, K);
     return hipGetLastError();
 }
 
