@@ -179,7 +179,7 @@ def main():
         return
 
     # ---------------------------------------------------------- headline ----
-    w = W.config_large_cube()
+    w = W.config_large_cube(coloring="smallest_last")
     log(f"[bench] building topology: {w.name}, {w.n_verts} verts, {w.n_tets} tets")
     t0 = time.perf_counter()
     topo = Topology.from_workload(w)
@@ -227,7 +227,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "tet cube 65x65x65 vertices (274,625 verts, 1,572,864 tets), "
                                "per-tet E log-uniform [1e4,1e6] Pa, nu 0.3, h 1/60 s, 100 iterations x "
-                               "frames, 8 greedy colors, bottom face pinned",
+                               "frames, greedy vertex coloring (first fit in smallest-last order, "
+                               f"{topo.n_colors} colors), bottom face pinned",
                    "launch_mode": best, "launch_config": topo.launch_config,
                    "free_vertices": int((w.pinned == 0).sum()), "iterations": w.params.n_iters},
         "roofline": {"bound": "hbm", "achieved": roof["achieved_gbs"], "peak": HBM_PEAK_GBS,
@@ -240,6 +241,25 @@ def main():
     torch.cuda.empty_cache()
 
     extra = {"cube_modes": per_mode}
+    if not args.no_extras:
+        # the same cube and iterations with other colorings: greedy first fit in
+        # vertex-id order (8 colors) and the caller-supplied lattice coloring
+        for name, coloring in (("cube_greedy_id_order", "id"), ("cube_lattice_4_colors", "lattice4")):
+            w4 = W.config_large_cube(coloring=coloring)
+            t4 = Topology.from_workload(w4)
+            n = min(args.steps, 20)
+            secs, upd = time_frames(t4, w4, MODES["graph"], n, args.warmup, dev)
+            r4 = kernel_roofline(t4, w4, dev)
+            extra[name] = dict(updates_per_s=upd * n / secs, ms_per_frame=secs / n * 1e3,
+                               colors=t4.n_colors, config=t4.launch_config,
+                               solve_kernel=dict(avg_launch_us=r4["avg_ms"] * 1e3,
+                                                 achieved_gbs=r4["achieved_gbs"],
+                                                 frac=r4["achieved_gbs"] / HBM_PEAK_GBS))
+            log(f"[bench] 65^3, {coloring} coloring ({t4.n_colors} colors): "
+                f"{extra[name]['updates_per_s']:.3e} v-upd/s, {r4['avg_ms'] * 1e3:.1f} us/launch, "
+                f"{r4['achieved_gbs']:.0f} GB/s")
+            del t4
+            torch.cuda.empty_cache()
     if not args.no_extras:
         # copy probe: achievable streaming bandwidth
         n = 1 << 28
@@ -257,7 +277,7 @@ def main():
     out["extra"] = extra
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(W.config_large_cube(), args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(W.config_large_cube(coloring="smallest_last"), args.cpu_iters)
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} v-upd/s ({out['cpu_baseline']['sample']})")
     print(json.dumps(out))
 

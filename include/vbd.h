@@ -95,6 +95,28 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *desc, vbd_topology *out);
  * colors_out: host [n_verts] or NULL. */
 vbd_status vbd_color(vbd_topology topo, int32_t *n_colors_out, int32_t *colors_out);
 
+/* Vertex orders of the greedy first-fit coloring (vbd_color_greedy). */
+enum { VBD_COLOR_ID_ORDER = 0,      /* ascending vertex id (what vbd_color uses) */
+       VBD_COLOR_SMALLEST_LAST = 1  /* smallest-last order: repeatedly remove a vertex of
+                                       smallest remaining degree (ties: smallest id),
+                                       color in reverse removal order (Matula and Beck
+                                       1983); 4 colors on a Kuhn-split lattice */
+};
+/* vbd_color with a choice of vertex order: each vertex, in that order, takes
+ * the smallest color not used by an already colored neighbour.  Recoloring
+ * with another order is allowed before vbd_bind_workspace. */
+vbd_status vbd_color_greedy(vbd_topology topo, int32_t order, int32_t *n_colors_out,
+                            int32_t *colors_out);
+
+/* Alternative to vbd_color: the caller supplies the coloring (host
+ * colors[n_verts], values in [0, 65536)), for example a lattice coloring with
+ * fewer colors than first-fit greedy finds.  Validated as Sec. 3.9 requires:
+ * no tet or spring may have two vertices of one color (VBD_E_INVALID_ARG
+ * otherwise, naming the element).  Colors are processed in ascending order;
+ * unused color values give empty phases.  Then builds the same permutation
+ * and incidence as vbd_color.  Must precede vbd_bind_workspace. */
+vbd_status vbd_color_given(vbd_topology topo, const int32_t *colors);
+
 /* Device bytes the workspace needs.  max_backward_iters: largest n_iters that
  * vbd_step_backward will be called with (0 = forward only). */
 vbd_status vbd_workspace_size(vbd_topology topo, int32_t max_backward_iters, size_t *bytes);

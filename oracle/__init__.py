@@ -28,6 +28,8 @@ def lib():
         d, i32, p = C.c_double, C.c_int32, C.c_void_p
         L.oracle_color_greedy.argtypes = [i32, i32, p, i32, p, p]
         L.oracle_color_greedy.restype = i32
+        L.oracle_color_smallest_last.argtypes = [i32, i32, p, i32, p, p]
+        L.oracle_color_smallest_last.restype = i32
         L.oracle_tet_rest.argtypes = [i32, p, p, p, p]
         L.oracle_tet_rest.restype = i32
         L.oracle_lumped_mass.argtypes = [i32, i32, p, p, d, p]
@@ -93,12 +95,15 @@ def set_threads(n: int) -> None:
     lib().oracle_set_threads(int(n))
 
 
-def color_greedy(n_verts, tets, springs=None):
+def color_greedy(n_verts, tets, springs=None, order="id"):
+    """Greedy first-fit coloring; order "id" (ascending vertex id) or
+    "smallest_last" (Matula-Beck smallest-last order)."""
     tets = np.ascontiguousarray(tets, np.int32)
     sp = None if springs is None or len(springs) == 0 else np.ascontiguousarray(springs, np.int32)
     colors = np.zeros(n_verts, np.int32)
-    nc = lib().oracle_color_greedy(n_verts, tets.shape[0], _ptr(tets),
-                                   0 if sp is None else sp.shape[0], _ptr(sp), _ptr(colors))
+    fn = {"id": lib().oracle_color_greedy, "smallest_last": lib().oracle_color_smallest_last}[order]
+    nc = fn(n_verts, tets.shape[0], _ptr(tets), 0 if sp is None else sp.shape[0], _ptr(sp),
+            _ptr(colors))
     return colors, int(nc)
 
 
@@ -178,7 +183,8 @@ class Model:
     """Oracle-side model: rest data, masses and coloring computed by the oracle."""
 
     def __init__(self, rest, tets, pinned, *, density=1000.0, nu=0.3, springs=None,
-                 spring_rest_len=None, spring_k=0.0, mass=None, vert_offsets=None):
+                 spring_rest_len=None, spring_k=0.0, mass=None, vert_offsets=None,
+                 coloring="id"):
         self.rest = np.ascontiguousarray(rest, np.float64)
         self.n_verts = self.rest.shape[0]
         self.tets = np.ascontiguousarray(tets, np.int32).reshape(-1, 4)
@@ -200,7 +206,7 @@ class Model:
                                 else np.ascontiguousarray(spring_rest_len, np.float64))
         else:
             self.spring_rest = np.zeros(0)
-        self.colors, self.n_colors = color_greedy(self.n_verts, self.tets, self.springs)
+        self.colors, self.n_colors = color_greedy(self.n_verts, self.tets, self.springs, coloring)
         self.surf_tris = (surface(self.tets, self.rest) if self.tets.shape[0]
                           else np.zeros((0, 3), np.int32))
         self.vert_mesh = np.zeros(self.n_verts, np.int32)
@@ -215,9 +221,12 @@ class Model:
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.rest, w.tets, w.pinned, density=w.density, nu=w.nu, springs=w.springs,
-                   spring_rest_len=w.spring_rest, spring_k=w.spring_k, mass=w.mass,
-                   vert_offsets=w.vert_offsets)
+        m = cls(w.rest, w.tets, w.pinned, density=w.density, nu=w.nu, springs=w.springs,
+                spring_rest_len=w.spring_rest, spring_k=w.spring_k, mass=w.mass,
+                vert_offsets=w.vert_offsets, coloring=getattr(w, "coloring", "id"))
+        if getattr(w, "colors", None) is not None:
+            m.set_colors(w.colors)
+        return m
 
     def set_colors(self, colors):
         """Replace the coloring (tests of coloring-dependent behaviour)."""

@@ -57,6 +57,105 @@ int32_t oracle_color_greedy(int32_t n_verts, int32_t n_tets, const int32_t *tets
     return n_colors;
 }
 
+/* binary min-heap of (degree, vertex) keys, lexicographic */
+typedef struct { int64_t *k; size_t n; } Heap;
+
+static int64_t hkey(int32_t deg, int32_t v) { return ((int64_t)deg << 32) | (int64_t)(uint32_t)v; }
+
+static void heap_push(Heap *h, int64_t key)
+{
+    size_t i = h->n++;
+    h->k[i] = key;
+    while (i > 0) {
+        size_t parent = (i - 1) / 2;
+        if (h->k[parent] <= h->k[i]) break;
+        int64_t t = h->k[parent]; h->k[parent] = h->k[i]; h->k[i] = t;
+        i = parent;
+    }
+}
+
+static int64_t heap_pop(Heap *h)
+{
+    int64_t top = h->k[0];
+    h->k[0] = h->k[--h->n];
+    size_t i = 0;
+    for (;;) {
+        size_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < h->n && h->k[l] < h->k[m]) m = l;
+        if (r < h->n && h->k[r] < h->k[m]) m = r;
+        if (m == i) break;
+        int64_t t = h->k[m]; h->k[m] = h->k[i]; h->k[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+/* Greedy first fit over the smallest-last order (Matula and Beck, J. ACM
+ * 30(3), 1983): repeatedly remove a vertex of smallest degree among the
+ * remaining ones (ties: smallest id); color in the reverse of the removal
+ * order, each vertex taking the smallest color not used by an already
+ * colored neighbour.  Same adjacency as oracle_color_greedy. */
+int32_t oracle_color_smallest_last(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                                   int32_t n_springs, const int32_t *springs, int32_t *colors)
+{
+    size_t np = (size_t)n_tets * 12 + (size_t)n_springs * 2;
+    Pair *pr = (Pair *)malloc(sizeof(Pair) * (np + 1));
+    size_t q = 0;
+    for (int t = 0; t < n_tets; ++t)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (a != b) { pr[q].a = tets[4 * t + a]; pr[q].b = tets[4 * t + b]; ++q; }
+    for (int s = 0; s < n_springs; ++s) {
+        pr[q].a = springs[2 * s]; pr[q].b = springs[2 * s + 1]; ++q;
+        pr[q].a = springs[2 * s + 1]; pr[q].b = springs[2 * s]; ++q;
+    }
+    qsort(pr, q, sizeof(Pair), pair_cmp);
+    /* drop repeated pairs (an edge shared by several tets) */
+    size_t u = 0;
+    for (size_t k = 0; k < q; ++k)
+        if (u == 0 || pair_cmp(&pr[u - 1], &pr[k]) != 0) pr[u++] = pr[k];
+    q = u;
+    int32_t *row = (int32_t *)calloc((size_t)n_verts + 1, sizeof(int32_t));
+    for (size_t k = 0; k < q; ++k) row[pr[k].a + 1]++;
+    for (int i = 0; i < n_verts; ++i) row[i + 1] += row[i];
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n_verts + 1));
+    uint8_t *gone = (uint8_t *)calloc((size_t)n_verts + 1, 1);
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n_verts + 1));
+    Heap h = {(int64_t *)malloc(sizeof(int64_t) * (q + (size_t)n_verts + 1)), 0};
+    for (int v = 0; v < n_verts; ++v) {
+        deg[v] = row[v + 1] - row[v];
+        heap_push(&h, hkey(deg[v], v));
+    }
+    int32_t removed = 0;
+    while (h.n > 0) {
+        int64_t key = heap_pop(&h);
+        int32_t v = (int32_t)(key & 0xffffffff), d = (int32_t)(key >> 32);
+        if (gone[v] || d != deg[v]) continue;      /* stale entry */
+        gone[v] = 1;
+        order[removed++] = v;
+        for (int k = row[v]; k < row[v + 1]; ++k) {
+            int w = pr[k].b;
+            if (!gone[w]) { deg[w]--; heap_push(&h, hkey(deg[w], w)); }
+        }
+    }
+    int32_t n_colors = 0;
+    int32_t *used = (int32_t *)calloc((size_t)n_verts + 2, sizeof(int32_t));
+    for (int v = 0; v < n_verts; ++v) colors[v] = -1;
+    for (int i = n_verts - 1; i >= 0; --i) {
+        int v = order[i];
+        for (int k = row[v]; k < row[v + 1]; ++k) {
+            int w = pr[k].b;
+            if (colors[w] >= 0) used[colors[w]] = i + 1;
+        }
+        int c = 0;
+        while (used[c] == i + 1) ++c;
+        colors[v] = c;
+        if (c + 1 > n_colors) n_colors = c + 1;
+    }
+    free(used); free(h.k); free(order); free(gone); free(deg); free(row); free(pr);
+    return n_colors;
+}
+
 /* D_m = [X1-X0, X2-X0, X3-X0]; Dminv by Gauss-Jordan elimination with partial
  * pivoting; V = |det D_m| / 6. */
 int32_t oracle_tet_rest(int32_t n_tets, const int32_t *tets, const double *rest,

@@ -69,6 +69,10 @@ typedef struct {
  * of all material elements (Sec. 3.9).  Returns the number of colors. */
 int32_t oracle_color_greedy(int32_t n_verts, int32_t n_tets, const int32_t *tets,
                             int32_t n_springs, const int32_t *springs, int32_t *colors);
+/* Greedy first fit over the smallest-last order (min remaining degree, ties
+ * by smallest id; colored in reverse removal order).  Returns n_colors. */
+int32_t oracle_color_smallest_last(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                                   int32_t n_springs, const int32_t *springs, int32_t *colors);
 /* Rest edge matrix inverse and volume per tet; returns 0, or -1-t for the first
  * degenerate tet t. */
 int32_t oracle_tet_rest(int32_t n_tets, const int32_t *tets, const double *rest,

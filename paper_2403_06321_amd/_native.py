@@ -12,13 +12,14 @@ STATUS_NAMES = {0: "VBD_OK", -1: "VBD_E_INVALID_ARG", -2: "VBD_E_TOPOLOGY", -3: 
                 -7: "VBD_E_NONFINITE", -8: "VBD_E_DEVICE"}
 
 LAUNCH_PLAIN, LAUNCH_GRAPH, LAUNCH_PERSISTENT, LAUNCH_PERSISTENT_GRAPH = 0, 1, 2, 3
+COLOR_ID_ORDER, COLOR_SMALLEST_LAST = 0, 1
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
  Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME, Q_SURFACE,
  Q_SURFACE_COUNTS) = range(16)
 
 # every symbol include/vbd.h declares
-EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_workspace_size", "vbd_bind_workspace",
+EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_color_greedy", "vbd_color_given", "vbd_workspace_size", "vbd_bind_workspace",
            "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_backward",
            "vbd_get_launch_config", "vbd_set_launch_config", "vbd_autotune",
            "vbd_profile_enable", "vbd_profile_read", "vbd_check", "vbd_probe_copy",
@@ -74,6 +75,8 @@ def lib():
     p, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
     L.vbd_build_topology.argtypes = [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]
     L.vbd_color.argtypes = [p, C.POINTER(i32), p]
+    L.vbd_color_given.argtypes = [p, p]
+    L.vbd_color_greedy.argtypes = [p, i32, C.POINTER(i32), p]
     L.vbd_workspace_size.argtypes = [p, i32, C.POINTER(sz)]
     L.vbd_bind_workspace.argtypes = [p, p, sz, p]
     L.vbd_topology_query.argtypes = [p, i32, p, sz]

@@ -56,7 +56,9 @@ class Topology:
     def __init__(self, rest, tets=None, *, springs=None, pinned=None, mass=None, density=1000.0,
                  nu=0.3, spring_k=0.0, spring_rest=None, vert_offsets=None, tet_offsets=None,
                  max_backward_iters: int = 0, device: Optional[torch.device] = None,
-                 bind: bool = True):
+                 bind: bool = True, colors=None, coloring: str = "id"):
+        """colors: optional caller-supplied vertex coloring; else greedy first fit
+        in the vertex order `coloring` ("id" or "smallest_last")."""
         L = N.lib()
         self._keep = []
 
@@ -87,15 +89,25 @@ class Topology:
         self.n_tets = tets.shape[0]
         self.n_springs = 0 if springs is None else springs.shape[0]
         self.max_backward_iters = int(max_backward_iters)
-        nc = C.c_int32()
-        N.check(L.vbd_color(self._h, C.byref(nc), None))
-        self.n_colors = nc.value
+        if colors is not None:
+            col = arr(colors, np.int32).reshape(-1)
+            if col.shape[0] != self.n_verts:
+                raise ValueError("colors must hold one entry per vertex")
+            N.check(L.vbd_color_given(self._h, _np_ptr(col)))
+            self.n_colors = int(col.max()) + 1 if col.size else 0
+        else:
+            order = {"id": N.COLOR_ID_ORDER, "smallest_last": N.COLOR_SMALLEST_LAST}[coloring]
+            nc = C.c_int32()
+            N.check(L.vbd_color_greedy(self._h, order, C.byref(nc), None))
+            self.n_colors = nc.value
         self.workspace = None
         if bind:
             self.bind(device)
 
     @classmethod
     def from_workload(cls, w: Workload, **kw):
+        kw.setdefault("colors", w.colors)
+        kw.setdefault("coloring", w.coloring)
         return cls(w.rest, w.tets, springs=w.springs, pinned=w.pinned, mass=w.mass,
                    density=w.density, nu=w.nu, spring_k=w.spring_k, spring_rest=w.spring_rest,
                    vert_offsets=w.vert_offsets if w.n_meshes > 1 else None,

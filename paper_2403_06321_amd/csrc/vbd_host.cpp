@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -104,6 +105,7 @@ struct vbd_topology_s {
     double nu = 0.3, spring_k = 0.0;
     // coloring and CSR
     bool colored = false;
+    int color_order = -1;               // VBD_COLOR_* of the greedy coloring, -1: given
     int n_colors = 0, n_free = 0;
     std::vector<int32_t> colors, perm, iperm, color_off;
     std::vector<int32_t> tet_row, tet_ent, spr_row, spr_nbr_orig;
@@ -348,28 +350,71 @@ StepConsts make_consts(const vbd_topology_s &T, const vbd_step_params *p)
 // --------------------------------------------------------------- coloring --
 // First-fit greedy over the union adjacency of tets and springs, vertices in
 // ascending id; neighbour colors are tracked in a growable bitset.
-void greedy_color(vbd_topology_s &T)
+// Vertex order of the greedy coloring.  VBD_COLOR_ID_ORDER: ascending id.
+// VBD_COLOR_SMALLEST_LAST: the reverse of the order in which repeatedly
+// removing a vertex of smallest remaining degree (ties: smallest id) empties
+// the graph (Matula and Beck, J. ACM 30(3), 1983).
+std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, int order)
+{
+    const int nv = (int)nbr.size();
+    std::vector<int32_t> ord(nv);
+    if (order == VBD_COLOR_ID_ORDER) {
+        for (int v = 0; v < nv; ++v) ord[v] = v;
+        return ord;
+    }
+    std::vector<int32_t> deg(nv);
+    std::set<std::pair<int32_t, int32_t>> q;   // (remaining degree, id)
+    for (int v = 0; v < nv; ++v) {
+        deg[v] = (int32_t)nbr[v].size();
+        q.insert({deg[v], v});
+    }
+    std::vector<char> gone(nv, 0);
+    for (int i = nv - 1; i >= 0; --i) {
+        const int v = q.begin()->second;
+        q.erase(q.begin());
+        gone[v] = 1;
+        ord[i] = v;
+        for (int32_t w : nbr[v])
+            if (!gone[w]) {
+                q.erase({deg[w], w});
+                q.insert({--deg[w], w});
+            }
+    }
+    return ord;
+}
+
+void greedy_color(vbd_topology_s &T, int order)
 {
     const int nv = T.nv;
-    std::vector<std::vector<int32_t>> adj(nv);
+    // neighbour lists: in id order only the lower-id neighbours are colored
+    // before a vertex; the smallest-last order needs them all, without repeats
+    const bool all = order != VBD_COLOR_ID_ORDER;
+    std::vector<std::vector<int32_t>> nbr(nv);
     for (int t = 0; t < T.nt; ++t) {
         const int32_t *q = &T.tets[4 * (size_t)t];
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b)
-                if (a != b && q[b] < q[a]) adj[q[a]].push_back(q[b]);
+                if (a != b && (all || q[b] < q[a])) nbr[q[a]].push_back(q[b]);
     }
     for (int s = 0; s < T.ns; ++s) {
         const int a = T.springs[2 * (size_t)s], b = T.springs[2 * (size_t)s + 1];
-        if (b < a) adj[a].push_back(b);
-        else adj[b].push_back(a);
+        if (all || b < a) nbr[a].push_back(b);
+        if (all || a < b) nbr[b].push_back(a);
     }
-    T.colors.assign(nv, 0);
+    if (all)
+        for (auto &l : nbr) {
+            std::sort(l.begin(), l.end());
+            l.erase(std::unique(l.begin(), l.end()), l.end());
+        }
+    const std::vector<int32_t> ord = color_order(nbr, order);
+    T.colors.assign(nv, -1);
     int nc = 0;
     std::vector<uint64_t> used;
-    for (int v = 0; v < nv; ++v) {
+    for (int v : ord) {
         used.assign((size_t)(nc / 64 + 1), 0ull);
-        for (int32_t u : adj[v]) {
+        for (int32_t u : nbr[v]) {
             const int c = T.colors[u];
+            if (c < 0) continue;
             used[(size_t)c >> 6] |= 1ull << (c & 63);
         }
         int c = 0;
@@ -546,43 +591,63 @@ void build_surface(vbd_topology_s &T)
     for (int m = 0; m < T.n_meshes; ++m)
         for (int64_t v = T.vert_off[m]; v < T.vert_off[m + 1]; ++v) T.vert_mesh[v] = m;
     if (T.n_meshes < 2 || T.nt == 0) return;
-    struct Face { std::array<int32_t, 3> key; int32_t t, opp; };
-    std::vector<Face> f;
-    f.reserve(4 * (size_t)T.nt);
+    // faces bucketed by their smallest vertex id (counting sort), then each
+    // bucket sorted by the other two ids: the output is in ascending order of
+    // the sorted id triples, linear in the number of faces
+    struct Face { int32_t mid, hi, t, opp; };
+    const int nv = T.nv;
+    std::vector<int64_t> off((size_t)nv + 1, 0);
+    auto face_ids = [&](int t, int o, int32_t v[3]) {
+        int k = 0;
+        for (int j = 0; j < 4; ++j)
+            if (j != o) v[k++] = T.tets[4 * (size_t)t + j];
+    };
     for (int t = 0; t < T.nt; ++t)
         for (int o = 0; o < 4; ++o) {
-            Face x{};
-            int k = 0;
-            for (int j = 0; j < 4; ++j)
-                if (j != o) x.key[k++] = T.tets[4 * (size_t)t + j];
-            std::sort(x.key.begin(), x.key.end());
-            x.t = t;
-            x.opp = o;
-            f.push_back(x);
+            int32_t v[3];
+            face_ids(t, o, v);
+            off[(size_t)std::min(v[0], std::min(v[1], v[2])) + 1]++;
         }
-    std::sort(f.begin(), f.end(), [](const Face &a, const Face &b) { return a.key < b.key; });
-    auto P = [&](int v, int r) { return T.rest[3 * (size_t)v + r]; };
-    for (size_t i = 0; i < f.size();) {
-        size_t j = i + 1;
-        while (j < f.size() && f[j].key == f[i].key) ++j;
-        if (j - i == 1) {
-            const int32_t *q = &T.tets[4 * (size_t)f[i].t];
-            int v[3], k = 0;
-            for (int a = 0; a < 4; ++a)
-                if (a != f[i].opp) v[k++] = q[a];
-            const int d = q[f[i].opp];
-            double e1[3], e2[3], e3[3];
-            for (int r = 0; r < 3; ++r) {
-                e1[r] = P(v[1], r) - P(v[0], r);
-                e2[r] = P(v[2], r) - P(v[0], r);
-                e3[r] = P(d, r) - P(v[0], r);
+    for (int v = 0; v < nv; ++v) off[v + 1] += off[v];
+    std::vector<Face> f((size_t)off[nv]);
+    {
+        std::vector<int64_t> pos(off.begin(), off.end() - 1);
+        for (int t = 0; t < T.nt; ++t)
+            for (int o = 0; o < 4; ++o) {
+                int32_t v[3];
+                face_ids(t, o, v);
+                std::sort(v, v + 3);
+                f[(size_t)pos[v[0]]++] = Face{v[1], v[2], t, o};
             }
-            const double n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2],
-                         n2 = e1[0] * e2[1] - e1[1] * e2[0];
-            if (n0 * e3[0] + n1 * e3[1] + n2 * e3[2] > 0.0) std::swap(v[1], v[2]);
-            T.surf.insert(T.surf.end(), {v[0], v[1], v[2]});
+    }
+    auto P = [&](int v, int r) { return T.rest[3 * (size_t)v + r]; };
+    for (int lo = 0; lo < nv; ++lo) {
+        Face *b = f.data() + off[lo], *e = f.data() + off[lo + 1];
+        std::sort(b, e, [](const Face &x, const Face &y) {
+            return x.mid != y.mid ? x.mid < y.mid : x.hi < y.hi;
+        });
+        for (Face *i = b; i < e;) {
+            Face *j = i + 1;
+            while (j < e && j->mid == i->mid && j->hi == i->hi) ++j;
+            if (j - i == 1) {
+                const int32_t *q = &T.tets[4 * (size_t)i->t];
+                int v[3], k = 0;
+                for (int a = 0; a < 4; ++a)
+                    if (a != i->opp) v[k++] = q[a];
+                const int d = q[i->opp];
+                double e1[3], e2[3], e3[3];
+                for (int r = 0; r < 3; ++r) {
+                    e1[r] = P(v[1], r) - P(v[0], r);
+                    e2[r] = P(v[2], r) - P(v[0], r);
+                    e3[r] = P(d, r) - P(v[0], r);
+                }
+                const double n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2],
+                             n2 = e1[0] * e2[1] - e1[1] * e2[0];
+                if (n0 * e3[0] + n1 * e3[1] + n2 * e3[2] > 0.0) std::swap(v[1], v[2]);
+                T.surf.insert(T.surf.end(), {v[0], v[1], v[2]});
+            }
+            i = j;
         }
-        i = j;
     }
     const int ntri = (int)(T.surf.size() / 3);
     // edge adjacency: (min, max, triangle, edge) sorted by the undirected edge
@@ -929,15 +994,56 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *d, vbd_topology *out)
 
 vbd_status vbd_color(vbd_topology T, int32_t *n_colors_out, int32_t *colors_out)
 {
+    return vbd_color_greedy(T, VBD_COLOR_ID_ORDER, n_colors_out, colors_out);
+}
+
+vbd_status vbd_color_greedy(vbd_topology T, int32_t order, int32_t *n_colors_out, int32_t *colors_out)
+{
     if (!T) return fail(VBD_E_INVALID_ARG, "NULL topology");
+    if (order != VBD_COLOR_ID_ORDER && order != VBD_COLOR_SMALLEST_LAST)
+        return fail(VBD_E_INVALID_ARG, "unknown coloring order %d", order);
+    if (T->colored && T->color_order != order) {
+        if (T->bound) return fail(VBD_E_INVALID_ARG, "the topology is bound: color before vbd_bind_workspace");
+        T->colored = false;
+    }
     if (!T->colored) {
-        greedy_color(*T);
+        greedy_color(*T, order);
+        T->color_order = order;
         build_csr(*T);
         build_surface(*T);
         T->colored = true;
     }
     if (n_colors_out) *n_colors_out = T->n_colors;
     if (colors_out) std::copy(T->colors.begin(), T->colors.end(), colors_out);
+    return VBD_OK;
+}
+
+vbd_status vbd_color_given(vbd_topology T, const int32_t *colors)
+{
+    if (!T || (!colors && T->nv > 0)) return fail(VBD_E_INVALID_ARG, "NULL argument");
+    if (T->bound) return fail(VBD_E_INVALID_ARG, "the topology is bound: color before vbd_bind_workspace");
+    int nc = 0;
+    for (int v = 0; v < T->nv; ++v) {
+        if (colors[v] < 0 || colors[v] >= 65536)
+            return fail(VBD_E_INVALID_ARG, "color of vertex %d out of range [0, 65536)", v);
+        nc = std::max(nc, colors[v] + 1);
+    }
+    for (int t = 0; t < T->nt; ++t) {
+        const int32_t *q = &T->tets[4 * (size_t)t];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < a; ++b)
+                if (colors[q[a]] == colors[q[b]])
+                    return fail(VBD_E_INVALID_ARG, "tet %d has two vertices of color %d", t, colors[q[a]]);
+    }
+    for (int e = 0; e < T->ns; ++e)
+        if (colors[T->springs[2 * (size_t)e]] == colors[T->springs[2 * (size_t)e + 1]])
+            return fail(VBD_E_INVALID_ARG, "spring %d joins two vertices of one color", e);
+    T->colors.assign(colors, colors + T->nv);
+    T->n_colors = nc;
+    T->color_order = -1;
+    build_csr(*T);
+    build_surface(*T);
+    T->colored = true;
     return VBD_OK;
 }
 

@@ -82,6 +82,8 @@ class Workload:
     params: StepParams = dataclasses.field(default_factory=StepParams)
     frames: int = 1
     target: Optional[np.ndarray] = None        # [3] loss target (differentiable workload)
+    colors: Optional[np.ndarray] = None        # [nv] given vertex coloring (None: greedy)
+    coloring: str = "id"                       # greedy vertex order: "id" or "smallest_last"
 
     @property
     def n_verts(self) -> int:
@@ -206,10 +208,32 @@ def config_small_cube() -> Workload:
     return tet_cube(11, 0, E=1e5, n_iters=20, frames=10, name="tet cube 11^3")
 
 
-def config_large_cube(frames: int = 60) -> Workload:
-    """65^3 vertices, 1,572,864 tets, per-tet E log-uniform in [1e4, 1e6]."""
-    return tet_cube(65, 1, E_range=(1e4, 1e6), n_iters=100, frames=frames,
-                    name="tet cube 65^3")
+def lattice_colors(nx: int, ny: int, nz: int) -> np.ndarray:
+    """(i + j + k) mod 4 for vertex i + nx*(j + ny*k) of cube_lattice: every
+    Kuhn-split edge vector is a nonzero 0/1 vector (up to sign), so the two
+    ends of an edge differ by 1..3 in i + j + k and never share a color; the
+    four vertices of each tet take all four colors."""
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    s = (i + j + k).transpose(2, 1, 0).ravel()
+    return (s % 4).astype(np.int32)
+
+
+def config_large_cube(frames: int = 60, coloring: str = "id") -> Workload:
+    """65^3 vertices, 1,572,864 tets, per-tet E log-uniform in [1e4, 1e6].
+    coloring: greedy first fit in vertex-id order ("id", 8 colors) or in the
+    smallest-last order ("smallest_last", 4 colors), or the given lattice
+    coloring ("lattice4", 4 colors)."""
+    w = tet_cube(65, 1, E_range=(1e4, 1e6), n_iters=100, frames=frames, name="tet cube 65^3")
+    if coloring == "lattice4":
+        w.colors = lattice_colors(65, 65, 65)
+        w.name += ", 4-color lattice coloring"
+    elif coloring in ("id", "smallest_last"):
+        w.coloring = coloring
+        if coloring == "smallest_last":
+            w.name += ", smallest-last greedy coloring"
+    else:
+        raise ValueError(f"unknown coloring {coloring}")
+    return w
 
 
 def config_cloth(n: int = 1024, frames: int = 120, spacing: float = 1e-3,

@@ -36,6 +36,17 @@ def test_coloring_matches_oracle_bit_exact(n):
     assert np.array_equal(t.query(N.Q_COLORS), m.colors)
 
 
+@pytest.mark.parametrize("make", [lambda: W.tet_cube(9, 1), lambda: W.config_cloth(32),
+                                  lambda: W.config_batch(n_meshes=6, lo=3, hi=7)])
+def test_smallest_last_coloring_matches_oracle_bit_exact(make):
+    w = make()
+    w.coloring = "smallest_last"
+    t = Topology.from_workload(w, bind=False)
+    m = O.Model.from_workload(w)
+    assert t.n_colors == m.n_colors
+    assert np.array_equal(t.query(N.Q_COLORS), m.colors)
+
+
 def test_cloth_coloring_matches_oracle():
     w = W.config_cloth(32)
     t = Topology.from_workload(w, bind=False)
@@ -219,3 +230,21 @@ def test_surface_matches_oracle_with_outward_orientation():
     # a single mesh has no surface (contacts are between meshes)
     t1 = Topology.from_workload(W.tet_cube(4, 0), bind=False)
     assert tuple(t1.query(N.Q_SURFACE_COUNTS)) == (0, 0)
+
+
+def test_given_coloring_layout_and_validation():
+    w = W.tet_cube(5, 2)
+    colors = W.lattice_colors(5, 5, 5)
+    t = Topology.from_workload(w, bind=False, colors=colors)
+    assert t.n_colors == 4
+    assert np.array_equal(t.query(N.Q_COLORS), colors)
+    perm, rows, ents = _expected_layout(w, colors)
+    assert np.array_equal(t.query(N.Q_PERM), perm)
+    assert np.array_equal(t.query(N.Q_TET_ROWS), rows)
+    assert np.array_equal(t.query(N.Q_TET_ENTRIES), ents)
+    bad = colors.copy()
+    q = w.tets[17]
+    bad[q[1]] = bad[q[0]]
+    assert _status(lambda: Topology.from_workload(w, bind=False, colors=bad)) == -1
+    neg = colors.copy(); neg[3] = -1
+    assert _status(lambda: Topology.from_workload(w, bind=False, colors=neg)) == -1

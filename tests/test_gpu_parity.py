@@ -103,6 +103,34 @@ def test_large_cube_full_size_prefix():
         assert_parity(w, xg, xo, label=f"65^3 mode {mode}")
 
 
+@pytest.mark.parametrize("coloring", ["lattice4", "smallest_last"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_small_cube_four_colorings(mode, coloring):
+    """The caller-supplied lattice coloring and the smallest-last greedy
+    coloring (4 colors each): both sides run the same color order (the oracle
+    colors by itself, or takes the given coloring as an input)."""
+    w = W.config_small_cube()
+    if coloring == "lattice4":
+        w.colors = W.lattice_colors(11, 11, 11)
+    else:
+        w.coloring = coloring
+    xo, _ = oracle_rollout(w, w.frames, threads=THREADS)
+    xg, _, t = gpu_rollout(w, w.frames, launch_mode=mode)
+    assert t.n_colors == 4
+    assert_parity(w, xg, xo, label=f"11^3 {coloring} coloring mode {mode}")
+
+
+@pytest.mark.parametrize("coloring", ["lattice4", "smallest_last"])
+def test_large_cube_four_colorings_prefix(coloring):
+    w = W.config_large_cube(frames=2, coloring=coloring)
+    p = replace(w.params, n_iters=3)
+    say(f"oracle 65^3 prefix, {coloring} coloring ...")
+    xo, _ = oracle_rollout(w, 2, params=p, threads=THREADS)
+    for mode in (0, 3):
+        xg, _, _ = gpu_rollout(w, 2, params=p, launch_mode=mode, autotune=True)
+        assert_parity(w, xg, xo, label=f"65^3 {coloring} coloring mode {mode}")
+
+
 def test_cloth_with_contacts():
     """64^2 cloth over the same 1.023 m square as the 1024^2 benchmark cloth
     (16 mm springs, same total mass): drapes over the sphere, reaches the

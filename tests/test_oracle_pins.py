@@ -521,3 +521,57 @@ def test_spring_psd_clamp_by_hand():
         x, _, _, _ = O.step(m, p, x0, v0, v0, np.zeros(0))
         H = mass / h ** 2 * np.eye(3) + k * np.outer(u, u) + trans * (np.eye(3) - np.outer(u, u))
         assert np.allclose(x[1], x0[1] + np.linalg.solve(H, f), atol=1e-14)
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 3), (4, 5, 6), (7, 2, 3)])
+def test_lattice_four_coloring_is_valid(dims):
+    """(i + j + k) mod 4 is a proper coloring of the Kuhn lattice: checked by
+    brute force over every tet (no two vertices of a tet share a color)."""
+    rest, tets = W.cube_lattice(*dims)
+    c = W.lattice_colors(*dims)
+    assert c.shape[0] == rest.shape[0]
+    assert all(len(set(c[q].tolist())) == 4 for q in tets)
+    assert set(c.tolist()) == {0, 1, 2, 3}
+
+
+def test_coloring_changes_the_path_not_the_solution():
+    """Sec. 3.9: any valid coloring gives a Gauss-Seidel order; iterated to
+    convergence, the greedy 8-color and the lattice 4-color orders reach the
+    same implicit-Euler solution, while a few iterations differ."""
+    w = W.tet_cube(4, 21, E_range=(1e4, 1e6))
+    m8 = O.Model.from_workload(w)
+    m4 = O.Model.from_workload(w)
+    m4.set_colors(W.lattice_colors(4, 4, 4))
+    assert m8.n_colors == 7 and m4.n_colors == 4
+    rng = np.random.default_rng(5)
+    v0 = rng.normal(scale=0.2, size=w.x0.shape) * (1 - w.pinned[:, None])
+    few = P(n_iters=3)
+    a = O.step(m8, few, w.x0, v0, v0, w.tet_E)[0]
+    b = O.step(m4, few, w.x0, v0, v0, w.tet_E)[0]
+    assert np.abs(a - b).max() > 1e-6
+    many = P(n_iters=4000)
+    a = O.step(m8, many, w.x0, v0, v0, w.tet_E)[0]
+    b = O.step(m4, many, w.x0, v0, v0, w.tet_E)[0]
+    diag = np.linalg.norm(a.max(0) - a.min(0))
+    assert np.abs(a - b).max() <= 1e-9 * diag
+
+
+def test_smallest_last_order_on_a_path_by_hand():
+    """Springs 0-1, 1-2, 2-3 (degrees 1, 2, 2, 1).  Removing a smallest-degree
+    vertex (ties: smallest id) gives 0, 1, 2, 3; coloring in reverse order
+    3, 2, 1, 0 by first fit gives colors 1, 0, 1, 0 (id order: 0, 1, 0, 1)."""
+    sp = np.array([[0, 1], [1, 2], [2, 3]])
+    c, nc = O.color_greedy(4, np.zeros((0, 4)), sp, order="smallest_last")
+    assert c.tolist() == [1, 0, 1, 0] and nc == 2
+    c, nc = O.color_greedy(4, np.zeros((0, 4)), sp, order="id")
+    assert c.tolist() == [0, 1, 0, 1] and nc == 2
+
+
+@pytest.mark.parametrize("n", [3, 6, 11])
+def test_smallest_last_colors_a_lattice_with_four(n):
+    """Each tet is a 4-clique, so 4 colors is the optimum; the smallest-last
+    order reaches it on Kuhn lattices (first fit in id order needs 7-8)."""
+    rest, tets = W.cube_lattice(n, n, n)
+    c, nc = O.color_greedy(rest.shape[0], tets, order="smallest_last")
+    assert nc == 4
+    assert all(len(set(c[q].tolist())) == 4 for q in tets)
