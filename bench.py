@@ -286,7 +286,7 @@ def extras(dev, W, Topology):
     import torch
     res = {}
     # batched: 512 meshes, persistent hipGraph vs the plain kernel mesh by mesh
-    wb = W.config_batch()
+    wb = W.config_batch(coloring="smallest_last")
     log(f"[bench] batch: {wb.n_meshes} meshes, {wb.n_verts} verts, {wb.n_tets} tets")
     t0 = time.perf_counter()
     tb = Topology.from_workload(wb)

@@ -3,8 +3,10 @@
 This module only builds inputs: lattice and cloth topologies, rest shapes,
 pins, jittered initial positions, velocities and per-tet Young's moduli, all
 drawn from ``numpy.random.default_rng(seed)``.  It contains none of the
-solver's arithmetic (no rest-shape inverses, masses, colorings, forces or
-Hessians); both the FP64 oracle and the HIP library consume what it returns.
+solver's arithmetic (no rest-shape inverses, masses, greedy colorings, forces
+or Hessians); both the FP64 oracle and the HIP library consume what it
+returns.  The one coloring built here, ``lattice_colors``, is an input: a
+caller-supplied coloring handed to both sides as is.
 
 Workload shapes follow the paper's setting (Sec. 5: fixed frame time 1/60 s,
 fixed iteration count, stable Neo-Hookean tets, linear springs for mass-spring
@@ -261,8 +263,9 @@ def config_cloth_coarse(n: int = 64, frames: int = 60) -> Workload:
 
 
 def config_batch(n_meshes: int = 512, seed: int = 3, lo: int = 4, hi: int = 33,
-                 frames: int = 60, n_iters: int = 40) -> Workload:
-    """Independent free cubes with per-axis dims U{lo..hi}, per-mesh E, rigid v0."""
+                 frames: int = 60, n_iters: int = 40, coloring: str = "id") -> Workload:
+    """Independent free cubes with per-axis dims U{lo..hi}, per-mesh E, rigid v0.
+    coloring: greedy vertex order, "id" or "smallest_last"."""
     rng = np.random.default_rng(seed)
     dims = rng.integers(lo, hi + 1, size=(n_meshes, 3))
     Em = _log_uniform(rng, 1e4, 1e6, n_meshes)
@@ -289,7 +292,7 @@ def config_batch(n_meshes: int = 512, seed: int = 3, lo: int = 4, hi: int = 33,
                     pinned=np.zeros(nv, np.uint8), x0=x0, v0=v0,
                     tet_E=np.concatenate(Es), vert_offsets=np.array(vo, np.int64),
                     tet_offsets=np.array(to, np.int64),
-                    params=StepParams(n_iters=n_iters), frames=frames)
+                    params=StepParams(n_iters=n_iters), frames=frames, coloring=coloring)
 
 
 def config_block_stack(cols: int = 2, levels: int = 3, n: int = 5, seed: int = 5,
@@ -375,8 +378,11 @@ def subset_meshes(w: Workload, ids: List[int]) -> Workload:
         pins.append(w.pinned[a:b])
         tetss.append(w.tets[ta:tb] - a + nvo[-1]); Es.append(w.tet_E[ta:tb])
         nvo.append(nvo[-1] + b - a); nto.append(nto[-1] + tb - ta)
+    colors = None
+    if w.colors is not None:
+        colors = np.concatenate([w.colors[int(vo[m]):int(vo[m + 1])] for m in ids])
     return dataclasses.replace(
-        w, name=f"{w.name} [meshes {ids}]", rest=np.concatenate(rests),
+        w, name=f"{w.name} [meshes {ids}]", rest=np.concatenate(rests), colors=colors,
         tets=np.concatenate(tetss).astype(np.int32), pinned=np.concatenate(pins),
         x0=np.concatenate(x0s), v0=np.concatenate(v0s), tet_E=np.concatenate(Es),
         vert_offsets=np.array(nvo, np.int64), tet_offsets=np.array(nto, np.int64))
