@@ -48,7 +48,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, ell_info, spr_row, spr_ent, perm, mass, color_off;
+    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, pa, ps, pt, pair_tet, ell_info, spr_row, spr_ent,
+        perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib, ebar;
     // mesh-mesh contacts (only when the topology has a surface)
@@ -162,6 +163,10 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.tet_row = take(sizeof(int32_t) * (size_t)(T.nv + 1));
     L.tet_ent = take(sizeof(PairEnt) * T.tet_ent.size());
     L.ell = take(sizeof(PairEnt) * T.ell_total);
+    L.pa = take(sizeof(int4) * T.ell_total);
+    L.ps = take(sizeof(float4) * T.ell_total);
+    L.pt = take(sizeof(float2) * T.ell_total);
+    L.pair_tet = take(sizeof(int32_t) * T.ell_total);
     L.ell_info = take(sizeof(int2) * (size_t)T.n_colors);
     L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
     L.spr_ent = take(sizeof(int2) * T.spr_nbr_orig.size());
@@ -227,6 +232,11 @@ void set_dev_pointers(vbd_topology_s &T)
     D.tet_row = (const int *)(b + L.tet_row);
     D.tet_ent = (const PairEnt *)(b + L.tet_ent);
     D.ell = (const PairEnt *)(b + L.ell);
+    D.pa = (int4 *)(b + L.pa);
+    D.ps = (const float4 *)(b + L.ps);
+    D.pt = (const float2 *)(b + L.pt);
+    D.pair_tet = (const int *)(b + L.pair_tet);
+    D.n_pairs = (long long)T.ell_total;
     D.ell_info = (const int2 *)(b + L.ell_info);
     D.spr_row = (const int *)(b + L.spr_row);
     D.spr_ent = (const int2 *)(b + L.spr_ent);
@@ -548,9 +558,9 @@ void build_csr(vbd_topology_s &T)
             T.tet_rank[key[i].second] = i;
         }
     }
-    // algorithmic bytes of one color solve: 32 B tet record + 16 B incidence
-    // entry per tet pair, 8 B per spring entry, 48 B own state per vertex
-    // (x read, y read, x write), 16 B per distinct neighbour position.
+    // algorithmic bytes of one color solve: 40 B pair record per tet pair, 8 B
+    // per spring entry, 48 B own state per vertex (x read, y read, x write),
+    // 16 B per distinct neighbour position.
     T.phase_bytes.assign(T.n_colors, 0.0);
     T.phase_updates.assign(T.n_colors, 0);
     std::vector<int32_t> stamp(nv, -1);
@@ -560,7 +570,7 @@ void build_csr(vbd_topology_s &T)
         for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
             const int pairs = T.tet_row[s + 1] - T.tet_row[s];
             const int sp = T.spr_row[s + 1] - T.spr_row[s];
-            bytes += (double)(sizeof(TetRec) + sizeof(PairEnt)) * pairs + 8.0 * sp + 48.0;
+            bytes += (double)(sizeof(int4) + sizeof(float4) + sizeof(float2)) * pairs + 8.0 * sp + 48.0;
             for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
                 const int t = T.tet_ent[e] >> 2;
                 for (int k = 0; k < 4; ++k) {
@@ -1137,6 +1147,37 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
             }
         }
         HIP_TRY(up(T->lay.ell, ell.data(), sizeof(PairEnt) * ell.size()));
+        // pair records: the rest frame of each (vertex, tet) pair with the
+        // vertex as origin, the other three vertices in slot order
+        std::vector<int4> pa(T->ell_total, make_int4(-1, 0, 0, 0));
+        std::vector<float4> ps(T->ell_total, make_float4(0.f, 0.f, 0.f, 0.f));
+        std::vector<float2> pt(T->ell_total, make_float2(0.f, 0.f));
+        std::vector<int32_t> ptet(T->ell_total, -1);
+        for (int c = 0; c < T->n_colors; ++c) {
+            const int2 info = T->ell_info[c];
+            for (int sl = T->color_off[c]; sl < T->color_off[c + 1]; ++sl) {
+                const size_t base = (size_t)info.x + (size_t)(sl - T->color_off[c]) * (size_t)info.y;
+                for (int e = T->tet_row[sl]; e < T->tet_row[sl + 1]; ++e) {
+                    const int t = T->tet_ent[e] >> 2, k = T->tet_ent[e] & 3;
+                    const int32_t *q = &T->tets[4 * (size_t)t];
+                    int32_t ord[4] = {q[k], 0, 0, 0};
+                    int n = 1;
+                    for (int j = 0; j < 4; ++j)
+                        if (j != k) ord[n++] = q[j];
+                    double S[6];
+                    rest_frame_inverse(T->rest, ord, S);
+                    const size_t i = base + (size_t)(e - T->tet_row[sl]);
+                    pa[i] = make_int4(T->iperm[ord[1]], T->iperm[ord[2]], T->iperm[ord[3]], 0);
+                    ps[i] = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
+                    pt[i] = make_float2((float)S[4], (float)S[5]);
+                    ptet[i] = T->tet_rank[t];
+                }
+            }
+        }
+        HIP_TRY(up(T->lay.pa, pa.data(), sizeof(int4) * pa.size()));
+        HIP_TRY(up(T->lay.ps, ps.data(), sizeof(float4) * ps.size()));
+        HIP_TRY(up(T->lay.pt, pt.data(), sizeof(float2) * pt.size()));
+        HIP_TRY(up(T->lay.pair_tet, ptet.data(), 4 * ptet.size()));
         HIP_TRY(up(T->lay.ell_info, T->ell_info.data(), sizeof(int2) * T->ell_info.size()));
     }
     HIP_TRY(up(T->lay.spr_row, T->spr_row.data(), 4 * T->spr_row.size()));

@@ -58,12 +58,26 @@ struct DevTopo {
     const int *tet_perm;               // stored tet -> caller's tet index
     const int *tet_row;                // CSR over all permuted vertices (adjoint)
     const PairEnt *tet_ent;            // (tet, slot, other vertices) per entry
-    // Color-solve incidence, per color c: every free vertex of the color owns
+    // Per-color padded incidence: every free vertex of color c owns
     // ell_info[c].y consecutive entries starting at ell_info[c].x +
-    // (slot - color_off[c]) * ell_info[c].y, padded with x = -1, so the entry
-    // addresses follow from the slot alone.
+    // (slot - color_off[c]) * ell_info[c].y, so entry addresses follow from the
+    // slot alone.  Two views of each (vertex, tet) pair:
+    //   ell                 shared-record entries (adjoint), padding x = -1;
+    //   pa / ps / pt        the color solve's pair records: pa = {the other
+    //                       three vertices (slot order), float bits of V*E},
+    //                       ps = {S00, S01, S02, S11}, pt = {S12, S22}, where
+    //                       S = R^{-1} of the tet's rest edges taken from this
+    //                       vertex (D_m' = Q R, Q proper); padding pa.x = -1.
+    //                       F = D_s' S equals the tet's F times a rotation, so
+    //                       energy, forces and Hessians are unchanged, and
+    //                       this vertex's shape gradient is -(rows of S summed).
     const PairEnt *ell;
+    int4 *pa;
+    const float4 *ps;
+    const float2 *pt;
+    const int *pair_tet;               // stored tet of each pair entry (-1: padding)
     const int2 *ell_info;              // [n_colors] {first entry, padded degree}
+    long long n_pairs;                 // padded entries over all colors
     const int *spr_row;
     const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
     const int *perm;                   // permuted slot -> original id
@@ -116,6 +130,7 @@ struct LaunchCfg {
 };
 
 // ---- kernel launchers (vbd_kernels.hip) ----
+// V*mu, V*lambda of the shared records and V*E of the pair records.
 hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K,
                            hipStream_t s);
 hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,

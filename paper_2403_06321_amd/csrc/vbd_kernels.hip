@@ -102,27 +102,6 @@ __device__ __forceinline__ void acc_zero(Acc &a)
     a.fx = a.fy = a.fz = a.hxx = a.hxy = a.hxz = a.hyy = a.hyz = a.hzz = 0.f;
 }
 
-__device__ __forceinline__ void tet_accumulate(const TetRec &r, int k, float4 q0, float4 q1,
-                                               float4 q2, float4 q3, float alpha, Acc &a)
-{
-    TetLocal L;
-    tet_local(r, q0, q1, q2, q3, L);
-    const float3 mk = shape_grad(L, k);
-    const float3 Fm = Fmul(L, mk), cm = Cmul(L, mk);
-    const float Vmu = r.b.z, Vlam = r.b.w;
-    const float s = Vlam * (L.J - alpha);
-    a.fx -= Vmu * Fm.x + s * cm.x;
-    a.fy -= Vmu * Fm.y + s * cm.y;
-    a.fz -= Vmu * Fm.z + s * cm.z;
-    const float d = Vmu * dot3(mk, mk);
-    a.hxx += d + Vlam * cm.x * cm.x;
-    a.hxy += Vlam * cm.x * cm.y;
-    a.hxz += Vlam * cm.x * cm.z;
-    a.hyy += d + Vlam * cm.y * cm.y;
-    a.hyz += Vlam * cm.y * cm.z;
-    a.hzz += d + Vlam * cm.z * cm.z;
-}
-
 // Positions of a tet's four slots from the vertex's own position (slot k)
 // and the other three in slot order (a, b, c): slot s < k -> others[s],
 // s == k -> own, s > k -> others[s - 1].
@@ -135,40 +114,72 @@ __device__ __forceinline__ void slot_positions(int k, float4 own, float4 a, floa
     q3 = k < 3 ? c : own;
 }
 
-// Tet terms of one vertex from its D consecutive incidence entries at E:
-// the lanes of the group take entries lane, lane + L, ...; each lane issues
-// the loads of KU entries level by level (incidence entries, then records and
-// neighbour positions together).  The entry addresses depend on the slot
-// only, so the first level is issued with the vertex's own state.
+// One tet seen from the vertex it is solved for, from a pair record: the
+// vertex is the origin of the rest edges, so its shape gradient is
+// m = -(r0 + r1 + r2) = (-S00, -(S01 + S11), -(S02 + S12 + S22)) and
+//   f -= V (mu F m + lam (J - alpha) cof(F) m),
+//   H += V (mu |m|^2 I + lam (cof(F) m)(cof(F) m)^T).
+__device__ __forceinline__ void pair_accumulate(float4 S, float2 S2, float VE, float4 own, float4 qa,
+                                                float4 qb, float4 qc, const StepConsts &K, Acc &a)
+{
+    const float3 e1 = xyz(qa) - xyz(own), e2 = xyz(qb) - xyz(own), e3 = xyz(qc) - xyz(own);
+    const float3 f0 = e1 * S.x;
+    const float3 f1 = e1 * S.y + e2 * S.w;
+    const float3 f2 = e1 * S.z + e2 * S2.x + e3 * S2.y;
+    const float3 c0 = cross3(f1, f2), c1 = cross3(f2, f0), c2 = cross3(f0, f1);
+    const float J = dot3(f0, c0);
+    const float3 m = make_float3(-S.x, -(S.y + S.w), -(S.z + S2.x + S2.y));
+    const float3 Fm = f0 * m.x + f1 * m.y + f2 * m.z;
+    const float3 cm = c0 * m.x + c1 * m.y + c2 * m.z;
+    const float Vmu = VE * K.k_mu, Vlam = VE * K.k_lam;
+    const float s = Vlam * (J - K.alpha);
+    a.fx -= Vmu * Fm.x + s * cm.x;
+    a.fy -= Vmu * Fm.y + s * cm.y;
+    a.fz -= Vmu * Fm.z + s * cm.z;
+    const float d = Vmu * dot3(m, m);
+    a.hxx += d + Vlam * cm.x * cm.x;
+    a.hxy += Vlam * cm.x * cm.y;
+    a.hxz += Vlam * cm.x * cm.z;
+    a.hyy += d + Vlam * cm.y * cm.y;
+    a.hyz += Vlam * cm.y * cm.z;
+    a.hzz += d + Vlam * cm.z * cm.z;
+}
+
+// Tet terms of one vertex from its D consecutive pair records starting at
+// index e0: the lanes of the group take records lane, lane + L, ...; each lane
+// issues the loads of KU records together (their addresses follow from the
+// slot alone, so they go out with the vertex's own state), then the KU x 3
+// neighbour positions together.
 template <int L, int KU>
-__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own,
-                                          const PairEnt *E, int D, int lane, float alpha, Acc &a)
+__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own, size_t e0,
+                                          int D, int lane, const StepConsts &K, Acc &a)
 {
     for (int base = lane; base < D; base += L * KU) {
-        PairEnt ent[KU];
+        int4 pa[KU];
+        float4 ps[KU];
+        float2 pt[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j) {
             const int e = base + j * L;
-            ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
+            if (e < D) {
+                pa[j] = T.pa[e0 + e];
+                ps[j] = T.ps[e0 + e];
+                pt[j] = T.pt[e0 + e];
+            } else {
+                pa[j] = make_int4(-1, 0, 0, 0);
+            }
         }
-        TetRec r[KU];
         float4 qa[KU], qb[KU], qc[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (ent[j].x >= 0) {
-                r[j] = T.rec[ent[j].x >> 2];
-                qa[j] = X[ent[j].y];
-                qb[j] = X[ent[j].z];
-                qc[j] = X[ent[j].w];
+            if (pa[j].x >= 0) {
+                qa[j] = X[pa[j].x];
+                qb[j] = X[pa[j].y];
+                qc[j] = X[pa[j].z];
             }
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (ent[j].x >= 0) {
-                const int k = ent[j].x & 3;
-                float4 q0, q1, q2, q3;
-                slot_positions(k, own, qa[j], qb[j], qc[j], q0, q1, q2, q3);
-                tet_accumulate(r[j], k, q0, q1, q2, q3, alpha, a);
-            }
+            if (pa[j].x >= 0) pair_accumulate(ps[j], pt[j], __int_as_float(pa[j].w), own, qa[j], qb[j], qc[j], K, a);
     }
 }
 
@@ -382,8 +393,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
         xi4 = T.x[p];
         yv = T.y[p];
         if (TETS)
-            tet_terms<L, KU>(T, T.x, xi4, T.ell + ell.x + (size_t)(p - vb) * ell.y, ell.y, lane,
-                             K.alpha, a);
+            tet_terms<L, KU>(T, T.x, xi4, (size_t)ell.x + (size_t)(p - vb) * ell.y, ell.y, lane, K, a);
         if (SPRINGS) {
             const int e1 = T.spr_row[p + 1];
             for (int e = T.spr_row[p] + lane; e < e1; e += L)
@@ -435,6 +445,17 @@ __global__ void k_material(TetRec *rec, const float *vol, const int *tet_perm, c
     b.z = VE * k_mu;
     b.w = VE * k_lam;
     rec[t].b = b;
+}
+
+// V*E of every pair record (padding entries have pair_tet = -1).
+__global__ void k_material_pairs(int4 *pa, const int *pair_tet, const float *vol, const int *tet_perm,
+                                 const float *E, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = pair_tet[i];
+    if (t < 0) return;
+    reinterpret_cast<int *>(pa + i)[3] = __float_as_int(vol[t] * E[tet_perm[t]]);
 }
 
 // y = x^t + h v^t + h^2 a_ext (Eq. inertia) and the initial guess (Sec. 3.7).
@@ -891,6 +912,9 @@ hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConst
     if (T.n_tets == 0) return hipSuccess;
     hipLaunchKernelGGL(k_material, dim3(cdiv(T.n_tets, 256)), dim3(256), 0, s, T.rec, T.vol,
                        T.tet_perm, tet_E, T.n_tets, K.k_mu, K.k_lam);
+    if (T.n_pairs > 0)
+        hipLaunchKernelGGL(k_material_pairs, dim3(cdiv(T.n_pairs, 256)), dim3(256), 0, s, T.pa,
+                           T.pair_tet, T.vol, T.tet_perm, tet_E, T.n_pairs);
     return hipGetLastError();
 }
 
