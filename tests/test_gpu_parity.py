@@ -1,11 +1,13 @@
 """GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
 the same seeded inputs.  Positions must agree within 1e-5 x the bounding-box
 diagonal of each mesh after every step (free-running rollouts)."""
+import dataclasses
 import os
 
 import numpy as np
 import pytest
 
+import oracle as O
 from gpu_util import (assert_parity, gpu_rollout, oracle_rollout, oracle_states, replace,
                       resync_errors, resync_parity, say)
 from paper_2403_06321_amd import workloads as W
@@ -118,6 +120,37 @@ def test_small_cube_four_colorings(mode, coloring):
     xg, _, t = gpu_rollout(w, w.frames, launch_mode=mode)
     assert t.n_colors == 4
     assert_parity(w, xg, xo, label=f"11^3 {coloring} coloring mode {mode}")
+
+
+def test_large_cube_late_state_in_the_benchmarked_configuration():
+    """Full size and full depth: 60 frames x 100 iterations of the benchmarked
+    65^3 workload (smallest-last coloring, autotuned graph launches), then
+    from that GPU state both sides take two 3-iteration steps (the GPU's state
+    resynchronised to the oracle's before each)."""
+    import torch
+    from paper_2403_06321_amd.api import Topology
+    w = W.config_large_cube(coloring="smallest_last")
+    t = Topology.from_workload(w)
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(w.x0, dtype=torch.float32, device=dev).contiguous()
+    v = torch.tensor(w.v0, dtype=torch.float32, device=dev).contiguous()
+    vp = v.clone()
+    E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).contiguous()
+    t.autotune(x, v, vp, E, w.params, 1)
+    for _ in range(60):
+        t.step(x, v, vp, E, w.params, 1)
+    torch.cuda.synchronize()
+    t.check()
+    late = dataclasses.replace(w, x0=x.double().cpu().numpy(), v0=v.double().cpu().numpy())
+    p = replace(w.params, n_iters=3)
+    say("oracle 65^3 from the state after 60 frames ...")
+    states = [(late.x0, late.v0, vp.double().cpu().numpy())]
+    m = O.Model.from_workload(late)
+    O.set_threads(THREADS)
+    for _ in range(2):
+        xo, vo_, vpo, _ = O.step(m, p, *states[-1], w.tet_E)
+        states.append((xo, vo_, vpo))
+    resync_parity(late, states, params=p, launch_mode=1, label="65^3 after 60 frames")
 
 
 @pytest.mark.parametrize("coloring", ["lattice4", "smallest_last"])
