@@ -48,8 +48,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, pa, ps, pt, pair_tet, ell_info, spr_row, spr_ent,
-        perm, mass, color_off;
+    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, pa, ps, pt, pair_tet, ell_info, spr_ell,
+        spr_info, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib, ebar;
     // mesh-mesh contacts (only when the topology has a surface)
@@ -113,6 +113,8 @@ struct vbd_topology_s {
     std::vector<int32_t> tet_order, tet_rank;   // stored position <-> caller's tet id
     std::vector<int2> ell_info;                 // per color {first entry, padded degree}
     size_t ell_total = 0;
+    std::vector<int2> spr_info;                 // the same for springs
+    size_t spr_total = 0;
     std::vector<float> spr_len;
     std::vector<double> phase_bytes;
     std::vector<int64_t> phase_updates;
@@ -168,8 +170,8 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.pt = take(sizeof(float2) * T.ell_total);
     L.pair_tet = take(sizeof(int32_t) * T.ell_total);
     L.ell_info = take(sizeof(int2) * (size_t)T.n_colors);
-    L.spr_row = take(sizeof(int32_t) * (size_t)(T.n_free + 1));
-    L.spr_ent = take(sizeof(int2) * T.spr_nbr_orig.size());
+    L.spr_ell = take(sizeof(int2) * T.spr_total);
+    L.spr_info = take(sizeof(int2) * (size_t)T.n_colors);
     L.perm = take(sizeof(int32_t) * nv);
     L.mass = take(sizeof(float) * nv);
     L.color_off = take(sizeof(int32_t) * (size_t)(T.n_colors + 1));
@@ -238,8 +240,8 @@ void set_dev_pointers(vbd_topology_s &T)
     D.pair_tet = (const int *)(b + L.pair_tet);
     D.n_pairs = (long long)T.ell_total;
     D.ell_info = (const int2 *)(b + L.ell_info);
-    D.spr_row = (const int *)(b + L.spr_row);
-    D.spr_ent = (const int2 *)(b + L.spr_ent);
+    D.spr_ell = (const int2 *)(b + L.spr_ell);
+    D.spr_info = (const int2 *)(b + L.spr_info);
     D.perm = (const int *)(b + L.perm);
     D.mass = (const float *)(b + L.mass);
     D.color_off = (const int *)(b + L.color_off);
@@ -537,6 +539,15 @@ void build_csr(vbd_topology_s &T)
         T.ell_info[c] = make_int2((int)T.ell_total, dmax);
         T.ell_total += (size_t)dmax * (size_t)(T.color_off[c + 1] - T.color_off[c]);
     }
+    T.spr_info.assign(T.n_colors, make_int2(0, 0));
+    T.spr_total = 0;
+    for (int c = 0; c < T.n_colors; ++c) {
+        int dmax = 0;
+        for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s)
+            dmax = std::max(dmax, T.spr_row[s + 1] - T.spr_row[s]);
+        T.spr_info[c] = make_int2((int)T.spr_total, dmax);
+        T.spr_total += (size_t)dmax * (size_t)(T.color_off[c + 1] - T.color_off[c]);
+    }
     // stored tet order: grouped by the sorted colors of the tet's 4 vertices
     // (then by tet id), so tets sharing a cache line are read in the same
     // color phases
@@ -694,6 +705,13 @@ void build_surface(vbd_topology_s &T)
         for (int k = 0; k < 3; ++k) T.sv_tri[pos[idx[T.iperm[T.surf[3 * (size_t)t + k]]]]++] = t;
 }
 
+// {first tet entry, padded tet degree, first spring entry, padded spring
+// degree} of color c
+int4 incidence(const vbd_topology_s &T, int c)
+{
+    return make_int4(T.ell_info[c].x, T.ell_info[c].y, T.spr_info[c].x, T.spr_info[c].y);
+}
+
 // --------------------------------------------------------------- profiling --
 vbd_status prof_begin(vbd_topology_s &T, hipStream_t s, ProfileEvent &ev)
 {
@@ -756,12 +774,12 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
                 if (mc) {
                     if (T.color_off[c + 1] > T.color_off[c]) {
                         HIP_TRY(launch_solve_contacts(T.dev, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
-                                                      T.ell_info[c], pend_b, pend_e, tets, springs, T.cfg, s));
+                                                      incidence(T, c), pend_b, pend_e, tets, springs, T.cfg, s));
                         pend_b = T.color_off[c];
                         pend_e = T.color_off[c + 1];
                     }
                 } else
-                    HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], T.ell_info[c], tets, springs, T.cfg, s));
+                    HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), tets, springs, T.cfg, s));
                 if (T.color_off[c + 1] > T.color_off[c]) {
                     ++launches;
                     ev.bytes += T.phase_bytes[c];
@@ -849,7 +867,7 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
         HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
         D.x = Sn;
         for (int c = 0; c < T.n_colors; ++c)
-            HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], T.ell_info[c], true, false, T.cfg, s));
+            HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), true, false, T.cfg, s));
     }
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
@@ -1071,8 +1089,9 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     if (!T || !dev_ptr) return fail(VBD_E_INVALID_ARG, "NULL argument");
     if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color first");
     if ((uintptr_t)dev_ptr % kAlign) return fail(VBD_E_INVALID_ARG, "workspace must be 256-byte aligned");
-    if (T->ell_total > (size_t)INT32_MAX)
-        return fail(VBD_E_INVALID_ARG, "topology too large: %zu padded incidence entries", T->ell_total);
+    if (T->ell_total > (size_t)INT32_MAX || T->spr_total > (size_t)INT32_MAX)
+        return fail(VBD_E_INVALID_ARG, "topology too large: %zu / %zu padded incidence entries",
+                    T->ell_total, T->spr_total);
     // the largest backward iteration count that fits
     Layout L0 = make_layout(*T, 0);
     if (bytes < L0.total) return fail(VBD_E_NO_WORKSPACE, "workspace too small: %zu < %zu", bytes, L0.total);
@@ -1118,12 +1137,18 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
             if (j != k) o[n++] = T->iperm[q[j]];
         tet_ent_dev[e] = make_int4((T->tet_rank[t] << 2) | k, o[0], o[1], o[2]);
     }
-    std::vector<int2> spr(T->spr_nbr_orig.size());
-    for (size_t e = 0; e < spr.size(); ++e) {
-        float L = T->spr_len[e];
-        int bits;
-        std::memcpy(&bits, &L, 4);
-        spr[e] = make_int2(T->iperm[T->spr_nbr_orig[e]], bits);
+    std::vector<int2> spr(T->spr_total, make_int2(-1, 0));
+    for (int c = 0; c < T->n_colors; ++c) {
+        const int2 info = T->spr_info[c];
+        for (int sl = T->color_off[c]; sl < T->color_off[c + 1]; ++sl) {
+            const size_t base = (size_t)info.x + (size_t)(sl - T->color_off[c]) * (size_t)info.y;
+            for (int e = T->spr_row[sl]; e < T->spr_row[sl + 1]; ++e) {
+                float L = T->spr_len[e];
+                int bits;
+                std::memcpy(&bits, &L, 4);
+                spr[base + (size_t)(e - T->spr_row[sl])] = make_int2(T->iperm[T->spr_nbr_orig[e]], bits);
+            }
+        }
     }
     std::vector<float> massp(T->nv);
     for (int sl = 0; sl < T->nv; ++sl) massp[sl] = (float)T->mass[T->perm[sl]];
@@ -1180,8 +1205,8 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         HIP_TRY(up(T->lay.pair_tet, ptet.data(), 4 * ptet.size()));
         HIP_TRY(up(T->lay.ell_info, T->ell_info.data(), sizeof(int2) * T->ell_info.size()));
     }
-    HIP_TRY(up(T->lay.spr_row, T->spr_row.data(), 4 * T->spr_row.size()));
-    HIP_TRY(up(T->lay.spr_ent, spr.data(), sizeof(int2) * spr.size()));
+    HIP_TRY(up(T->lay.spr_ell, spr.data(), sizeof(int2) * spr.size()));
+    HIP_TRY(up(T->lay.spr_info, T->spr_info.data(), sizeof(int2) * T->spr_info.size()));
     HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));
     HIP_TRY(up(T->lay.mass, massp.data(), 4 * massp.size()));
     HIP_TRY(up(T->lay.color_off, T->color_off.data(), 4 * T->color_off.size()));
@@ -1416,7 +1441,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
         } else {
             for (int it = 0; it < sweeps; ++it)
                 for (int c = 0; c < T->n_colors; ++c)
-                    HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], T->ell_info[c], tets, springs, cf, s));
+                    HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], incidence(*T, c), tets, springs, cf, s));
         }
         HIP_TRY(hipEventRecord(b, s));
         HIP_TRY(hipEventSynchronize(b));

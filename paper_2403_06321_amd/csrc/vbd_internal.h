@@ -78,8 +78,11 @@ struct DevTopo {
     const int *pair_tet;               // stored tet of each pair entry (-1: padding)
     const int2 *ell_info;              // [n_colors] {first entry, padded degree}
     long long n_pairs;                 // padded entries over all colors
-    const int *spr_row;
-    const int2 *spr_ent;               // {neighbour permuted id, float bits of rest length}
+    // springs of every free vertex in the same per-color padded layout:
+    // spr_info[c] = {first entry, padded degree}; entries {neighbour slot,
+    // float bits of rest length}, padding x = -1
+    const int2 *spr_ell;
+    const int2 *spr_info;
     const int *perm;                   // permuted slot -> original id
     const float *mass;                 // permuted
     const int *color_off;              // [n_colors + 1]
@@ -135,15 +138,16 @@ hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConst
                            hipStream_t s);
 hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,
                           const StepConsts &K, bool reset_flags, hipStream_t s);
-// ell: {first entry, padded degree} of the color (DevTopo::ell_info).
-hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end, int2 ell,
+// inc: {first tet entry, padded tet degree, first spring entry, padded spring
+// degree} of the color (DevTopo::ell_info, DevTopo::spr_info).
+hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end, int4 inc,
                         bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
 // Color solve with mesh-mesh contact elements.  Updates T.x in place; contact
 // partners of the same color are read from S.xsnap (their positions before
 // the phase).  [prev_begin, prev_end): the previously solved color, whose
 // snapshot the kernel refreshes from T.x.
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K,
-                                 int v_begin, int v_end, int2 ell, int prev_begin, int prev_end,
+                                 int v_begin, int v_end, int4 inc, int prev_begin, int prev_end,
                                  bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
 // Detection on the permuted positions X (T.xt or T.x) into S.ctri and the
 // corner CSR (S.crow, S.cent).

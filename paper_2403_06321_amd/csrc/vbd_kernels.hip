@@ -208,6 +208,26 @@ __device__ __forceinline__ void spring_contrib(const float4 *X, float3 xi, int2 
     a.hzz += ci + cu * u.z * u.z;
 }
 
+// Spring terms of one vertex from its D consecutive padded entries at E: each
+// lane loads up to 4 entries together, then their neighbour positions.
+template <int L>
+__device__ __forceinline__ void spring_terms(const float4 *X, float3 xi, const int2 *E, int D,
+                                             int lane, const StepConsts &K, Acc &a)
+{
+    constexpr int SU = 4;
+    for (int base = lane; base < D; base += L * SU) {
+        int2 se[SU];
+#pragma unroll
+        for (int j = 0; j < SU; ++j) {
+            const int e = base + j * L;
+            se[j] = (e < D) ? E[e] : make_int2(-1, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < SU; ++j)
+            if (se[j].x >= 0) spring_contrib(X, xi, se[j], K.spring_k, K.spring_psd, a);
+    }
+}
+
 template <int L>
 __device__ __forceinline__ void acc_reduce(Acc &a)
 {
@@ -378,11 +398,11 @@ __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &
 
 // One vertex update by a group of L lanes.  All lanes of the wave must call
 // this (inactive groups pass active = false) because of the DPP reduction.
-// The phase covers slots [vb, ve) of one color with incidence layout ell.
+// The phase covers slots [vb, ve) of one color with incidence layout inc.
 // MC: mesh-mesh contacts.
 template <int L, int KU, bool TETS, bool SPRINGS, bool MC = false>
 __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
-                                             int lane, bool active, int vb, int ve, int2 ell,
+                                             int lane, bool active, int vb, int ve, int4 inc,
                                              const DevSurf *S = nullptr)
 {
     Acc a;
@@ -393,12 +413,10 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
         xi4 = T.x[p];
         yv = T.y[p];
         if (TETS)
-            tet_terms<L, KU>(T, T.x, xi4, (size_t)ell.x + (size_t)(p - vb) * ell.y, ell.y, lane, K, a);
-        if (SPRINGS) {
-            const int e1 = T.spr_row[p + 1];
-            for (int e = T.spr_row[p] + lane; e < e1; e += L)
-                spring_contrib(T.x, xyz(xi4), T.spr_ent[e], K.spring_k, K.spring_psd, a);
-        }
+            tet_terms<L, KU>(T, T.x, xi4, (size_t)inc.x + (size_t)(p - vb) * inc.y, inc.y, lane, K, a);
+        if (SPRINGS)
+            spring_terms<L>(T.x, xyz(xi4), T.spr_ell + (size_t)inc.z + (size_t)(p - vb) * inc.w, inc.w,
+                            lane, K, a);
     }
     if (MC) {
         // Rayleigh damping applies to the material Hessian only: contact
@@ -504,12 +522,12 @@ constexpr int kMaxBlock = 512;
 
 template <int L, int KU, bool TETS, bool SPRINGS>
 __global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, int v_begin,
-                                                     int v_end, int2 ell, int remap)
+                                                     int v_end, int4 inc, int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin, v_end, ell);
+    solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin, v_end, inc);
 }
 
 // Color phase with mesh contacts.  The previously solved color's snapshot is
@@ -517,7 +535,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, in
 // snapshot is read.
 template <int L, int KU, bool TETS, bool SPRINGS>
 __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, StepConsts K,
-                                                        int v_begin, int v_end, int2 ell,
+                                                        int v_begin, int v_end, int4 inc,
                                                         int prev_begin, int prev_end, int remap)
 {
     for (int q = prev_begin + blockIdx.x * blockDim.x + threadIdx.x; q < prev_end;
@@ -527,7 +545,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, St
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
     solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin,
-                                             v_end, ell, &S);
+                                             v_end, inc, &S);
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -630,7 +648,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
     for (int it = 1; it <= n_iters; ++it) {
         for (int c = 0; c < T.n_colors; ++c) {
             const int vb = T.color_off[c], ve = T.color_off[c + 1];
-            const int2 ell = T.ell_info[c];
+            const int2 te = T.ell_info[c], se = T.spr_info[c];
+            const int4 inc = make_int4(te.x, te.y, se.x, se.y);
             // contiguous chunk of the color per logical block
             const int n = ve - vb;
             const int chunk = (n + nb - 1) / nb;
@@ -638,7 +657,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
             const int cend = min(cb + chunk, ve);
             for (int base = cb; base < cb + chunk; base += G) {
                 const int p = base + g;
-                solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, lane, p < cend, vb, ve, ell);
+                solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, lane, p < cend, vb, ve, inc);
             }
             ++nbar;
             if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
@@ -927,88 +946,88 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
 }
 
 template <int L, int KU>
-static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, int2 ell,
+static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, int4 inc,
                                  bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
     if (tets && springs)
-        hipLaunchKernelGGL((k_solve<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, ell, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     return hipGetLastError();
 }
 
 template <int L>
-static hipError_t solve_unroll(const DevTopo &T, const StepConsts &K, int vb, int ve, int2 ell,
+static hipError_t solve_unroll(const DevTopo &T, const StepConsts &K, int vb, int ve, int4 inc,
                                bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     switch (cfg.unroll) {
-    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, ell, tets, springs, cfg, s);
-    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, ell, tets, springs, cfg, s);
-    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, inc, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, int2 ell, bool tets,
+hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, int4 inc, bool tets,
                         bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
-    case 4: return solve_unroll<4>(T, K, vb, ve, ell, tets, springs, cfg, s);
-    case 8: return solve_unroll<8>(T, K, vb, ve, ell, tets, springs, cfg, s);
-    case 16: return solve_unroll<16>(T, K, vb, ve, ell, tets, springs, cfg, s);
-    case 32: return solve_unroll<32>(T, K, vb, ve, ell, tets, springs, cfg, s);
+    case 4: return solve_unroll<4>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 8: return solve_unroll<8>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 16: return solve_unroll<16>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 32: return solve_unroll<32>(T, K, vb, ve, inc, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int L, int KU>
 static hipError_t solve_mc_dispatch(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                    int ve, int2 ell, int pb, int pe, bool tets, bool springs,
+                                    int ve, int4 inc, int pb, int pe, bool tets, bool springs,
                                     const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
     if (tets && springs)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, ell, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     return hipGetLastError();
 }
 
 template <int L>
 static hipError_t solve_mc_unroll(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                  int ve, int2 ell, int pb, int pe, bool tets, bool springs,
+                                  int ve, int4 inc, int pb, int pe, bool tets, bool springs,
                                   const LaunchCfg &cfg, hipStream_t s)
 {
     switch (cfg.unroll) {
-    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
-    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
-    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
-                                 int ve, int2 ell, int pb, int pe, bool tets, bool springs,
+                                 int ve, int4 inc, int pb, int pe, bool tets, bool springs,
                                  const LaunchCfg &cfg, hipStream_t s)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
-    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
-    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
-    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
-    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, ell, pb, pe, tets, springs, cfg, s);
+    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
