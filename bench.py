@@ -157,7 +157,7 @@ def main():
 
     if args.profile_only == "stack":
         # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, plain launches
-        ws = W.config_block_stack(cols=8, levels=4, n=9)
+        ws = W.config_block_stack(cols=8, levels=4, n=9, coloring="smallest_last")
         ts = Topology.from_workload(ws)
         secs, upd = time_frames(ts, ws, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
         print(json.dumps({"profile": "stack", "ms_per_frame": secs / args.steps * 1e3}))
@@ -166,7 +166,7 @@ def main():
     if args.profile_only == "adjoint":
         # forward + backward through the 33^3 differentiable workload
         from paper_2403_06321_amd.api import Rollout
-        wd = W.config_differentiable()
+        wd = W.config_differentiable(coloring="smallest_last")
         td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
         x0, v0, _, E = state(wd, dev)
         v0.requires_grad_(True); E.requires_grad_(True)
@@ -325,7 +325,7 @@ def extras(dev, W, Topology):
     torch.cuda.empty_cache()
     # adjoint: differentiable 33^3 workload, forward + backward through 30 frames
     from paper_2403_06321_amd.api import Rollout
-    wd = W.config_differentiable()
+    wd = W.config_differentiable(coloring="smallest_last")
     td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
     x0, v0, _, E = state(wd, dev)
     v0.requires_grad_(True); E.requires_grad_(True)
@@ -355,11 +355,12 @@ def extras(dev, W, Topology):
     res["adjoint"] = dict(forward_backward_ms=ms, forward_only_ms=ms_fwd,
                           updates_per_s_forward_backward=upd / (ms * 1e-3),
                           updates_per_s_forward=upd / (ms_fwd * 1e-3),
-                          workload="33^3 cube, 30 frames x 20 iterations, loss on final centroid")
+                          workload="33^3 cube, 30 frames x 20 iterations, loss on final centroid, "
+                                   f"smallest-last coloring ({td.n_colors} colors)")
     log(f"[bench] adjoint fwd+bwd {ms:.1f} ms, forward {ms_fwd:.1f} ms")
     del td
     # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, graph launches
-    ws = W.config_block_stack(cols=8, levels=4, n=9)
+    ws = W.config_block_stack(cols=8, levels=4, n=9, coloring="smallest_last")
     ts = Topology.from_workload(ws)
     secs, upd = time_frames(ts, ws, MODES["graph"], 10, 2, dev)
     xs = state(ws, dev)[0]
@@ -372,7 +373,8 @@ def extras(dev, W, Topology):
     res["block_stack_contacts_graph"] = dict(
         updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100,
         detection_ms=a.elapsed_time(b) / 10, contacts_at_rest=int((tri >= 0).sum().item()),
-        workload=f"{ws.name}: {ws.n_verts} vertices, {ws.n_tets} tets, {ws.params.n_iters} iterations")
+        workload=f"{ws.name}: {ws.n_verts} vertices, {ws.n_tets} tets, {ws.params.n_iters} iterations, "
+                 f"smallest-last coloring ({ts.n_colors} colors)")
     log(f"[bench] block stack {res['block_stack_contacts_graph']['updates_per_s']:.3e} v-upd/s, "
         f"detection {res['block_stack_contacts_graph']['detection_ms']:.3f} ms")
     del ts

@@ -297,7 +297,7 @@ def config_batch(n_meshes: int = 512, seed: int = 3, lo: int = 4, hi: int = 33,
 
 def config_block_stack(cols: int = 2, levels: int = 3, n: int = 5, seed: int = 5,
                        overlap: float = 0.002, gap: float = 0.5 * EDGE, frames: int = 10,
-                       n_iters: int = 20, contact_k: float = 1e4) -> Workload:
+                       n_iters: int = 20, contact_k: float = 1e4, coloring: str = "id") -> Workload:
     """cols x cols columns of `levels` stacked n^3 lattice cubes (separate
     meshes).  Each cube sinks `overlap` into the one below it; odd levels are
     shifted by (0.33, 0.41) lattice cells so no vertex lies above an edge of
@@ -334,10 +334,12 @@ def config_block_stack(cols: int = 2, levels: int = 3, n: int = 5, seed: int = 5
     return Workload(name=f"stack of {levels} x {cols}x{cols} cubes {n}^3", rest=rest, tets=tets,
                     pinned=np.concatenate(pins), x0=rest.copy(), v0=np.zeros((nv, 3)),
                     tet_E=np.concatenate(Es), vert_offsets=np.array(vo, np.int64),
-                    tet_offsets=np.array(to, np.int64), params=params, frames=frames)
+                    tet_offsets=np.array(to, np.int64), params=params, frames=frames,
+                    coloring=coloring)
 
 
-def config_differentiable(n: int = 33, seed: int = 4, frames: int = 30, n_iters: int = 20) -> Workload:
+def config_differentiable(n: int = 33, seed: int = 4, frames: int = 30, n_iters: int = 20,
+                          coloring: str = "id") -> Workload:
     """n^3 cube, per-tet E log-uniform, v0 = 0, seeded target for a centroid loss."""
     rng = np.random.default_rng(seed)
     rest, tets = cube_lattice(n, n, n)
@@ -352,7 +354,7 @@ def config_differentiable(n: int = 33, seed: int = 4, frames: int = 30, n_iters:
     target = x0.mean(axis=0) + rng.uniform(-0.5, 0.5, size=3)
     return Workload(name=f"differentiable cube {n}^3", rest=rest, tets=tets, pinned=pinned,
                     x0=x0, v0=v0, tet_E=tet_E, params=StepParams(n_iters=n_iters),
-                    frames=frames, target=target)
+                    frames=frames, target=target, coloring=coloring)
 
 
 def single_particle_chain(n: int = 2, length: float = 0.1, k: float = 100.0, m: float = 0.01):
