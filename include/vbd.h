@@ -91,7 +91,8 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *desc, vbd_topology *out);
  * two vertices of one color; first-fit in ascending vertex id.  Then builds
  * the color-sorted vertex permutation (free vertices by (color, id), pinned
  * vertices last by id), the tet incidence CSR of every vertex slot and the
- * spring incidence CSR of every free slot.  Host, synchronous.
+ * spring incidence CSR of every free slot (from which vbd_bind_workspace lays
+ * out the per-color padded records the kernels read).  Host, synchronous.
  * colors_out: host [n_verts] or NULL. */
 vbd_status vbd_color(vbd_topology topo, int32_t *n_colors_out, int32_t *colors_out);
 

@@ -1,6 +1,8 @@
 // Host side of the VBD library: C ABI, topology preprocessing (FP64 rest
-// data, greedy coloring, color-sorted CSR), workspace layout, step
-// orchestration (plain / hipGraph / persistent), autotuner and profiling.
+// data, greedy or given coloring, color-sorted incidence, per-color padded
+// pair records, mesh surfaces), workspace layout, step orchestration (plain /
+// hipGraph / persistent, mesh-contact detection), backward, autotuner and
+// profiling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

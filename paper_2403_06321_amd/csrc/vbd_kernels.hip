@@ -3,8 +3,9 @@
 // Vertex Block Descent (Chen, Liu, Yang, Yuksel, ACM TOG 2024).  A color
 // phase updates every free vertex of one color in parallel (Sec. 3.9).  One
 // vertex is handled by a group of L lanes of a wave64: the lanes stride over
-// the vertex's incident elements (color-sorted CSR), each accumulating the
-// element force and 3x3 Hessian block, then the group reduces the 9 values
+// the vertex's incident elements (per-color padded records whose addresses
+// follow from the vertex's slot), each accumulating the element force and
+// 3x3 Hessian block, then the group reduces the 9 values
 // with DPP row operations, adds inertia / damping / contact / friction terms
 // and solves the 3x3 system analytically (Sec. 3.2).
 #include "vbd_device.h"
