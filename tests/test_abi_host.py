@@ -248,3 +248,17 @@ def test_given_coloring_layout_and_validation():
     assert _status(lambda: Topology.from_workload(w, bind=False, colors=bad)) == -1
     neg = colors.copy(); neg[3] = -1
     assert _status(lambda: Topology.from_workload(w, bind=False, colors=neg)) == -1
+
+
+def test_coloring_order_errors():
+    L = N.lib()
+    w = W.tet_cube(3, 0)
+    t = Topology.from_workload(w, bind=False)
+    nc = C.c_int32()
+    assert L.vbd_color_greedy(t._h, 7, C.byref(nc), None) == -1
+    assert b"order" in L.vbd_last_error()
+    # switching the order before binding recolors
+    assert L.vbd_color_greedy(t._h, N.COLOR_SMALLEST_LAST, C.byref(nc), None) == 0 and nc.value == 4
+    assert L.vbd_color_greedy(t._h, N.COLOR_ID_ORDER, C.byref(nc), None) == 0
+    assert nc.value == O.color_greedy(w.n_verts, w.tets)[1]
+    assert np.array_equal(t.query(N.Q_COLORS), O.color_greedy(w.n_verts, w.tets)[0])

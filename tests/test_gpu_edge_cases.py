@@ -108,3 +108,20 @@ def test_determinant_skip_everywhere():
     xg, _, _ = gpu_rollout(w, 1, params=p)
     say(f"skip-all: max |x_gpu - x_oracle| = {np.abs(xg[0] - xo).max():.2e}")
     assert np.allclose(xg[0], xo, rtol=0, atol=1e-6)
+
+
+def test_recoloring_after_bind_and_detection_without_contacts_are_refused():
+    import ctypes as C
+    import torch
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    w = W.config_block_stack(cols=1, levels=2, n=3)
+    t = Topology.from_workload(w)
+    nc = C.c_int32()
+    assert N.lib().vbd_color_greedy(t._h, N.COLOR_SMALLEST_LAST, C.byref(nc), None) == -1
+    colors = np.zeros(w.n_verts, np.int32)
+    assert N.lib().vbd_color_given(t._h, colors.ctypes.data) == -1
+    x = torch.tensor(w.x0, dtype=torch.float32, device="cuda")
+    with pytest.raises(N.VBDError) as e:
+        t.detect_contacts(x, dataclasses.replace(w.params, mesh_contacts=False))
+    assert e.value.status == -1
