@@ -391,6 +391,19 @@ def extras(dev, W, Topology):
                                      frac=roof["achieved_gbs"] / HBM_PEAK_GBS)
     log(f"[bench] cloth {res['cloth_persistent_graph']['updates_per_s']:.3e} / "
         f"{res['cloth_graph']['updates_per_s']:.3e} v-upd/s")
+    del tc
+    # the same cloth colored by DSATUR: 5 colors instead of 7
+    wd = W.config_cloth(coloring="dsatur")
+    td = Topology.from_workload(wd)
+    secs, upd = time_frames(td, wd, MODES["persistent_graph"], 10, 3, dev)
+    res["cloth_dsatur_persistent_graph"] = dict(updates_per_s=upd * 10 / secs,
+                                                ms_per_frame=secs * 100, n_colors=td.n_colors)
+    secs, upd = time_frames(td, wd, MODES["graph"], 10, 3, dev)
+    res["cloth_dsatur_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100,
+                                     n_colors=td.n_colors)
+    log(f"[bench] cloth dsatur ({td.n_colors} colors) "
+        f"{res['cloth_dsatur_persistent_graph']['updates_per_s']:.3e} / "
+        f"{res['cloth_dsatur_graph']['updates_per_s']:.3e} v-upd/s")
     return res
 
 

@@ -98,13 +98,18 @@ vbd_status vbd_color(vbd_topology topo, int32_t *n_colors_out, int32_t *colors_o
 
 /* Vertex orders of the greedy first-fit coloring (vbd_color_greedy). */
 enum { VBD_COLOR_ID_ORDER = 0,      /* ascending vertex id (what vbd_color uses) */
-       VBD_COLOR_SMALLEST_LAST = 1  /* smallest-last order: repeatedly remove a vertex of
+       VBD_COLOR_SMALLEST_LAST = 1, /* smallest-last order: repeatedly remove a vertex of
                                        smallest remaining degree (ties: smallest id),
                                        color in reverse removal order (Matula and Beck
                                        1983); 4 colors on a Kuhn-split lattice */
+       VBD_COLOR_DSATUR = 2         /* DSATUR (Brelaz 1979): next the uncolored vertex with
+                                       the most distinct neighbour colors (ties: larger
+                                       degree, then smaller id), smallest free color; 5
+                                       colors on the spring cloth */
 };
 /* vbd_color with a choice of vertex order: each vertex, in that order, takes
- * the smallest color not used by an already colored neighbour.  Recoloring
+ * the smallest color not used by an already colored neighbour (for DSATUR
+ * the order is chosen as the coloring proceeds).  Recoloring
  * with another order is allowed before vbd_bind_workspace. */
 vbd_status vbd_color_greedy(vbd_topology topo, int32_t order, int32_t *n_colors_out,
                             int32_t *colors_out);

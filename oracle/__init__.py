@@ -30,6 +30,8 @@ def lib():
         L.oracle_color_greedy.restype = i32
         L.oracle_color_smallest_last.argtypes = [i32, i32, p, i32, p, p]
         L.oracle_color_smallest_last.restype = i32
+        L.oracle_color_dsatur.argtypes = [i32, i32, p, i32, p, p]
+        L.oracle_color_dsatur.restype = i32
         L.oracle_tet_rest.argtypes = [i32, p, p, p, p]
         L.oracle_tet_rest.restype = i32
         L.oracle_lumped_mass.argtypes = [i32, i32, p, p, d, p]
@@ -96,12 +98,14 @@ def set_threads(n: int) -> None:
 
 
 def color_greedy(n_verts, tets, springs=None, order="id"):
-    """Greedy first-fit coloring; order "id" (ascending vertex id) or
-    "smallest_last" (Matula-Beck smallest-last order)."""
+    """Greedy coloring; order "id" (first fit in ascending vertex id),
+    "smallest_last" (first fit in Matula-Beck smallest-last order) or
+    "dsatur" (Brelaz's saturation order)."""
     tets = np.ascontiguousarray(tets, np.int32)
     sp = None if springs is None or len(springs) == 0 else np.ascontiguousarray(springs, np.int32)
     colors = np.zeros(n_verts, np.int32)
-    fn = {"id": lib().oracle_color_greedy, "smallest_last": lib().oracle_color_smallest_last}[order]
+    fn = {"id": lib().oracle_color_greedy, "smallest_last": lib().oracle_color_smallest_last,
+          "dsatur": lib().oracle_color_dsatur}[order]
     nc = fn(n_verts, tets.shape[0], _ptr(tets), 0 if sp is None else sp.shape[0], _ptr(sp),
             _ptr(colors))
     return colors, int(nc)

@@ -156,6 +156,79 @@ int32_t oracle_color_smallest_last(int32_t n_verts, int32_t n_tets, const int32_
     return n_colors;
 }
 
+/* DSATUR (Brelaz, Comm. ACM 22(4), 1979): repeatedly color the uncolored
+ * vertex with the most distinct colors among its neighbours (ties: larger
+ * degree, then smaller id) with the smallest color none of its neighbours
+ * has.  Same adjacency as oracle_color_greedy. */
+int32_t oracle_color_dsatur(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                            int32_t n_springs, const int32_t *springs, int32_t *colors)
+{
+    size_t np = (size_t)n_tets * 12 + (size_t)n_springs * 2;
+    Pair *pr = (Pair *)malloc(sizeof(Pair) * (np + 1));
+    size_t q = 0;
+    for (int t = 0; t < n_tets; ++t)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (a != b) { pr[q].a = tets[4 * t + a]; pr[q].b = tets[4 * t + b]; ++q; }
+    for (int s = 0; s < n_springs; ++s) {
+        pr[q].a = springs[2 * s]; pr[q].b = springs[2 * s + 1]; ++q;
+        pr[q].a = springs[2 * s + 1]; pr[q].b = springs[2 * s]; ++q;
+    }
+    qsort(pr, q, sizeof(Pair), pair_cmp);
+    size_t u = 0;
+    for (size_t k = 0; k < q; ++k)
+        if (u == 0 || pair_cmp(&pr[u - 1], &pr[k]) != 0) pr[u++] = pr[k];
+    q = u;
+    int32_t *row = (int32_t *)calloc((size_t)n_verts + 1, sizeof(int32_t));
+    for (size_t k = 0; k < q; ++k) row[pr[k].a + 1]++;
+    for (int i = 0; i < n_verts; ++i) row[i + 1] += row[i];
+    /* per vertex: saturation count and a bitset of neighbour colors, grown on demand */
+    int32_t *sat = (int32_t *)calloc((size_t)n_verts + 1, sizeof(int32_t));
+    int32_t words = 1;
+    uint64_t *seen = (uint64_t *)calloc((size_t)n_verts * words + 1, sizeof(uint64_t));
+    /* heap key, smaller first: (2047 - sat, maxdeg - deg, id) */
+    int32_t maxdeg = 0;
+    for (int v = 0; v < n_verts; ++v) if (row[v + 1] - row[v] > maxdeg) maxdeg = row[v + 1] - row[v];
+    /* the degree field has 20 bits */
+    const int64_t SAT_SHIFT = 52, DEG_SHIFT = 32;
+    /* 11 bits of saturation keep the key positive (at most 2047 colors) */
+    #define DKEY(v, s) ((((int64_t)(2047 - (s))) << SAT_SHIFT) | (((int64_t)(maxdeg - (row[(v) + 1] - row[(v)]))) << DEG_SHIFT) | (int64_t)(uint32_t)(v))
+    Heap h = {(int64_t *)malloc(sizeof(int64_t) * (q + (size_t)n_verts + 1)), 0};
+    for (int v = 0; v < n_verts; ++v) { colors[v] = -1; heap_push(&h, DKEY(v, 0)); }
+    int32_t n_colors = 0;
+    while (h.n > 0) {
+        int64_t key = heap_pop(&h);
+        int32_t v = (int32_t)(key & 0xffffffff);
+        int32_t s = 2047 - (int32_t)(key >> SAT_SHIFT);
+        if (colors[v] >= 0 || s != sat[v]) continue;      /* stale */
+        int c = 0;
+        while (c < 64 * words && (seen[(size_t)v * words + (size_t)(c >> 6)] >> (c & 63) & 1ull)) ++c;
+        colors[v] = c;
+        if (c + 1 > n_colors) n_colors = c + 1;
+        if (c >= 64 * words) {
+            /* widen every bitset */
+            int32_t nw = words * 2;
+            uint64_t *ns = (uint64_t *)calloc((size_t)n_verts * nw + 1, sizeof(uint64_t));
+            for (int x = 0; x < n_verts; ++x)
+                for (int k = 0; k < words; ++k) ns[(size_t)x * nw + k] = seen[(size_t)x * words + k];
+            free(seen); seen = ns; words = nw;
+        }
+        for (int k = row[v]; k < row[v + 1]; ++k) {
+            int w = pr[k].b;
+            if (colors[w] >= 0) continue;
+            uint64_t *bits = seen + (size_t)w * words;
+            if (!(bits[c >> 6] >> (c & 63) & 1ull)) {
+                bits[c >> 6] |= 1ull << (c & 63);
+                sat[w]++;
+                heap_push(&h, DKEY(w, sat[w]));
+            }
+        }
+    }
+    #undef DKEY
+    free(h.k); free(seen); free(sat); free(row); free(pr);
+    return n_colors;
+}
+
 /* D_m = [X1-X0, X2-X0, X3-X0]; Dminv by Gauss-Jordan elimination with partial
  * pivoting; V = |det D_m| / 6. */
 int32_t oracle_tet_rest(int32_t n_tets, const int32_t *tets, const double *rest,

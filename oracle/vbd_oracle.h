@@ -73,6 +73,10 @@ int32_t oracle_color_greedy(int32_t n_verts, int32_t n_tets, const int32_t *tets
  * by smallest id; colored in reverse removal order).  Returns n_colors. */
 int32_t oracle_color_smallest_last(int32_t n_verts, int32_t n_tets, const int32_t *tets,
                                    int32_t n_springs, const int32_t *springs, int32_t *colors);
+/* DSATUR: most distinct neighbour colors first (ties: larger degree, then
+ * smaller id), smallest free color.  Returns n_colors. */
+int32_t oracle_color_dsatur(int32_t n_verts, int32_t n_tets, const int32_t *tets,
+                            int32_t n_springs, const int32_t *springs, int32_t *colors);
 /* Rest edge matrix inverse and volume per tet; returns 0, or -1-t for the first
  * degenerate tet t. */
 int32_t oracle_tet_rest(int32_t n_tets, const int32_t *tets, const double *rest,

@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "VBD_OK", -1: "VBD_E_INVALID_ARG", -2: "VBD_E_TOPOLOGY", -3: 
                 -7: "VBD_E_NONFINITE", -8: "VBD_E_DEVICE"}
 
 LAUNCH_PLAIN, LAUNCH_GRAPH, LAUNCH_PERSISTENT, LAUNCH_PERSISTENT_GRAPH = 0, 1, 2, 3
-COLOR_ID_ORDER, COLOR_SMALLEST_LAST = 0, 1
+COLOR_ID_ORDER, COLOR_SMALLEST_LAST, COLOR_DSATUR = 0, 1, 2
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
  Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME, Q_SURFACE,

@@ -58,7 +58,7 @@ class Topology:
                  max_backward_iters: int = 0, device: Optional[torch.device] = None,
                  bind: bool = True, colors=None, coloring: str = "id"):
         """colors: optional caller-supplied vertex coloring; else greedy first fit
-        in the vertex order `coloring` ("id" or "smallest_last")."""
+        in the vertex order `coloring` ("id", "smallest_last" or "dsatur")."""
         L = N.lib()
         self._keep = []
 
@@ -96,7 +96,8 @@ class Topology:
             N.check(L.vbd_color_given(self._h, _np_ptr(col)))
             self.n_colors = int(col.max()) + 1 if col.size else 0
         else:
-            order = {"id": N.COLOR_ID_ORDER, "smallest_last": N.COLOR_SMALLEST_LAST}[coloring]
+            order = {"id": N.COLOR_ID_ORDER, "smallest_last": N.COLOR_SMALLEST_LAST,
+                     "dsatur": N.COLOR_DSATUR}[coloring]
             nc = C.c_int32()
             N.check(L.vbd_color_greedy(self._h, order, C.byref(nc), None))
             self.n_colors = nc.value

@@ -397,6 +397,39 @@ std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, i
     return ord;
 }
 
+// DSATUR (Brelaz, Comm. ACM 22(4), 1979): the next vertex is the uncolored
+// one with the most distinct colors among its neighbours (ties: larger
+// degree, then smaller id); it takes the smallest color none of them has.
+void dsatur_color(const std::vector<std::vector<int32_t>> &nbr, std::vector<int32_t> &colors, int &nc)
+{
+    const int nv = (int)nbr.size();
+    colors.assign(nv, -1);
+    nc = 0;
+    std::vector<std::vector<char>> seen(nv);   // neighbour colors seen so far
+    std::vector<int32_t> sat(nv, 0);
+    // ordered by (saturation desc, degree desc, id asc)
+    std::set<std::tuple<int32_t, int32_t, int32_t>> q;
+    for (int v = 0; v < nv; ++v) q.insert({0, -(int32_t)nbr[v].size(), v});
+    while (!q.empty()) {
+        const int v = std::get<2>(*q.begin());
+        q.erase(q.begin());
+        int c = 0;
+        while (c < (int)seen[v].size() && seen[v][c]) ++c;
+        colors[v] = c;
+        nc = std::max(nc, c + 1);
+        for (int32_t w : nbr[v]) {
+            if (colors[w] >= 0) continue;
+            if ((int)seen[w].size() <= c) seen[w].resize((size_t)c + 1, 0);
+            if (!seen[w][c]) {
+                seen[w][c] = 1;
+                q.erase({-sat[w], -(int32_t)nbr[w].size(), w});
+                ++sat[w];
+                q.insert({-sat[w], -(int32_t)nbr[w].size(), w});
+            }
+        }
+    }
+}
+
 void greedy_color(vbd_topology_s &T, int order)
 {
     const int nv = T.nv;
@@ -420,6 +453,12 @@ void greedy_color(vbd_topology_s &T, int order)
             std::sort(l.begin(), l.end());
             l.erase(std::unique(l.begin(), l.end()), l.end());
         }
+    if (order == VBD_COLOR_DSATUR) {
+        int nc = 0;
+        dsatur_color(nbr, T.colors, nc);
+        T.n_colors = nc;
+        return;
+    }
     const std::vector<int32_t> ord = color_order(nbr, order);
     T.colors.assign(nv, -1);
     int nc = 0;
@@ -1030,7 +1069,7 @@ vbd_status vbd_color(vbd_topology T, int32_t *n_colors_out, int32_t *colors_out)
 vbd_status vbd_color_greedy(vbd_topology T, int32_t order, int32_t *n_colors_out, int32_t *colors_out)
 {
     if (!T) return fail(VBD_E_INVALID_ARG, "NULL topology");
-    if (order != VBD_COLOR_ID_ORDER && order != VBD_COLOR_SMALLEST_LAST)
+    if (order != VBD_COLOR_ID_ORDER && order != VBD_COLOR_SMALLEST_LAST && order != VBD_COLOR_DSATUR)
         return fail(VBD_E_INVALID_ARG, "unknown coloring order %d", order);
     if (T->colored && T->color_order != order) {
         if (T->bound) return fail(VBD_E_INVALID_ARG, "the topology is bound: color before vbd_bind_workspace");

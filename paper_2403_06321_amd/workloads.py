@@ -85,7 +85,7 @@ class Workload:
     frames: int = 1
     target: Optional[np.ndarray] = None        # [3] loss target (differentiable workload)
     colors: Optional[np.ndarray] = None        # [nv] given vertex coloring (None: greedy)
-    coloring: str = "id"                       # greedy vertex order: "id" or "smallest_last"
+    coloring: str = "id"                       # greedy vertex order: "id", "smallest_last", "dsatur"
 
     @property
     def n_verts(self) -> int:
@@ -239,8 +239,10 @@ def config_large_cube(frames: int = 60, coloring: str = "id") -> Workload:
 
 
 def config_cloth(n: int = 1024, frames: int = 120, spacing: float = 1e-3,
-                 mass: float = 1e-4) -> Workload:
-    """Mass-spring cloth (n x n, 1 mm spacing) over a sphere and a ground plane."""
+                 mass: float = 1e-4, coloring: str = "id") -> Workload:
+    """Mass-spring cloth (n x n, 1 mm spacing) over a sphere and a ground plane.
+    coloring: greedy vertex order, "id" (7 colors), "smallest_last" or
+    "dsatur" (5 colors)."""
     rest, springs = cloth_grid(n, spacing, 0.62)
     nv = rest.shape[0]
     pinned = np.zeros(nv, np.uint8)
@@ -249,17 +251,19 @@ def config_cloth(n: int = 1024, frames: int = 120, spacing: float = 1e-3,
     p = StepParams(n_iters=50, contact_k=1e5, contact_thickness=1e-3, spring_psd=True,
                    spheres=np.array([[0.0, 0.0, 0.3, 0.3]]),
                    planes=np.array([[0.0, 0.0, 1.0, 0.0]]))
-    return Workload(name=f"cloth {n}^2", rest=rest, tets=np.zeros((0, 4), np.int32),
+    name = f"cloth {n}^2" + ("" if coloring == "id" else f", {coloring.replace('_', '-')} coloring")
+    return Workload(name=name, rest=rest, tets=np.zeros((0, 4), np.int32),
                     pinned=pinned, x0=rest.copy(), v0=np.zeros((nv, 3)),
                     tet_E=np.zeros(0), springs=springs, spring_k=1e3,
-                    mass=np.full(nv, mass), params=p, frames=frames)
+                    mass=np.full(nv, mass), params=p, frames=frames, coloring=coloring)
 
 
-def config_cloth_coarse(n: int = 64, frames: int = 60) -> Workload:
+def config_cloth_coarse(n: int = 64, frames: int = 60, coloring: str = "id") -> Workload:
     """The cloth of config_cloth over the same 1.023 m square with n x n
     vertices: spacing 1.023/(n-1) m and the same total mass."""
     spacing = 1.023 / (n - 1)
-    return config_cloth(n, frames, spacing=spacing, mass=1e-4 * (1024.0 / n) ** 2)
+    return config_cloth(n, frames, spacing=spacing, mass=1e-4 * (1024.0 / n) ** 2,
+                        coloring=coloring)
 
 
 def config_batch(n_meshes: int = 512, seed: int = 3, lo: int = 4, hi: int = 33,

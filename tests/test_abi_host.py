@@ -36,11 +36,12 @@ def test_coloring_matches_oracle_bit_exact(n):
     assert np.array_equal(t.query(N.Q_COLORS), m.colors)
 
 
+@pytest.mark.parametrize("order", ["smallest_last", "dsatur"])
 @pytest.mark.parametrize("make", [lambda: W.tet_cube(9, 1), lambda: W.config_cloth(32),
                                   lambda: W.config_batch(n_meshes=6, lo=3, hi=7)])
-def test_smallest_last_coloring_matches_oracle_bit_exact(make):
+def test_ordered_coloring_matches_oracle_bit_exact(make, order):
     w = make()
-    w.coloring = "smallest_last"
+    w.coloring = order
     t = Topology.from_workload(w, bind=False)
     m = O.Model.from_workload(w)
     assert t.n_colors == m.n_colors
@@ -259,6 +260,21 @@ def test_coloring_order_errors():
     assert b"order" in L.vbd_last_error()
     # switching the order before binding recolors
     assert L.vbd_color_greedy(t._h, N.COLOR_SMALLEST_LAST, C.byref(nc), None) == 0 and nc.value == 4
+    assert L.vbd_color_greedy(t._h, N.COLOR_DSATUR, C.byref(nc), None) == 0 and nc.value == 4
     assert L.vbd_color_greedy(t._h, N.COLOR_ID_ORDER, C.byref(nc), None) == 0
     assert nc.value == O.color_greedy(w.n_verts, w.tets)[1]
     assert np.array_equal(t.query(N.Q_COLORS), O.color_greedy(w.n_verts, w.tets)[0])
+
+
+@pytest.mark.parametrize("n", [4, 7])
+def test_dsatur_on_crown_graph_matches_oracle(n):
+    """Bipartite crown graph with interleaved ids: 2 colors for DSATUR, n for
+    first fit in id order, on both sides."""
+    sp = np.array([[2 * i, 2 * j + 1] for i in range(n) for j in range(n) if i != j], np.int32)
+    rest = np.zeros((2 * n, 3))
+    rest[:, 0] = np.arange(2 * n)
+    for order, expect in (("dsatur", 2), ("id", n)):
+        t = Topology(rest, None, springs=sp, mass=np.ones(2 * n), coloring=order, bind=False)
+        c, nc = O.color_greedy(2 * n, np.zeros((0, 4)), sp, order=order)
+        assert t.n_colors == nc == expect
+        assert np.array_equal(t.query(N.Q_COLORS), c)

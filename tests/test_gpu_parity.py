@@ -189,6 +189,17 @@ def test_cloth_with_contacts():
         assert np.median(np.concatenate(errs)) <= 2e-5
 
 
+@pytest.mark.parametrize("coloring", ["dsatur", "smallest_last"])
+def test_cloth_other_colorings_free_running(coloring):
+    """The 64^2 cloth colored by DSATUR (5 colors) or smallest-last order, the
+    first 5 frames before any contact, in the plain and graph modes."""
+    w = W.config_cloth_coarse(64, frames=5, coloring=coloring)
+    xo, _ = oracle_rollout(w, w.frames, threads=THREADS)
+    for mode in (0, 3):
+        xg, _, _ = gpu_rollout(w, w.frames, launch_mode=mode)
+        assert_parity(w, xg, xo, label=f"cloth 64^2 {coloring} mode {mode}")
+
+
 def test_full_size_cloth_properties():
     """1024^2 cloth, 1 mm springs, 8 frames in the benchmark's launch mode:
     finite, pinned corners fixed, no vertex deeper than 2 mm inside the

@@ -575,3 +575,59 @@ def test_smallest_last_colors_a_lattice_with_four(n):
     c, nc = O.color_greedy(rest.shape[0], tets, order="smallest_last")
     assert nc == 4
     assert all(len(set(c[q].tolist())) == 4 for q in tets)
+
+
+def test_dsatur_order_on_a_path_by_hand():
+    """Springs 0-1, 1-2, 2-3.  DSATUR: all saturations 0, largest degree with
+    the smallest id is 1 -> color 0; then saturation 1 for 0 and 2, larger
+    degree 2 -> color 1; then 0 and 3 (saturation 1, degree 1), smaller id 0
+    -> color 1 (0 is taken by 1); last 3 -> color 0."""
+    sp = np.array([[0, 1], [1, 2], [2, 3]])
+    c, nc = O.color_greedy(4, np.zeros((0, 4)), sp, order="dsatur")
+    assert c.tolist() == [1, 0, 1, 0] and nc == 2
+
+
+def _crown(n):
+    """K_{n,n} minus a perfect matching, ids interleaved: u_i = 2i, w_i =
+    2i + 1, spring u_i-w_j for i != j."""
+    return np.array([[2 * i, 2 * j + 1] for i in range(n) for j in range(n) if i != j])
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_dsatur_is_exact_on_bipartite_graphs(n):
+    """Brelaz (1979): DSATUR colors every bipartite graph with 2 colors.  On
+    the crown graph first fit in id order needs n (u_i and w_i both take
+    color i)."""
+    sp = _crown(n)
+    c, nc = O.color_greedy(2 * n, np.zeros((0, 4)), sp, order="dsatur")
+    assert nc == 2 and all(c[a] != c[b] for a, b in sp)
+    c, nc = O.color_greedy(2 * n, np.zeros((0, 4)), sp, order="id")
+    assert nc == n and c.tolist() == [i // 2 for i in range(2 * n)]
+
+
+def test_dsatur_on_a_structural_spring_grid_uses_two():
+    """Structural springs of a grid alone form a bipartite graph (checkerboard)."""
+    n = 9
+    idx = np.arange(n * n).reshape(n, n)
+    sp = np.concatenate([np.stack([idx[:, :-1].ravel(), idx[:, 1:].ravel()], 1),
+                         np.stack([idx[:-1, :].ravel(), idx[1:, :].ravel()], 1)])
+    c, nc = O.color_greedy(n * n, np.zeros((0, 4)), sp, order="dsatur")
+    assert nc == 2 and all(c[a] != c[b] for a, b in sp)
+
+
+@pytest.mark.parametrize("make,expect", [(lambda: W.cloth_grid(16, 1e-3, 0.0), 5),
+                                         (lambda: W.cloth_grid(64, 1e-3, 0.0), 5)])
+def test_dsatur_colors_the_cloth_with_five(make, expect):
+    """The cloth's spring graph holds 4-cliques (a cell and its two shears),
+    so 4 is a lower bound; DSATUR needs 5, first fit in id order 7."""
+    rest, springs = make()
+    c, nc = O.color_greedy(rest.shape[0], np.zeros((0, 4), np.int32), springs, order="dsatur")
+    assert nc == expect and all(c[a] != c[b] for a, b in springs)
+
+
+@pytest.mark.parametrize("n", [3, 6, 11])
+def test_dsatur_colors_a_lattice_with_four(n):
+    rest, tets = W.cube_lattice(n, n, n)
+    c, nc = O.color_greedy(rest.shape[0], tets, order="dsatur")
+    assert nc == 4
+    assert all(len(set(c[q].tolist())) == 4 for q in tets)
