@@ -50,7 +50,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, pa, ps, pt, pair_tet, ell_info, spr_ell,
+    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, pa, pw, pb, pws, pair_tet, ell_info, spr_ell,
         spr_info, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib, ebar;
@@ -168,8 +168,9 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.tet_ent = take(sizeof(PairEnt) * T.tet_ent.size());
     L.ell = take(sizeof(PairEnt) * T.ell_total);
     L.pa = take(sizeof(int4) * T.ell_total);
-    L.ps = take(sizeof(float4) * T.ell_total);
-    L.pt = take(sizeof(float2) * T.ell_total);
+    L.pw = take(sizeof(float4) * T.ell_total);
+    L.pb = take(sizeof(float) * T.ell_total);
+    L.pws = take(sizeof(float4) * T.ell_total);
     L.pair_tet = take(sizeof(int32_t) * T.ell_total);
     L.ell_info = take(sizeof(int2) * (size_t)T.n_colors);
     L.spr_ell = take(sizeof(int2) * T.spr_total);
@@ -237,8 +238,9 @@ void set_dev_pointers(vbd_topology_s &T)
     D.tet_ent = (const PairEnt *)(b + L.tet_ent);
     D.ell = (const PairEnt *)(b + L.ell);
     D.pa = (int4 *)(b + L.pa);
-    D.ps = (const float4 *)(b + L.ps);
-    D.pt = (const float2 *)(b + L.pt);
+    D.pw = (float4 *)(b + L.pw);
+    D.pb = (const float *)(b + L.pb);
+    D.pws = (const float4 *)(b + L.pws);
     D.pair_tet = (const int *)(b + L.pair_tet);
     D.n_pairs = (long long)T.ell_total;
     D.ell_info = (const int2 *)(b + L.ell_info);
@@ -610,7 +612,7 @@ void build_csr(vbd_topology_s &T)
             T.tet_rank[key[i].second] = i;
         }
     }
-    // algorithmic bytes of one color solve: 40 B pair record per tet pair, 8 B
+    // algorithmic bytes of one color solve: 36 B pair record per tet pair, 8 B
     // per spring entry, 48 B own state per vertex (x read, y read, x write),
     // 16 B per distinct neighbour position.
     T.phase_bytes.assign(T.n_colors, 0.0);
@@ -622,7 +624,7 @@ void build_csr(vbd_topology_s &T)
         for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
             const int pairs = T.tet_row[s + 1] - T.tet_row[s];
             const int sp = T.spr_row[s + 1] - T.spr_row[s];
-            bytes += (double)(sizeof(int4) + sizeof(float4) + sizeof(float2)) * pairs + 8.0 * sp + 48.0;
+            bytes += (double)(sizeof(int4) + sizeof(float4) + sizeof(float)) * pairs + 8.0 * sp + 48.0;
             for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
                 const int t = T.tet_ent[e] >> 2;
                 for (int k = 0; k < 4; ++k) {
@@ -1213,11 +1215,12 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
             }
         }
         HIP_TRY(up(T->lay.ell, ell.data(), sizeof(PairEnt) * ell.size()));
-        // pair records: the rest frame of each (vertex, tet) pair with the
-        // vertex as origin, the other three vertices in slot order
+        // pair records: from the rest frame S of each (vertex, tet) pair with
+        // the vertex as origin (the other three vertices in slot order), in
+        // double: m = -(rows of S summed), w = S m, sigma = det S
         std::vector<int4> pa(T->ell_total, make_int4(-1, 0, 0, 0));
-        std::vector<float4> ps(T->ell_total, make_float4(0.f, 0.f, 0.f, 0.f));
-        std::vector<float2> pt(T->ell_total, make_float2(0.f, 0.f));
+        std::vector<float4> pws(T->ell_total, make_float4(0.f, 0.f, 0.f, 0.f));
+        std::vector<float> pb(T->ell_total, 0.f);
         std::vector<int32_t> ptet(T->ell_total, -1);
         for (int c = 0; c < T->n_colors; ++c) {
             const int2 info = T->ell_info[c];
@@ -1230,19 +1233,23 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
                     int n = 1;
                     for (int j = 0; j < 4; ++j)
                         if (j != k) ord[n++] = q[j];
-                    double S[6];
+                    double S[6];   // S00, S01, S02, S11, S12, S22
                     rest_frame_inverse(T->rest, ord, S);
+                    const double m0 = -S[0], m1 = -(S[1] + S[3]), m2 = -(S[2] + S[4] + S[5]);
+                    const double w0 = S[0] * m0 + S[1] * m1 + S[2] * m2;
+                    const double w1 = S[3] * m1 + S[4] * m2;
+                    const double w2 = S[5] * m2;
                     const size_t i = base + (size_t)(e - T->tet_row[sl]);
                     pa[i] = make_int4(T->iperm[ord[1]], T->iperm[ord[2]], T->iperm[ord[3]], 0);
-                    ps[i] = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
-                    pt[i] = make_float2((float)S[4], (float)S[5]);
+                    pws[i] = make_float4((float)w0, (float)w1, (float)w2, (float)(m0 * m0 + m1 * m1 + m2 * m2));
+                    pb[i] = (float)(S[0] * S[3] * S[5]);
                     ptet[i] = T->tet_rank[t];
                 }
             }
         }
         HIP_TRY(up(T->lay.pa, pa.data(), sizeof(int4) * pa.size()));
-        HIP_TRY(up(T->lay.ps, ps.data(), sizeof(float4) * ps.size()));
-        HIP_TRY(up(T->lay.pt, pt.data(), sizeof(float2) * pt.size()));
+        HIP_TRY(up(T->lay.pws, pws.data(), sizeof(float4) * pws.size()));
+        HIP_TRY(up(T->lay.pb, pb.data(), sizeof(float) * pb.size()));
         HIP_TRY(up(T->lay.pair_tet, ptet.data(), 4 * ptet.size()));
         HIP_TRY(up(T->lay.ell_info, T->ell_info.data(), sizeof(int2) * T->ell_info.size()));
     }

@@ -63,18 +63,20 @@ struct DevTopo {
     // (slot - color_off[c]) * ell_info[c].y, so entry addresses follow from the
     // slot alone.  Two views of each (vertex, tet) pair:
     //   ell                 shared-record entries (adjoint), padding x = -1;
-    //   pa / ps / pt        the color solve's pair records: pa = {the other
-    //                       three vertices (slot order), float bits of V*E},
-    //                       ps = {S00, S01, S02, S11}, pt = {S12, S22}, where
-    //                       S = R^{-1} of the tet's rest edges taken from this
-    //                       vertex (D_m' = Q R, Q proper); padding pa.x = -1.
-    //                       F = D_s' S equals the tet's F times a rotation, so
-    //                       energy, forces and Hessians are unchanged, and
-    //                       this vertex's shape gradient is -(rows of S summed).
+    //   pa / pw / pb        the color solve's pair records, from the rest
+    //                       frame S = R^{-1} of the tet's rest edges taken from
+    //                       this vertex (D_m' = Q R, Q proper; F' = D_s' S is
+    //                       F times a rotation), this vertex's shape gradient
+    //                       m = -(rows of S summed), w = S m and sigma = det S:
+    //                       pa = {the other three vertices (slot order), float
+    //                       bits of V lam}, pw = V mu {w, |m|^2}, pb = sigma;
+    //                       padding pa.x = -1;
+    //   pws                 {w, |m|^2}, the E-free part of pw (material input).
     const PairEnt *ell;
     int4 *pa;
-    const float4 *ps;
-    const float2 *pt;
+    float4 *pw;
+    const float *pb;
+    const float4 *pws;
     const int *pair_tet;               // stored tet of each pair entry (-1: padding)
     const int2 *ell_info;              // [n_colors] {first entry, padded degree}
     long long n_pairs;                 // padded entries over all colors

@@ -115,35 +115,36 @@ __device__ __forceinline__ void slot_positions(int k, float4 own, float4 a, floa
     q3 = k < 3 ? c : own;
 }
 
-// One tet seen from the vertex it is solved for, from a pair record: the
-// vertex is the origin of the rest edges, so its shape gradient is
-// m = -(r0 + r1 + r2) = (-S00, -(S01 + S11), -(S02 + S12 + S22)) and
-//   f -= V (mu F m + lam (J - alpha) cof(F) m),
-//   H += V (mu |m|^2 I + lam (cof(F) m)(cof(F) m)^T).
-__device__ __forceinline__ void pair_accumulate(float4 S, float2 S2, float VE, float4 own, float4 qa,
-                                                float4 qb, float4 qc, const StepConsts &K, Acc &a)
+// One tet seen from the vertex i it is solved for (stable Neo-Hookean,
+// Sec. 3.3): f_i -= V (mu F m + lam (J - alpha) cof(F) m) and
+// H_ii += V (mu |m|^2 I + lam (cof(F) m)(cof(F) m)^T), m the vertex's shape
+// gradient.  With the pair's rest frame S (F' = D_s' S, D_s' = [e1 e2 e3],
+// e_k = x_k - x_i for the other vertices a, b, c):
+//   F m = D_s' (S m) = w0 e1 + w1 e2 + w2 e3                (w = S m),
+//   cof(F) m = dJ/dx_i = -sigma (x_b - x_a) x (x_c - x_a) = -n (sigma = det S),
+//   J = sigma det D_s' = e1 . n,
+// so f_i += V lam (J - alpha) n - V mu F m and H_ii += V mu |m|^2 I + V lam n n^T.
+// Record: pa.w = V lam, pw = V mu {w, |m|^2}, sigma.
+__device__ __forceinline__ void pair_accumulate(float Vlam, float4 W, float sigma, float4 own,
+                                                float4 qa, float4 qb, float4 qc, const StepConsts &K,
+                                                Acc &a)
 {
-    const float3 e1 = xyz(qa) - xyz(own), e2 = xyz(qb) - xyz(own), e3 = xyz(qc) - xyz(own);
-    const float3 f0 = e1 * S.x;
-    const float3 f1 = e1 * S.y + e2 * S.w;
-    const float3 f2 = e1 * S.z + e2 * S2.x + e3 * S2.y;
-    const float3 c0 = cross3(f1, f2), c1 = cross3(f2, f0), c2 = cross3(f0, f1);
-    const float J = dot3(f0, c0);
-    const float3 m = make_float3(-S.x, -(S.y + S.w), -(S.z + S2.x + S2.y));
-    const float3 Fm = f0 * m.x + f1 * m.y + f2 * m.z;
-    const float3 cm = c0 * m.x + c1 * m.y + c2 * m.z;
-    const float Vmu = VE * K.k_mu, Vlam = VE * K.k_lam;
+    const float3 xi = xyz(own), xa = xyz(qa), xb = xyz(qb), xc = xyz(qc);
+    const float3 e1 = xa - xi, e2 = xb - xi, e3 = xc - xi;
+    const float3 n = cross3(xb - xa, xc - xa) * sigma;
+    const float J = dot3(e1, n);
     const float s = Vlam * (J - K.alpha);
-    a.fx -= Vmu * Fm.x + s * cm.x;
-    a.fy -= Vmu * Fm.y + s * cm.y;
-    a.fz -= Vmu * Fm.z + s * cm.z;
-    const float d = Vmu * dot3(m, m);
-    a.hxx += d + Vlam * cm.x * cm.x;
-    a.hxy += Vlam * cm.x * cm.y;
-    a.hxz += Vlam * cm.x * cm.z;
-    a.hyy += d + Vlam * cm.y * cm.y;
-    a.hyz += Vlam * cm.y * cm.z;
-    a.hzz += d + Vlam * cm.z * cm.z;
+    const float3 Fm = e1 * W.x + e2 * W.y + e3 * W.z;
+    a.fx += s * n.x - Fm.x;
+    a.fy += s * n.y - Fm.y;
+    a.fz += s * n.z - Fm.z;
+    const float3 ln = n * Vlam;
+    a.hxx += W.w + ln.x * n.x;
+    a.hxy += ln.x * n.y;
+    a.hxz += ln.x * n.z;
+    a.hyy += W.w + ln.y * n.y;
+    a.hyz += ln.y * n.z;
+    a.hzz += W.w + ln.z * n.z;
 }
 
 // Tet terms of one vertex from its D consecutive pair records starting at
@@ -157,15 +158,15 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
 {
     for (int base = lane; base < D; base += L * KU) {
         int4 pa[KU];
-        float4 ps[KU];
-        float2 pt[KU];
+        float4 pw[KU];
+        float pb[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j) {
             const int e = base + j * L;
             if (e < D) {
                 pa[j] = T.pa[e0 + e];
-                ps[j] = T.ps[e0 + e];
-                pt[j] = T.pt[e0 + e];
+                pw[j] = T.pw[e0 + e];
+                pb[j] = T.pb[e0 + e];
             } else {
                 pa[j] = make_int4(-1, 0, 0, 0);
             }
@@ -180,7 +181,7 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
             }
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (pa[j].x >= 0) pair_accumulate(ps[j], pt[j], __int_as_float(pa[j].w), own, qa[j], qb[j], qc[j], K, a);
+            if (pa[j].x >= 0) pair_accumulate(__int_as_float(pa[j].w), pw[j], pb[j], own, qa[j], qb[j], qc[j], K, a);
     }
 }
 
@@ -466,15 +467,21 @@ __global__ void k_material(TetRec *rec, const float *vol, const int *tet_perm, c
     rec[t].b = b;
 }
 
-// V*E of every pair record (padding entries have pair_tet = -1).
-__global__ void k_material_pairs(int4 *pa, const int *pair_tet, const float *vol, const int *tet_perm,
-                                 const float *E, long long n)
+// The E-dependent parts of every pair record: V lam into pa.w and
+// V mu {w, |m|^2} into pw (padding entries have pair_tet = -1).
+__global__ void k_material_pairs(int4 *pa, float4 *pw, const float4 *pws, const int *pair_tet,
+                                 const float *vol, const int *tet_perm, const float *E, long long n,
+                                 float k_mu, float k_lam)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = pair_tet[i];
     if (t < 0) return;
-    reinterpret_cast<int *>(pa + i)[3] = __float_as_int(vol[t] * E[tet_perm[t]]);
+    const float VE = vol[t] * E[tet_perm[t]];
+    const float Vmu = VE * k_mu;
+    reinterpret_cast<int *>(pa + i)[3] = __float_as_int(VE * k_lam);
+    const float4 w = pws[i];
+    pw[i] = make_float4(w.x * Vmu, w.y * Vmu, w.z * Vmu, w.w * Vmu);
 }
 
 // y = x^t + h v^t + h^2 a_ext (Eq. inertia) and the initial guess (Sec. 3.7).
@@ -933,8 +940,8 @@ hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConst
     hipLaunchKernelGGL(k_material, dim3(cdiv(T.n_tets, 256)), dim3(256), 0, s, T.rec, T.vol,
                        T.tet_perm, tet_E, T.n_tets, K.k_mu, K.k_lam);
     if (T.n_pairs > 0)
-        hipLaunchKernelGGL(k_material_pairs, dim3(cdiv(T.n_pairs, 256)), dim3(256), 0, s, T.pa,
-                           T.pair_tet, T.vol, T.tet_perm, tet_E, T.n_pairs);
+        hipLaunchKernelGGL(k_material_pairs, dim3(cdiv(T.n_pairs, 256)), dim3(256), 0, s, T.pa, T.pw,
+                           T.pws, T.pair_tet, T.vol, T.tet_perm, tet_E, T.n_pairs, K.k_mu, K.k_lam);
     return hipGetLastError();
 }
 

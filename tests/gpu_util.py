@@ -88,13 +88,15 @@ def resync_errors(w, states, params=None, launch_mode=0):
     return out
 
 
-def resync_parity(w, states, params=None, launch_mode=0, tol=1e-5, label=""):
+def resync_parity(w, states, params=None, launch_mode=0, tol=1e-5, label="", cfg=None):
     """Per-step parity: the GPU takes every frame from the oracle's state
     (rounded to FP32) and its one-step result is compared with the oracle's."""
     import torch
     from paper_2403_06321_amd.api import Topology
     p = params or w.params
     t = Topology.from_workload(w)
+    if cfg:
+        t.launch_config = cfg
     dev = torch.device("cuda", 0)
     E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).contiguous()
     worst = 0.0

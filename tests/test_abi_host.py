@@ -176,8 +176,8 @@ def test_phase_bytes_model():
     for c in range(t.n_colors):
         pairs = rows[co[c + 1]] - rows[co[c]]
         nvc = co[c + 1] - co[c]
-        assert pb[c] >= 40 * pairs + 48 * nvc
-        assert pb[c] <= 40 * pairs + 48 * nvc + 16 * w.n_verts
+        assert pb[c] >= 36 * pairs + 48 * nvc
+        assert pb[c] <= 36 * pairs + 48 * nvc + 16 * w.n_verts
 
 
 def test_tet_order_groups_tets_by_vertex_colors():
