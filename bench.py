@@ -169,6 +169,7 @@ def main():
         wd = W.config_differentiable(coloring="smallest_last")
         td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
         x0, v0, _, E = state(wd, dev)
+        td.autotune(x0, v0, v0.clone(), E, wd.params, MODES["graph"])
         v0.requires_grad_(True); E.requires_grad_(True)
         target = torch.tensor(wd.target, dtype=torch.float32, device=dev)
         for _ in range(args.steps):
@@ -328,6 +329,7 @@ def extras(dev, W, Topology):
     wd = W.config_differentiable(coloring="smallest_last")
     td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
     x0, v0, _, E = state(wd, dev)
+    td.autotune(x0, v0, v0.clone(), E, wd.params, MODES["graph"])
     v0.requires_grad_(True); E.requires_grad_(True)
     target = torch.tensor(wd.target, dtype=torch.float32, device=dev)
 
@@ -356,7 +358,8 @@ def extras(dev, W, Topology):
                           updates_per_s_forward_backward=upd / (ms * 1e-3),
                           updates_per_s_forward=upd / (ms_fwd * 1e-3),
                           workload="33^3 cube, 30 frames x 20 iterations, loss on final centroid, "
-                                   f"smallest-last coloring ({td.n_colors} colors)")
+                                   f"smallest-last coloring ({td.n_colors} colors)",
+                          config=td.launch_config)
     log(f"[bench] adjoint fwd+bwd {ms:.1f} ms, forward {ms_fwd:.1f} ms")
     del td
     # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, graph launches

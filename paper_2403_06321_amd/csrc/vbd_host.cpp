@@ -50,7 +50,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec, vol, tet_perm, tet_row, tet_ent, ell, pa, pw, pb, pws, pair_tet, ell_info, spr_ell,
+    size_t vol, tet_perm, tet_row, tet_ent, ell, pa, pw, pb, pws, pair_tet, ell_info, spr_ell,
         spr_info, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib, ebar;
@@ -161,7 +161,6 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes ? bytes : 1); return o; };
     const size_t nv = (size_t)T.nv;
-    L.rec = take(sizeof(TetRec) * (size_t)T.nt);
     L.vol = take(sizeof(float) * (size_t)T.nt);
     L.tet_perm = take(sizeof(int32_t) * (size_t)T.nt);
     L.tet_row = take(sizeof(int32_t) * (size_t)(T.nv + 1));
@@ -231,7 +230,6 @@ void set_dev_pointers(vbd_topology_s &T)
     char *b = T.ws;
     const Layout &L = T.lay;
     DevTopo &D = T.dev;
-    D.rec = (TetRec *)(b + L.rec);
     D.vol = (const float *)(b + L.vol);
     D.tet_perm = (const int *)(b + L.tet_perm);
     D.tet_row = (const int *)(b + L.tet_row);
@@ -1159,17 +1157,8 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     T->lay = make_layout(*T, nb);
     set_dev_pointers(*T);
     // host staging of every static array
-    std::vector<TetRec> rec(T->nt);
     std::vector<float> volf(T->nt);
-    for (int i = 0; i < T->nt; ++i) {
-        const int t = T->tet_order[i];
-        const int32_t *q = &T->tets[4 * (size_t)t];
-        double S[6];
-        rest_frame_inverse(T->rest, q, S);
-        rec[i].a = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
-        rec[i].b = make_float4((float)S[4], (float)S[5], 0.f, 0.f);
-        volf[i] = (float)T->vol[t];
-    }
+    for (int i = 0; i < T->nt; ++i) volf[i] = (float)T->vol[T->tet_order[i]];
     std::vector<PairEnt> tet_ent_dev(T->tet_ent.size());
     for (size_t e = 0; e < tet_ent_dev.size(); ++e) {
         const int32_t v = T->tet_ent[e];
@@ -1199,7 +1188,6 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         if (n == 0) return hipSuccess;
         return hipMemcpyAsync(T->ws + off, src, n, hipMemcpyHostToDevice, s);
     };
-    HIP_TRY(up(T->lay.rec, rec.data(), sizeof(TetRec) * rec.size()));
     HIP_TRY(up(T->lay.vol, volf.data(), 4 * volf.size()));
     HIP_TRY(up(T->lay.tet_perm, T->tet_order.data(), 4 * T->tet_order.size()));
     HIP_TRY(up(T->lay.tet_row, T->tet_row.data(), 4 * T->tet_row.size()));

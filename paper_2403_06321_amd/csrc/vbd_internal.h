@@ -7,21 +7,6 @@
 
 namespace vbd {
 
-// 32-byte tet record: a = {S00, S01, S02, S11}, b = {S12, S22, V*mu, V*lambda}.
-// S = R^{-1}, the inverse of the triangular factor of the rest edge matrix
-// D_m = Q R (Q a proper rotation).  The stable Neo-Hookean energy depends on
-// F only through F^T F and det F, both unchanged by F -> F Q, so
-// F' = D_s R^{-1} = F Q gives the same energy, forces and Hessians; row l of
-// S is the shape-function gradient of slot l+1 in that rotated frame.
-// V*mu and V*lambda are rewritten from the per-tet Young's modulus at the
-// start of every step.  Records are stored in tet_perm order (tets grouped by
-// the colors of their four vertices, so a cache line only holds tets that
-// are touched in the same color phases).
-struct __align__(16) TetRec {
-    float4 a, b;
-};
-static_assert(sizeof(TetRec) == 32, "tet record must be 32 bytes");
-
 // Incidence entry of a (vertex, tet) pair, 16 bytes:
 //   x = (stored tet << 2) | slot of the vertex in the tet,
 //   y, z, w = permuted ids of the tet's other three vertices in slot order.
@@ -53,8 +38,7 @@ struct StepConsts {
 
 // Device-side view of a bound workspace.
 struct DevTopo {
-    TetRec *rec;                       // [n_tets] in tet_perm order
-    const float *vol;                  // [n_tets] rest volume, tet_perm order
+    const float *vol;                  // [n_tets] rest volume, in stored order (tet_perm)
     const int *tet_perm;               // stored tet -> caller's tet index
     const int *tet_row;                // CSR over all permuted vertices (adjoint)
     const PairEnt *tet_ent;            // (tet, slot, other vertices) per entry
@@ -62,7 +46,7 @@ struct DevTopo {
     // ell_info[c].y consecutive entries starting at ell_info[c].x +
     // (slot - color_off[c]) * ell_info[c].y, so entry addresses follow from the
     // slot alone.  Two views of each (vertex, tet) pair:
-    //   ell                 shared-record entries (adjoint), padding x = -1;
+    //   ell                 (tet, slot, other vertices) entries (adjoint), padding x = -1;
     //   pa / pw / pb        the color solve's pair records, from the rest
     //                       frame S = R^{-1} of the tet's rest edges taken from
     //                       this vertex (D_m' = Q R, Q proper; F' = D_s' S is
@@ -135,7 +119,7 @@ struct LaunchCfg {
 };
 
 // ---- kernel launchers (vbd_kernels.hip) ----
-// V*mu, V*lambda of the shared records and V*E of the pair records.
+// The E-dependent parts of the pair records (V lam, V mu {w, |m|^2}).
 hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K,
                            hipStream_t s);
 hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,

@@ -42,58 +42,6 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int remap)
 }
 
 // --------------------------------------------------------- element terms --
-// Stable Neo-Hookean tet without the log term (Sec. 5):
-//   Psi = mu/2 (|F|^2 - 3) + lam/2 (J - alpha)^2, alpha = 1 + mu/lam.
-// For the vertex in slot k with shape gradient m_k:
-//   dE/dx_k = V (mu F m_k + lam (J - alpha) c_k),  c_k = cof(F) m_k,
-//   d2E/dx_k2 = V (mu |m_k|^2 I + lam c_k c_k^T)   (J is affine in x_k).
-struct TetLocal {
-    float3 f0, f1, f2;   // columns of F (rotated rest frame, see TetRec)
-    float3 c0, c1, c2;   // columns of cof(F)
-    float J;
-    float3 r0, r1, r2;   // rows of S = shape gradients of slots 1..3
-};
-
-__device__ __forceinline__ void tet_local(const TetRec &r, float4 q0, float4 q1, float4 q2,
-                                          float4 q3, TetLocal &L)
-{
-    const float3 e1 = xyz(q1) - xyz(q0), e2 = xyz(q2) - xyz(q0), e3 = xyz(q3) - xyz(q0);
-    // S is upper triangular: F = [e1 e2 e3] S
-    L.r0 = make_float3(r.a.x, r.a.y, r.a.z);
-    L.r1 = make_float3(0.f, r.a.w, r.b.x);
-    L.r2 = make_float3(0.f, 0.f, r.b.y);
-    L.f0 = e1 * r.a.x;
-    L.f1 = e1 * r.a.y + e2 * r.a.w;
-    L.f2 = e1 * r.a.z + e2 * r.b.x + e3 * r.b.y;
-    L.c0 = cross3(L.f1, L.f2);
-    L.c1 = cross3(L.f2, L.f0);
-    L.c2 = cross3(L.f0, L.f1);
-    L.J = dot3(L.f0, L.c0);
-}
-
-__device__ __forceinline__ float3 sel3(bool c, float3 a, float3 b)
-{
-    return make_float3(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z);
-}
-
-// slot 0 -> m_0 = -(r0 + r1 + r2), slot 1..3 -> r0..r2; written as two
-// levels of per-component selects so that no private array is formed.
-__device__ __forceinline__ float3 shape_grad(const TetLocal &L, int k)
-{
-    const float3 m0 = -(L.r0 + L.r1 + L.r2);
-    const bool b0 = (k & 1) != 0, b1 = (k & 2) != 0;
-    return sel3(b1, sel3(b0, L.r2, L.r1), sel3(b0, L.r0, m0));
-}
-
-__device__ __forceinline__ float3 Fmul(const TetLocal &L, float3 m)
-{
-    return L.f0 * m.x + L.f1 * m.y + L.f2 * m.z;
-}
-__device__ __forceinline__ float3 Cmul(const TetLocal &L, float3 m)
-{
-    return L.c0 * m.x + L.c1 * m.y + L.c2 * m.z;
-}
-
 struct Acc {
     float fx, fy, fz, hxx, hxy, hxz, hyy, hyz, hzz;
 };
@@ -101,18 +49,6 @@ struct Acc {
 __device__ __forceinline__ void acc_zero(Acc &a)
 {
     a.fx = a.fy = a.fz = a.hxx = a.hxy = a.hxz = a.hyy = a.hyz = a.hzz = 0.f;
-}
-
-// Positions of a tet's four slots from the vertex's own position (slot k)
-// and the other three in slot order (a, b, c): slot s < k -> others[s],
-// s == k -> own, s > k -> others[s - 1].
-__device__ __forceinline__ void slot_positions(int k, float4 own, float4 a, float4 b, float4 c,
-                                               float4 &q0, float4 &q1, float4 &q2, float4 &q3)
-{
-    q0 = k == 0 ? own : a;
-    q1 = k < 1 ? a : (k == 1 ? own : b);
-    q2 = k < 2 ? b : (k == 2 ? own : c);
-    q3 = k < 3 ? c : own;
 }
 
 // One tet seen from the vertex i it is solved for (stable Neo-Hookean,
@@ -455,18 +391,6 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
 }
 
 // ----------------------------------------------------------------- kernels --
-__global__ void k_material(TetRec *rec, const float *vol, const int *tet_perm, const float *E,
-                           int n, float k_mu, float k_lam)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    float4 b = rec[t].b;
-    const float VE = vol[t] * E[tet_perm[t]];
-    b.z = VE * k_mu;
-    b.w = VE * k_lam;
-    rec[t].b = b;
-}
-
 // The E-dependent parts of every pair record: V lam into pa.w and
 // V mu {w, |m|^2} into pw (padding entries have pair_tet = -1).
 __global__ void k_material_pairs(int4 *pa, float4 *pw, const float4 *pws, const int *pair_tet,
@@ -718,12 +642,18 @@ __global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const fl
 // Reverse of one color phase.  The update x_i' = argmin G_i (exact for
 // these tets, G_i quadratic in x_i) satisfies grad_i G_i(x_i'; x_nbr, y_i, E)
 // = 0, so with w = H_i^{-1} xbar_i:
-//   xbar_i <- 0,  ybar_i += (m/h^2) w,  xbar_j -= K_ij^T w  (K = d2E/dx_i dx_j),
-//   Ebar_t -= w . (dE_t/dx_i) / E_t,
+//   xbar_i <- 0,  ybar_i += (m/h^2) w,  xbar_q -= d(w . grad_i Psi)/dx_q,
+//   Ebar_t -= (w . grad_i Psi_t) / E_t,
 // all at the state right after the update: vertices of colors <= c from
-// iteration n (Sn), the others from iteration n-1 (Sp).
-//   K_kq^T w = V [mu (m_k.m_q) w + lam c_q (c_k.w) + lam (J - alpha) (u x w)],
-//   u = F (m_k x m_q)   (d2J/dx_k dx_q w' = w' x u).
+// iteration n (Sn), the others from iteration n-1 (Sp).  In a tet's pair frame
+// (the forward's records: e_k = x_k - x_i for the other vertices a, b, c,
+// w_k = (S m)_k, sigma = det S, n = sigma (x_b - x_a) x (x_c - x_a), J = e1 . n):
+//   w . grad_i Psi = V mu sum_k w_k (w . e_k) - V lam (J - alpha) (n . w),
+// and for the neighbour q (index k of a, b, c)
+//   d/dx_q = V mu w_k w - V lam (n . w) c_q - V lam (J - alpha) g_q,
+//   c_q = dJ/dx_q = sigma {e2 x e3, e3 x e1, e1 x e2},
+//   g_q = d(n . w)/dx_q = sigma {w x (x_c - x_b), (x_c - x_a) x w, w x (x_b - x_a)}.
+// H_i = V mu |m|^2 I + V lam n n^T as in the forward solve.
 // Neighbour adjoints go to per-(tet, slot) cells instead of the neighbours
 // themselves: in a color phase a tet has at most one vertex of that color, so
 // its cells are written by one thread only (no atomics, deterministic).  A
@@ -737,9 +667,53 @@ __device__ __forceinline__ float4 adj_pos(const float4 *Sn, const float4 *Sp, in
     return (q < c_end ? Sn : Sp)[q];
 }
 
+// One tet's share of H_i: V mu |m|^2 I + V lam n n^T.
+__device__ __forceinline__ void adj_hess(float4 qa, float4 qb, float4 qc, float hmu, float vlam,
+                                         float sg, Acc &a)
+{
+    const float3 xa = xyz(qa);
+    const float3 n = cross3(xyz(qb) - xa, xyz(qc) - xa) * sg;
+    const float3 ln = n * vlam;
+    a.hxx += hmu + ln.x * n.x; a.hxy += ln.x * n.y; a.hxz += ln.x * n.z;
+    a.hyy += hmu + ln.y * n.y; a.hyz += ln.y * n.z; a.hzz += hmu + ln.z * n.z;
+}
+
+// One tet's reverse terms: -d(w . grad_i Psi)/dx_q added to the cells of the
+// other three slots (c0, c1, c2 in slot order); returns (w . grad_i Psi)/(V E).
+__device__ __forceinline__ float adj_pair(float3 xi, float4 qa, float4 qb, float4 qc, float4 ws,
+                                          float Vlam, float sg, float3 w, float mu_lam,
+                                          const StepConsts &K, float4 &c0, float4 &c1, float4 &c2)
+{
+    const float3 xa = xyz(qa), xb = xyz(qb), xc = xyz(qc);
+    const float3 e1 = xa - xi, e2 = xb - xi, e3 = xc - xi;
+    const float3 dab = xb - xa, dac = xc - xa;
+    const float3 n = cross3(dab, dac) * sg;
+    const float J = dot3(e1, n);
+    const float nw = dot3(n, w);
+    const float Vmu = Vlam * mu_lam;
+    // coefficients of c_q / sigma and g_q / sigma
+    const float kc = Vlam * nw * sg, kg = Vlam * (J - K.alpha) * sg;
+    const float3 ca = cross3(e2, e3), cb = cross3(e3, e1), cc = cross3(e1, e2);
+    const float3 ga = cross3(w, xc - xb), gb = cross3(dac, w), gc = cross3(w, dab);
+    const float3 ma = w * (Vmu * ws.x), mb = w * (Vmu * ws.y), mc = w * (Vmu * ws.z);
+    c0.x -= ma.x - kc * ca.x - kg * ga.x;
+    c0.y -= ma.y - kc * ca.y - kg * ga.y;
+    c0.z -= ma.z - kc * ca.z - kg * ga.z;
+    c1.x -= mb.x - kc * cb.x - kg * gb.x;
+    c1.y -= mb.y - kc * cb.y - kg * gb.y;
+    c1.z -= mb.z - kc * cb.z - kg * gb.z;
+    c2.x -= mc.x - kc * cc.x - kg * gc.x;
+    c2.y -= mc.y - kc * cc.y - kg * gc.y;
+    c2.z -= mc.z - kc * cc.z - kg * gc.z;
+    // k_mu sum_k w_k (w . e_k) - k_lam (J - alpha) (n . w)
+    const float wF = ws.x * dot3(w, e1) + ws.y * dot3(w, e2) + ws.z * dot3(w, e3);
+    return K.k_mu * wF - K.k_lam * (J - K.alpha) * nw;
+}
+
 // The entries come from the same per-color padded incidence as the forward
-// solve; each lane handles KU entries at a time with their loads issued
-// together (records, neighbour positions and contribution cells).
+// solve (the (tet, slot) entries for the cells, the pair records for
+// the frame quantities); each lane handles KU entries at a time with their
+// loads issued together (records, neighbour positions and contribution cells).
 template <int L, int KU>
 __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K,
                                                              const float4 *Sn, const float4 *Sp,
@@ -753,7 +727,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
     const bool active = p < v_end;
     const int c_end = v_end;   // permuted slots < c_end have color <= c
     const int D = active ? ell.y : 0;
-    const PairEnt *E = T.ell + ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
+    const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
+    const PairEnt *E = T.ell + e0;
     Acc a;
     acc_zero(a);
     float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
@@ -763,6 +738,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         xb4 = T.xbar[p];
         wm = T.y[p].w;
     }
+    const float3 xi = xyz(own);
     // pass 1: H_i at the post-update state, and this vertex's pending cells
     for (int base = lane; base < D; base += L * KU) {
         PairEnt ent[KU];
@@ -771,12 +747,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             const int e = base + j * L;
             ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
-        TetRec r[KU];
         float4 qa[KU], qb[KU], qc[KU], g[KU];
+        float hmu[KU], vlam[KU], sig[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
             if (ent[j].x >= 0) {
-                r[j] = T.rec[ent[j].x >> 2];
+                const size_t e = e0 + base + j * L;
+                hmu[j] = reinterpret_cast<const float *>(T.pw + e)[3];
+                vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e)[3]);
+                sig[j] = T.pb[e];
                 qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
                 qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
                 qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
@@ -785,19 +764,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
 #pragma unroll
         for (int j = 0; j < KU; ++j)
             if (ent[j].x >= 0) {
-                const int t = ent[j].x >> 2, k = ent[j].x & 3;
-                float4 q0, q1, q2, q3;
-                slot_positions(k, own, qa[j], qb[j], qc[j], q0, q1, q2, q3);
-                TetLocal Lc;
-                tet_local(r[j], q0, q1, q2, q3, Lc);
-                const float3 mk = shape_grad(Lc, k);
-                const float3 cm = Cmul(Lc, mk);
-                const float Vmu = r[j].b.z, Vlam = r[j].b.w;
-                const float d = Vmu * dot3(mk, mk);
-                a.hxx += d + Vlam * cm.x * cm.x; a.hxy += Vlam * cm.x * cm.y; a.hxz += Vlam * cm.x * cm.z;
-                a.hyy += d + Vlam * cm.y * cm.y; a.hyz += Vlam * cm.y * cm.z; a.hzz += d + Vlam * cm.z * cm.z;
+                adj_hess(qa[j], qb[j], qc[j], hmu[j], vlam[j], sig[j], a);
                 a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
-                T.contrib[4 * (size_t)t + k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
     }
     acc_reduce<L>(a);
@@ -816,11 +785,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
         T.ybar[p] = yb;
     }
-    // pass 2: -K_kq^T w into the cells of the other three slots, and Ebar
-    // (in stored tet order; k_bwd_final scatters it to the caller's order).
-    // All loads of KU entries, their cells included, are issued before the
-    // stores, which would otherwise order every cell's read after the
-    // previous cell's write.
+    const float mu_lam = K.k_mu / K.k_lam;
+    // pass 2: -d(w . grad_i Psi)/dx_q into the cells of the other three slots,
+    // and Ebar (in stored tet order; k_bwd_final scatters it to the caller's
+    // order).  All loads of KU entries, their cells included, are issued
+    // before the stores, which would otherwise order every cell's read after
+    // the previous cell's write.
     for (int base = lane; base < D; base += L * KU) {
         PairEnt ent[KU];
 #pragma unroll
@@ -828,14 +798,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             const int e = base + j * L;
             ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
-        TetRec r[KU];
-        float4 qa[KU], qb[KU], qc[KU], c0[KU], c1[KU], c2[KU];
-        float vol[KU], eb[KU];
+        float4 qa[KU], qb[KU], qc[KU], c0[KU], c1[KU], c2[KU], ws[KU];
+        float vol[KU], eb[KU], vlam[KU], sig[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
             if (ent[j].x >= 0) {
                 const int t = ent[j].x >> 2, k = ent[j].x & 3;
-                r[j] = T.rec[t];
+                const size_t e = e0 + base + j * L;
+                ws[j] = T.pws[e];
+                vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e)[3]);
+                sig[j] = T.pb[e];
                 qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
                 qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
                 qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
@@ -851,34 +823,117 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         for (int j = 0; j < KU; ++j)
             if (ent[j].x >= 0) {
                 const int t = ent[j].x >> 2, k = ent[j].x & 3;
-                float4 q0, q1, q2, q3;
-                slot_positions(k, own, qa[j], qb[j], qc[j], q0, q1, q2, q3);
-                TetLocal Lc;
-                tet_local(r[j], q0, q1, q2, q3, Lc);
-                const float3 mk = shape_grad(Lc, k);
-                const float3 ck = Cmul(Lc, mk);
-                const float cw = dot3(ck, w);
-                const float Vmu = r[j].b.z, Vlam = r[j].b.w;
-                const float s = Vlam * (Lc.J - K.alpha);
+                const float r = adj_pair(xi, qa[j], qb[j], qc[j], ws[j], vlam[j], sig[j], w, mu_lam, K,
+                                         c0[j], c1[j], c2[j]);
                 float4 *cell = T.contrib + 4 * (size_t)t;
-#pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    const int q = o + (o >= k ? 1 : 0);
-                    const float3 mq = shape_grad(Lc, q);
-                    const float3 cq = Cmul(Lc, mq);
-                    const float3 u = Fmul(Lc, cross3(mk, mq));
-                    const float3 uw = cross3(u, w);
-                    const float mm = Vmu * dot3(mk, mq);
-                    float4 gq = o == 0 ? c0[j] : (o == 1 ? c1[j] : c2[j]);
-                    gq.x -= mm * w.x + Vlam * cw * cq.x + s * uw.x;
-                    gq.y -= mm * w.y + Vlam * cw * cq.y + s * uw.y;
-                    gq.z -= mm * w.z + Vlam * cw * cq.z + s * uw.z;
-                    cell[q] = gq;
-                }
-                const float3 Fm = Fmul(Lc, mk);
-                T.ebar[t] = eb[j] - vol[j] * (K.k_mu * dot3(w, Fm) + K.k_lam * (Lc.J - K.alpha) * cw);
+                cell[k == 0 ? 1 : 0] = c0[j];
+                cell[k <= 1 ? 2 : 1] = c1[j];
+                cell[k <= 2 ? 3 : 2] = c2[j];
+                T.ebar[t] = eb[j] - vol[j] * r;
             }
     }
+}
+
+// Single-batch form of k_adjoint_color for D <= L * KU: every load of the
+// phase's vertex (its entries and pair records, then the neighbour positions,
+// all four cells of each tet, volumes and Ebar) is issued before any
+// arithmetic, so a vertex costs two dependent memory round trips instead of
+// four.  A tet has one vertex of the phase's color, so no other thread
+// touches its cells or its Ebar during the phase.
+template <int L, int KU>
+__global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts K,
+                                                           const float4 *Sn, const float4 *Sp,
+                                                           int v_begin, int v_end, int2 ell,
+                                                           int remap)
+{
+    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int gid = b * blockDim.x + threadIdx.x;
+    const int p = v_begin + gid / L;
+    const int lane = threadIdx.x & (L - 1);
+    const bool active = p < v_end;
+    const int c_end = v_end;   // permuted slots < c_end have color <= c
+    const int D = active ? ell.y : 0;
+    const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
+    PairEnt ent[KU];
+    float4 ws[KU];
+    float hmu[KU], vlam[KU], sig[KU];
+#pragma unroll
+    for (int j = 0; j < KU; ++j) {
+        const int e = lane + j * L;
+        if (e < D) {
+            ent[j] = T.ell[e0 + e];
+            ws[j] = T.pws[e0 + e];
+            hmu[j] = reinterpret_cast<const float *>(T.pw + e0 + e)[3];
+            vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e0 + e)[3]);
+            sig[j] = T.pb[e0 + e];
+        } else {
+            ent[j] = make_int4(-1, 0, 0, 0);
+        }
+    }
+    float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
+    float wm = 0.f;
+    if (active) {
+        own = Sn[p];
+        xb4 = T.xbar[p];
+        wm = T.y[p].w;
+    }
+    float4 qa[KU], qb[KU], qc[KU], g[KU], c0[KU], c1[KU], c2[KU];
+    float vol[KU], eb[KU];
+#pragma unroll
+    for (int j = 0; j < KU; ++j)
+        if (ent[j].x >= 0) {
+            const int t = ent[j].x >> 2, k = ent[j].x & 3;
+            qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
+            qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
+            qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
+            const float4 *cell = T.contrib + 4 * (size_t)t;
+            g[j] = cell[k];
+            c0[j] = cell[k == 0 ? 1 : 0];
+            c1[j] = cell[k <= 1 ? 2 : 1];
+            c2[j] = cell[k <= 2 ? 3 : 2];
+            vol[j] = T.vol[t];
+            eb[j] = T.ebar[t];
+        }
+    // pass 1: H_i at the post-update state; this vertex's pending cells fold in
+    Acc a;
+    acc_zero(a);
+#pragma unroll
+    for (int j = 0; j < KU; ++j)
+        if (ent[j].x >= 0) {
+            adj_hess(qa[j], qb[j], qc[j], hmu[j], vlam[j], sig[j], a);
+            a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
+            T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    acc_reduce<L>(a);
+    if (!active) return;
+    a.hxx += wm; a.hyy += wm; a.hzz += wm;
+    a.fx += xb4.x; a.fy += xb4.y; a.fz += xb4.z;
+    float3 w;
+    if (!solve_sym3(a, K.det_eps_rel, w)) {
+        if (lane == 0) T.xbar[p] = make_float4(a.fx, a.fy, a.fz, 0.f);
+        return;
+    }
+    if (lane == 0) {
+        T.xbar[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 yb = T.ybar[p];
+        yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
+        T.ybar[p] = yb;
+    }
+    // pass 2 from the registers
+    const float mu_lam = K.k_mu / K.k_lam;
+    const float3 xi = xyz(own);
+#pragma unroll
+    for (int j = 0; j < KU; ++j)
+        if (ent[j].x >= 0) {
+            const int t = ent[j].x >> 2, k = ent[j].x & 3;
+            const float r = adj_pair(xi, qa[j], qb[j], qc[j], ws[j], vlam[j], sig[j], w, mu_lam, K, c0[j],
+                                     c1[j], c2[j]);
+            float4 *cell = T.contrib + 4 * (size_t)t;
+            cell[k == 0 ? 1 : 0] = c0[j];
+            cell[k <= 1 ? 2 : 1] = c1[j];
+            cell[k <= 2 ? 3 : 2] = c2[j];
+            T.ebar[t] = eb[j] - vol[j] * r;
+        }
 }
 
 // End of the reverse sweep: every vertex (pinned ones included) folds the
@@ -937,8 +992,6 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K, hipStream_t s)
 {
     if (T.n_tets == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_material, dim3(cdiv(T.n_tets, 256)), dim3(256), 0, s, T.rec, T.vol,
-                       T.tet_perm, tet_E, T.n_tets, K.k_mu, K.k_lam);
     if (T.n_pairs > 0)
         hipLaunchKernelGGL(k_material_pairs, dim3(cdiv(T.n_pairs, 256)), dim3(256), 0, s, T.pa, T.pw,
                            T.pws, T.pair_tet, T.vol, T.tet_perm, tet_E, T.n_pairs, K.k_mu, K.k_lam);
@@ -1150,7 +1203,13 @@ static void adjoint_go(const DevTopo &T, const StepConsts &K, const float4 *Sn, 
                        int vb, int ve, int2 ell, const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
-    if (cfg.unroll >= 2)
+    // a color whose padded degree fits one batch of up to 2 entries per lane
+    // takes the single-batch kernel
+    if (ell.y <= L)
+        hipLaunchKernelGGL((k_adjoint_one<L, 1>), dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, ell, cfg.xcd_remap);
+    else if (ell.y <= 2 * L)
+        hipLaunchKernelGGL((k_adjoint_one<L, 2>), dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, ell, cfg.xcd_remap);
+    else if (cfg.unroll >= 2)
         hipLaunchKernelGGL((k_adjoint_color<L, 2>), dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, ell, cfg.xcd_remap);
     else
         hipLaunchKernelGGL((k_adjoint_color<L, 1>), dim3(grid), dim3(cfg.block), 0, s, T, K, Sn, Sp, vb, ve, ell, cfg.xcd_remap);

@@ -86,6 +86,51 @@ def test_adjoint_full_depth_small_cube_vs_oracle():
     compare("7^3 dL/dx0", gx, gxo)
 
 
+def _star(n_ring=20, seed=7):
+    """A center vertex shared by 2 * n_ring tets (a ring in the xy plane and two
+    apexes), so the color holding it has a padded tet degree above 32: its
+    phases take the general two-pass reverse kernel, the others the
+    single-batch one.  The bottom apex is pinned."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * np.arange(n_ring) / n_ring
+    ring = np.stack([0.1 * np.cos(ang), 0.1 * np.sin(ang), np.zeros(n_ring)], 1)
+    rest = np.concatenate([[[0.0, 0.0, 0.0]], ring, [[0.0, 0.0, 0.08]], [[0.0, 0.0, -0.08]]])
+    c, top, bot = 0, n_ring + 1, n_ring + 2
+    tets = []
+    for i in range(n_ring):
+        a, b = 1 + i, 1 + (i + 1) % n_ring
+        tets.append([c, a, b, top])
+        tets.append([c, b, a, bot])
+    tets = np.array(tets, np.int32)
+    pinned = np.zeros(rest.shape[0], np.uint8)
+    pinned[bot] = 1
+    x0 = rest + rng.uniform(-2e-3, 2e-3, rest.shape) * (1 - pinned[:, None])
+    w = W.Workload(name="star", rest=rest, tets=tets, pinned=pinned, x0=x0,
+                   v0=rng.normal(scale=0.05, size=rest.shape) * (1 - pinned[:, None]),
+                   tet_E=rng.uniform(1e4, 1e5, tets.shape[0]), params=W.StepParams(n_iters=15),
+                   frames=6, target=x0.mean(0) + np.array([0.05, -0.02, 0.03]))
+    return w
+
+
+def test_adjoint_high_degree_vertex_general_kernel():
+    """Reverse phases of a color whose padded degree exceeds two entries per
+    lane (the general two-pass kernel) next to single-batch phases."""
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    w = _star()
+    t = Topology.from_workload(w, bind=False)
+    rows, co = t.query(N.Q_TET_ROWS), t.query(N.Q_COLOR_OFFSETS)
+    deg = [int((rows[co[c] + 1:co[c + 1] + 1] - rows[co[c]:co[c + 1]]).max()) for c in range(t.n_colors)]
+    say(f"star: padded tet degree per color {deg}")
+    assert max(deg) > 32 and min(deg) <= 32
+    lo, gEo, gvo, gxo = oracle_grad(w)
+    lg, gE, gv, gx = gpu_grad(w)
+    assert lg == pytest.approx(lo, rel=1e-4)
+    compare("star dL/dE", gE, gEo)
+    compare("star dL/dv0", gv, gvo)
+    compare("star dL/dx0", gx, gxo)
+
+
 def test_adjoint_full_size_prefix_vs_oracle():
     """33^3 cube (196,608 tets), the first 2 frames x 20 iterations."""
     w = W.config_differentiable()
