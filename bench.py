@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--block", type=int, default=128, help="--profile-only: block size")
     ap.add_argument("--remap", type=int, default=1, help="--profile-only: XCD remap")
     ap.add_argument("--unroll", type=int, default=3, help="--profile-only: tet entries per lane")
+    ap.add_argument("--compact", type=int, default=0, help="--profile-only: 32-B pair records")
     return ap.parse_args()
 
 
@@ -187,7 +188,8 @@ def main():
     log(f"[bench] topology built in {time.perf_counter() - t0:.1f} s, {topo.n_colors} colors")
     if args.profile_only == "cube":
         topo.launch_config = dict(lanes_per_vertex=args.lanes, block_size=args.block,
-                                  xcd_remap=args.remap, tet_unroll=args.unroll)
+                                  xcd_remap=args.remap, tet_unroll=args.unroll,
+                                  compact_records=args.compact)
         secs, upd = time_frames(topo, w, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
         print(json.dumps({"profile": "cube", "ms_per_frame": secs / args.steps * 1e3}))
         return

@@ -252,6 +252,9 @@ typedef struct {
     int32_t xcd_remap;          /* 1: give each XCD a contiguous range of blocks */
     int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */
     int32_t tet_unroll;         /* 1..3 tet entries per lane loaded together */
+    int32_t compact_records;    /* 1: 32-B pair records (|m|^2 summed from w in the
+                                   solve; fewer bytes), 0: 36-B records (|m|^2
+                                   stored; fewer registers) */
 } vbd_launch_config;
 vbd_status vbd_get_launch_config(vbd_topology topo, vbd_launch_config *cfg);
 vbd_status vbd_set_launch_config(vbd_topology topo, const vbd_launch_config *cfg);

@@ -46,7 +46,8 @@ class StepParamsC(C.Structure):
 
 class LaunchConfig(C.Structure):
     _fields_ = [("lanes_per_vertex", C.c_int32), ("block_size", C.c_int32),
-                ("xcd_remap", C.c_int32), ("blocks_per_cu", C.c_int32), ("tet_unroll", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("blocks_per_cu", C.c_int32), ("tet_unroll", C.c_int32),
+                ("compact_records", C.c_int32)]
 
 
 class ProfileStats(C.Structure):

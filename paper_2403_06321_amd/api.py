@@ -205,14 +205,15 @@ class Topology:
         c = N.LaunchConfig()
         N.check(N.lib().vbd_get_launch_config(self._h, C.byref(c)))
         return dict(lanes_per_vertex=c.lanes_per_vertex, block_size=c.block_size,
-                    xcd_remap=c.xcd_remap, blocks_per_cu=c.blocks_per_cu, tet_unroll=c.tet_unroll)
+                    xcd_remap=c.xcd_remap, blocks_per_cu=c.blocks_per_cu, tet_unroll=c.tet_unroll,
+                    compact_records=c.compact_records)
 
     @launch_config.setter
     def launch_config(self, cfg):
         cur = self.launch_config
         cur.update(cfg)
         c = N.LaunchConfig(cur["lanes_per_vertex"], cur["block_size"], cur["xcd_remap"],
-                           cur["blocks_per_cu"], cur["tet_unroll"])
+                           cur["blocks_per_cu"], cur["tet_unroll"], cur["compact_records"])
         N.check(N.lib().vbd_set_launch_config(self._h, C.byref(c)))
 
     def profile_enable(self, on: bool = True):

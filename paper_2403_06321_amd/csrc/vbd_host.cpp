@@ -118,7 +118,9 @@ struct vbd_topology_s {
     std::vector<int2> spr_info;                 // the same for springs
     size_t spr_total = 0;
     std::vector<float> spr_len;
-    std::vector<double> phase_bytes;
+    std::vector<double> phase_bytes;            // for the current launch configuration
+    std::vector<std::array<int64_t, 3>> phase_cnt;  // per color: pairs, spring entries,
+                                                    // distinct neighbours
     std::vector<int64_t> phase_updates;
     // surface (extracted by vbd_color when there is more than one mesh)
     std::vector<int32_t> surf;          // [n_tri][3] original ids, outward
@@ -135,7 +137,7 @@ struct vbd_topology_s {
     DevTopo dev{};
     int n_cu = 0;
     std::string arch;
-    LaunchCfg cfg{8, 128, 1, 0, 2};
+    LaunchCfg cfg{8, 128, 1, 0, 2, 0};
     // graph caches of vbd_step and vbd_step_backward
     hipStream_t cap_stream = nullptr;   // library-owned stream used only for capture
     GraphCache fwd_graph, bwd_graph;
@@ -153,6 +155,21 @@ struct vbd_topology_s {
 };
 
 namespace {
+
+// Algorithmic bytes of one color solve under the current launch
+// configuration: per tet pair the 32-B compact or 36-B full record, 8 B per
+// spring entry, 48 B own state per vertex (x read, y read, x write), 16 B per
+// distinct neighbour position.
+void update_phase_bytes(vbd_topology_s &T)
+{
+    const double rec = T.cfg.compact ? 32.0 : 36.0;
+    T.phase_bytes.assign(T.phase_cnt.size(), 0.0);
+    for (size_t c = 0; c < T.phase_cnt.size(); ++c) {
+        const auto &n = T.phase_cnt[c];
+        T.phase_bytes[c] = rec * (double)n[0] + 8.0 * (double)n[1] + 48.0 * (double)T.phase_updates[c] +
+                           16.0 * (double)n[2];
+    }
+}
 
 // ----------------------------------------------------------------- layout --
 Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
@@ -610,34 +627,31 @@ void build_csr(vbd_topology_s &T)
             T.tet_rank[key[i].second] = i;
         }
     }
-    // algorithmic bytes of one color solve: 36 B pair record per tet pair, 8 B
-    // per spring entry, 48 B own state per vertex (x read, y read, x write),
-    // 16 B per distinct neighbour position.
-    T.phase_bytes.assign(T.n_colors, 0.0);
+    // per color: tet pairs, spring entries and distinct neighbours, for the
+    // algorithmic bytes of a color solve (update_phase_bytes)
+    T.phase_cnt.assign(T.n_colors, {0, 0, 0});
     T.phase_updates.assign(T.n_colors, 0);
     std::vector<int32_t> stamp(nv, -1);
     for (int c = 0; c < T.n_colors; ++c) {
-        double bytes = 0;
-        int64_t distinct = 0;
+        auto &n = T.phase_cnt[c];
         for (int s = T.color_off[c]; s < T.color_off[c + 1]; ++s) {
-            const int pairs = T.tet_row[s + 1] - T.tet_row[s];
-            const int sp = T.spr_row[s + 1] - T.spr_row[s];
-            bytes += (double)(sizeof(int4) + sizeof(float4) + sizeof(float)) * pairs + 8.0 * sp + 48.0;
+            n[0] += T.tet_row[s + 1] - T.tet_row[s];
+            n[1] += T.spr_row[s + 1] - T.spr_row[s];
             for (int e = T.tet_row[s]; e < T.tet_row[s + 1]; ++e) {
                 const int t = T.tet_ent[e] >> 2;
                 for (int k = 0; k < 4; ++k) {
                     const int u = T.iperm[T.tets[4 * (size_t)t + k]];
-                    if (u != s && stamp[u] != c) { stamp[u] = c; ++distinct; }
+                    if (u != s && stamp[u] != c) { stamp[u] = c; ++n[2]; }
                 }
             }
             for (int e = T.spr_row[s]; e < T.spr_row[s + 1]; ++e) {
                 const int u = T.iperm[T.spr_nbr_orig[e]];
-                if (stamp[u] != c) { stamp[u] = c; ++distinct; }
+                if (stamp[u] != c) { stamp[u] = c; ++n[2]; }
             }
         }
-        T.phase_bytes[c] = bytes + 16.0 * (double)distinct;
         T.phase_updates[c] = T.color_off[c + 1] - T.color_off[c];
     }
+    update_phase_bytes(T);
 }
 
 // ----------------------------------------------------------------- surface --
@@ -769,7 +783,7 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
                         bool persistent, bool in_capture)
 {
     const bool tets = T.nt > 0, springs = T.ns > 0;
-    HIP_TRY(launch_material(T.dev, E, K, s));
+    HIP_TRY(launch_material(T.dev, E, K, T.cfg.compact != 0, s));
     HIP_TRY(launch_predict(T.dev, x, v, vp, K, persistent, s));
     const bool prof = T.profiling && !in_capture;
     if (persistent) {
@@ -901,7 +915,7 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
     // forward recompute, snapshot n = iterate after iteration n
     DevTopo D = T.dev;
     D.x = D.snaps;
-    HIP_TRY(launch_material(D, E, K, s));
+    HIP_TRY(launch_material(D, E, K, T.cfg.compact != 0, s));
     HIP_TRY(launch_predict(D, x_t, v_t, v_prev, K, false, s));
     for (int it = 1; it <= p->n_iters; ++it) {
         float4 *Sn = T.dev.snaps + nv * it;
@@ -1229,8 +1243,8 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
                     const double w2 = S[5] * m2;
                     const size_t i = base + (size_t)(e - T->tet_row[sl]);
                     pa[i] = make_int4(T->iperm[ord[1]], T->iperm[ord[2]], T->iperm[ord[3]], 0);
-                    pws[i] = make_float4((float)w0, (float)w1, (float)w2, (float)(m0 * m0 + m1 * m1 + m2 * m2));
-                    pb[i] = (float)(S[0] * S[3] * S[5]);
+                    pws[i] = make_float4((float)w0, (float)w1, (float)w2, (float)(S[0] * S[3] * S[5]));
+                    pb[i] = pws[i].w;
                     ptet[i] = T->tet_rank[t];
                 }
             }
@@ -1411,6 +1425,7 @@ vbd_status vbd_get_launch_config(vbd_topology T, vbd_launch_config *c)
     c->xcd_remap = T->cfg.xcd_remap;
     c->blocks_per_cu = T->cfg.blocks_per_cu;
     c->tet_unroll = T->cfg.unroll;
+    c->compact_records = T->cfg.compact;
     return VBD_OK;
 }
 
@@ -1423,7 +1438,11 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
         return fail(VBD_E_INVALID_ARG, "block_size must be a multiple of 64 in [64, 512]");
     if (c->blocks_per_cu < 0) return fail(VBD_E_INVALID_ARG, "blocks_per_cu < 0");
     if (c->tet_unroll < 1 || c->tet_unroll > 3) return fail(VBD_E_INVALID_ARG, "tet_unroll must be 1, 2 or 3");
-    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu, c->tet_unroll};
+    if (c->compact_records != 0 && c->compact_records != 1)
+        return fail(VBD_E_INVALID_ARG, "compact_records must be 0 or 1");
+    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu, c->tet_unroll,
+                       c->compact_records};
+    update_phase_bytes(*T);
     T->fwd_graph.reset();
     T->bwd_graph.reset();
     return VBD_OK;
@@ -1443,6 +1462,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             T->cfg = it->second;
+            update_phase_bytes(*T);
             return VBD_OK;
         }
     }
@@ -1450,17 +1470,20 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     hipStream_t s = (hipStream_t)stream;
     const bool tets = T->nt > 0, springs = T->ns > 0;
     std::vector<LaunchCfg> cands;
-    for (int L : {4, 8, 16})
-        for (int U : {1, 2, 3}) {
-            if (!tets && U > 1) continue;
-            for (int B : {64, 128, 256, 512})
-                for (int rm : {0, 1}) {
-                    if (persistent)
-                        for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc, U});
-                    else
-                        cands.push_back(LaunchCfg{L, B, rm, 0, U});
-                }
-        }
+    for (int cr : {0, 1}) {
+        if (!tets && cr) continue;
+        for (int L : {4, 8, 16})
+            for (int U : {1, 2, 3}) {
+                if (!tets && U > 1) continue;
+                for (int B : {64, 128, 256, 512})
+                    for (int rm : {0, 1}) {
+                        if (persistent)
+                            for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc, U, cr});
+                        else
+                            cands.push_back(LaunchCfg{L, B, rm, 0, U, cr});
+                    }
+            }
+    }
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
@@ -1468,7 +1491,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     float best = 1e30f;
     LaunchCfg best_cfg = T->cfg;
     for (const LaunchCfg &cf : cands) {
-        HIP_TRY(launch_material(T->dev, E, K, s));
+        HIP_TRY(launch_material(T->dev, E, K, cf.compact != 0, s));
         HIP_TRY(launch_predict(T->dev, x, v, vp, K, true, s));
         HIP_TRY(hipEventRecord(a, s));
         if (persistent) {
@@ -1499,6 +1522,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     T->cfg = best_cfg;
+    update_phase_bytes(*T);
     T->fwd_graph.reset();
     T->bwd_graph.reset();
     std::lock_guard<std::mutex> g(g_tune_mu);

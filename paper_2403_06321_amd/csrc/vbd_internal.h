@@ -51,11 +51,14 @@ struct DevTopo {
     //                       frame S = R^{-1} of the tet's rest edges taken from
     //                       this vertex (D_m' = Q R, Q proper; F' = D_s' S is
     //                       F times a rotation), this vertex's shape gradient
-    //                       m = -(rows of S summed), w = S m and sigma = det S:
+    //                       m = -(rows of S summed), w = S m (so that
+    //                       w0 + w1 + w2 = -|m|^2) and sigma = det S:
     //                       pa = {the other three vertices (slot order), float
-    //                       bits of V lam}, pw = V mu {w, |m|^2}, pb = sigma;
-    //                       padding pa.x = -1;
-    //   pws                 {w, |m|^2}, the E-free part of pw (material input).
+    //                       bits of V lam}, pw = {V mu w, last}, pb = sigma, in
+    //                       two layouts: compact (32 B: last = sigma, pb not
+    //                       read, V mu |m|^2 summed from w) or full (36 B:
+    //                       last = V mu |m|^2); padding pa.x = -1;
+    //   pws                 {w, sigma}, the E-free record (material input).
     const PairEnt *ell;
     int4 *pa;
     float4 *pw;
@@ -116,11 +119,12 @@ struct LaunchCfg {
     int xcd_remap;
     int blocks_per_cu;
     int unroll;       // tet entries per lane whose loads are issued together (1..3)
+    int compact;      // 1: 32-B pair records (see DevTopo), 0: 36-B
 };
 
 // ---- kernel launchers (vbd_kernels.hip) ----
-// The E-dependent parts of the pair records (V lam, V mu {w, |m|^2}).
-hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K,
+// The E-dependent parts of the pair records (V lam, V mu w).
+hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K, bool compact,
                            hipStream_t s);
 hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, const float *vp,
                           const StepConsts &K, bool reset_flags, hipStream_t s);

@@ -12,10 +12,14 @@
 
 namespace vbd {
 
+// Lane permutation within a row of 16 lanes.  Every pattern used here reads a
+// valid lane of the same row, so the 0 written for an invalid source lane
+// (bound_ctrl) never appears; with that 0 (the identity of the add that
+// follows) the compiler folds the move into the add as one DPP instruction.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v)
 {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over aligned groups of L lanes (L = 4, 8, 16, 32, 64); every lane of
@@ -59,11 +63,12 @@ __device__ __forceinline__ void acc_zero(Acc &a)
 //   F m = D_s' (S m) = w0 e1 + w1 e2 + w2 e3                (w = S m),
 //   cof(F) m = dJ/dx_i = -sigma (x_b - x_a) x (x_c - x_a) = -n (sigma = det S),
 //   J = sigma det D_s' = e1 . n,
-// so f_i += V lam (J - alpha) n - V mu F m and H_ii += V mu |m|^2 I + V lam n n^T.
-// Record: pa.w = V lam, pw = V mu {w, |m|^2}, sigma.
-__device__ __forceinline__ void pair_accumulate(float Vlam, float4 W, float sigma, float4 own,
-                                                float4 qa, float4 qb, float4 qc, const StepConsts &K,
-                                                Acc &a)
+// so f_i += V lam (J - alpha) n - V mu F m and H_ii += V mu |m|^2 I + V lam n n^T,
+// where |m|^2 = -(w0 + w1 + w2) (w_k = s_k . m for the rows s_k of S, which sum
+// to -m).  Record: pa.w = V lam, W.xyz = V mu w, hmu = V mu |m|^2.
+__device__ __forceinline__ void pair_accumulate(float Vlam, float4 W, float sigma, float hmu,
+                                                float4 own, float4 qa, float4 qb, float4 qc,
+                                                const StepConsts &K, Acc &a)
 {
     const float3 xi = xyz(own), xa = xyz(qa), xb = xyz(qb), xc = xyz(qc);
     const float3 e1 = xa - xi, e2 = xb - xi, e3 = xc - xi;
@@ -75,20 +80,20 @@ __device__ __forceinline__ void pair_accumulate(float Vlam, float4 W, float sigm
     a.fy += s * n.y - Fm.y;
     a.fz += s * n.z - Fm.z;
     const float3 ln = n * Vlam;
-    a.hxx += W.w + ln.x * n.x;
+    a.hxx += hmu + ln.x * n.x;
     a.hxy += ln.x * n.y;
     a.hxz += ln.x * n.z;
-    a.hyy += W.w + ln.y * n.y;
+    a.hyy += hmu + ln.y * n.y;
     a.hyz += ln.y * n.z;
-    a.hzz += W.w + ln.z * n.z;
+    a.hzz += hmu + ln.z * n.z;
 }
 
 // Tet terms of one vertex from its D consecutive pair records starting at
 // index e0: the lanes of the group take records lane, lane + L, ...; each lane
 // issues the loads of KU records together (their addresses follow from the
 // slot alone, so they go out with the vertex's own state), then the KU x 3
-// neighbour positions together.
-template <int L, int KU>
+// neighbour positions together.  CR: compact (32-B) records.
+template <int L, int KU, bool CR>
 __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own, size_t e0,
                                           int D, int lane, const StepConsts &K, Acc &a)
 {
@@ -102,7 +107,7 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
             if (e < D) {
                 pa[j] = T.pa[e0 + e];
                 pw[j] = T.pw[e0 + e];
-                pb[j] = T.pb[e0 + e];
+                if (!CR) pb[j] = T.pb[e0 + e];
             } else {
                 pa[j] = make_int4(-1, 0, 0, 0);
             }
@@ -117,7 +122,11 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
             }
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (pa[j].x >= 0) pair_accumulate(__int_as_float(pa[j].w), pw[j], pb[j], own, qa[j], qb[j], qc[j], K, a);
+            if (pa[j].x >= 0) {
+                const float sigma = CR ? pw[j].w : pb[j];
+                const float hmu = CR ? -(pw[j].x + pw[j].y + pw[j].z) : pw[j].w;
+                pair_accumulate(__int_as_float(pa[j].w), pw[j], sigma, hmu, own, qa[j], qb[j], qc[j], K, a);
+            }
     }
 }
 
@@ -188,7 +197,7 @@ __device__ __forceinline__ bool solve_sym3(const Acc &a, float eps_rel, float3 &
     const float fro = sqrtf(a.hxx * a.hxx + a.hyy * a.hyy + a.hzz * a.hzz +
                             2.f * (a.hxy * a.hxy + a.hxz * a.hxz + a.hyz * a.hyz));
     if (!(fabsf(det) > eps_rel * fro * fro * fro)) return false;
-    const float inv = 1.0f / det;
+    const float inv = __builtin_amdgcn_rcpf(det);   // v_rcp_f32, 1 ulp
     dx.x = (A00 * a.fx + A01 * a.fy + A02 * a.fz) * inv;
     dx.y = (A01 * a.fx + A11 * a.fy + A12 * a.fz) * inv;
     dx.z = (A02 * a.fx + A12 * a.fy + A22 * a.fz) * inv;
@@ -337,8 +346,8 @@ __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &
 // One vertex update by a group of L lanes.  All lanes of the wave must call
 // this (inactive groups pass active = false) because of the DPP reduction.
 // The phase covers slots [vb, ve) of one color with incidence layout inc.
-// MC: mesh-mesh contacts.
-template <int L, int KU, bool TETS, bool SPRINGS, bool MC = false>
+// MC: mesh-mesh contacts; CR: compact pair records.
+template <int L, int KU, bool TETS, bool SPRINGS, bool MC, bool CR>
 __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts &K, int p,
                                              int lane, bool active, int vb, int ve, int4 inc,
                                              const DevSurf *S = nullptr)
@@ -351,7 +360,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
         xi4 = T.x[p];
         yv = T.y[p];
         if (TETS)
-            tet_terms<L, KU>(T, T.x, xi4, (size_t)inc.x + (size_t)(p - vb) * inc.y, inc.y, lane, K, a);
+            tet_terms<L, KU, CR>(T, T.x, xi4, (size_t)inc.x + (size_t)(p - vb) * inc.y, inc.y, lane, K, a);
         if (SPRINGS)
             spring_terms<L>(T.x, xyz(xi4), T.spr_ell + (size_t)inc.z + (size_t)(p - vb) * inc.w, inc.w,
                             lane, K, a);
@@ -391,11 +400,12 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
 }
 
 // ----------------------------------------------------------------- kernels --
-// The E-dependent parts of every pair record: V lam into pa.w and
-// V mu {w, |m|^2} into pw (padding entries have pair_tet = -1).
+// The E-dependent parts of every pair record: V lam into pa.w and V mu w into
+// pw, whose last entry is sigma (compact) or V mu |m|^2 = -V mu (w0 + w1 + w2)
+// (padding entries have pair_tet = -1).
 __global__ void k_material_pairs(int4 *pa, float4 *pw, const float4 *pws, const int *pair_tet,
                                  const float *vol, const int *tet_perm, const float *E, long long n,
-                                 float k_mu, float k_lam)
+                                 float k_mu, float k_lam, int compact)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -405,7 +415,7 @@ __global__ void k_material_pairs(int4 *pa, float4 *pw, const float4 *pws, const 
     const float Vmu = VE * k_mu;
     reinterpret_cast<int *>(pa + i)[3] = __float_as_int(VE * k_lam);
     const float4 w = pws[i];
-    pw[i] = make_float4(w.x * Vmu, w.y * Vmu, w.z * Vmu, w.w * Vmu);
+    pw[i] = make_float4(w.x * Vmu, w.y * Vmu, w.z * Vmu, compact ? w.w : -(w.x + w.y + w.z) * Vmu);
 }
 
 // y = x^t + h v^t + h^2 a_ext (Eq. inertia) and the initial guess (Sec. 3.7).
@@ -452,20 +462,21 @@ __global__ void k_predict(DevTopo T, const float *x, const float *v, const float
 
 constexpr int kMaxBlock = 512;
 
-template <int L, int KU, bool TETS, bool SPRINGS>
-__global__ __launch_bounds__(kMaxBlock) void k_solve(DevTopo T, StepConsts K, int v_begin,
-                                                     int v_end, int4 inc, int remap)
+template <int L, int KU, bool TETS, bool SPRINGS, bool CR>
+__global__ __launch_bounds__(kMaxBlock) void k_solve(
+    DevTopo T, StepConsts K, int v_begin, int v_end, int4 inc, int remap)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin, v_end, inc);
+    solve_vertex<L, KU, TETS, SPRINGS, false, CR>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin, v_end,
+                                                  inc);
 }
 
 // Color phase with mesh contacts.  The previously solved color's snapshot is
 // refreshed here: during this phase neither its positions change nor its
 // snapshot is read.
-template <int L, int KU, bool TETS, bool SPRINGS>
+template <int L, int KU, bool TETS, bool SPRINGS, bool CR>
 __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, StepConsts K,
                                                         int v_begin, int v_end, int4 inc,
                                                         int prev_begin, int prev_end, int remap)
@@ -476,8 +487,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, St
     const int b = xcd_block(blockIdx.x, gridDim.x, remap);
     const int gid = b * blockDim.x + threadIdx.x;
     const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS, true>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin,
-                                             v_end, inc, &S);
+    solve_vertex<L, KU, TETS, SPRINGS, true, CR>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin,
+                                                 v_end, inc, &S);
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -568,7 +579,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned target)
     return s_abort != 0;
 }
 
-template <int L, int KU, bool TETS, bool SPRINGS>
+template <int L, int KU, bool TETS, bool SPRINGS, bool CR>
 __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts K, int n_iters,
                                                           int remap)
 {
@@ -589,7 +600,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
             const int cend = min(cb + chunk, ve);
             for (int base = cb; base < cb + chunk; base += G) {
                 const int p = base + g;
-                solve_vertex<L, KU, TETS, SPRINGS>(T, K, p, lane, p < cend, vb, ve, inc);
+                solve_vertex<L, KU, TETS, SPRINGS, false, CR>(T, K, p, lane, p < cend, vb, ve, inc);
             }
             ++nbar;
             if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
@@ -653,7 +664,7 @@ __global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const fl
 //   d/dx_q = V mu w_k w - V lam (n . w) c_q - V lam (J - alpha) g_q,
 //   c_q = dJ/dx_q = sigma {e2 x e3, e3 x e1, e1 x e2},
 //   g_q = d(n . w)/dx_q = sigma {w x (x_c - x_b), (x_c - x_a) x w, w x (x_b - x_a)}.
-// H_i = V mu |m|^2 I + V lam n n^T as in the forward solve.
+// H_i = V mu |m|^2 I + V lam n n^T as in the forward solve (|m|^2 = -(w0 + w1 + w2)).
 // Neighbour adjoints go to per-(tet, slot) cells instead of the neighbours
 // themselves: in a color phase a tet has at most one vertex of that color, so
 // its cells are written by one thread only (no atomics, deterministic).  A
@@ -729,6 +740,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
     const int D = active ? ell.y : 0;
     const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
     const PairEnt *E = T.ell + e0;
+    const float mu_lam = K.k_mu / K.k_lam;
     Acc a;
     acc_zero(a);
     float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
@@ -753,9 +765,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         for (int j = 0; j < KU; ++j)
             if (ent[j].x >= 0) {
                 const size_t e = e0 + base + j * L;
-                hmu[j] = reinterpret_cast<const float *>(T.pw + e)[3];
+                const float4 ws = T.pws[e];
                 vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e)[3]);
-                sig[j] = T.pb[e];
+                hmu[j] = -(ws.x + ws.y + ws.z) * (vlam[j] * mu_lam);
+                sig[j] = ws.w;
                 qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
                 qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
                 qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
@@ -785,7 +798,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
         yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
         T.ybar[p] = yb;
     }
-    const float mu_lam = K.k_mu / K.k_lam;
     // pass 2: -d(w . grad_i Psi)/dx_q into the cells of the other three slots,
     // and Ebar (in stored tet order; k_bwd_final scatters it to the caller's
     // order).  All loads of KU entries, their cells included, are issued
@@ -807,7 +819,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
                 const size_t e = e0 + base + j * L;
                 ws[j] = T.pws[e];
                 vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e)[3]);
-                sig[j] = T.pb[e];
+                sig[j] = ws[j].w;
                 qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
                 qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
                 qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
@@ -854,6 +866,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
     const int c_end = v_end;   // permuted slots < c_end have color <= c
     const int D = active ? ell.y : 0;
     const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
+    const float mu_lam = K.k_mu / K.k_lam;
     PairEnt ent[KU];
     float4 ws[KU];
     float hmu[KU], vlam[KU], sig[KU];
@@ -863,9 +876,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
         if (e < D) {
             ent[j] = T.ell[e0 + e];
             ws[j] = T.pws[e0 + e];
-            hmu[j] = reinterpret_cast<const float *>(T.pw + e0 + e)[3];
             vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e0 + e)[3]);
-            sig[j] = T.pb[e0 + e];
+            // V mu |m|^2 = -V lam (k_mu / k_lam) (w0 + w1 + w2)
+            hmu[j] = -(ws[j].x + ws[j].y + ws[j].z) * (vlam[j] * mu_lam);
+            sig[j] = ws[j].w;
         } else {
             ent[j] = make_int4(-1, 0, 0, 0);
         }
@@ -920,7 +934,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
         T.ybar[p] = yb;
     }
     // pass 2 from the registers
-    const float mu_lam = K.k_mu / K.k_lam;
     const float3 xi = xyz(own);
 #pragma unroll
     for (int j = 0; j < KU; ++j)
@@ -989,12 +1002,14 @@ __global__ void k_bwd_final(DevTopo T, const float *v_t, const float *v_prev, fl
 // -------------------------------------------------------------- launchers --
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
-hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K, hipStream_t s)
+hipError_t launch_material(const DevTopo &T, const float *tet_E, const StepConsts &K, bool compact,
+                           hipStream_t s)
 {
     if (T.n_tets == 0) return hipSuccess;
     if (T.n_pairs > 0)
         hipLaunchKernelGGL(k_material_pairs, dim3(cdiv(T.n_pairs, 256)), dim3(256), 0, s, T.pa, T.pw,
-                           T.pws, T.pair_tet, T.vol, T.tet_perm, tet_E, T.n_pairs, K.k_mu, K.k_lam);
+                           T.pws, T.pair_tet, T.vol, T.tet_perm, tet_E, T.n_pairs, K.k_mu, K.k_lam,
+                           compact ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1011,14 +1026,19 @@ static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, 
                                  bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
-    if (tets && springs)
-        hipLaunchKernelGGL((k_solve<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+    const bool cr = cfg.compact != 0;
+    if (tets && springs && cr)
+        hipLaunchKernelGGL((k_solve<L, KU, true, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+    else if (tets && springs)
+        hipLaunchKernelGGL((k_solve<L, KU, true, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+    else if (tets && cr)
+        hipLaunchKernelGGL((k_solve<L, KU, true, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
     return hipGetLastError();
 }
 
@@ -1054,14 +1074,19 @@ static hipError_t solve_mc_dispatch(const DevTopo &T, const DevSurf &S, const St
                                     const LaunchCfg &cfg, hipStream_t s)
 {
     const int grid = cdiv((long)(ve - vb) * L, cfg.block);
-    if (tets && springs)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+    const bool cr = cfg.compact != 0;
+    if (tets && springs && cr)
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+    else if (tets && springs)
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+    else if (tets && cr)
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     else if (tets)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     else if (springs)
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     else
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
     return hipGetLastError();
 }
 
@@ -1108,12 +1133,12 @@ hipError_t launch_finalize(const DevTopo &T, float *x, float *v, float *vp, cons
     return hipGetLastError();
 }
 
-template <int L, int KU, bool TE, bool SP>
+template <int L, int KU, bool TE, bool SP, bool CR>
 static hipError_t persistent_go(const DevTopo &T, const StepConsts &K, int n_iters,
                                 const LaunchCfg &cfg, int n_cu, bool coop, hipStream_t s,
                                 int *grid_out)
 {
-    auto fn = k_persistent<L, KU, TE, SP>;
+    auto fn = k_persistent<L, KU, TE, SP, CR>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, cfg.block, 0);
     if (e != hipSuccess) return e;
@@ -1142,10 +1167,13 @@ static hipError_t persistent_kinds(const DevTopo &T, const StepConsts &K, int n_
                                    bool springs, const LaunchCfg &cfg, int n_cu, bool coop,
                                    hipStream_t s, int *grid_out)
 {
-    if (tets && springs) return persistent_go<L, KU, true, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
-    if (tets) return persistent_go<L, KU, true, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
-    if (springs) return persistent_go<L, 1, false, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
-    return persistent_go<L, 1, false, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    const bool cr = cfg.compact != 0;
+    if (tets && springs && cr) return persistent_go<L, KU, true, true, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (tets && springs) return persistent_go<L, KU, true, true, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (tets && cr) return persistent_go<L, KU, true, false, true>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (tets) return persistent_go<L, KU, true, false, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    if (springs) return persistent_go<L, 1, false, true, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
+    return persistent_go<L, 1, false, false, false>(T, K, n_iters, cfg, n_cu, coop, s, grid_out);
 }
 
 template <int L>

@@ -180,6 +180,24 @@ def test_phase_bytes_model():
         assert pb[c] <= 36 * pairs + 48 * nvc + 16 * w.n_verts
 
 
+def test_phase_bytes_follow_the_record_layout():
+    """Compact pair records are 32 B, full ones 36 B; nothing else changes."""
+    w = W.tet_cube(4, 0)
+    t = Topology.from_workload(w, bind=False)
+    pb0 = t.query(N.Q_PHASE_BYTES).copy()
+    rows = t.query(N.Q_TET_ROWS)
+    co = t.query(N.Q_COLOR_OFFSETS)
+    t.launch_config = dict(compact_records=1)
+    assert t.launch_config["compact_records"] == 1
+    pb1 = t.query(N.Q_PHASE_BYTES)
+    for c in range(t.n_colors):
+        assert pb0[c] - pb1[c] == 4 * (rows[co[c + 1]] - rows[co[c]])
+    t.launch_config = dict(compact_records=0)
+    assert np.array_equal(t.query(N.Q_PHASE_BYTES), pb0)
+    with pytest.raises(N.VBDError):
+        t.launch_config = dict(compact_records=2)
+
+
 def test_tet_order_groups_tets_by_vertex_colors():
     w = W.tet_cube(7, 2)
     t = Topology.from_workload(w, bind=False)
@@ -209,6 +227,52 @@ def test_rest_frame_preserves_deformation_invariants():
         Q = np.linalg.solve(F, Fp)
         assert np.allclose(Q.T @ Q, np.eye(3), atol=1e-10)
         assert np.linalg.det(Fp) == pytest.approx(np.linalg.det(F), rel=1e-12)
+
+
+def test_pair_frame_identities():
+    """The identities the color solve and its reverse rest on, checked on the
+    library's rest frames (vertex in slot 0 as origin) against full matrix
+    algebra with F = D_s D_m^{-1}: with the rows s_k of S, m = -(s0 + s1 + s2),
+    w = S m and sigma = det S,
+      sum_k w_k = -|m|^2,   F m = sum_k w_k e_k,
+      cof(F) m = -sigma (x_b - x_a) x (x_c - x_a),   J = e1 . sigma (x_b - x_a) x (x_c - x_a),
+    and the gradient of (cof(F) m) . w with respect to x_a, x_b, x_c."""
+    w_ = W.tet_cube(4, 3)
+    t = Topology.from_workload(w_, bind=False)
+    S6 = t.query(N.Q_REST_FRAME).reshape(-1, 6)
+    Dminv = t.query(N.Q_DMINV).reshape(-1, 3, 3)
+    rng = np.random.default_rng(1)
+    x = w_.rest + rng.normal(scale=0.02, size=w_.rest.shape)
+    for k in rng.choice(w_.n_tets, 40, replace=False):
+        S = np.array([[S6[k, 0], S6[k, 1], S6[k, 2]], [0, S6[k, 3], S6[k, 4]], [0, 0, S6[k, 5]]])
+        m = -S.sum(axis=0)
+        wv = S @ m
+        sig = np.linalg.det(S)
+        assert wv.sum() == pytest.approx(-m @ m, rel=1e-12)
+        q = w_.tets[k]
+        xi, xa, xb, xc = x[q]
+        e = np.stack([xa - xi, xb - xi, xc - xi], 1)
+        F = e @ Dminv[k]
+        # shape gradient of slot 0 for F = D_s D_m^{-1}
+        m_true = -Dminv[k].sum(axis=0)
+        cof = np.linalg.det(F) * np.linalg.inv(F).T
+        n = sig * np.cross(xb - xa, xc - xa)
+        # F' = F Q and m = Q^T m_true, so F' m = F m_true
+        assert np.allclose(e @ wv, F @ m_true, rtol=1e-10, atol=1e-12)
+        assert np.allclose(-n, cof @ m_true, rtol=1e-9, atol=1e-12)
+        assert e[:, 0] @ n == pytest.approx(np.linalg.det(F), rel=1e-10)
+        # d(n . u)/dx_q by central differences for a random u
+        u = rng.normal(size=3)
+        g = [sig * np.cross(u, xc - xb), sig * np.cross(xc - xa, u), sig * np.cross(u, xb - xa)]
+        for j, idx in enumerate((1, 2, 3)):
+            for d in range(3):
+                h = 1e-6
+                xp, xm = x[q].copy(), x[q].copy()
+                xp[idx, d] += h
+                xm[idx, d] -= h
+                fp = sig * np.cross(xp[2] - xp[1], xp[3] - xp[1]) @ u
+                fm = sig * np.cross(xm[2] - xm[1], xm[3] - xm[1]) @ u
+                assert (fp - fm) / (2 * h) == pytest.approx(g[j][d], rel=1e-6, abs=1e-6 * abs(sig))
 
 
 def test_surface_matches_oracle_with_outward_orientation():

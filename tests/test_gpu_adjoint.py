@@ -16,12 +16,14 @@ THREADS = min(16, os.cpu_count() or 1)
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_cube33.npz")
 
 
-def gpu_grad(w, frames=None):
+def gpu_grad(w, frames=None, cfg=None):
     import torch
     from paper_2403_06321_amd.api import Rollout, Topology
     frames = frames or w.frames
     dev = torch.device("cuda", 0)
     topo = Topology.from_workload(w, max_backward_iters=w.params.n_iters)
+    if cfg:
+        topo.launch_config = cfg
     x0 = torch.tensor(w.x0, dtype=torch.float32, device=dev)
     v0 = torch.tensor(w.v0, dtype=torch.float32, device=dev).requires_grad_(True)
     E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).requires_grad_(True)
@@ -129,6 +131,17 @@ def test_adjoint_high_degree_vertex_general_kernel():
     compare("star dL/dE", gE, gEo)
     compare("star dL/dv0", gv, gvo)
     compare("star dL/dx0", gx, gxo)
+
+
+def test_adjoint_with_compact_records_in_the_forward():
+    """7^3 cube, 30 frames x 20 iterations, the forward (and its replay in the
+    backward) on 32-B pair records."""
+    w = W.config_differentiable(n=7)
+    lo, gEo, gvo, gxo = oracle_grad(w)
+    lg, gE, gv, gx = gpu_grad(w, cfg=dict(compact_records=1))
+    assert lg == pytest.approx(lo, rel=1e-4)
+    compare("7^3 compact records dL/dE", gE, gEo)
+    compare("7^3 compact records dL/dv0", gv, gvo)
 
 
 def test_adjoint_full_size_prefix_vs_oracle():

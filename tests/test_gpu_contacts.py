@@ -60,11 +60,13 @@ def test_detection_on_rotated_jittered_blocks():
     say(f"rotated stack: {sum(k is not None for k in ko)} contacts, {len(diff)} equal-distance ties")
 
 
+@pytest.mark.parametrize("compact", [0, 1])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_block_stack_steps_match_oracle(mode):
+def test_block_stack_steps_match_oracle(mode, compact):
     w = W.config_block_stack(cols=2, levels=3, n=5, frames=6)
     st = oracle_states(w, w.frames)
-    resync_parity(w, st, launch_mode=mode, tol=1e-5, label=f"block stack mode {mode}")
+    resync_parity(w, st, launch_mode=mode, tol=1e-5, cfg=dict(compact_records=compact),
+                  label=f"block stack mode {mode} compact records {compact}")
 
 
 def test_block_stack_friction_redetection_and_acceleration():

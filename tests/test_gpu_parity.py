@@ -41,6 +41,14 @@ def test_small_cube_launch_configs(small_cube_oracle, lanes, block, remap):
     assert_parity(w, xp, xo, label=f"lanes {lanes} persistent")
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_small_cube_compact_records(small_cube_oracle, mode):
+    """32-B pair records (|m|^2 summed from w in the solve) in every launch mode."""
+    w, (xo, _) = small_cube_oracle
+    xg, _, _ = gpu_rollout(w, w.frames, cfg=dict(compact_records=1), launch_mode=mode)
+    assert_parity(w, xg, xo, label=f"11^3 compact records mode {mode}")
+
+
 def test_deterministic_and_modes_bit_identical():
     w = W.tet_cube(7, 3, E_range=(1e4, 1e6), n_iters=10, frames=3)
     a, _, _ = gpu_rollout(w, 3)
@@ -162,6 +170,11 @@ def test_large_cube_four_colorings_prefix(coloring):
     for mode in (0, 3):
         xg, _, _ = gpu_rollout(w, 2, params=p, launch_mode=mode, autotune=True)
         assert_parity(w, xg, xo, label=f"65^3 {coloring} coloring mode {mode}")
+    # both pair-record layouts explicitly, whichever the autotuner picked
+    for cr in (0, 1):
+        cfg = dict(lanes_per_vertex=16, block_size=64, xcd_remap=1, tet_unroll=2, compact_records=cr)
+        xg, _, _ = gpu_rollout(w, 2, params=p, cfg=cfg)
+        assert_parity(w, xg, xo, label=f"65^3 {coloring} coloring compact records {cr}")
 
 
 def test_cloth_with_contacts():
