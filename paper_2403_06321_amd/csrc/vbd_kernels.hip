@@ -139,8 +139,9 @@ __device__ __forceinline__ void spring_contrib(const float4 *X, float3 xi, int2 
     const float3 xj = xyz(X[se.x]);
     const float L = __int_as_float(se.y);
     const float3 d = xi - xj;
-    const float l = sqrtf(dot3(d, d));
-    const float inv_l = 1.0f / l;
+    const float l2 = dot3(d, d);
+    const float inv_l = __builtin_amdgcn_rsqf(l2);   // v_rsq_f32, 1 ulp
+    const float l = l2 * inv_l;
     const float3 u = d * inv_l;
     const float g = k * (l - L);
     a.fx -= g * u.x; a.fy -= g * u.y; a.fz -= g * u.z;
@@ -236,8 +237,10 @@ __device__ __forceinline__ bool vertex_terms(const DevTopo &T, const StepConsts 
         if (o < K.n_spheres) {
             const float4 s = K.spheres[o];
             const float3 r = xi - make_float3(s.x, s.y, s.z);
-            const float dist = sqrtf(dot3(r, r));
-            n = r * (1.0f / dist);
+            const float r2 = dot3(r, r);
+            const float inv = __builtin_amdgcn_rsqf(r2);   // v_rsq_f32, 1 ulp
+            const float dist = r2 * inv;
+            n = r * inv;
             pen = s.w + K.delta - dist;
         } else {
             const float4 pl = K.planes[o - K.n_spheres];
