@@ -247,7 +247,7 @@ vbd_status vbd_detect_contacts(vbd_topology topo, const vbd_step_params *params,
 
 /* Kernel launch configuration of the color solve. */
 typedef struct {
-    int32_t lanes_per_vertex;   /* 4, 8, 16 or 32 lanes of a wave64 per vertex */
+    int32_t lanes_per_vertex;   /* 2, 4, 8, 16 or 32 lanes of a wave64 per vertex */
     int32_t block_size;         /* 64..512, multiple of 64 */
     int32_t xcd_remap;          /* 1: give each XCD a contiguous range of blocks */
     int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */

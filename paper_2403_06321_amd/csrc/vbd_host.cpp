@@ -1433,7 +1433,8 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
 {
     if (!T || !c) return fail(VBD_E_INVALID_ARG, "NULL argument");
     const int L = c->lanes_per_vertex;
-    if (L != 4 && L != 8 && L != 16 && L != 32) return fail(VBD_E_INVALID_ARG, "lanes_per_vertex must be 4, 8, 16 or 32");
+    if (L != 2 && L != 4 && L != 8 && L != 16 && L != 32)
+        return fail(VBD_E_INVALID_ARG, "lanes_per_vertex must be 2, 4, 8, 16 or 32");
     if (c->block_size < 64 || c->block_size > 512 || c->block_size % 64)
         return fail(VBD_E_INVALID_ARG, "block_size must be a multiple of 64 in [64, 512]");
     if (c->blocks_per_cu < 0) return fail(VBD_E_INVALID_ARG, "blocks_per_cu < 0");
@@ -1472,7 +1473,8 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     std::vector<LaunchCfg> cands;
     for (int cr : {0, 1}) {
         if (!tets && cr) continue;
-        for (int L : {4, 8, 16})
+        for (int L : {2, 4, 8, 16}) {
+            if (tets && L == 2) continue;   // tets: 24 pairs per vertex want more lanes
             for (int U : {1, 2, 3}) {
                 if (!tets && U > 1) continue;
                 for (int B : {64, 128, 256, 512})
@@ -1483,6 +1485,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
                             cands.push_back(LaunchCfg{L, B, rm, 0, U, cr});
                     }
             }
+        }
     }
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));

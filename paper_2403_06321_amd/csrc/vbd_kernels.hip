@@ -22,13 +22,13 @@ __device__ __forceinline__ float dpp_mov(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over aligned groups of L lanes (L = 4, 8, 16, 32, 64); every lane of
+// Sum over aligned groups of L lanes (L = 2, 4, 8, 16, 32, 64); every lane of
 // the group receives the total.  Must be called with the whole wave active.
 template <int L>
 __device__ __forceinline__ float group_sum(float v)
 {
     v += dpp_mov<0xB1>(v);              // quad_perm [1,0,3,2]  (xor 1)
-    v += dpp_mov<0x4E>(v);              // quad_perm [2,3,0,1]  (xor 2)
+    if (L >= 4) v += dpp_mov<0x4E>(v);  // quad_perm [2,3,0,1]  (xor 2)
     if (L >= 8) v += dpp_mov<0x141>(v); // row_half_mirror      (lane i <-> 7-i)
     if (L >= 16) v += dpp_mov<0x140>(v);// row_mirror           (lane i <-> 15-i)
     if (L >= 32) v += __shfl_xor(v, 16);
@@ -1063,6 +1063,7 @@ hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, i
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
+    case 2: return solve_unroll<2>(T, K, vb, ve, inc, tets, springs, cfg, s);
     case 4: return solve_unroll<4>(T, K, vb, ve, inc, tets, springs, cfg, s);
     case 8: return solve_unroll<8>(T, K, vb, ve, inc, tets, springs, cfg, s);
     case 16: return solve_unroll<16>(T, K, vb, ve, inc, tets, springs, cfg, s);
@@ -1113,6 +1114,7 @@ hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepC
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
+    case 2: return solve_mc_unroll<2>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
     case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
     case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
     case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
@@ -1198,6 +1200,7 @@ hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters,
 {
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
     switch (cfg.lanes) {
+    case 2: return persistent_unroll<2>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
     case 4: return persistent_unroll<4>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
     case 8: return persistent_unroll<8>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
     case 16: return persistent_unroll<16>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
@@ -1254,6 +1257,7 @@ hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const flo
     // at least 16 lanes per vertex: a phase has few vertices on small meshes
     // and the reverse work per vertex is about three times the forward's
     switch (cfg.lanes) {
+    case 2:
     case 4:
     case 8:
     case 16: adjoint_go<16>(T, K, Sn, Sp, vb, ve, ell, cfg, s); break;

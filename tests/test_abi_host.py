@@ -198,6 +198,17 @@ def test_phase_bytes_follow_the_record_layout():
         t.launch_config = dict(compact_records=2)
 
 
+def test_launch_config_lanes_validation():
+    w = W.tet_cube(3, 0)
+    t = Topology.from_workload(w, bind=False)
+    for lanes in (2, 4, 8, 16, 32):
+        t.launch_config = dict(lanes_per_vertex=lanes)
+        assert t.launch_config["lanes_per_vertex"] == lanes
+    for lanes in (1, 3, 64):
+        with pytest.raises(N.VBDError):
+            t.launch_config = dict(lanes_per_vertex=lanes)
+
+
 def test_tet_order_groups_tets_by_vertex_colors():
     w = W.tet_cube(7, 2)
     t = Topology.from_workload(w, bind=False)

@@ -30,7 +30,7 @@ def test_small_cube_all_launch_modes(small_cube_oracle, mode):
     assert_parity(w, xg, xo, label=f"11^3 mode {mode}")
 
 
-@pytest.mark.parametrize("lanes,block,remap", [(4, 64, 0), (8, 256, 1), (16, 512, 1), (32, 128, 0)])
+@pytest.mark.parametrize("lanes,block,remap", [(2, 128, 1), (4, 64, 0), (8, 256, 1), (16, 512, 1), (32, 128, 0)])
 def test_small_cube_launch_configs(small_cube_oracle, lanes, block, remap):
     w, (xo, _) = small_cube_oracle
     say(f"small cube lanes={lanes} block={block} remap={remap}")
@@ -211,6 +211,17 @@ def test_cloth_other_colorings_free_running(coloring):
     for mode in (0, 3):
         xg, _, _ = gpu_rollout(w, w.frames, launch_mode=mode)
         assert_parity(w, xg, xo, label=f"cloth 64^2 {coloring} mode {mode}")
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_cloth_few_lanes_free_running(lanes):
+    """The spring solve with 2 and 4 lanes per vertex (DSATUR coloring), the
+    first 5 frames before any contact, in the plain and graph modes."""
+    w = W.config_cloth_coarse(64, frames=5, coloring="dsatur")
+    xo, _ = oracle_rollout(w, w.frames, threads=THREADS)
+    for mode in (0, 1):
+        xg, _, _ = gpu_rollout(w, w.frames, cfg=dict(lanes_per_vertex=lanes, block_size=128), launch_mode=mode)
+        assert_parity(w, xg, xo, label=f"cloth 64^2 {lanes} lanes mode {mode}")
 
 
 def test_full_size_cloth_properties():
