@@ -208,7 +208,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.ybar = take(sizeof(float4) * nv);
         L.xtbar = take(sizeof(float4) * nv);
         L.vbar = take(sizeof(float4) * nv);
-        L.contrib = take(sizeof(float4) * 4 * (size_t)T.nt);
+        L.contrib = take(sizeof(float3) * 4 * (size_t)T.nt);
         L.ebar = take(sizeof(float) * (size_t)T.nt);
     }
     const size_t ntri = T.surf.size() / 3, nsv = T.sv_slot.size();
@@ -276,7 +276,7 @@ void set_dev_pointers(vbd_topology_s &T)
     D.ybar = L.max_bwd_iters > 0 ? (float4 *)(b + L.ybar) : nullptr;
     D.xtbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xtbar) : nullptr;
     D.vbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.vbar) : nullptr;
-    D.contrib = L.max_bwd_iters > 0 ? (float4 *)(b + L.contrib) : nullptr;
+    D.contrib = L.max_bwd_iters > 0 ? (float3 *)(b + L.contrib) : nullptr;
     D.ebar = L.max_bwd_iters > 0 ? (float *)(b + L.ebar) : nullptr;
     D.n_verts = T.nv;
     D.n_tets = T.nt;
@@ -927,7 +927,7 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
     if (T.nt > 0) {
-        HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 16 * T.nt, s));
+        HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 12 * T.nt, s));
         HIP_TRY(launch_zero_u32((unsigned *)D.ebar, T.nt, s));
     }
     for (int it = p->n_iters; it >= 1; --it) {

@@ -7,6 +7,8 @@
 
 namespace vbd {
 
+static_assert(sizeof(float3) == 12, "float3 cells must be 12 bytes");
+
 // Incidence entry of a (vertex, tet) pair, 16 bytes:
 //   x = (stored tet << 2) | slot of the vertex in the tet,
 //   y, z, w = permuted ids of the tet's other three vertices in slot order.
@@ -81,7 +83,7 @@ struct DevTopo {
     unsigned *flags;                   // [0] barrier counter, [1] abort flag, [2] skip count
     float4 *snaps;                     // backward: (n_iters + 1) iterates
     float4 *xbar, *ybar, *xtbar, *vbar;
-    float4 *contrib;                   // backward: [n_tets][4] pending neighbour adjoints
+    float3 *contrib;                   // backward: [n_tets][4] pending neighbour adjoints (12 B)
     float *ebar;                       // backward: [n_tets] Ebar of this step, stored order
     int n_verts, n_tets, n_free, n_colors;
 };

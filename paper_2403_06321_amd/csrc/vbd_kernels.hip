@@ -696,7 +696,7 @@ __device__ __forceinline__ void adj_hess(float4 qa, float4 qb, float4 qc, float 
 // other three slots (c0, c1, c2 in slot order); returns (w . grad_i Psi)/(V E).
 __device__ __forceinline__ float adj_pair(float3 xi, float4 qa, float4 qb, float4 qc, float4 ws,
                                           float Vlam, float sg, float3 w, float mu_lam,
-                                          const StepConsts &K, float4 &c0, float4 &c1, float4 &c2)
+                                          const StepConsts &K, float3 &c0, float3 &c1, float3 &c2)
 {
     const float3 xa = xyz(qa), xb = xyz(qb), xc = xyz(qc);
     const float3 e1 = xa - xi, e2 = xb - xi, e3 = xc - xi;
@@ -762,7 +762,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             const int e = base + j * L;
             ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
-        float4 qa[KU], qb[KU], qc[KU], g[KU];
+        float4 qa[KU], qb[KU], qc[KU];
+        float3 g[KU];
         float hmu[KU], vlam[KU], sig[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
@@ -782,7 +783,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             if (ent[j].x >= 0) {
                 adj_hess(qa[j], qb[j], qc[j], hmu[j], vlam[j], sig[j], a);
                 a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
-                T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float4(0.f, 0.f, 0.f, 0.f);
+                T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float3(0.f, 0.f, 0.f);
             }
     }
     acc_reduce<L>(a);
@@ -813,7 +814,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
             const int e = base + j * L;
             ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
         }
-        float4 qa[KU], qb[KU], qc[KU], c0[KU], c1[KU], c2[KU], ws[KU];
+        float4 qa[KU], qb[KU], qc[KU], ws[KU];
+        float3 c0[KU], c1[KU], c2[KU];
         float vol[KU], eb[KU], vlam[KU], sig[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
@@ -829,7 +831,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
                 vol[j] = T.vol[t];
                 eb[j] = T.ebar[t];
                 // the cells of the other slots in ascending slot order
-                const float4 *cell = T.contrib + 4 * (size_t)t;
+                const float3 *cell = T.contrib + 4 * (size_t)t;
                 c0[j] = cell[k == 0 ? 1 : 0];
                 c1[j] = cell[k <= 1 ? 2 : 1];
                 c2[j] = cell[k <= 2 ? 3 : 2];
@@ -840,7 +842,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
                 const int t = ent[j].x >> 2, k = ent[j].x & 3;
                 const float r = adj_pair(xi, qa[j], qb[j], qc[j], ws[j], vlam[j], sig[j], w, mu_lam, K,
                                          c0[j], c1[j], c2[j]);
-                float4 *cell = T.contrib + 4 * (size_t)t;
+                float3 *cell = T.contrib + 4 * (size_t)t;
                 cell[k == 0 ? 1 : 0] = c0[j];
                 cell[k <= 1 ? 2 : 1] = c1[j];
                 cell[k <= 2 ? 3 : 2] = c2[j];
@@ -894,7 +896,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
         xb4 = T.xbar[p];
         wm = T.y[p].w;
     }
-    float4 qa[KU], qb[KU], qc[KU], g[KU], c0[KU], c1[KU], c2[KU];
+    float4 qa[KU], qb[KU], qc[KU];
+    float3 g[KU], c0[KU], c1[KU], c2[KU];
     float vol[KU], eb[KU];
 #pragma unroll
     for (int j = 0; j < KU; ++j)
@@ -903,7 +906,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
             qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
             qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
             qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
-            const float4 *cell = T.contrib + 4 * (size_t)t;
+            const float3 *cell = T.contrib + 4 * (size_t)t;
             g[j] = cell[k];
             c0[j] = cell[k == 0 ? 1 : 0];
             c1[j] = cell[k <= 1 ? 2 : 1];
@@ -919,7 +922,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
         if (ent[j].x >= 0) {
             adj_hess(qa[j], qb[j], qc[j], hmu[j], vlam[j], sig[j], a);
             a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
-            T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float4(0.f, 0.f, 0.f, 0.f);
+            T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float3(0.f, 0.f, 0.f);
         }
     acc_reduce<L>(a);
     if (!active) return;
@@ -944,7 +947,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
             const int t = ent[j].x >> 2, k = ent[j].x & 3;
             const float r = adj_pair(xi, qa[j], qb[j], qc[j], ws[j], vlam[j], sig[j], w, mu_lam, K, c0[j],
                                      c1[j], c2[j]);
-            float4 *cell = T.contrib + 4 * (size_t)t;
+            float3 *cell = T.contrib + 4 * (size_t)t;
             cell[k == 0 ? 1 : 0] = c0[j];
             cell[k <= 1 ? 2 : 1] = c1[j];
             cell[k <= 2 ? 3 : 2] = c2[j];
@@ -961,7 +964,7 @@ __global__ void k_bwd_fold(DevTopo T)
     float4 xb = T.xbar[p];
     for (int e = T.tet_row[p]; e < T.tet_row[p + 1]; ++e) {
         const int ent = T.tet_ent[e].x;
-        const float4 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
+        const float3 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
         xb.x += g.x; xb.y += g.y; xb.z += g.z;
     }
     T.xbar[p] = xb;
