@@ -216,7 +216,7 @@ def main():
     traffic = kernel_traffic()
 
     out = {
-        "metric": "VBD vertex-updates/s, 65^3-vertex stable Neo-Hookean tet cube (100 iterations/frame)",
+        "metric": "VBD vertex-updates/s + HBM GB/s, 64³ tet cube; batched & adjoint vs plain",
         "value": value,
         "unit": "vertex-updates/s",
         "n_gpus": 1,
