@@ -158,7 +158,8 @@ def test_large_cube_late_state_in_the_benchmarked_configuration():
     for _ in range(2):
         xo, vo_, vpo, _ = O.step(m, p, *states[-1], w.tet_E)
         states.append((xo, vo_, vpo))
-    resync_parity(late, states, params=p, launch_mode=1, label="65^3 after 60 frames")
+    resync_parity(late, states, params=p, launch_mode=1, cfg=t.launch_config,
+                  label=f"65^3 after 60 frames, {t.launch_config}")
 
 
 @pytest.mark.parametrize("coloring", ["lattice4", "smallest_last"])
@@ -303,14 +304,17 @@ def test_batched_small_meshes_vs_oracle_and_single():
 
 
 def test_batch_full_size_sampled_meshes():
-    """512-mesh batch at full size, persistent hipGraph launch; the oracle
-    checks 8 seeded sample meshes."""
-    w = W.config_batch(frames=2)
+    """512-mesh batch at full size (smallest-last coloring, as benchmarked),
+    autotuned hipGraph of per-color launches and persistent hipGraph; the
+    oracle checks 8 seeded sample meshes."""
+    w = W.config_batch(frames=2, coloring="smallest_last")
     say(f"batch: {w.n_verts} verts, {w.n_tets} tets")
-    xg, _, _ = gpu_rollout(w, 2, launch_mode=3, autotune=True)
     ids = sorted(np.random.default_rng(3).choice(w.n_meshes, 8, replace=False).tolist())
     sub = W.subset_meshes(w, ids)
     xo, _ = oracle_rollout(sub, 2, threads=THREADS)
     vo, _ = w.offsets()
     rows = np.concatenate([np.arange(vo[k], vo[k + 1]) for k in ids])
-    assert_parity(sub, [x[rows] for x in xg], xo, label="batch sampled meshes")
+    for mode in (1, 3):
+        xg, _, t = gpu_rollout(w, 2, launch_mode=mode, autotune=True)
+        assert_parity(sub, [x[rows] for x in xg], xo,
+                      label=f"batch sampled meshes mode {mode}, {t.launch_config}")
