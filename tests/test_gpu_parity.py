@@ -225,19 +225,22 @@ def test_cloth_few_lanes_free_running(lanes):
         assert_parity(w, xg, xo, label=f"cloth 64^2 {lanes} lanes mode {mode}")
 
 
-def test_full_size_cloth_properties():
+@pytest.mark.parametrize("coloring", ["id", "dsatur"])
+def test_full_size_cloth_properties(coloring):
     """1024^2 cloth, 1 mm springs, 8 frames in the benchmark's launch mode:
     finite, pinned corners fixed, no vertex deeper than 2 mm inside the
     sphere or below the ground."""
-    w = W.config_cloth(1024, frames=8)
-    xg, _, _ = gpu_rollout(w, w.frames, launch_mode=3, autotune=True)
-    x = xg[-1]
-    assert np.all(np.isfinite(x))
-    pin = w.pinned.astype(bool)
-    assert np.array_equal(x[pin], w.x0[pin].astype(np.float32).astype(np.float64))
-    r = np.linalg.norm(x - np.array([0.0, 0.0, 0.3]), axis=1)
-    assert r.min() >= 0.3 - 2e-3
-    assert x[:, 2].min() >= -2e-3
+    w = W.config_cloth(1024, frames=8, coloring=coloring)
+    for mode in (1, 3):
+        xg, _, t = gpu_rollout(w, w.frames, launch_mode=mode, autotune=True)
+        say(f"cloth {coloring} mode {mode}: {t.launch_config}")
+        x = xg[-1]
+        assert np.all(np.isfinite(x))
+        pin = w.pinned.astype(bool)
+        assert np.array_equal(x[pin], w.x0[pin].astype(np.float32).astype(np.float64))
+        r = np.linalg.norm(x - np.array([0.0, 0.0, 0.3]), axis=1)
+        assert r.min() >= 0.3 - 2e-3
+        assert x[:, 2].min() >= -2e-3
 
 
 def test_chebyshev_damping_friction():
