@@ -156,10 +156,12 @@ int32_t oracle_color_smallest_last(int32_t n_verts, int32_t n_tets, const int32_
     return n_colors;
 }
 
-/* DSATUR (Brelaz, Comm. ACM 22(4), 1979): repeatedly color the uncolored
- * vertex with the most distinct colors among its neighbours (ties: larger
- * degree, then smaller id) with the smallest color none of its neighbours
- * has.  Same adjacency as oracle_color_greedy. */
+/* DSATUR (Brelaz, Comm. ACM 22(4), 1979), one more greedy vertex order for
+ * the coloring of Sec. 3.9 (any coloring in which no element joins two
+ * vertices of one color serves; the paper names no algorithm): repeatedly
+ * color the uncolored vertex with the most distinct colors among its
+ * neighbours (ties: larger degree, then smaller id) with the smallest color
+ * none of its neighbours has.  Same adjacency as oracle_color_greedy. */
 int32_t oracle_color_dsatur(int32_t n_verts, int32_t n_tets, const int32_t *tets,
                             int32_t n_springs, const int32_t *springs, int32_t *colors)
 {
