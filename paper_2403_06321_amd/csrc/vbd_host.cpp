@@ -927,7 +927,7 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
     if (T.nt > 0) {
-        HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 12 * T.nt, s));
+        HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 12 * (long long)T.nt, s));
         HIP_TRY(launch_zero_u32((unsigned *)D.ebar, T.nt, s));
     }
     for (int it = p->n_iters; it >= 1; --it) {

@@ -159,7 +159,7 @@ hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters,
                              bool springs, const LaunchCfg &cfg, int n_cu, bool cooperative,
                              hipStream_t s, int *grid_out);
 hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s);
-hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s);
+hipError_t launch_zero_u32(unsigned *p, long long n, hipStream_t s);
 
 // backward
 hipError_t launch_bwd_init(const DevTopo &T, const float *gx_out, const float *gv_out,

@@ -10,6 +10,8 @@
 // and solves the 3x3 system analytically (Sec. 3.2).
 #include "vbd_device.h"
 
+#include <algorithm>
+
 namespace vbd {
 
 // Lane permutation within a row of 16 lanes.  Every pattern used here reads a
@@ -633,10 +635,10 @@ __global__ void k_copy4(float4 *dst, const float4 *src, int n)
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
-__global__ void k_zero_u32(unsigned *p, int n)
+__global__ void k_zero_u32(unsigned *p, long long n)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- adjoint --
@@ -1221,10 +1223,11 @@ hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s)
+hipError_t launch_zero_u32(unsigned *p, long long n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n);
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<long long>(blocks, 1 << 16)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
