@@ -156,7 +156,12 @@ enum {
                                one tet; extracted when n_meshes > 1), original vertex ids,
                                ordered so (b - a) x (c - a) points out of the mesh;
                                sorted by their ascending vertex-id triples */
-    VBD_Q_SURFACE_COUNTS = 15 /* int64[2]: n_surf_tris, n_surf_verts */
+    VBD_Q_SURFACE_COUNTS = 15, /* int64[2]: n_surf_tris, n_surf_verts */
+    VBD_Q_SNAPSHOT_REGION = 16 /* int64[3]: byte offset of the iterate snapshots in the bound
+                                  workspace (-1 when max_backward_iters is 0), bytes per
+                                  snapshot (n_verts float4 in slot order), snapshot count - 1
+                                  (max_backward_iters); a step of n_iters iterations uses the
+                                  first (n_iters + 1) snapshots */
 };
 vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
 vbd_status vbd_topology_destroy(vbd_topology topo);
@@ -196,6 +201,11 @@ typedef struct {
     int32_t mesh_contacts;         /* 1 = on */
     float collision_radius;        /* > 0 when mesh_contacts is on */
     int32_t n_col;                 /* >= 0 */
+    /* vbd_step_backward only: 1 = the workspace snapshot region already holds
+     * this step's iterates (left there by vbd_step_record with the same
+     * inputs, or copied back by the caller, see VBD_Q_SNAPSHOT_REGION), so the
+     * forward recompute is skipped; 0 = recompute them. */
+    int32_t backward_recorded;
 } vbd_step_params;
 
 /* One implicit-Euler time step of every mesh (Alg. 1):
@@ -234,6 +244,20 @@ vbd_status vbd_step_backward(vbd_topology topo, const vbd_step_params *params,
                              const float *tet_E, const float *gx_out, const float *gv_out,
                              const float *gvp_out, float *gx_in, float *gv_in, float *gvp_in,
                              float *g_tet_E, void *stream);
+
+/* vbd_step for the differentiable path (tets, inertia and pins only, as
+ * vbd_step_backward), in the form vbd_step_backward recomputes: the same
+ * update, with snapshot n of the workspace left holding the iterate after
+ * iteration n (0: the initial guess).  The caller may copy the snapshot
+ * region (VBD_Q_SNAPSHOT_REGION) away and back, then call vbd_step_backward
+ * with backward_recorded = 1 and the same x^t, v^t, v^{t-1}, tet_E to skip the
+ * recompute.  x, v, v_prev: device float [n_verts][3], updated in place as by
+ * vbd_step; tet_E as for vbd_step.  The workspace must have been sized with
+ * max_backward_iters >= params->n_iters.  Launch modes as for
+ * vbd_step_backward (GRAPH: captured and replayed while pointers, parameters
+ * and stream stay the same).  Errors: as vbd_step_backward. */
+vbd_status vbd_step_record(vbd_topology topo, const vbd_step_params *params, float *x, float *v,
+                           float *v_prev, const float *tet_E, void *stream);
 
 /* Runs the mesh-mesh contact detection that vbd_step does at x^t (params:
  * mesh_contacts must be 1; collision_radius and contact_thickness are used) on

@@ -16,11 +16,11 @@ COLOR_ID_ORDER, COLOR_SMALLEST_LAST, COLOR_DSATUR = 0, 1, 2
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
  Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME, Q_SURFACE,
- Q_SURFACE_COUNTS) = range(16)
+ Q_SURFACE_COUNTS, Q_SNAPSHOT_REGION) = range(17)
 
 # every symbol include/vbd.h declares
 EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_color_greedy", "vbd_color_given", "vbd_workspace_size", "vbd_bind_workspace",
-           "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_backward",
+           "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_record", "vbd_step_backward",
            "vbd_get_launch_config", "vbd_set_launch_config", "vbd_autotune",
            "vbd_profile_enable", "vbd_profile_read", "vbd_check", "vbd_probe_copy",
            "vbd_detect_contacts", "vbd_last_error"]
@@ -41,7 +41,8 @@ class StepParamsC(C.Structure):
                 ("n_planes", C.c_int32), ("planes", C.c_void_p), ("kd", C.c_float),
                 ("cheb_rho", C.c_float), ("friction_mu", C.c_float), ("friction_eps_v", C.c_float),
                 ("spring_psd", C.c_int32), ("launch_mode", C.c_int32),
-                ("mesh_contacts", C.c_int32), ("collision_radius", C.c_float), ("n_col", C.c_int32)]
+                ("mesh_contacts", C.c_int32), ("collision_radius", C.c_float), ("n_col", C.c_int32),
+                ("backward_recorded", C.c_int32)]
 
 
 class LaunchConfig(C.Structure):
@@ -83,6 +84,7 @@ def lib():
     L.vbd_topology_query.argtypes = [p, i32, p, sz]
     L.vbd_topology_destroy.argtypes = [p]
     L.vbd_step.argtypes = [p, C.POINTER(StepParamsC), p, p, p, p, p]
+    L.vbd_step_record.argtypes = [p, C.POINTER(StepParamsC), p, p, p, p, p]
     L.vbd_step_backward.argtypes = [p, C.POINTER(StepParamsC)] + [p] * 12
     L.vbd_get_launch_config.argtypes = [p, C.POINTER(LaunchConfig)]
     L.vbd_set_launch_config.argtypes = [p, C.POINTER(LaunchConfig)]

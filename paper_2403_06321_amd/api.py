@@ -28,7 +28,7 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN):
+def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN, backward_recorded: bool = False):
     """StepParams -> (vbd_step_params, keep-alive arrays)."""
     sph = None if p.spheres is None else np.ascontiguousarray(p.spheres, np.float32).reshape(-1, 4)
     pl = None if p.planes is None else np.ascontiguousarray(p.planes, np.float32).reshape(-1, 4)
@@ -39,7 +39,8 @@ def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN):
                       float(p.friction_mu), float(p.friction_eps_v),
                       int(bool(getattr(p, "spring_psd", False))), int(launch_mode),
                       int(bool(getattr(p, "mesh_contacts", False))),
-                      float(getattr(p, "collision_radius", 0.0)), int(getattr(p, "n_col", 0)))
+                      float(getattr(p, "collision_radius", 0.0)), int(getattr(p, "n_col", 0)),
+                      1 if backward_recorded else 0)
     return s, (sph, pl)
 
 
@@ -144,7 +145,7 @@ class Topology:
                 N.Q_PHASE_BYTES: (np.float64, c["n_colors"]),
                 N.Q_TET_ORDER: (np.int32, c["n_tets"]),
                 N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"]),
-                N.Q_SURFACE_COUNTS: (np.int64, 2)}
+                N.Q_SURFACE_COUNTS: (np.int64, 2), N.Q_SNAPSHOT_REGION: (np.int64, 3)}
         if what == N.Q_SURFACE:
             n_tri = int(self.query(N.Q_SURFACE_COUNTS)[0])
             out = np.zeros((n_tri, 3), np.int32)
@@ -179,14 +180,34 @@ class Topology:
         N.check(N.lib().vbd_step(self._h, C.byref(ps), _t_ptr(x), _t_ptr(v), _t_ptr(v_prev),
                                  _t_ptr(tet_E) if self.n_tets else None, _stream_handle(stream)))
 
+    def step_record(self, x, v, v_prev, tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
+                    stream=None):
+        """step() for the differentiable path, leaving the step's iterates in
+        the workspace snapshots (see snapshots())."""
+        for t, name in ((x, "x"), (v, "v"), (v_prev, "v_prev")):
+            _check_state(t, self.n_verts, name)
+        ps, keep = params_struct(params, launch_mode)
+        N.check(N.lib().vbd_step_record(self._h, C.byref(ps), _t_ptr(x), _t_ptr(v), _t_ptr(v_prev),
+                                        _t_ptr(tet_E) if self.n_tets else None, _stream_handle(stream)))
+
+    def snapshots(self, n_iters: int):
+        """The workspace bytes holding a step's n_iters + 1 iterate snapshots
+        (a uint8 view into the bound workspace tensor)."""
+        off, per, cap = (int(a) for a in self.query(N.Q_SNAPSHOT_REGION))
+        if off < 0 or n_iters > cap:
+            raise ValueError(f"the workspace holds {cap} backward iterations, need {n_iters}")
+        return self.workspace[off:off + per * (n_iters + 1)]
+
     def step_backward(self, x_t, v_t, v_prev, tet_E, gx_out, gv_out, gvp_out, gx_in, gv_in,
                       gvp_in, g_tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
-                      stream=None):
+                      stream=None, recorded: bool = False):
+        """recorded: the snapshots already hold this step's iterates (from
+        step_record, or copied back into snapshots()); the recompute is skipped."""
         for t, name in ((x_t, "x_t"), (v_t, "v_t"), (v_prev, "v_prev"), (gx_out, "gx_out"),
                         (gv_out, "gv_out"), (gvp_out, "gvp_out"), (gx_in, "gx_in"),
                         (gv_in, "gv_in"), (gvp_in, "gvp_in")):
             _check_state(t, self.n_verts, name)
-        ps, keep = params_struct(params, launch_mode)
+        ps, keep = params_struct(params, launch_mode, backward_recorded=recorded)
         N.check(N.lib().vbd_step_backward(self._h, C.byref(ps), _t_ptr(x_t), _t_ptr(v_t),
                                           _t_ptr(v_prev), _t_ptr(tet_E), _t_ptr(gx_out),
                                           _t_ptr(gv_out), _t_ptr(gvp_out), _t_ptr(gx_in),
@@ -244,43 +265,59 @@ def probe_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
 
 
 class Rollout(torch.autograd.Function):
-    """Unrolled VBD frames with per-frame checkpoints; backward recomputes
-    each frame's iterates and runs the hand-written adjoint kernels.
+    """Unrolled VBD frames with per-frame checkpoints and the hand-written
+    adjoint kernels in the backward.
 
-    apply(x0, v0, tet_E, topo, params, frames) -> (x_T, v_T); the state
-    before frame 0 has v^{-1} = v^0.  Both directions work on fixed buffers
-    so that one captured hipGraph per direction is replayed for every frame.
+    apply(x0, v0, tet_E, topo, params, frames, record_bytes=2**33) -> (x_T, v_T);
+    the state before frame 0 has v^{-1} = v^0.  When the iterates of all
+    frames fit in record_bytes of device memory, the forward keeps each
+    frame's iterate snapshots and the backward skips its recompute; else the
+    backward recomputes them frame by frame.  Both directions work on fixed
+    buffers so that one captured hipGraph per direction is replayed for every
+    frame.
     """
 
     @staticmethod
-    def forward(ctx, x0, v0, tet_E, topo: Topology, params: StepParams, frames: int):
+    def forward(ctx, x0, v0, tet_E, topo: Topology, params: StepParams, frames: int,
+                record_bytes: int = 1 << 33):
         x = x0.detach().clone().contiguous()
         v = v0.detach().clone().contiguous()
         vp = v.clone()
         E = tet_E.detach().contiguous()
-        states = []
-        for _ in range(frames):
+        states, records = [], None
+        snaps = topo.snapshots(params.n_iters) if topo.max_backward_iters >= params.n_iters else None
+        if snaps is not None and frames * snaps.numel() <= record_bytes:
+            records = torch.empty((frames, snaps.numel()), dtype=torch.uint8, device=x.device)
+        for f in range(frames):
             states.append((x.clone(), v.clone(), vp.clone()))
-            topo.step(x, v, vp, E, params, N.LAUNCH_GRAPH)
-        ctx.topo, ctx.params, ctx.states = topo, params, states
+            if records is None:
+                topo.step(x, v, vp, E, params, N.LAUNCH_GRAPH)
+            else:
+                topo.step_record(x, v, vp, E, params, N.LAUNCH_GRAPH)
+                records[f].copy_(snaps)
+        ctx.topo, ctx.params, ctx.states, ctx.records = topo, params, states, records
         ctx.save_for_backward(E)
         return x, v
 
     @staticmethod
     def backward(ctx, gx, gv):
         (E,) = ctx.saved_tensors
-        topo, params = ctx.topo, ctx.params
+        topo, params, records = ctx.topo, ctx.params, ctx.records
         ref = ctx.states[0][0]
         g_out = [torch.zeros_like(ref) if g is None else g.contiguous().float().clone()
                  for g in (gx, gv)] + [torch.zeros_like(ref)]
         g_in = [torch.empty_like(ref) for _ in range(3)]
         stage = [torch.empty_like(ref) for _ in range(3)]
         gE = torch.zeros_like(E)
-        for state in reversed(ctx.states):
-            for dst, src in zip(stage, state):
+        snaps = topo.snapshots(params.n_iters) if records is not None else None
+        for f in reversed(range(len(ctx.states))):
+            for dst, src in zip(stage, ctx.states[f]):
                 dst.copy_(src)
-            topo.step_backward(*stage, E, *g_out, *g_in, gE, params, N.LAUNCH_GRAPH)
+            if records is not None:
+                snaps.copy_(records[f])
+            topo.step_backward(*stage, E, *g_out, *g_in, gE, params, N.LAUNCH_GRAPH,
+                               recorded=records is not None)
             for dst, src in zip(g_out, g_in):
                 dst.copy_(src)
         gx0, gv0, gvp0 = g_out
-        return gx0, gv0 + gvp0, gE, None, None, None
+        return gx0, gv0 + gvp0, gE, None, None, None, None

@@ -140,7 +140,7 @@ struct vbd_topology_s {
     LaunchCfg cfg{8, 128, 1, 0, 2, 0};
     // graph caches of vbd_step and vbd_step_backward
     hipStream_t cap_stream = nullptr;   // library-owned stream used only for capture
-    GraphCache fwd_graph, bwd_graph;
+    GraphCache fwd_graph, bwd_graph, rec_graph;
     // profiling
     bool profiling = false;
     std::vector<ProfileEvent> events;
@@ -149,6 +149,7 @@ struct vbd_topology_s {
     {
         fwd_graph.reset();
         bwd_graph.reset();
+        rec_graph.reset();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (auto &e : events) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     }
@@ -873,6 +874,7 @@ GraphKey make_key(const vbd_step_params *p, std::vector<const void *> ptrs, void
     push(&p->spring_psd, 4);
     push(&p->launch_mode, 4);
     push(&p->mesh_contacts, 4); push(&p->collision_radius, 4); push(&p->n_col, 4);
+    push(&p->backward_recorded, 4);
     return k;
 }
 
@@ -906,13 +908,13 @@ vbd_status run_graph(vbd_topology_s &T, GraphCache &C, GraphKey key, hipStream_t
 // Backward of one step: forward recompute with an iterate snapshot per
 // iteration, then the reverse color sweeps, the fold of the pending cells and
 // the adjoints of the initial guess and of y.
-vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
-                            const float *x_t, const float *v_t, const float *v_prev, const float *E,
-                            const float *gx_out, const float *gv_out, const float *gvp_out,
-                            float *gx_in, float *gv_in, float *gvp_in, float *g_E, hipStream_t s)
+// The step's iterates into the workspace snapshots: snapshot n = the iterate
+// after iteration n (snapshot 0 = the initial guess).
+vbd_status enqueue_record(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
+                          const float *x_t, const float *v_t, const float *v_prev, const float *E,
+                          hipStream_t s)
 {
     const size_t nv = (size_t)T.nv;
-    // forward recompute, snapshot n = iterate after iteration n
     DevTopo D = T.dev;
     D.x = D.snaps;
     HIP_TRY(launch_material(D, E, K, T.cfg.compact != 0, s));
@@ -924,6 +926,27 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
         for (int c = 0; c < T.n_colors; ++c)
             HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), true, false, T.cfg, s));
     }
+    return VBD_OK;
+}
+
+vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
+                            const float *x_t, const float *v_t, const float *v_prev, const float *E,
+                            const float *gx_out, const float *gv_out, const float *gvp_out,
+                            float *gx_in, float *gv_in, float *gvp_in, float *g_E, hipStream_t s)
+{
+    const size_t nv = (size_t)T.nv;
+    DevTopo D = T.dev;
+    if (p->backward_recorded) {
+        // the snapshots hold this step's iterates already: only the material
+        // records and the inertia target (into the library's own x, so that
+        // snapshot 0 stays as recorded) are rebuilt
+        HIP_TRY(launch_material(D, E, K, T.cfg.compact != 0, s));
+        HIP_TRY(launch_predict(D, x_t, v_t, v_prev, K, false, s));
+    } else {
+        vbd_status st = enqueue_record(T, p, K, x_t, v_t, v_prev, E, s);
+        if (st) return st;
+    }
+    D.x = T.dev.snaps;
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
     if (T.nt > 0) {
@@ -1289,6 +1312,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     T->bound = true;
     T->fwd_graph.reset();
     T->bwd_graph.reset();
+    T->rec_graph.reset();
     return VBD_OK;
 }
 
@@ -1322,6 +1346,13 @@ vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t by
     case VBD_Q_SURFACE: return give(T->surf.data(), 4 * T->surf.size());
     case VBD_Q_SURFACE_COUNTS: {
         int64_t c[2] = {(int64_t)(T->surf.size() / 3), (int64_t)T->sv_slot.size()};
+        return give(c, sizeof(c));
+    }
+    case VBD_Q_SNAPSHOT_REGION: {
+        if (!T->bound) return fail(VBD_E_NO_WORKSPACE, "no workspace bound");
+        int64_t c[3] = {(int64_t)T->lay.snaps, (int64_t)(sizeof(float4) * (size_t)T->nv),
+                        (int64_t)T->lay.max_bwd_iters};
+        if (T->lay.max_bwd_iters <= 0) c[0] = -1;
         return give(c, sizeof(c));
     }
     case VBD_Q_REST_FRAME: {
@@ -1368,10 +1399,9 @@ vbd_status vbd_step(vbd_topology T, const vbd_step_params *p, float *x, float *v
     });
 }
 
-vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const float *x_t,
-                             const float *v_t, const float *v_prev, const float *E,
-                             const float *gx_out, const float *gv_out, const float *gvp_out,
-                             float *gx_in, float *gv_in, float *gvp_in, float *g_E, void *stream)
+namespace {
+// What the differentiable step supports, and the workspace it needs.
+vbd_status check_differentiable(vbd_topology T, const vbd_step_params *p)
 {
     vbd_status st = check_ready(T);
     if (st) return st;
@@ -1382,6 +1412,39 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
     if (p->n_iters > T->lay.max_bwd_iters)
         return fail(VBD_E_NO_WORKSPACE, "workspace holds %d backward iterations, need %d",
                     T->lay.max_bwd_iters, p->n_iters);
+    return VBD_OK;
+}
+}  // namespace
+
+vbd_status vbd_step_record(vbd_topology T, const vbd_step_params *p, float *x, float *v, float *vp,
+                           const float *E, void *stream)
+{
+    vbd_status st = check_differentiable(T, p);
+    if (st) return st;
+    if (T->nv == 0) return VBD_OK;
+    if (!x || !v || !vp || (T->nt > 0 && !E)) return fail(VBD_E_INVALID_ARG, "NULL array");
+    const StepConsts K = make_consts(*T, p);
+    hipStream_t s = (hipStream_t)stream;
+    auto enqueue = [&](hipStream_t q) -> vbd_status {
+        vbd_status r = enqueue_record(*T, p, K, x, v, vp, E, q);
+        if (r) return r;
+        DevTopo D = T->dev;
+        D.x = T->dev.snaps + (size_t)T->nv * p->n_iters;
+        HIP_TRY(launch_finalize(D, x, v, vp, K, q));
+        return VBD_OK;
+    };
+    if (p->launch_mode == VBD_LAUNCH_PLAIN || p->launch_mode == VBD_LAUNCH_PERSISTENT || T->profiling)
+        return enqueue(s);
+    return run_graph(*T, T->rec_graph, make_key(p, {x, v, vp, E}, stream), s, enqueue);
+}
+
+vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const float *x_t,
+                             const float *v_t, const float *v_prev, const float *E,
+                             const float *gx_out, const float *gv_out, const float *gvp_out,
+                             float *gx_in, float *gv_in, float *gvp_in, float *g_E, void *stream)
+{
+    vbd_status st = check_differentiable(T, p);
+    if (st) return st;
     if (T->nv == 0) return VBD_OK;
     if (!x_t || !v_t || !v_prev || !gx_out || !gv_out || !gvp_out || !gx_in || !gv_in || !gvp_in ||
         (T->nt > 0 && (!E || !g_E)))
@@ -1446,6 +1509,7 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
     update_phase_bytes(*T);
     T->fwd_graph.reset();
     T->bwd_graph.reset();
+    T->rec_graph.reset();
     return VBD_OK;
 }
 
@@ -1528,6 +1592,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
     update_phase_bytes(*T);
     T->fwd_graph.reset();
     T->bwd_graph.reset();
+    T->rec_graph.reset();
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = best_cfg;
     return VBD_OK;

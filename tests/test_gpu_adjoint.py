@@ -2,6 +2,7 @@
 oracle's reverse mode and against central finite differences of the FP32
 forward.  Gradients of the centroid loss w.r.t. per-tet Young's modulus and
 the initial velocity field: relative L2 error <= 1e-3 and cosine >= 0.9999."""
+import dataclasses
 import os
 
 import numpy as np
@@ -16,7 +17,7 @@ THREADS = min(16, os.cpu_count() or 1)
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_cube33.npz")
 
 
-def gpu_grad(w, frames=None, cfg=None):
+def gpu_grad(w, frames=None, cfg=None, record_bytes=1 << 33):
     import torch
     from paper_2403_06321_amd.api import Rollout, Topology
     frames = frames or w.frames
@@ -29,7 +30,7 @@ def gpu_grad(w, frames=None, cfg=None):
     E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).requires_grad_(True)
     x0.requires_grad_(True)
     target = torch.tensor(w.target, dtype=torch.float64, device=dev)
-    xT, _ = Rollout.apply(x0, v0, E, topo, w.params, frames)
+    xT, _ = Rollout.apply(x0, v0, E, topo, w.params, frames, record_bytes)
     loss = ((xT.double().mean(0) - target) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
@@ -241,3 +242,64 @@ def test_backward_graph_replays_match_plain_launches_bitwise():
         for u, v in zip(a, b):
             assert np.array_equal(u, v)
     assert np.array_equal(out[N.LAUNCH_PLAIN][1], out[N.LAUNCH_GRAPH][1])
+
+
+def test_recorded_backward_equals_recompute_bitwise():
+    """Rollout keeping every frame's iterate snapshots (the backward skips its
+    recompute) against the recomputing backward: the same kernels in the same
+    order, so loss and gradients agree to the bit."""
+    w = W.config_differentiable(n=9, frames=6)
+    a = gpu_grad(w)                     # recorded
+    xa = gpu_grad.last_x
+    b = gpu_grad(w, record_bytes=0)     # recompute
+    assert a[0] == b[0]
+    assert np.array_equal(xa, gpu_grad.last_x)
+    for ga, gb in zip(a[1:], b[1:]):
+        assert np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_step_record_equals_step_and_fills_the_snapshots(mode):
+    import torch
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    w = W.config_differentiable(n=7, frames=3)
+    p = w.params
+    out = []
+    for record in (False, True):
+        t = Topology.from_workload(w, max_backward_iters=p.n_iters)
+        x = torch.tensor(w.x0, dtype=torch.float32, device="cuda").contiguous()
+        v = torch.tensor(w.v0, dtype=torch.float32, device="cuda").contiguous()
+        vp = v.clone()
+        E = torch.tensor(w.tet_E, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            (t.step_record if record else t.step)(x, v, vp, E, p, mode)
+        torch.cuda.synchronize()
+        out.append((x.cpu().numpy(), v.cpu().numpy(), vp.cpu().numpy()))
+        if record:
+            off, per, cap = (int(a) for a in t.query(N.Q_SNAPSHOT_REGION))
+            assert off >= 0 and per == 16 * w.n_verts and cap >= p.n_iters
+            snaps = t.snapshots(p.n_iters).view(torch.float32).reshape(p.n_iters + 1, w.n_verts, 4)
+            # the last snapshot is the final iterate, in slot order
+            perm = t.query(N.Q_PERM)
+            assert np.array_equal(snaps[-1, :, :3].cpu().numpy(), out[-1][0][perm])
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_step_record_rejects_what_the_backward_does_not_support():
+    import torch
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    w = W.config_differentiable(n=4, frames=1)
+    t = Topology.from_workload(w, max_backward_iters=w.params.n_iters)
+    x = torch.tensor(w.x0, dtype=torch.float32, device="cuda").contiguous()
+    v = torch.zeros_like(x)
+    E = torch.tensor(w.tet_E, dtype=torch.float32, device="cuda")
+    with pytest.raises(N.VBDError) as e:
+        t.step_record(x, v, v.clone(), E, dataclasses.replace(w.params, kd=1e-5))
+    assert e.value.status == -6   # VBD_E_UNSUPPORTED
+    t0 = Topology.from_workload(w)   # no backward workspace
+    with pytest.raises(N.VBDError) as e:
+        t0.step_record(x, v, v.clone(), E, w.params)
+    assert e.value.status == -4   # VBD_E_NO_WORKSPACE
