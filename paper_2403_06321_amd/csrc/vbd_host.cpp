@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <set>
@@ -394,22 +395,39 @@ std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, i
         for (int v = 0; v < nv; ++v) ord[v] = v;
         return ord;
     }
+    // one min-heap of ids per remaining degree, entries invalidated lazily: a
+    // vertex enters each bucket at most once (degrees only decrease), so the
+    // first live entry of the lowest non-empty bucket is the vertex of
+    // smallest remaining degree and, among those, of smallest id
     std::vector<int32_t> deg(nv);
-    std::set<std::pair<int32_t, int32_t>> q;   // (remaining degree, id)
+    int maxd = 0;
     for (int v = 0; v < nv; ++v) {
         deg[v] = (int32_t)nbr[v].size();
-        q.insert({deg[v], v});
+        maxd = std::max(maxd, (int)deg[v]);
     }
+    std::vector<std::vector<int32_t>> bucket((size_t)maxd + 1);
+    for (int v = 0; v < nv; ++v) bucket[deg[v]].push_back(v);   // ascending: already heaps
+    const std::greater<int32_t> later;
     std::vector<char> gone(nv, 0);
+    int lo = 0;
     for (int i = nv - 1; i >= 0; --i) {
-        const int v = q.begin()->second;
-        q.erase(q.begin());
+        int v = -1;
+        while (v < 0) {
+            while (bucket[lo].empty()) ++lo;
+            std::vector<int32_t> &b = bucket[lo];
+            const int32_t u = b.front();
+            std::pop_heap(b.begin(), b.end(), later);
+            b.pop_back();
+            if (!gone[u] && deg[u] == lo) v = u;
+        }
         gone[v] = 1;
         ord[i] = v;
         for (int32_t w : nbr[v])
             if (!gone[w]) {
-                q.erase({deg[w], w});
-                q.insert({--deg[w], w});
+                const int d = --deg[w];
+                bucket[d].push_back(w);
+                std::push_heap(bucket[d].begin(), bucket[d].end(), later);
+                if (d < lo) lo = d;
             }
     }
     return ord;
