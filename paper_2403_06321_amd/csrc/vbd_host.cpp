@@ -381,15 +381,71 @@ StepConsts make_consts(const vbd_topology_s &T, const vbd_step_params *p)
 }
 
 // --------------------------------------------------------------- coloring --
-// First-fit greedy over the union adjacency of tets and springs, vertices in
-// ascending id; neighbour colors are tracked in a growable bitset.
+// Vertex adjacency of the tets and springs as CSR, each neighbour once.
+// Rows are not sorted: none of the colorings below depends on the order in
+// which a vertex's neighbours are visited.
+struct Adjacency {
+    std::vector<int64_t> row;
+    std::vector<int32_t> col;
+    int n() const { return (int)row.size() - 1; }
+    int32_t degree(int v) const { return (int32_t)(row[v + 1] - row[v]); }
+    const int32_t *begin(int v) const { return col.data() + row[v]; }
+    const int32_t *end(int v) const { return col.data() + row[v + 1]; }
+};
+
+// lower_only: keep only neighbours of smaller id.
+Adjacency build_adjacency(const vbd_topology_s &T, bool lower_only)
+{
+    const int nv = T.nv;
+    // vertex -> incident tets and springs, by counting
+    std::vector<int64_t> trow((size_t)nv + 1, 0), srow((size_t)nv + 1, 0);
+    for (size_t i = 0; i < 4 * (size_t)T.nt; ++i) ++trow[(size_t)T.tets[i] + 1];
+    for (size_t i = 0; i < 2 * (size_t)T.ns; ++i) ++srow[(size_t)T.springs[i] + 1];
+    for (int v = 0; v < nv; ++v) {
+        trow[v + 1] += trow[v];
+        srow[v + 1] += srow[v];
+    }
+    std::vector<int32_t> tinc((size_t)trow[nv]), sinc((size_t)srow[nv]);
+    {
+        std::vector<int64_t> cur(trow.begin(), trow.end() - 1);
+        for (int t = 0; t < T.nt; ++t)
+            for (int a = 0; a < 4; ++a) tinc[(size_t)cur[T.tets[4 * (size_t)t + a]]++] = t;
+        cur.assign(srow.begin(), srow.end() - 1);
+        for (int s = 0; s < T.ns; ++s)
+            for (int a = 0; a < 2; ++a) sinc[(size_t)cur[T.springs[2 * (size_t)s + a]]++] = s;
+    }
+    Adjacency A;
+    A.row.assign((size_t)nv + 1, 0);
+    A.col.reserve((size_t)trow[nv] * 3 / 2 + (size_t)srow[nv]);
+    std::vector<int32_t> stamp(nv, -1);   // last vertex that listed this neighbour
+    for (int v = 0; v < nv; ++v) {
+        stamp[v] = v;
+        auto take = [&](int32_t u) {
+            if (stamp[u] == v || (lower_only && u > v)) return;
+            stamp[u] = v;
+            A.col.push_back(u);
+        };
+        for (int64_t i = trow[v]; i < trow[v + 1]; ++i) {
+            const int32_t *q = &T.tets[4 * (size_t)tinc[(size_t)i]];
+            for (int a = 0; a < 4; ++a) take(q[a]);
+        }
+        for (int64_t i = srow[v]; i < srow[v + 1]; ++i) {
+            const int32_t *e = &T.springs[2 * (size_t)sinc[(size_t)i]];
+            take(e[0]);
+            take(e[1]);
+        }
+        A.row[(size_t)v + 1] = (int64_t)A.col.size();
+    }
+    return A;
+}
+
 // Vertex order of the greedy coloring.  VBD_COLOR_ID_ORDER: ascending id.
 // VBD_COLOR_SMALLEST_LAST: the reverse of the order in which repeatedly
 // removing a vertex of smallest remaining degree (ties: smallest id) empties
 // the graph (Matula and Beck, J. ACM 30(3), 1983).
-std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, int order)
+std::vector<int32_t> color_order(const Adjacency &nbr, int order)
 {
-    const int nv = (int)nbr.size();
+    const int nv = nbr.n();
     std::vector<int32_t> ord(nv);
     if (order == VBD_COLOR_ID_ORDER) {
         for (int v = 0; v < nv; ++v) ord[v] = v;
@@ -402,7 +458,7 @@ std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, i
     std::vector<int32_t> deg(nv);
     int maxd = 0;
     for (int v = 0; v < nv; ++v) {
-        deg[v] = (int32_t)nbr[v].size();
+        deg[v] = nbr.degree(v);
         maxd = std::max(maxd, (int)deg[v]);
     }
     std::vector<std::vector<int32_t>> bucket((size_t)maxd + 1);
@@ -422,10 +478,10 @@ std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, i
         }
         gone[v] = 1;
         ord[i] = v;
-        for (int32_t w : nbr[v])
-            if (!gone[w]) {
-                const int d = --deg[w];
-                bucket[d].push_back(w);
+        for (const int32_t *w = nbr.begin(v); w != nbr.end(v); ++w)
+            if (!gone[*w]) {
+                const int d = --deg[*w];
+                bucket[d].push_back(*w);
                 std::push_heap(bucket[d].begin(), bucket[d].end(), later);
                 if (d < lo) lo = d;
             }
@@ -436,16 +492,16 @@ std::vector<int32_t> color_order(const std::vector<std::vector<int32_t>> &nbr, i
 // DSATUR (Brelaz, Comm. ACM 22(4), 1979): the next vertex is the uncolored
 // one with the most distinct colors among its neighbours (ties: larger
 // degree, then smaller id); it takes the smallest color none of them has.
-void dsatur_color(const std::vector<std::vector<int32_t>> &nbr, std::vector<int32_t> &colors, int &nc)
+void dsatur_color(const Adjacency &nbr, std::vector<int32_t> &colors, int &nc)
 {
-    const int nv = (int)nbr.size();
+    const int nv = nbr.n();
     colors.assign(nv, -1);
     nc = 0;
     std::vector<std::vector<char>> seen(nv);   // neighbour colors seen so far
     std::vector<int32_t> sat(nv, 0);
     // ordered by (saturation desc, degree desc, id asc)
     std::set<std::tuple<int32_t, int32_t, int32_t>> q;
-    for (int v = 0; v < nv; ++v) q.insert({0, -(int32_t)nbr[v].size(), v});
+    for (int v = 0; v < nv; ++v) q.insert({0, -nbr.degree(v), v});
     while (!q.empty()) {
         const int v = std::get<2>(*q.begin());
         q.erase(q.begin());
@@ -453,42 +509,29 @@ void dsatur_color(const std::vector<std::vector<int32_t>> &nbr, std::vector<int3
         while (c < (int)seen[v].size() && seen[v][c]) ++c;
         colors[v] = c;
         nc = std::max(nc, c + 1);
-        for (int32_t w : nbr[v]) {
+        for (const int32_t *pw = nbr.begin(v); pw != nbr.end(v); ++pw) {
+            const int32_t w = *pw;
             if (colors[w] >= 0) continue;
             if ((int)seen[w].size() <= c) seen[w].resize((size_t)c + 1, 0);
             if (!seen[w][c]) {
                 seen[w][c] = 1;
-                q.erase({-sat[w], -(int32_t)nbr[w].size(), w});
+                q.erase({-sat[w], -nbr.degree(w), w});
                 ++sat[w];
-                q.insert({-sat[w], -(int32_t)nbr[w].size(), w});
+                q.insert({-sat[w], -nbr.degree(w), w});
             }
         }
     }
 }
 
+// First-fit greedy over the union adjacency of tets and springs in the given
+// vertex order (DSATUR chooses its order as it colors); neighbour colors are
+// tracked in a growable bitset.
 void greedy_color(vbd_topology_s &T, int order)
 {
     const int nv = T.nv;
     // neighbour lists: in id order only the lower-id neighbours are colored
-    // before a vertex; the smallest-last order needs them all, without repeats
-    const bool all = order != VBD_COLOR_ID_ORDER;
-    std::vector<std::vector<int32_t>> nbr(nv);
-    for (int t = 0; t < T.nt; ++t) {
-        const int32_t *q = &T.tets[4 * (size_t)t];
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b)
-                if (a != b && (all || q[b] < q[a])) nbr[q[a]].push_back(q[b]);
-    }
-    for (int s = 0; s < T.ns; ++s) {
-        const int a = T.springs[2 * (size_t)s], b = T.springs[2 * (size_t)s + 1];
-        if (all || b < a) nbr[a].push_back(b);
-        if (all || a < b) nbr[b].push_back(a);
-    }
-    if (all)
-        for (auto &l : nbr) {
-            std::sort(l.begin(), l.end());
-            l.erase(std::unique(l.begin(), l.end()), l.end());
-        }
+    // before a vertex; the other orders need them all
+    const Adjacency nbr = build_adjacency(T, order == VBD_COLOR_ID_ORDER);
     if (order == VBD_COLOR_DSATUR) {
         int nc = 0;
         dsatur_color(nbr, T.colors, nc);
@@ -501,8 +544,8 @@ void greedy_color(vbd_topology_s &T, int order)
     std::vector<uint64_t> used;
     for (int v : ord) {
         used.assign((size_t)(nc / 64 + 1), 0ull);
-        for (int32_t u : nbr[v]) {
-            const int c = T.colors[u];
+        for (const int32_t *u = nbr.begin(v); u != nbr.end(v); ++u) {
+            const int c = T.colors[*u];
             if (c < 0) continue;
             used[(size_t)c >> 6] |= 1ull << (c & 63);
         }
