@@ -83,8 +83,9 @@ typedef struct {
 /* Validates the description and precomputes, in FP64, each tet's inverse
  * rest edge matrix and rest volume (F = D_s D_m^{-1}, V = |det D_m|/6) and
  * the lumped vertex masses.  Host only, synchronous.  Errors:
- * VBD_E_INVALID_ARG, VBD_E_TOPOLOGY (|det D_m| <= 1e-12 * (max edge)^3 counts
- * as degenerate).  *out receives a library-owned handle. */
+ * VBD_E_INVALID_ARG (also for more than 2^28 vertices or 2^29 tets),
+ * VBD_E_TOPOLOGY (|det D_m| <= 1e-12 * (max edge)^3 counts as degenerate).
+ * *out receives a library-owned handle. */
 vbd_status vbd_build_topology(const vbd_mesh_desc *desc, vbd_topology *out);
 
 /* Greedy vertex coloring (Sec. 3.9): no force element (tet, spring) may use

@@ -14,6 +14,13 @@ __device__ __forceinline__ float3 cross3(float3 a, float3 b)
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.x, a.y, a.z); }
+// X[q] for a slot q >= 0, addressed by a 32-bit byte offset from the array
+// base (a topology holds at most 2^28 vertices), so that the load takes its
+// base from scalar registers and the address costs one shift.
+__device__ __forceinline__ float4 ld_slot(const float4 *X, int q)
+{
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(X) + ((unsigned)q << 4));
+}
 __device__ __forceinline__ float3 ld3(const float *p, int i)
 {
     return make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);

@@ -1053,6 +1053,7 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *d, vbd_topology *out)
     if (d->n_tets > 0 && !d->tets) return fail(VBD_E_INVALID_ARG, "tets is NULL");
     if (d->n_springs > 0 && !d->springs) return fail(VBD_E_INVALID_ARG, "springs is NULL");
     if (d->n_tets > (1 << 29)) return fail(VBD_E_INVALID_ARG, "too many tets (max 2^29)");
+    if (d->n_verts > (1 << 28)) return fail(VBD_E_INVALID_ARG, "too many vertices (max 2^28)");
     if (!(d->poisson_nu >= 0.0 && d->poisson_nu < 0.5) && d->n_tets > 0)
         return fail(VBD_E_INVALID_ARG, "poisson_nu must be in [0, 0.5)");
     if (d->n_meshes > 1 && (!d->vert_offsets || !d->tet_offsets))
@@ -1331,6 +1332,9 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
                     pb[i] = pws[i].w;
                     ptet[i] = T->tet_rank[t];
                 }
+                // padding: the vertex itself as all three neighbours, V lam = 0
+                for (size_t i = base + (size_t)(T->tet_row[sl + 1] - T->tet_row[sl]); i < base + (size_t)info.y; ++i)
+                    pa[i] = make_int4(sl, sl, sl, 0);
             }
         }
         HIP_TRY(up(T->lay.pa, pa.data(), sizeof(int4) * pa.size()));

@@ -59,7 +59,9 @@ struct DevTopo {
     //                       bits of V lam}, pw = {V mu w, last}, pb = sigma, in
     //                       two layouts: compact (32 B: last = sigma, pb not
     //                       read, V mu |m|^2 summed from w) or full (36 B:
-    //                       last = V mu |m|^2); padding pa.x = -1;
+    //                       last = V mu |m|^2); padding entries name the
+    //                       vertex itself as all three others, with V lam = 0
+    //                       and pw = 0 (written by the material kernel);
     //   pws                 {w, sigma}, the E-free record (material input).
     const PairEnt *ell;
     int4 *pa;

@@ -77,10 +77,10 @@ __device__ __forceinline__ void pair_accumulate(float Vlam, float4 W, float sigm
     const float3 n = cross3(xb - xa, xc - xa) * sigma;
     const float J = dot3(e1, n);
     const float s = Vlam * (J - K.alpha);
-    const float3 Fm = e1 * W.x + e2 * W.y + e3 * W.z;
-    a.fx += s * n.x - Fm.x;
-    a.fy += s * n.y - Fm.y;
-    a.fz += s * n.z - Fm.z;
+    // f += s n - F m, F m = W.x e1 + W.y e2 + W.z e3, as four FMAs per component
+    a.fx = fmaf(-W.z, e3.x, fmaf(-W.y, e2.x, fmaf(-W.x, e1.x, fmaf(s, n.x, a.fx))));
+    a.fy = fmaf(-W.z, e3.y, fmaf(-W.y, e2.y, fmaf(-W.x, e1.y, fmaf(s, n.y, a.fy))));
+    a.fz = fmaf(-W.z, e3.z, fmaf(-W.y, e2.z, fmaf(-W.x, e1.z, fmaf(s, n.z, a.fz))));
     const float3 ln = n * Vlam;
     a.hxx += hmu + ln.x * n.x;
     a.hxy += ln.x * n.y;
@@ -90,14 +90,17 @@ __device__ __forceinline__ void pair_accumulate(float Vlam, float4 W, float sigm
     a.hzz += hmu + ln.z * n.z;
 }
 
-// Tet terms of one vertex from its D consecutive pair records starting at
-// index e0: the lanes of the group take records lane, lane + L, ...; each lane
-// issues the loads of KU records together (their addresses follow from the
-// slot alone, so they go out with the vertex's own state), then the KU x 3
-// neighbour positions together.  CR: compact (32-B) records.
+// Tet terms of one vertex (permuted slot p) from its D consecutive pair
+// records starting at index e0: the lanes of the group take records lane,
+// lane + L, ...; each lane issues the loads of KU records together (their
+// addresses follow from the slot alone, so they go out with the vertex's own
+// state), then the KU x 3 neighbour positions together.  Padding records
+// (and slots past D) name p itself as all three neighbours with V lam = 0 and
+// V mu w = 0, so they add exactly zero and the accumulation needs no
+// per-lane branch.  CR: compact (32-B) records.
 template <int L, int KU, bool CR>
-__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own, size_t e0,
-                                          int D, int lane, const StepConsts &K, Acc &a)
+__device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, float4 own, int p,
+                                          size_t e0, int D, int lane, const StepConsts &K, Acc &a)
 {
     for (int base = lane; base < D; base += L * KU) {
         int4 pa[KU];
@@ -109,22 +112,29 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
             if (e < D) {
                 pa[j] = T.pa[e0 + e];
                 pw[j] = T.pw[e0 + e];
-                if (!CR) pb[j] = T.pb[e0 + e];
+                pb[j] = CR ? 0.f : T.pb[e0 + e];
             } else {
-                pa[j] = make_int4(-1, 0, 0, 0);
+                pa[j] = make_int4(p, p, p, 0);
+                pw[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                pb[j] = 0.f;
             }
         }
+        // a slot that is padding in every lane of the wave is skipped (the
+        // branch is uniform); a real record never names its own vertex
+        bool live[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j) live[j] = __builtin_amdgcn_ballot_w64(pa[j].x != p) != 0;
         float4 qa[KU], qb[KU], qc[KU];
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (pa[j].x >= 0) {
-                qa[j] = X[pa[j].x];
-                qb[j] = X[pa[j].y];
-                qc[j] = X[pa[j].z];
+            if (live[j]) {
+                qa[j] = ld_slot(X, pa[j].x);
+                qb[j] = ld_slot(X, pa[j].y);
+                qc[j] = ld_slot(X, pa[j].z);
             }
 #pragma unroll
         for (int j = 0; j < KU; ++j)
-            if (pa[j].x >= 0) {
+            if (live[j]) {
                 const float sigma = CR ? pw[j].w : pb[j];
                 const float hmu = CR ? -(pw[j].x + pw[j].y + pw[j].z) : pw[j].w;
                 pair_accumulate(__int_as_float(pa[j].w), pw[j], sigma, hmu, own, qa[j], qb[j], qc[j], K, a);
@@ -138,7 +148,7 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
 __device__ __forceinline__ void spring_contrib(const float4 *X, float3 xi, int2 se, float k, int psd,
                                                Acc &a)
 {
-    const float3 xj = xyz(X[se.x]);
+    const float3 xj = xyz(ld_slot(X, se.x));
     const float L = __int_as_float(se.y);
     const float3 d = xi - xj;
     const float l2 = dot3(d, d);
@@ -184,6 +194,11 @@ __device__ __forceinline__ void acc_reduce(Acc &a)
     a.fx = group_sum<L>(a.fx); a.fy = group_sum<L>(a.fy); a.fz = group_sum<L>(a.fz);
     a.hxx = group_sum<L>(a.hxx); a.hxy = group_sum<L>(a.hxy); a.hxz = group_sum<L>(a.hxz);
     a.hyy = group_sum<L>(a.hyy); a.hyz = group_sum<L>(a.hyz); a.hzz = group_sum<L>(a.hzz);
+    // The sums are consumed only by the group's active vertices; without this
+    // use here the compiler moves the last add of each sum below that branch,
+    // apart from its cross-lane move, which then cannot fold into a DPP add.
+    asm volatile("" ::"v"(a.fx), "v"(a.fy), "v"(a.fz), "v"(a.hxx), "v"(a.hxy), "v"(a.hxz),
+                 "v"(a.hyy), "v"(a.hyz), "v"(a.hzz));
 }
 
 // Analytic 3x3 solve with the determinant skip of Sec. 3.2:
@@ -365,7 +380,8 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
         xi4 = T.x[p];
         yv = T.y[p];
         if (TETS)
-            tet_terms<L, KU, CR>(T, T.x, xi4, (size_t)inc.x + (size_t)(p - vb) * inc.y, inc.y, lane, K, a);
+            tet_terms<L, KU, CR>(T, T.x, xi4, p, (size_t)inc.x + (size_t)(p - vb) * inc.y, inc.y, lane, K,
+                                 a);
         if (SPRINGS)
             spring_terms<L>(T.x, xyz(xi4), T.spr_ell + (size_t)inc.z + (size_t)(p - vb) * inc.w, inc.w,
                             lane, K, a);
@@ -415,7 +431,10 @@ __global__ void k_material_pairs(int4 *pa, float4 *pw, const float4 *pws, const 
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = pair_tet[i];
-    if (t < 0) return;
+    if (t < 0) {
+        pw[i] = make_float4(0.f, 0.f, 0.f, 0.f);   // padding: adds zero in the solve
+        return;
+    }
     const float VE = vol[t] * E[tet_perm[t]];
     const float Vmu = VE * k_mu;
     reinterpret_cast<int *>(pa + i)[3] = __float_as_int(VE * k_lam);

@@ -157,6 +157,21 @@ def test_step_before_color_and_bind():
     assert L.vbd_topology_destroy(h) == 0
 
 
+def test_size_limits_rejected():
+    """More than 2^28 vertices or 2^29 tets is refused before any array is read
+    (the solve addresses positions by 32-bit byte offsets)."""
+    L = N.lib()
+    rest, tets = W.cube_lattice(2, 2, 2)
+    rest = np.ascontiguousarray(rest); tets = np.ascontiguousarray(tets)
+    h = C.c_void_p()
+    for nv, nt in (((1 << 28) + 1, tets.shape[0]), (8, (1 << 29) + 1)):
+        desc = N.MeshDesc(nv, nt, 0, 1, None, None, tets.ctypes.data, None, rest.ctypes.data,
+                          None, 0.0, None, 1000.0, 0.3, None)
+        assert L.vbd_build_topology(C.byref(desc), C.byref(h)) == -1
+        assert b"too many" in L.vbd_last_error()
+        assert not h.value
+
+
 def test_batched_offsets_validated():
     w = W.config_batch(n_meshes=3, lo=3, hi=4)
     vo = w.vert_offsets.copy(); vo[-1] += 1
