@@ -145,11 +145,8 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
 // Linear spring E = k/2 (l - L)^2: dE/dx_i = k (l - L) u,
 // d2E/dx_i2 = k (1 - L/l) I + k (L/l) u u^T, unprojected (Sec. 3.2) unless
 // the transverse clamp is requested.
-__device__ __forceinline__ void spring_contrib(const float4 *X, float3 xi, int2 se, float k, int psd,
-                                               Acc &a)
+__device__ __forceinline__ void spring_contrib(float3 xi, float3 xj, float L, float k, int psd, Acc &a)
 {
-    const float3 xj = xyz(ld_slot(X, se.x));
-    const float L = __int_as_float(se.y);
     const float3 d = xi - xj;
     const float l2 = dot3(d, d);
     const float inv_l = __builtin_amdgcn_rsqf(l2);   // v_rsq_f32, 1 ulp
@@ -169,7 +166,9 @@ __device__ __forceinline__ void spring_contrib(const float4 *X, float3 xi, int2 
 }
 
 // Spring terms of one vertex from its D consecutive padded entries at E: each
-// lane loads up to 4 entries together, then their neighbour positions.
+// lane loads up to 4 entries together, then all their neighbour positions
+// before any of the arithmetic (a gather inside each entry's branch would wait
+// for the previous entry's terms).
 template <int L>
 __device__ __forceinline__ void spring_terms(const float4 *X, float3 xi, const int2 *E, int D,
                                              int lane, const StepConsts &K, Acc &a)
@@ -182,9 +181,13 @@ __device__ __forceinline__ void spring_terms(const float4 *X, float3 xi, const i
             const int e = base + j * L;
             se[j] = (e < D) ? E[e] : make_int2(-1, 0);
         }
+        float3 xj[SU];
 #pragma unroll
         for (int j = 0; j < SU; ++j)
-            if (se[j].x >= 0) spring_contrib(X, xi, se[j], K.spring_k, K.spring_psd, a);
+            if (se[j].x >= 0) xj[j] = xyz(ld_slot(X, se[j].x));
+#pragma unroll
+        for (int j = 0; j < SU; ++j)
+            if (se[j].x >= 0) spring_contrib(xi, xj[j], __int_as_float(se[j].y), K.spring_k, K.spring_psd, a);
     }
 }
 
