@@ -337,15 +337,16 @@ __device__ __forceinline__ float3 phase_pos(const float4 *X, const float4 *Xs, i
 // of another vertex's contact triangle).  Partners of p's color (slots in
 // [vb, ve)) are read at their positions from before the phase, the others
 // at their latest.  Returns the number of active elements this lane added.
+// own = S.ctri[p], [e0, e1) = p's corner entries (loaded by the caller with
+// the vertex's own state).
 template <int L>
 __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &S,
                                                const StepConsts &K, int p, float3 xi, int lane,
-                                               int vb, int ve, Acc &a)
+                                               int vb, int ve, int own, int e0, int e1, Acc &a)
 {
     float nc = 0.f;
     const float4 *X = T.x, *Xs = S.xsnap;
     if (lane == 0) {
-        const int own = S.ctri[p];
         if (own >= 0) {
             const int4 tr = S.tri[own];
             if (vt_term(K, T.xt, xi, p, phase_pos(X, Xs, tr.x, vb, ve), phase_pos(X, Xs, tr.y, vb, ve),
@@ -353,8 +354,7 @@ __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &
                 nc += 1.f;
         }
     }
-    const int e1 = (int)S.crow[p + 1];
-    for (int e = (int)S.crow[p] + lane; e < e1; e += L) {
+    for (int e = e0 + lane; e < e1; e += L) {
         const int va = S.cent[e];
         const int4 tr = S.tri[S.ctri[va]];
         const int role = (tr.x == p) ? 0 : ((tr.y == p) ? 1 : 2);
@@ -379,9 +379,15 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     acc_zero(a);
     float4 xi4 = make_float4(0.f, 0.f, 0.f, 0.f), yv = xi4;
     float nc = 0.f;
+    int c_own = -1, c_e0 = 0, c_e1 = 0;   // contact lookups, issued with the own state
     if (active) {
         xi4 = T.x[p];
         yv = T.y[p];
+        if (MC) {
+            c_own = S->ctri[p];
+            c_e0 = (int)S->crow[p];
+            c_e1 = (int)S->crow[p + 1];
+        }
         if (TETS)
             tet_terms<L, KU, CR>(T, T.x, xi4, p, (size_t)inc.x + (size_t)(p - vb) * inc.y, inc.y, lane, K,
                                  a);
@@ -392,7 +398,8 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     if (MC) {
         // Rayleigh damping applies to the material Hessian only: contact
         // terms are added after it (see below) when damping is on
-        if (active && K.kd_over_h == 0.f) nc = contact_terms<L>(T, *S, K, p, xyz(xi4), lane, vb, ve, a);
+        if (active && K.kd_over_h == 0.f)
+            nc = contact_terms<L>(T, *S, K, p, xyz(xi4), lane, vb, ve, c_own, c_e0, c_e1, a);
     }
     acc_reduce<L>(a);
     if (MC) nc = group_sum<L>(nc);
@@ -406,7 +413,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
         acc_zero(c);
         float ncl = 0.f;
         if (lane == 0) {
-            ncl = contact_terms<1>(T, *S, K, p, xi, 0, vb, ve, c);
+            ncl = contact_terms<1>(T, *S, K, p, xi, 0, vb, ve, c_own, c_e0, c_e1, c);
             a.fx += c.fx; a.fy += c.fy; a.fz += c.fz;
             a.hxx += c.hxx; a.hxy += c.hxy; a.hxz += c.hxz;
             a.hyy += c.hyy; a.hyz += c.hyz; a.hzz += c.hzz;
