@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--mode", default="auto", choices=["auto"] + list(MODES))
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=50)
     ap.add_argument("--profile-only", default="",
                     help="run only one workload for a profiler: cube|copy|stack|adjoint")
     ap.add_argument("--lanes", type=int, default=8, help="--profile-only: lanes per vertex")
@@ -138,8 +138,8 @@ def cpu_baseline(w, iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2403_06321_amd import workloads as W
