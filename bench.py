@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=50)
     ap.add_argument("--profile-only", default="",
-                    help="run only one workload for a profiler: cube|copy|stack|adjoint")
+                    help="run only one workload for a profiler: cube|batch|copy|stack|adjoint")
     ap.add_argument("--lanes", type=int, default=8, help="--profile-only: lanes per vertex")
     ap.add_argument("--block", type=int, default=128, help="--profile-only: block size")
     ap.add_argument("--remap", type=int, default=1, help="--profile-only: XCD remap")
@@ -162,6 +162,17 @@ def main():
         ts = Topology.from_workload(ws)
         secs, upd = time_frames(ts, ws, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
         print(json.dumps({"profile": "stack", "ms_per_frame": secs / args.steps * 1e3}))
+        return
+
+    if args.profile_only == "batch":
+        # the 512-mesh batch, plain launches in the given launch configuration
+        wb = W.config_batch(coloring="smallest_last")
+        tb = Topology.from_workload(wb)
+        tb.launch_config = dict(lanes_per_vertex=args.lanes, block_size=args.block,
+                                xcd_remap=args.remap, tet_unroll=args.unroll,
+                                compact_records=args.compact)
+        secs, upd = time_frames(tb, wb, MODES["plain"], args.steps, args.warmup, dev, autotune=False)
+        print(json.dumps({"profile": "batch", "ms_per_frame": secs / args.steps * 1e3}))
         return
 
     if args.profile_only == "adjoint":
