@@ -274,7 +274,10 @@ vbd_status vbd_detect_contacts(vbd_topology topo, const vbd_step_params *params,
 typedef struct {
     int32_t lanes_per_vertex;   /* 2, 4, 8, 16 or 32 lanes of a wave64 per vertex */
     int32_t block_size;         /* 64..512, multiple of 64 */
-    int32_t xcd_remap;          /* 1: give each XCD a contiguous range of blocks */
+    int32_t xcd_remap;          /* 0: blocks as launched (round-robin over the 8
+                                   XCDs), 1: each XCD a contiguous range of blocks,
+                                   2: chunks of 16 consecutive blocks dealt to the
+                                   XCDs in turn; other values: VBD_E_INVALID_ARG */
     int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */
     int32_t tet_unroll;         /* 1..3 tet entries per lane loaded together */
     int32_t compact_records;    /* 1: 32-B pair records (|m|^2 summed from w in the

@@ -1569,7 +1569,8 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
     if (c->tet_unroll < 1 || c->tet_unroll > 3) return fail(VBD_E_INVALID_ARG, "tet_unroll must be 1, 2 or 3");
     if (c->compact_records != 0 && c->compact_records != 1)
         return fail(VBD_E_INVALID_ARG, "compact_records must be 0 or 1");
-    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap ? 1 : 0, c->blocks_per_cu, c->tet_unroll,
+    if (c->xcd_remap < 0 || c->xcd_remap > 2) return fail(VBD_E_INVALID_ARG, "xcd_remap must be 0, 1 or 2");
+    T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap, c->blocks_per_cu, c->tet_unroll,
                        c->compact_records};
     update_phase_bytes(*T);
     T->fwd_graph.reset();
@@ -1607,7 +1608,7 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
             for (int U : {1, 2, 3}) {
                 if (!tets && U > 1) continue;
                 for (int B : {64, 128, 256, 512})
-                    for (int rm : {0, 1}) {
+                    for (int rm : {0, 1, 2}) {
                         if (persistent)
                             for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc, U, cr});
                         else

@@ -38,12 +38,24 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-// blockIdx -> logical block: each of the 8 XCDs (which receive blocks
-// round-robin) gets a contiguous range of logical blocks.
+// blockIdx -> logical block; the 8 XCDs receive blocks round-robin.
+// remap 1: each XCD gets a contiguous range of logical blocks.  remap 2:
+// chunks of kXcdChunk consecutive logical blocks are dealt to the XCDs in
+// turn (neighbouring vertices share an L2 within a chunk, and the XCDs' work
+// stays interleaved over the color); the blocks past the last whole round of
+// 8 chunks keep their index.  Both are bijections on [0, nb).
+constexpr int kXcdChunk = 16;
 __device__ __forceinline__ int xcd_block(int b, int nb, int remap)
 {
     if (!remap) return b;
-    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    const int x = b & 7;
+    if (remap == 2) {
+        const int full = nb / (8 * kXcdChunk) * (8 * kXcdChunk);
+        if (b >= full) return b;
+        const int k = b >> 3;   // this block's turn on its XCD
+        return ((k / kXcdChunk) * 8 + x) * kXcdChunk + k % kXcdChunk;
+    }
+    const int q = nb >> 3, r = nb & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 

@@ -224,6 +224,17 @@ def test_launch_config_lanes_validation():
             t.launch_config = dict(lanes_per_vertex=lanes)
 
 
+def test_launch_config_remap_validation():
+    w = W.tet_cube(3, 0)
+    t = Topology.from_workload(w, bind=False)
+    for rm in (0, 1, 2):
+        t.launch_config = dict(xcd_remap=rm)
+        assert t.launch_config["xcd_remap"] == rm
+    for rm in (-1, 3):
+        with pytest.raises(N.VBDError):
+            t.launch_config = dict(xcd_remap=rm)
+
+
 def test_tet_order_groups_tets_by_vertex_colors():
     w = W.tet_cube(7, 2)
     t = Topology.from_workload(w, bind=False)

@@ -30,7 +30,24 @@ def test_small_cube_all_launch_modes(small_cube_oracle, mode):
     assert_parity(w, xg, xo, label=f"11^3 mode {mode}")
 
 
-@pytest.mark.parametrize("lanes,block,remap", [(2, 128, 1), (4, 64, 0), (8, 256, 1), (16, 512, 1), (32, 128, 0)])
+@pytest.mark.parametrize("lanes,block,unroll", [(8, 64, 3), (16, 128, 2)])
+def test_xcd_remaps_bit_identical(lanes, block, unroll):
+    """The block-to-vertex mapping changes no vertex's arithmetic: on a grid of
+    more than 8 x 16 blocks per color (so the chunked remap deals whole rounds
+    of chunks), every remap gives bit-identical positions, i.e. each vertex of
+    each color is updated exactly once."""
+    w = W.tet_cube(33, 6, E_range=(5e4, 5e5), n_iters=10, frames=2)
+    say(f"33^3 cube, lanes={lanes} block={block}: xcd remap 0 / 1 / 2")
+    out = []
+    for remap in (0, 1, 2):
+        cfg = dict(lanes_per_vertex=lanes, block_size=block, xcd_remap=remap, tet_unroll=unroll)
+        xg, vg, _ = gpu_rollout(w, w.frames, cfg=cfg)
+        out.append((xg, vg))
+    for remap, (xg, vg) in zip((1, 2), out[1:]):
+        assert np.array_equal(xg, out[0][0]) and np.array_equal(vg, out[0][1]), f"remap {remap}"
+
+
+@pytest.mark.parametrize("lanes,block,remap", [(2, 128, 1), (4, 64, 0), (8, 256, 2), (16, 512, 1), (32, 128, 0)])
 def test_small_cube_launch_configs(small_cube_oracle, lanes, block, remap):
     w, (xo, _) = small_cube_oracle
     say(f"small cube lanes={lanes} block={block} remap={remap}")
