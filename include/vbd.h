@@ -76,13 +76,20 @@ typedef struct {
     const double *mass;            /* [n_verts] or NULL -> lumped: each tet adds
                                       density*V/4 to each of its vertices */
     double density;                /* kg/m^3, used for lumped masses */
-    double poisson_nu;             /* Poisson ratio of all tets, 0 <= nu < 0.5 */
+    double poisson_nu;             /* Poisson ratio of all tets, 0 < nu < 0.5 (the
+                                      energy's rest offset alpha = 1 + mu/lambda
+                                      needs lambda > 0) */
     const uint8_t *pinned;         /* [n_verts] 0/1 or NULL (none pinned) */
 } vbd_mesh_desc;
 
 /* Validates the description and precomputes, in FP64, each tet's inverse
- * rest edge matrix and rest volume (F = D_s D_m^{-1}, V = |det D_m|/6) and
- * the lumped vertex masses.  Host only, synchronous.  Errors:
+ * rest edge matrix and rest volume and the lumped vertex masses.
+ * Sec. 5: tets carry the stable Neo-Hookean energy V Psi(F) (Smith et al.
+ * 2018, without the logarithmic term) of the deformation gradient
+ * F = D_s D_m^{-1} (D_s, D_m: current and rest edge matrices, V = |det D_m|/6);
+ * Sec. 3.1, Eq. VariantionalFormOfImplicitEuler / VBDEnergy: the vertex masses
+ * m_i of the inertia term, lumped as density*V/4 per incident tet unless
+ * given.  Host only, synchronous.  Errors:
  * VBD_E_INVALID_ARG (also for more than 2^28 vertices or 2^29 tets),
  * VBD_E_TOPOLOGY (|det D_m| <= 1e-12 * (max edge)^3 counts as degenerate).
  * *out receives a library-owned handle. */
@@ -194,8 +201,9 @@ typedef struct {
      * surface vertex takes the closest surface triangle of another mesh within
      * collision_radius; the pair is a contact element when the vertex is inside
      * that mesh or closer than contact_thickness to its surface.  Detection is
-     * repeated on the current iterate before iterations 1 + k n_col (n_col > 0;
-     * 0 = only at x^t).  Elements use the penalty energy with the closest point
+     * repeated on the current iterate before iterations 1 + k n_col, k >= 0
+     * (Alg. 1's n mod n_col = 1, the first on the initial guess; n_col = 0:
+     * only at x^t).  Elements use the penalty energy with the closest point
      * recomputed at every evaluation and the triangle normal held fixed; same-
      * color updates read the positions from before the color (x_new buffer).
      * Needs launch_mode PLAIN or GRAPH (else VBD_E_UNSUPPORTED). */
@@ -207,6 +215,10 @@ typedef struct {
      * inputs, or copied back by the caller, see VBD_Q_SNAPSHOT_REGION), so the
      * forward recompute is skipped; 0 = recompute them. */
     int32_t backward_recorded;
+    /* 1 = after the step, count the non-finite values of the output x and v
+     * on the device (one extra pass over them); vbd_check then returns
+     * VBD_E_NONFINITE when any was found.  0 = no check. */
+    int32_t check_finite;
 } vbd_step_params;
 
 /* One implicit-Euler time step of every mesh (Alg. 1):
@@ -310,10 +322,26 @@ typedef struct {
 vbd_status vbd_profile_enable(vbd_topology topo, int32_t enable);
 vbd_status vbd_profile_read(vbd_topology topo, vbd_profile_stats *out, int32_t reset);
 
-/* Reads the device-side guard flags (persistent barrier time-out) on
- * `stream` (synchronizes).  VBD_E_DEVICE if a guard fired since the last
- * check; the flag is then cleared. */
+/* Reads the device-side guard flags on `stream` (synchronizes).
+ * VBD_E_DEVICE if the persistent kernel's barrier guard fired since the last
+ * check; VBD_E_NONFINITE if a step run with check_finite produced a
+ * non-finite position or velocity since the last check.  The flag that is
+ * reported is then cleared. */
 vbd_status vbd_check(vbd_topology topo, void *stream);
+
+/* Event counters of a topology, accumulated on the device over every step
+ * (vbd_step, vbd_step_record and the backward's recompute; the autotuner's
+ * timed sweeps are not counted) since the last reset. */
+typedef struct {
+    int64_t n_skips;       /* local solves skipped by the determinant rule of
+                              Sec. 3.2 (|det H_i| <= det_eps_rel ||H_i||_F^3:
+                              the vertex keeps its position) */
+    int64_t n_nonfinite;   /* non-finite output values found by check_finite */
+} vbd_counters;
+/* Copies the counters to *out on `stream` (synchronizes); reset != 0 then
+ * clears them.  Errors: VBD_E_INVALID_ARG, VBD_E_NOT_COLORED,
+ * VBD_E_NO_WORKSPACE, VBD_E_HIP. */
+vbd_status vbd_read_counters(vbd_topology topo, vbd_counters *out, int32_t reset, void *stream);
 
 /* Device copy probe: copies n_bytes (multiple of 16) from src to dst with
  * the library's own streaming kernel; used to measure achievable HBM

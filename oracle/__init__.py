@@ -197,6 +197,9 @@ class Model:
         self.pinned = np.ascontiguousarray(pinned, np.uint8)
         self.nu = float(nu)
         self.spring_k = float(spring_k)
+        if self.tets.shape[0] and not (0.0 < self.nu < 0.5):
+            # the energy's rest offset alpha = 1 + mu/lambda needs lambda > 0
+            raise ValueError("nu must be in (0, 0.5)")
         if self.tets.shape[0]:
             self.Dminv, self.vol = tet_rest(self.tets, self.rest)
         else:

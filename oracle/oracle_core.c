@@ -827,8 +827,11 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
     }
 
     for (int it = 1; it <= P->n_iters; ++it) {
-        if (CT && P->n_col > 0 && it > 1 && (it - 1) % P->n_col == 0) {
-            detect_R(M, P, x, CTs.tri);        /* re-detection every n_col iterations */
+        /* Alg. 1: the collision pass on the current iterate runs when
+         * n mod n_col = 1, i.e. before iterations 1, 1 + n_col, ... (the
+         * first one on the initial guess); n_col = 1 means every iteration */
+        if (CT && P->n_col > 0 && (it - 1) % P->n_col == 0) {
+            detect_R(M, P, x, CTs.tri);
             contacts_index(M, &CTs);
         }
         for (int c = 0; c < C; ++c) {

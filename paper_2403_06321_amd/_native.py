@@ -23,7 +23,7 @@ EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_color_greedy", "vbd_color_giv
            "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_record", "vbd_step_backward",
            "vbd_get_launch_config", "vbd_set_launch_config", "vbd_autotune",
            "vbd_profile_enable", "vbd_profile_read", "vbd_check", "vbd_probe_copy",
-           "vbd_detect_contacts", "vbd_last_error"]
+           "vbd_detect_contacts", "vbd_read_counters", "vbd_last_error"]
 
 
 class MeshDesc(C.Structure):
@@ -42,7 +42,7 @@ class StepParamsC(C.Structure):
                 ("cheb_rho", C.c_float), ("friction_mu", C.c_float), ("friction_eps_v", C.c_float),
                 ("spring_psd", C.c_int32), ("launch_mode", C.c_int32),
                 ("mesh_contacts", C.c_int32), ("collision_radius", C.c_float), ("n_col", C.c_int32),
-                ("backward_recorded", C.c_int32)]
+                ("backward_recorded", C.c_int32), ("check_finite", C.c_int32)]
 
 
 class LaunchConfig(C.Structure):
@@ -54,6 +54,10 @@ class LaunchConfig(C.Structure):
 class ProfileStats(C.Structure):
     _fields_ = [("n_launches", C.c_int64), ("total_ms", C.c_double), ("total_bytes", C.c_double),
                 ("n_vertex_updates", C.c_int64)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("n_skips", C.c_int64), ("n_nonfinite", C.c_int64)]
 
 
 class VBDError(RuntimeError):
@@ -94,6 +98,7 @@ def lib():
     L.vbd_check.argtypes = [p, p]
     L.vbd_probe_copy.argtypes = [p, p, sz, p]
     L.vbd_detect_contacts.argtypes = [p, C.POINTER(StepParamsC), p, p, p]
+    L.vbd_read_counters.argtypes = [p, C.POINTER(Counters), i32, p]
     L.vbd_last_error.argtypes = []
     L.vbd_last_error.restype = C.c_char_p
     for name in EXPORTS:

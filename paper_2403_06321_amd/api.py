@@ -28,7 +28,8 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN, backward_recorded: bool = False):
+def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN, backward_recorded: bool = False,
+                  check_finite: bool = False):
     """StepParams -> (vbd_step_params, keep-alive arrays)."""
     sph = None if p.spheres is None else np.ascontiguousarray(p.spheres, np.float32).reshape(-1, 4)
     pl = None if p.planes is None else np.ascontiguousarray(p.planes, np.float32).reshape(-1, 4)
@@ -40,7 +41,7 @@ def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN, backward_rec
                       int(bool(getattr(p, "spring_psd", False))), int(launch_mode),
                       int(bool(getattr(p, "mesh_contacts", False))),
                       float(getattr(p, "collision_radius", 0.0)), int(getattr(p, "n_col", 0)),
-                      1 if backward_recorded else 0)
+                      1 if backward_recorded else 0, 1 if check_finite else 0)
     return s, (sph, pl)
 
 
@@ -168,15 +169,17 @@ class Topology:
         return out
 
     def step(self, x, v, v_prev, tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
-             stream=None):
-        """One time step in place on (x, v, v_prev): device float32 [n_verts, 3]."""
+             stream=None, check_finite: bool = False):
+        """One time step in place on (x, v, v_prev): device float32 [n_verts, 3].
+        check_finite: count non-finite outputs on the device (check() then
+        raises VBD_E_NONFINITE)."""
         for t, name in ((x, "x"), (v, "v"), (v_prev, "v_prev")):
             _check_state(t, self.n_verts, name)
         if self.n_tets:
             if not (tet_E.is_cuda and tet_E.dtype == torch.float32 and tet_E.numel() == self.n_tets
                     and tet_E.is_contiguous()):
                 raise ValueError("tet_E must be a contiguous float32 CUDA tensor of n_tets")
-        ps, keep = params_struct(params, launch_mode)
+        ps, keep = params_struct(params, launch_mode, check_finite=check_finite)
         N.check(N.lib().vbd_step(self._h, C.byref(ps), _t_ptr(x), _t_ptr(v), _t_ptr(v_prev),
                                  _t_ptr(tet_E) if self.n_tets else None, _stream_handle(stream)))
 
@@ -248,6 +251,13 @@ class Topology:
 
     def check(self, stream=None):
         N.check(N.lib().vbd_check(self._h, _stream_handle(stream)))
+
+    def counters(self, reset: bool = False, stream=None):
+        """Device event counters: determinant-rule skips and non-finite outputs."""
+        c = N.Counters()
+        N.check(N.lib().vbd_read_counters(self._h, C.byref(c), 1 if reset else 0,
+                                          _stream_handle(stream)))
+        return dict(n_skips=int(c.n_skips), n_nonfinite=int(c.n_nonfinite))
 
     def __del__(self):
         h = getattr(self, "_h", None)

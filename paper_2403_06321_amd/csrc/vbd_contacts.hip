@@ -145,6 +145,10 @@ __device__ __forceinline__ int cell_coord(float v, float inv_s)
     return (int)fminf(fmaxf(c, -1048576.f), 1048576.f);
 }
 
+// Spatial hash of a grid cell: the XOR of the cell coordinates times three
+// large primes, as proposed by Teschner et al., "Optimized Spatial Hashing for
+// Collision Detection of Deformable Objects" (VMV 2003), masked to the
+// power-of-two bucket count.
 __device__ __forceinline__ unsigned cell_hash(int i, int j, int k, int mask)
 {
     const unsigned h = ((unsigned)i * 73856093u) ^ ((unsigned)j * 19349663u) ^ ((unsigned)k * 83492791u);

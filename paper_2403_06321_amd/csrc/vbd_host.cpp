@@ -885,7 +885,9 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
             HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.xt, K, s));
         }
         for (int it = 1; it <= p->n_iters; ++it) {
-            if (mc && p->n_col > 0 && it > 1 && (it - 1) % p->n_col == 0)
+            // Alg. 1: detection on the current iterate before iterations
+            // 1, 1 + n_col, ... (n mod n_col = 1; the first on the initial guess)
+            if (mc && p->n_col > 0 && (it - 1) % p->n_col == 0)
                 HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.x, K, s));
             for (int c = 0; c < T.n_colors; ++c) {
                 if (mc) {
@@ -915,6 +917,7 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
         }
     }
     HIP_TRY(launch_finalize(T.dev, x, v, vp, K, s));
+    if (p->check_finite) HIP_TRY(launch_check_finite(x, v, 3 * (long long)T.nv, T.dev.flags, s));
     return VBD_OK;
 }
 
@@ -936,6 +939,7 @@ GraphKey make_key(const vbd_step_params *p, std::vector<const void *> ptrs, void
     push(&p->launch_mode, 4);
     push(&p->mesh_contacts, 4); push(&p->collision_radius, 4); push(&p->n_col, 4);
     push(&p->backward_recorded, 4);
+    push(&p->check_finite, 4);
     return k;
 }
 
@@ -1054,8 +1058,10 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *d, vbd_topology *out)
     if (d->n_springs > 0 && !d->springs) return fail(VBD_E_INVALID_ARG, "springs is NULL");
     if (d->n_tets > (1 << 29)) return fail(VBD_E_INVALID_ARG, "too many tets (max 2^29)");
     if (d->n_verts > (1 << 28)) return fail(VBD_E_INVALID_ARG, "too many vertices (max 2^28)");
-    if (!(d->poisson_nu >= 0.0 && d->poisson_nu < 0.5) && d->n_tets > 0)
-        return fail(VBD_E_INVALID_ARG, "poisson_nu must be in [0, 0.5)");
+    // The stable Neo-Hookean energy as read here, mu/2 (tr F^T F - 3) +
+    // lam/2 (J - alpha)^2 with alpha = 1 + mu/lam, needs lam > 0, i.e. nu > 0.
+    if (!(d->poisson_nu > 0.0 && d->poisson_nu < 0.5) && d->n_tets > 0)
+        return fail(VBD_E_INVALID_ARG, "poisson_nu must be in (0, 0.5)");
     if (d->n_meshes > 1 && (!d->vert_offsets || !d->tet_offsets))
         return fail(VBD_E_INVALID_ARG, "batched description needs vert_offsets and tet_offsets");
     auto *T = new vbd_topology_s();
@@ -1496,6 +1502,7 @@ vbd_status vbd_step_record(vbd_topology T, const vbd_step_params *p, float *x, f
         DevTopo D = T->dev;
         D.x = T->dev.snaps + (size_t)T->nv * p->n_iters;
         HIP_TRY(launch_finalize(D, x, v, vp, K, q));
+        if (p->check_finite) HIP_TRY(launch_check_finite(x, v, 3 * (long long)T->nv, T->dev.flags, q));
         return VBD_OK;
     };
     if (p->launch_mode == VBD_LAUNCH_PLAIN || p->launch_mode == VBD_LAUNCH_PERSISTENT || T->profiling)
@@ -1617,6 +1624,10 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
             }
         }
     }
+    // the timed sweeps must not show in the caller's skip counter
+    uint32_t saved_skips[2] = {0, 0};
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(saved_skips, T->dev.flags + kFlagSkips, sizeof(saved_skips), hipMemcpyDeviceToHost));
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
@@ -1670,6 +1681,8 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
         }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(T->dev.flags + kFlagSkips, saved_skips, sizeof(saved_skips), hipMemcpyHostToDevice));
     T->cfg = best_cfg;
     update_phase_bytes(*T);
     T->fwd_graph.reset();
@@ -1722,6 +1735,31 @@ vbd_status vbd_check(vbd_topology T, void *stream)
         return fail(VBD_E_DEVICE,
                     "persistent kernel barrier timed out: arrivals seen %u of target %u, grid %u blocks "
                     "(%d CUs)", f[3], f[4], f[5], T->n_cu);
+    }
+    if (f[kFlagNonfinite] != 0) {
+        HIP_TRY(launch_zero_u32(T->dev.flags + kFlagNonfinite, 1, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return fail(VBD_E_NONFINITE, "%u non-finite position or velocity values after a step run with "
+                    "check_finite", f[kFlagNonfinite]);
+    }
+    return VBD_OK;
+}
+
+vbd_status vbd_read_counters(vbd_topology T, vbd_counters *out, int32_t reset, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if (!out) return fail(VBD_E_INVALID_ARG, "out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t f[4] = {0, 0, 0, 0};   // flags kFlagNonfinite .. kFlagSkips + 1
+    static_assert(kFlagNonfiniteTotal + 1 == kFlagSkips, "counter layout");
+    HIP_TRY(hipMemcpyAsync(f, T->dev.flags + kFlagNonfinite, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out->n_skips = (int64_t)((uint64_t)f[2] | ((uint64_t)f[3] << 32));
+    out->n_nonfinite = (int64_t)f[1];
+    if (reset) {
+        HIP_TRY(launch_zero_u32(T->dev.flags + kFlagNonfiniteTotal, 3, s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
     return VBD_OK;
 }

@@ -18,6 +18,15 @@ using PairEnt = int4;
 
 constexpr int kMaxObstacles = 8;
 
+// Entries of the device flag array (DevTopo::flags, 64 x 32 bit):
+//   0 barrier arrivals, 1 barrier abort, 3..5 abort diagnostics (arrivals
+//   seen, target, grid), kFlagNonfinite / kFlagNonfiniteTotal non-finite
+//   output values since the last vbd_check / counter reset, kFlagSkips a
+//   64-bit count of determinant-rule skips (8-byte aligned).
+constexpr int kFlagNonfinite = 6;
+constexpr int kFlagNonfiniteTotal = 7;
+constexpr int kFlagSkips = 8;
+
 // Per-step constants passed by value to every kernel.
 struct StepConsts {
     float h, inv_h;
@@ -82,7 +91,7 @@ struct DevTopo {
     float4 *x, *xt, *y;                // current iterate, x^t, inertia target (w = m/h^2)
     float4 *prev1, *prev2;             // Chebyshev history
     unsigned char *collided;           // sticky contact flag within a step
-    unsigned *flags;                   // [0] barrier counter, [1] abort flag, [2] skip count
+    unsigned *flags;                   // see kFlag* above
     float4 *snaps;                     // backward: (n_iters + 1) iterates
     float4 *xbar, *ybar, *xtbar, *vbar;
     float3 *contrib;                   // backward: [n_tets][4] pending neighbour adjoints (12 B)
@@ -162,6 +171,9 @@ hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters,
                              hipStream_t s, int *grid_out);
 hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s);
 hipError_t launch_zero_u32(unsigned *p, long long n, hipStream_t s);
+// Non-finite values among a[0..n) and b[0..n) into the flag counters.
+hipError_t launch_check_finite(const float *a, const float *b, long long n, unsigned *flags,
+                               hipStream_t s);
 
 // backward
 hipError_t launch_bwd_init(const DevTopo &T, const float *gx_out, const float *gv_out,

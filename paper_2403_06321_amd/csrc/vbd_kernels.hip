@@ -69,8 +69,8 @@ __device__ __forceinline__ void acc_zero(Acc &a)
     a.fx = a.fy = a.fz = a.hxx = a.hxy = a.hxz = a.hyy = a.hyz = a.hzz = 0.f;
 }
 
-// One tet seen from the vertex i it is solved for (stable Neo-Hookean,
-// Sec. 3.3): f_i -= V (mu F m + lam (J - alpha) cof(F) m) and
+// One tet seen from the vertex i it is solved for (stable Neo-Hookean of
+// Sec. 5, in the local system of Sec. 3.2): f_i -= V (mu F m + lam (J - alpha) cof(F) m) and
 // H_ii += V (mu |m|^2 I + lam (cof(F) m)(cof(F) m)^T), m the vertex's shape
 // gradient.  With the pair's rest frame S (F' = D_s' S, D_s' = [e1 e2 e3],
 // e_k = x_k - x_i for the other vertices a, b, c):
@@ -437,7 +437,7 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     const bool ok = solve_sym3(a, K.det_eps_rel, dx);
     if (lane == 0) {
         if (ok) T.x[p] = make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w);
-        else atomicAdd(&T.flags[2], 1u);
+        else atomicAdd(reinterpret_cast<unsigned long long *>(T.flags + kFlagSkips), 1ull);
         if (contact) T.collided[p] = 1;
     }
 }
@@ -680,6 +680,23 @@ __global__ void k_zero_u32(unsigned *p, long long n)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+// Counts the non-finite values among the n floats of a and of b (the step's
+// output positions and velocities) into flags[kFlagNonfinite] (cleared by
+// vbd_check) and flags[kFlagNonfiniteTotal] (cleared by a counter reset):
+// one atomic per wave that found any.
+__global__ void k_check_finite(const float *a, const float *b, long long n, unsigned *flags)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    unsigned bad = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        bad += (isfinite(a[i]) ? 0u : 1u) + (isfinite(b[i]) ? 0u : 1u);
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((threadIdx.x & 63) == 0 && bad != 0) {
+        atomicAdd(&flags[kFlagNonfinite], bad);
+        atomicAdd(&flags[kFlagNonfiniteTotal], bad);
+    }
 }
 
 // ---------------------------------------------------------------- adjoint --
@@ -1261,6 +1278,16 @@ hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s)
     int grid = cdiv(n, 256);
     if (grid > 4096) grid = 4096;
     hipLaunchKernelGGL(k_copy4, dim3(grid), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float *a, const float *b, long long n, unsigned *flags,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<long long>(blocks, 2048)), dim3(256), 0, s,
+                       a, b, n, flags);
     return hipGetLastError();
 }
 

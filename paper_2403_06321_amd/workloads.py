@@ -361,6 +361,60 @@ def config_differentiable(n: int = 33, seed: int = 4, frames: int = 30, n_iters:
                     frames=frames, target=target, coloring=coloring)
 
 
+def spring_net(n: int = 24, seed: int = 9, spacing: float = 0.05, k: float = 100.0,
+               m: float = 0.05, rest_scale=(0.92, 1.08), n_massless: int = 6,
+               frames: int = 12, n_iters: int = 20) -> Workload:
+    """A hanging mass-spring net for the unprojected spring Hessian: an n x n
+    grid in the xz-plane (structural + shear springs) with its top row pinned,
+    jittered by U(+-10% spacing), each spring's rest length its jittered
+    length times U[rest_scale] (about half the springs start compressed, whose
+    transverse stiffness k(1 - L/l) is then negative).  Plus n_massless
+    massless particles, each hung from its own pinned anchor by one spring at
+    its rest length: their local Hessian k d d^T has rank one, so the
+    determinant rule skips them in every iteration."""
+    rng = np.random.default_rng(seed)
+    ii, kk = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ii, kk = ii.T.ravel(), kk.T.ravel()                 # vertex id = i + n k
+    grid = np.stack([ii * spacing, np.zeros(ii.size), 1.0 - kk * spacing], 1)
+    grid += rng.uniform(-0.1 * spacing, 0.1 * spacing, size=grid.shape)
+    sp = []
+    for k_ in range(n):
+        for i in range(n):
+            v = i + n * k_
+            if i + 1 < n:
+                sp.append((v, v + 1))
+            if k_ + 1 < n:
+                sp.append((v, v + n))
+            if i + 1 < n and k_ + 1 < n:
+                sp.append((v, v + n + 1))
+            if i > 0 and k_ + 1 < n:
+                sp.append((v, v + n - 1))
+    sp = np.array(sp, np.int64)
+    L = np.linalg.norm(grid[sp[:, 0]] - grid[sp[:, 1]], axis=1) * rng.uniform(*rest_scale, size=len(sp))
+    pinned = np.zeros(n * n, np.uint8)
+    pinned[np.flatnonzero(kk == 0)] = 1
+    mass = np.full(n * n, m)
+    # massless particles below the net, each on one spring from a pinned anchor
+    anchors = np.stack([np.arange(n_massless) * 2 * spacing, np.full(n_massless, 0.3),
+                        np.full(n_massless, 0.0)], 1)
+    hang = anchors + np.array([0.0, 0.0, -spacing])
+    base = n * n
+    ids_a = base + 2 * np.arange(n_massless)
+    extra_sp = np.stack([ids_a, ids_a + 1], 1)
+    extra_pos = np.empty((2 * n_massless, 3))
+    extra_pos[0::2], extra_pos[1::2] = anchors, hang
+    rest = np.concatenate([grid, extra_pos])
+    springs = np.concatenate([sp, extra_sp]).astype(np.int32)
+    spring_rest = np.concatenate([L, np.full(n_massless, spacing)])
+    pinned = np.concatenate([pinned, np.tile(np.array([1, 0], np.uint8), n_massless)])
+    mass = np.concatenate([mass, np.tile(np.array([m, 0.0]), n_massless)])
+    nv = rest.shape[0]
+    return Workload(name=f"spring net {n}^2", rest=rest, tets=np.zeros((0, 4), np.int32),
+                    pinned=pinned, x0=rest.copy(), v0=np.zeros((nv, 3)), tet_E=np.zeros(0),
+                    springs=springs, spring_rest=spring_rest, spring_k=k, mass=mass,
+                    params=StepParams(n_iters=n_iters), frames=frames)
+
+
 def single_particle_chain(n: int = 2, length: float = 0.1, k: float = 100.0, m: float = 0.01):
     """n particles on a vertical line joined by springs, the top one pinned."""
     rest = np.zeros((n, 3))

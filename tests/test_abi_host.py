@@ -132,6 +132,11 @@ def test_error_codes():
     flat = rest.copy(); flat[:, 2] = 0.0
     assert _status(lambda: Topology(flat, tets, bind=False)) == -2         # degenerate rest tet
     assert _status(lambda: Topology(rest, tets, nu=0.5, bind=False)) == -1  # bad Poisson ratio
+    # nu = 0 gives lambda = 0 and an infinite rest offset alpha = 1 + mu/lambda
+    assert _status(lambda: Topology(rest, tets, nu=0.0, bind=False)) == -1
+    assert _status(lambda: Topology(rest, tets, nu=-0.1, bind=False)) == -1
+    with pytest.raises(ValueError):
+        O.Model(rest, tets, np.zeros(len(rest), np.uint8), nu=0.0)
     sp = np.array([[0, 0]], np.int32)
     assert _status(lambda: Topology(rest, None, springs=sp, mass=np.ones(8), bind=False)) == -2
     assert _status(lambda: Topology(rest, None, springs=np.array([[0, 1]]), spring_rest=[0.0],

@@ -8,11 +8,13 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import (assert_parity, gpu_rollout, oracle_rollout, oracle_states, replace,
-                      resync_errors, resync_parity, say)
+from gpu_util import (assert_parity, bbox_diag, gpu_rollout, oracle_rollout, oracle_states,
+                      replace, resync_errors, resync_parity, say)
+from paper_2403_06321_amd import _native as N
 from paper_2403_06321_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+O_COLORS = N.Q_COLORS
 THREADS = min(16, os.cpu_count() or 1)
 
 
@@ -179,6 +181,47 @@ def test_large_cube_late_state_in_the_benchmarked_configuration():
                   label=f"65^3 after 60 frames, {t.launch_config}")
 
 
+@pytest.mark.parametrize("coloring", ["smallest_last", "id"])
+def test_large_cube_full_depth_frames(coloring):
+    """The benchmarked 65^3 workload at its full depth (Alg. 1 with n_max =
+    100 iterations per frame), greedy coloring in smallest-last order (4
+    colors, the benchmark's) and in vertex-id order (8 colors), autotuned
+    graph launches: two frames from x^0, per step against the oracle (the
+    second frame starts from the GPU's state of the first, rounded to FP32,
+    on both sides)."""
+    import torch
+    from paper_2403_06321_amd.api import Topology
+    w = W.config_large_cube(coloring=coloring)
+    assert w.params.n_iters == 100
+    t = Topology.from_workload(w)
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(w.x0, dtype=torch.float32, device=dev).contiguous()
+    v = torch.tensor(w.v0, dtype=torch.float32, device=dev).contiguous()
+    vp = v.clone()
+    E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).contiguous()
+    t.autotune(x, v, vp, E, w.params, 1)
+    m = O.Model.from_workload(w)
+    assert np.array_equal(m.colors, t.query(O_COLORS))
+    O.set_threads(THREADS)
+    start = (w.x0, w.v0, w.v0)
+    worst = 0.0
+    for f in range(2):
+        xs, vs, vps = (torch.tensor(a, dtype=torch.float32, device=dev).contiguous() for a in start)
+        t.step(xs, vs, vps, E, w.params, 1)
+        xg = xs.double().cpu().numpy()
+        say(f"oracle 65^3, {coloring} coloring, full-depth frame {f} ...")
+        s32 = tuple(a.astype(np.float32).astype(np.float64) for a in start)
+        xo, _, _, st = O.step(m, w.params, *s32, w.tet_E)
+        assert st["n_skips"] == 0
+        e = np.linalg.norm(xg - xo, axis=1).max() / np.linalg.norm(xo.max(0) - xo.min(0))
+        say(f"65^3 {coloring} frame {f}: bbox-relative error {e:.3e}")
+        worst = max(worst, e)
+        assert e <= 1e-5, f"frame {f}: {e:.3e}"
+        start = (xg, vs.double().cpu().numpy(), vps.double().cpu().numpy())
+    t.check()
+    assert t.counters()["n_skips"] == 0
+
+
 @pytest.mark.parametrize("coloring", ["lattice4", "smallest_last"])
 def test_large_cube_four_colorings_prefix(coloring):
     w = W.config_large_cube(frames=2, coloring=coloring)
@@ -338,3 +381,77 @@ def test_batch_full_size_sampled_meshes():
         xg, _, t = gpu_rollout(w, 2, launch_mode=mode, autotune=True)
         assert_parity(sub, [x[rows] for x in xg], xo,
                       label=f"batch sampled meshes mode {mode}, {t.launch_config}")
+
+
+@pytest.mark.parametrize("mode,lanes", [(0, 2), (1, 4), (3, 8), (0, 16)])
+def test_spring_net_unprojected_hessian_and_skips(mode, lanes):
+    """Sec. 3.2's default spring Hessian (no PSD projection): a hanging net
+    in which about a quarter of the springs stay compressed, so the
+    transverse stiffness k(1 - L/l) < 0 lowers the local Hessians' smallest
+    eigenvalue below m/h^2, and massless particles on one spring each whose
+    rank-one Hessian the determinant rule skips in every iteration.  Per-step
+    parity with the oracle, and the device skip counter equals the oracle's
+    count of skipped local solves."""
+    import torch
+    from paper_2403_06321_amd.api import Topology
+    w = W.spring_net()
+    assert not w.params.spring_psd
+    states = oracle_states(w, w.frames)
+    m = O.Model.from_workload(w)
+    skips = 0
+    for f in range(w.frames):
+        _, _, _, st = O.step(m, w.params, *states[f], w.tet_E)
+        skips += st["n_skips"]
+    # the projection changes the answer: the unclamped branch is exercised
+    xc, _, _, _ = O.step(m, replace(w.params, spring_psd=True), *states[-2], w.tet_E)
+    assert np.abs(xc - states[-1][0]).max() > 1e-3 * bbox_diag(states[-1][0])
+    t = Topology.from_workload(w)
+    t.launch_config = dict(lanes_per_vertex=lanes, block_size=128)
+    t.counters(reset=True)
+    dev = torch.device("cuda", 0)
+    worst = 0.0
+    for f in range(w.frames):
+        x, v, vp = (torch.tensor(a, dtype=torch.float32, device=dev).contiguous() for a in states[f])
+        t.step(x, v, vp, None, w.params, mode)
+        xg = x.double().cpu().numpy()
+        e = np.linalg.norm(xg - states[f + 1][0], axis=1).max() / bbox_diag(states[f + 1][0])
+        worst = max(worst, e)
+        assert e <= 1e-5, f"frame {f}: {e:.3e}"
+    t.check()
+    c = t.counters()
+    say(f"spring net mode {mode} lanes {lanes}: worst per-step error {worst:.3e}, "
+        f"skips {c['n_skips']} (oracle {skips})")
+    assert skips == w.frames * w.params.n_iters * 6
+    assert c["n_skips"] == skips
+    assert c["n_nonfinite"] == 0
+
+
+def test_nonfinite_check_and_counter_reset():
+    """check_finite: a NaN velocity on one free vertex poisons its
+    neighbourhood; the device check counts the non-finite outputs, vbd_check
+    reports VBD_E_NONFINITE once, and the counters reset.  A clean step with
+    the check on reports nothing."""
+    import torch
+    from paper_2403_06321_amd.api import Topology
+    w = W.tet_cube(6, 2, E=1e5, n_iters=5)
+    t = Topology.from_workload(w)
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(w.x0, dtype=torch.float32, device=dev).contiguous()
+    v = torch.zeros_like(x); vp = v.clone()
+    E = torch.tensor(w.tet_E, dtype=torch.float32, device=dev).contiguous()
+    for mode in (0, 1):
+        t.step(x, v, vp, E, w.params, mode, check_finite=True)
+    t.check()
+    assert t.counters() == dict(n_skips=0, n_nonfinite=0)
+    free = int(np.flatnonzero(w.pinned == 0)[50])
+    v[free, 0] = float("nan")
+    t.step(x, v, vp, E, w.params, 0, check_finite=True)
+    torch.cuda.synchronize()
+    bad = int((~torch.isfinite(x)).sum() + (~torch.isfinite(v)).sum())
+    assert bad > 0
+    with pytest.raises(N.VBDError) as ei:
+        t.check()
+    assert ei.value.status == -7
+    t.check()                                   # reported once
+    assert t.counters(reset=True)["n_nonfinite"] == bad
+    assert t.counters()["n_nonfinite"] == 0

@@ -136,19 +136,27 @@ def test_vertex_on_triangle_interior_equals_plane_contact():
     x0 = rest.copy()
     x0[v, 2] = top - 0.002
     m = O.Model(rest, tets, pinned, vert_offsets=vo)
-    for mu in (0.0, 0.4):
+    # friction in the sliding regime, and slow enough to stick (the static
+    # branch of Eq. IPC_friction, |u| < h eps_v, which the plane contact's
+    # closed-form pin fixes)
+    for mu, tang in ((0.0, (0.05, -0.02)), (0.4, (0.05, -0.02)), (0.4, (0.004, -0.002))):
         base = dict(n_iters=5, contact_k=1e4, contact_thickness=1e-3, init_mode=W.INIT_PREV,
                     friction_mu=mu, friction_eps_v=1e-2)
         pm = P(mesh_contacts=True, collision_radius=0.05, **base)
         pp = P(planes=np.array([[0.0, 0.0, 1.0, top]]), **base)
         tri = O.detect_contacts(m, pm, x0)
         assert np.flatnonzero(tri >= 0).tolist() == [v]
-        vel = np.zeros_like(rest); vel[v] = [0.05, -0.02, -0.1]
+        vel = np.zeros_like(rest); vel[v] = [tang[0], tang[1], -0.1]
         xm, vm, _, stm = O.step(m, pm, x0, vel, vel, E)
         xp, vp, _, stp = O.step(m, pp, x0, vel, vel, E)
         assert stm["n_contacts"] > 0 and stm["n_contacts"] == stp["n_contacts"]
         assert np.allclose(xm, xp, rtol=0, atol=1e-13)
         assert xm[v, 2] > x0[v, 2]
+        slide = np.linalg.norm(xm[v, :2] - x0[v, :2])
+        if tang[0] < 0.01:
+            assert 0.0 < slide < pm.h * pm.friction_eps_v      # stuck: static branch
+        elif mu > 0:
+            assert slide > pm.h * pm.friction_eps_v            # sliding branch
 
 
 def test_contact_forces_conserve_momentum_at_convergence():

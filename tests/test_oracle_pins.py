@@ -194,6 +194,21 @@ def test_lumped_mass_total():
     assert m.vol.sum() == pytest.approx(1.0, rel=1e-13)
 
 
+def test_lumped_mass_per_vertex_on_the_lattice():
+    """Sec. 5 reading of the vertex mass (lumped, a quarter of each incident
+    tet's mass): every Kuhn tet of the unjittered lattice has volume edge^3/6,
+    so m_i = rho * edge^3 / 24 times the number of tets that contain vertex i
+    (counted here from the tet list: 2, 4, 6, 8, 12 or 24 on this lattice).  Giving a tet's mass to one of its vertices, or splitting it
+    unevenly, changes some m_i."""
+    for n in (4, 7):
+        w = W.tet_cube(n, 0, E=1e5)
+        m = O.Model.from_workload(w)
+        count = np.bincount(w.tets.ravel(), minlength=w.n_verts)
+        expect = W.DENSITY * W.EDGE ** 3 / 24.0 * count
+        assert set(np.unique(count)) == {2, 4, 6, 8, 12, 24}
+        assert np.allclose(m.mass, expect, rtol=1e-13, atol=0)
+
+
 def test_degenerate_tet_rejected():
     rest = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 0, 1]], np.float64)
     with pytest.raises(ValueError):
@@ -455,6 +470,46 @@ def test_friction_dynamic_regime_closed_form():
     assert ux > h * 1e-2
     assert x[0, 2] == pytest.approx(z, rel=1e-10)
     assert x[0, 0] == pytest.approx(ux, rel=1e-10)
+
+
+def _static_friction_root(mh2, uy, mul, hev):
+    """Tangential balance of a particle resting on a plane while it sticks
+    (|u| < h eps_v): m/h^2 (u - u_y) + mu lambda f1(u) = 0 with
+    f1(u) = 2u/(h eps_v) - u^2/(h eps_v)^2 (Eq. IPC_friction, static branch),
+    i.e. a quadratic in u; its smaller root is the one in [0, h eps_v)."""
+    a = mul / hev ** 2
+    b = -(mh2 + 2.0 * mul / hev)
+    c = mh2 * uy
+    return (-b - np.sqrt(b * b - 4.0 * a * c)) / (2.0 * a)
+
+
+@pytest.mark.parametrize("vx", [0.005, 0.02, 0.05])
+def test_friction_static_regime_closed_form(vx):
+    """Eq. IPC_friction on a particle on the ground plane whose tangential
+    displacement stays below h eps_v (static regime): the converged position
+    solves the 1-D quadratic above, with the contact force lambda = k_c pen
+    from the normal balance.  A wrong factor or sign in the static branch of
+    f1, or a missing u^2 term, moves the root."""
+    mass, kc, mu_c, eps_v = 0.2, 1e5, 0.3, 1e-2
+    m = _lone(mass)
+    p = P(n_iters=200, contact_k=kc, contact_thickness=0.0, friction_mu=mu_c,
+          friction_eps_v=eps_v, planes=np.array([[0.0, 0.0, 1.0, 0.0]]), init_mode=W.INIT_PREV)
+    x0 = np.array([[0.0, 0.0, -1e-4]]); v0 = np.array([[vx, 0.0, 0.0]])
+    x, _, _, st = O.step(m, p, x0, v0, v0, np.zeros(0))
+    h, mh2 = p.h, mass / p.h ** 2
+    hev = h * eps_v
+    yz = x0[0, 2] - h * h * 9.8
+    z = mh2 * yz / (mh2 + kc)
+    lamc = kc * (-z)
+    u = _static_friction_root(mh2, h * vx, mu_c * lamc, hev)
+    assert 0.0 < u < hev                       # the static branch decides
+    assert x[0, 2] == pytest.approx(z, rel=1e-10)
+    assert x[0, 0] == pytest.approx(u, rel=1e-10)
+    assert x[0, 1] == 0.0
+    # the same particle without friction slides the full h vx
+    p0 = dataclasses.replace(p, friction_mu=0.0)
+    x_free, _, _, _ = O.step(m, p0, x0, v0, v0, np.zeros(0))
+    assert x_free[0, 0] == pytest.approx(h * vx, rel=1e-12)
 
 
 def test_chebyshev_weights_on_a_lone_vertex():
