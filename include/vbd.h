@@ -43,7 +43,7 @@ typedef enum {
     VBD_E_NO_WORKSPACE = -4,  /* step before bind, or workspace too small */
     VBD_E_HIP = -5,           /* HIP runtime failure (message has hipGetErrorString) */
     VBD_E_UNSUPPORTED = -6,   /* a feature combination this entry point does not do */
-    VBD_E_NONFINITE = -7,     /* reserved: non-finite state detected by vbd_check */
+    VBD_E_NONFINITE = -7,     /* a step run with check_finite left a non-finite value (vbd_check) */
     VBD_E_DEVICE = -8         /* a device-side guard fired (see vbd_check) */
 } vbd_status;
 
