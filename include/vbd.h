@@ -73,8 +73,11 @@ typedef struct {
     const double *rest_pos;        /* [n_verts][3] FP64 rest shape */
     const double *spring_rest;     /* [n_springs] or NULL -> rest distance */
     double spring_k;               /* spring stiffness (N/m), global */
-    const double *mass;            /* [n_verts] or NULL -> lumped: each tet adds
-                                      density*V/4 to each of its vertices */
+    const double *mass;            /* [n_verts] finite, >= 0, or NULL -> lumped:
+                                      each tet adds density*V/4 to each of its
+                                      vertices.  A massless free vertex is
+                                      allowed: while its local Hessian is
+                                      singular the determinant rule skips it */
     double density;                /* kg/m^3, used for lumped masses */
     double poisson_nu;             /* Poisson ratio of all tets, 0 < nu < 0.5 (the
                                       energy's rest offset alpha = 1 + mu/lambda
@@ -90,7 +93,8 @@ typedef struct {
  * Sec. 3.1, Eq. VariantionalFormOfImplicitEuler / VBDEnergy: the vertex masses
  * m_i of the inertia term, lumped as density*V/4 per incident tet unless
  * given.  Host only, synchronous.  Errors:
- * VBD_E_INVALID_ARG (also for more than 2^28 vertices or 2^29 tets),
+ * VBD_E_INVALID_ARG (also for more than 2^28 vertices or 2^29 tets, and for
+ * a negative or non-finite mass),
  * VBD_E_TOPOLOGY (|det D_m| <= 1e-12 * (max edge)^3 counts as degenerate).
  * *out receives a library-owned handle. */
 vbd_status vbd_build_topology(const vbd_mesh_desc *desc, vbd_topology *out);

@@ -1159,9 +1159,12 @@ vbd_status vbd_build_topology(const vbd_mesh_desc *d, vbd_topology *out)
         for (int t = 0; t < T->nt; ++t)
             for (int a = 0; a < 4; ++a) T->mass[T->tets[4 * (size_t)t + a]] += d->density * T->vol[t] / 4.0;
     }
+    // a free vertex may be massless: its local Hessian then comes from its
+    // elements alone and the determinant rule skips it while that is singular
     for (int i = 0; i < T->nv; ++i)
-        if (!(T->mass[i] > 0.0) && !T->pinned[i])
-            return reject(VBD_E_TOPOLOGY, "free vertex %d has no mass", i);
+        if (!(T->mass[i] >= 0.0) || !std::isfinite(T->mass[i]))
+            return reject(VBD_E_INVALID_ARG, "vertex %d has mass %g (must be finite and >= 0)", i,
+                          T->mass[i]);
     *out = T;
     return VBD_OK;
 }

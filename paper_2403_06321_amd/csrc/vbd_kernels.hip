@@ -155,8 +155,10 @@ __device__ __forceinline__ void tet_terms(const DevTopo &T, const float4 *X, flo
 }
 
 // Linear spring E = k/2 (l - L)^2: dE/dx_i = k (l - L) u,
-// d2E/dx_i2 = k (1 - L/l) I + k (L/l) u u^T, unprojected (Sec. 3.2) unless
-// the transverse clamp is requested.
+// d2E/dx_i2 = k u u^T + c (I - u u^T) with the transverse stiffness
+// c = k (1 - L/l), unprojected (Sec. 3.2) unless the clamp is requested: the
+// block's eigenvalues are k along u and c twice across it, so c -> max(c, 0)
+// is its PSD projection and leaves the axial k unchanged.
 __device__ __forceinline__ void spring_contrib(float3 xi, float3 xj, float L, float k, int psd, Acc &a)
 {
     const float3 d = xi - xj;
@@ -167,8 +169,8 @@ __device__ __forceinline__ void spring_contrib(float3 xi, float3 xj, float L, fl
     const float g = k * (l - L);
     a.fx -= g * u.x; a.fy -= g * u.y; a.fz -= g * u.z;
     float ci = k * (1.0f - L * inv_l);
-    const float cu = k - ci;                 // k L / l
     if (psd && ci < 0.f) ci = 0.f;           // transverse stiffness clamped (option)
+    const float cu = k - ci;                 // k L / l unclamped, k clamped
     a.hxx += ci + cu * u.x * u.x;
     a.hxy += cu * u.x * u.y;
     a.hxz += cu * u.x * u.z;

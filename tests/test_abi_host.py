@@ -141,6 +141,13 @@ def test_error_codes():
     assert _status(lambda: Topology(rest, None, springs=sp, mass=np.ones(8), bind=False)) == -2
     assert _status(lambda: Topology(rest, None, springs=np.array([[0, 1]]), spring_rest=[0.0],
                                     mass=np.ones(8), bind=False)) == -2
+    # masses: finite and >= 0; a massless free vertex is accepted (skipped while singular)
+    spr = np.array([[0, 1]], np.int32)
+    for bad_m in (-1.0, float("nan"), float("inf")):
+        mm = np.ones(8); mm[3] = bad_m
+        assert _status(lambda: Topology(rest, None, springs=spr, mass=mm, bind=False)) == -1
+    mm = np.ones(8); mm[1] = 0.0
+    assert _status(lambda: Topology(rest, None, springs=spr, mass=mm, bind=False)) == 0
 
 
 def test_step_before_color_and_bind():
