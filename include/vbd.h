@@ -239,6 +239,26 @@ typedef struct {
 vbd_status vbd_step(vbd_topology topo, const vbd_step_params *params, float *x, float *v,
                     float *v_prev, const float *tet_E, void *stream);
 
+/* vbd_step for callers that cannot allocate device memory during the call
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same step, arguments, results and errors, with the per-step
+ * state buffers (iterate, x^t, y, Chebyshev history, contact flags) taken
+ * from a fixed device array of 96 MiB that the library holds on every device
+ * it runs on until the process ends, instead of from the bound workspace.
+ * Nothing is allocated: no hipMalloc, no graph, no profiling events.  Limits:
+ * 3 x 16 + 1 bytes of state per vertex (5 x 16 + 1 with Chebyshev
+ * acceleration), each section 256-B aligned, within 96 MiB (about 2.0M
+ * vertices, 1.2M with acceleration; more: VBD_E_INVALID_ARG); launch_mode
+ * PLAIN or PERSISTENT (graph modes: VBD_E_UNSUPPORTED); no mesh contacts
+ * (VBD_E_UNSUPPORTED); the current device must be the one the workspace was
+ * bound on (VBD_E_INVALID_ARG).  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams, other topologies,
+ * other threads) race and must be ordered by the caller.  Each step writes
+ * every state entry it reads before reading it, so nothing carries over
+ * between calls.  The skip and non-finite counters stay in the workspace. */
+vbd_status vbd_step_static(vbd_topology topo, const vbd_step_params *params, float *x, float *v,
+                           float *v_prev, const float *tet_E, void *stream);
+
 /* Reverse mode of one vbd_step (tets + inertia + pins; springs, contacts,
  * damping and acceleration give VBD_E_UNSUPPORTED).  Recomputes the step's
  * iterates from the checkpoint S^t = (x_t, v_t, v_prev) and runs the adjoint

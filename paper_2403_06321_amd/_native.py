@@ -20,7 +20,7 @@ COLOR_ID_ORDER, COLOR_SMALLEST_LAST, COLOR_DSATUR = 0, 1, 2
 
 # every symbol include/vbd.h declares
 EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_color_greedy", "vbd_color_given", "vbd_workspace_size", "vbd_bind_workspace",
-           "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_record", "vbd_step_backward",
+           "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_static", "vbd_step_record", "vbd_step_backward",
            "vbd_get_launch_config", "vbd_set_launch_config", "vbd_autotune",
            "vbd_profile_enable", "vbd_profile_read", "vbd_check", "vbd_probe_copy",
            "vbd_detect_contacts", "vbd_read_counters", "vbd_last_error"]
@@ -88,6 +88,7 @@ def lib():
     L.vbd_topology_query.argtypes = [p, i32, p, sz]
     L.vbd_topology_destroy.argtypes = [p]
     L.vbd_step.argtypes = [p, C.POINTER(StepParamsC), p, p, p, p, p]
+    L.vbd_step_static.argtypes = [p, C.POINTER(StepParamsC), p, p, p, p, p]
     L.vbd_step_record.argtypes = [p, C.POINTER(StepParamsC), p, p, p, p, p]
     L.vbd_step_backward.argtypes = [p, C.POINTER(StepParamsC)] + [p] * 12
     L.vbd_get_launch_config.argtypes = [p, C.POINTER(LaunchConfig)]

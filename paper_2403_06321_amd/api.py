@@ -183,6 +183,22 @@ class Topology:
         N.check(N.lib().vbd_step(self._h, C.byref(ps), _t_ptr(x), _t_ptr(v), _t_ptr(v_prev),
                                  _t_ptr(tet_E) if self.n_tets else None, _stream_handle(stream)))
 
+    def step_static(self, x, v, v_prev, tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
+                    stream=None, check_finite: bool = False):
+        """step() without allocation: the step's state buffers come from the
+        library's fixed per-device scratch (vbd_step_static; PLAIN or
+        PERSISTENT launches, no mesh contacts)."""
+        for t, name in ((x, "x"), (v, "v"), (v_prev, "v_prev")):
+            _check_state(t, self.n_verts, name)
+        if self.n_tets:
+            if not (tet_E.is_cuda and tet_E.dtype == torch.float32 and tet_E.numel() == self.n_tets
+                    and tet_E.is_contiguous()):
+                raise ValueError("tet_E must be a contiguous float32 CUDA tensor of n_tets")
+        ps, keep = params_struct(params, launch_mode, check_finite=check_finite)
+        N.check(N.lib().vbd_step_static(self._h, C.byref(ps), _t_ptr(x), _t_ptr(v), _t_ptr(v_prev),
+                                        _t_ptr(tet_E) if self.n_tets else None,
+                                        _stream_handle(stream)))
+
     def step_record(self, x, v, v_prev, tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
                     stream=None):
         """step() for the differentiable path, leaving the step's iterates in

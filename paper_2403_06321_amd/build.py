@@ -19,7 +19,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["vbd_kernels.hip", "vbd_contacts.hip", "vbd_host.cpp"]
+SOURCES = ["vbd_kernels.hip", "vbd_contacts.hip", "vbd_static.hip", "vbd_host.cpp"]
 
 
 def build(verbose: bool = False) -> str:

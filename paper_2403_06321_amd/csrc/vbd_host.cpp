@@ -21,6 +21,7 @@
 
 #include "../../include/vbd.h"
 #include "vbd_internal.h"
+#include "vbd_static.h"
 
 using namespace vbd;
 
@@ -136,6 +137,7 @@ struct vbd_topology_s {
     Layout lay{};
     bool bound = false;
     DevTopo dev{};
+    int device = -1;                    // current device at vbd_bind_workspace
     int n_cu = 0;
     std::string arch;
     LaunchCfg cfg{8, 128, 1, 0, 2, 0};
@@ -840,14 +842,16 @@ vbd_status prof_begin(vbd_topology_s &T, hipStream_t s, ProfileEvent &ev)
 }
 
 // ------------------------------------------------------------ enqueue step --
-vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
-                        float *x, float *v, float *vp, const float *E, hipStream_t s,
-                        bool persistent, bool in_capture)
+// D: the device view the kernels use (D, or T.dev with the per-step state
+// buffers moved to the static scratch); profile: allow the event brackets.
+vbd_status enqueue_step(vbd_topology_s &T, const DevTopo &D, const vbd_step_params *p,
+                        const StepConsts &K, float *x, float *v, float *vp, const float *E,
+                        hipStream_t s, bool persistent, bool in_capture, bool profile = true)
 {
     const bool tets = T.nt > 0, springs = T.ns > 0;
-    HIP_TRY(launch_material(T.dev, E, K, T.cfg.compact != 0, s));
-    HIP_TRY(launch_predict(T.dev, x, v, vp, K, persistent, s));
-    const bool prof = T.profiling && !in_capture;
+    HIP_TRY(launch_material(D, E, K, T.cfg.compact != 0, s));
+    HIP_TRY(launch_predict(D, x, v, vp, K, persistent, s));
+    const bool prof = profile && T.profiling && !in_capture;
     if (persistent) {
         ProfileEvent ev{};
         if (prof) {
@@ -855,7 +859,7 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
             if (st) return st;
         }
         int grid = 0;
-        HIP_TRY(launch_persistent(T.dev, K, p->n_iters, tets, springs, T.cfg, T.n_cu,
+        HIP_TRY(launch_persistent(D, K, p->n_iters, tets, springs, T.cfg, T.n_cu,
                                   /*cooperative=*/!in_capture, s, &grid));
         if (prof) {
             HIP_TRY(hipEventRecord(ev.b, s));
@@ -881,24 +885,24 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
         // phase refreshes the snapshot of the color solved before it
         int pend_b = 0, pend_e = 0;
         if (mc) {
-            HIP_TRY(launch_copy4(T.surf_dev.xsnap, T.dev.x, T.nv, s));
-            HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.xt, K, s));
+            HIP_TRY(launch_copy4(T.surf_dev.xsnap, D.x, T.nv, s));
+            HIP_TRY(launch_detect(D, T.surf_dev, D.xt, K, s));
         }
         for (int it = 1; it <= p->n_iters; ++it) {
             // Alg. 1: detection on the current iterate before iterations
             // 1, 1 + n_col, ... (n mod n_col = 1; the first on the initial guess)
             if (mc && p->n_col > 0 && (it - 1) % p->n_col == 0)
-                HIP_TRY(launch_detect(T.dev, T.surf_dev, T.dev.x, K, s));
+                HIP_TRY(launch_detect(D, T.surf_dev, D.x, K, s));
             for (int c = 0; c < T.n_colors; ++c) {
                 if (mc) {
                     if (T.color_off[c + 1] > T.color_off[c]) {
-                        HIP_TRY(launch_solve_contacts(T.dev, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
+                        HIP_TRY(launch_solve_contacts(D, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
                                                       incidence(T, c), pend_b, pend_e, tets, springs, T.cfg, s));
                         pend_b = T.color_off[c];
                         pend_e = T.color_off[c + 1];
                     }
                 } else
-                    HIP_TRY(launch_solve(T.dev, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), tets, springs, T.cfg, s));
+                    HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), tets, springs, T.cfg, s));
                 if (T.color_off[c + 1] > T.color_off[c]) {
                     ++launches;
                     ev.bytes += T.phase_bytes[c];
@@ -906,7 +910,7 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
                 }
             }
             if (p->cheb_rho > 0.f) {
-                HIP_TRY(launch_cheb(T.dev, K, it, s, mc ? T.surf_dev.xsnap : nullptr));
+                HIP_TRY(launch_cheb(D, K, it, s, mc ? T.surf_dev.xsnap : nullptr));
                 pend_b = pend_e = 0;
             }
         }
@@ -916,8 +920,8 @@ vbd_status enqueue_step(vbd_topology_s &T, const vbd_step_params *p, const StepC
             T.events.push_back(ev);
         }
     }
-    HIP_TRY(launch_finalize(T.dev, x, v, vp, K, s));
-    if (p->check_finite) HIP_TRY(launch_check_finite(x, v, 3 * (long long)T.nv, T.dev.flags, s));
+    HIP_TRY(launch_finalize(D, x, v, vp, K, s));
+    if (p->check_finite) HIP_TRY(launch_check_finite(x, v, 3 * (long long)T.nv, D.flags, s));
     return VBD_OK;
 }
 
@@ -1258,6 +1262,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    T->device = dev;
     T->n_cu = prop.multiProcessorCount;
     T->arch = prop.gcnArchName;
     T->ws = (char *)dev_ptr;
@@ -1466,11 +1471,56 @@ vbd_status vbd_step(vbd_topology T, const vbd_step_params *p, float *x, float *v
     const bool persistent = mode == VBD_LAUNCH_PERSISTENT || mode == VBD_LAUNCH_PERSISTENT_GRAPH;
     if (T->nv == 0) return VBD_OK;
     if (mode == VBD_LAUNCH_PLAIN || mode == VBD_LAUNCH_PERSISTENT || T->profiling)
-        return enqueue_step(*T, p, K, x, v, vp, E, s, persistent, false);
+        return enqueue_step(*T, T->dev, p, K, x, v, vp, E, s, persistent, false);
     // graph modes: capture once per (pointers, parameters, stream), replay after
     return run_graph(*T, T->fwd_graph, make_key(p, {x, v, vp, E}, stream), s, [&](hipStream_t cs) {
-        return enqueue_step(*T, p, K, x, v, vp, E, cs, persistent, true);
+        return enqueue_step(*T, T->dev, p, K, x, v, vp, E, cs, persistent, true);
     });
+}
+
+vbd_status vbd_step_static(vbd_topology T, const vbd_step_params *p, float *x, float *v, float *vp,
+                           const float *E, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if ((st = validate_params(*T, p))) return st;
+    if (T->nv > 0 && (!x || !v || !vp)) return fail(VBD_E_INVALID_ARG, "state pointer is NULL");
+    if (T->nt > 0 && !E) return fail(VBD_E_INVALID_ARG, "tet_E is NULL");
+    const int mode = p->launch_mode;
+    if (mode != VBD_LAUNCH_PLAIN && mode != VBD_LAUNCH_PERSISTENT)
+        return fail(VBD_E_UNSUPPORTED, "vbd_step_static: launch_mode must be PLAIN or PERSISTENT "
+                                       "(graph instantiation allocates)");
+    if (p->mesh_contacts)
+        return fail(VBD_E_UNSUPPORTED, "vbd_step_static: mesh contacts are not supported");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != T->device)
+        return fail(VBD_E_INVALID_ARG, "vbd_step_static: the workspace is bound on device %d, "
+                                       "the current device is %d", T->device, dev);
+    // the per-step state sections, each 256-B aligned
+    const size_t nv = (size_t)T->nv;
+    const bool cheb = p->cheb_rho > 0.f;
+    const size_t s4 = align_up(sizeof(float4) * nv), need = (cheb ? 5 : 3) * s4 + align_up(nv);
+    if (need > kStaticScratchBytes)
+        return fail(VBD_E_INVALID_ARG, "vbd_step_static: %d vertices need %zu bytes of state, the "
+                                       "static scratch holds %zu (at most %zu vertices%s)", T->nv,
+                    need, kStaticScratchBytes,
+                    (size_t)((kStaticScratchBytes - 256) / (16 * (cheb ? 5 : 3) + 1)),
+                    cheb ? " with acceleration" : "");
+    if (T->nv == 0) return VBD_OK;
+    void *base = nullptr;
+    HIP_TRY(static_scratch(dev, &base));
+    char *b = (char *)base;
+    DevTopo D = T->dev;
+    D.x = (float4 *)b;
+    D.xt = (float4 *)(b + s4);
+    D.y = (float4 *)(b + 2 * s4);
+    D.prev1 = cheb ? (float4 *)(b + 3 * s4) : nullptr;
+    D.prev2 = cheb ? (float4 *)(b + 4 * s4) : nullptr;
+    D.collided = (unsigned char *)(b + (cheb ? 5 : 3) * s4);
+    const StepConsts K = make_consts(*T, p);
+    return enqueue_step(*T, D, p, K, x, v, vp, E, (hipStream_t)stream,
+                        mode == VBD_LAUNCH_PERSISTENT, false, /*profile=*/false);
 }
 
 namespace {
