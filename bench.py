@@ -107,6 +107,55 @@ def kernel_roofline(topo, w, dev, frames=3):
                 updates_per_s=st["n_vertex_updates"] / (st["total_ms"] * 1e-3))
 
 
+def adjoint_phases(topo, w, dev, frames=2):
+    """Average reverse color-phase time and algorithmic bytes: plain backward
+    launches of recorded frames, timed by the library's profiler."""
+    import torch
+    from paper_2403_06321_amd import _native as N
+    x, v, vp, E = state(w, dev)
+    g = [torch.full_like(x, 1e-3) for _ in range(3)]
+    o = [torch.zeros_like(x) for _ in range(3)]
+    gE = torch.zeros_like(E)
+    tot = None
+    for f in range(frames + 1):
+        xs = (x.clone(), v.clone(), vp.clone())
+        topo.step_record(x, v, vp, E, w.params, N.LAUNCH_PLAIN)
+        if f == 1:
+            topo.profile_enable(True)
+            topo.profile_read(reset=True)
+        topo.step_backward(*xs, E, *g, *o, gE, w.params, N.LAUNCH_PLAIN, recorded=True)
+    torch.cuda.synchronize()
+    st = topo.profile_read(reset=True)
+    topo.profile_enable(False)
+    avg_ms = st["total_ms"] / st["n_launches"]
+    avg_bytes = st["total_bytes"] / st["n_launches"]
+    return dict(avg_ms=avg_ms, avg_bytes=avg_bytes, achieved_gbs=avg_bytes / (avg_ms * 1e-3) / 1e9)
+
+
+def read_probe(dev):
+    """Best read-only streaming rate over a 2 GiB buffer (the library's probe,
+    a few grid sizes)."""
+    import torch
+    from paper_2403_06321_amd.api import probe_read
+    n = 1 << 29
+    src = torch.ones(n, device=dev)
+    best = 0.0
+    for blocks in (256, 512, 1024, 8192):
+        part = torch.zeros(blocks, device=dev)
+        probe_read(src, part)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            probe_read(src, part)
+        b.record()
+        torch.cuda.synchronize()
+        best = max(best, 5 * 4 * n / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del src
+    torch.cuda.empty_cache()
+    return best
+
+
 def kernel_traffic():
     """Measured HBM bytes per launch from committed rocprofv3 counter runs,
     valid only while the kernel source is unchanged."""
@@ -120,19 +169,81 @@ def kernel_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, iters):
-    import oracle as O
+def host_threads():
+    """The host's CPU share: the affinity mask, capped by OMP_NUM_THREADS when
+    the environment sets it."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(omp))) if omp.isdigit() else n
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, iters):
+    """The FP64 oracle (plain loops, OpenMP within a color) on bounded samples
+    of the benchmarked workloads, on the host's CPU share and on one thread."""
     import dataclasses
-    threads = min(16, os.cpu_count() or 1)
-    O.set_threads(threads)
+    import oracle as O
+    threads = host_threads()
+    res = {}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    # the headline cube: one frame x `iters` iterations on all threads, 2 on one
+    w = W.config_large_cube(coloring="smallest_last")
     m = O.Model.from_workload(w)
-    p = dataclasses.replace(w.params, n_iters=iters)
-    t0 = time.perf_counter()
-    O.step(m, p, w.x0, w.v0, w.v0, w.tet_E)
-    dt = time.perf_counter() - t0
     free = int((w.pinned == 0).sum())
-    return dict(value=free * iters / dt, unit="vertex-updates/s", cores=threads, kind="oracle",
-                sample=f"65^3 cube, 1 frame x {iters} iterations, FP64, {threads} threads, {dt:.1f} s")
+    O.set_threads(threads)
+    p = dataclasses.replace(w.params, n_iters=iters)
+    dt = timed(lambda: O.step(m, p, w.x0, w.v0, w.v0, w.tet_E))
+    O.set_threads(1)
+    p1 = dataclasses.replace(w.params, n_iters=1)
+    dt1 = timed(lambda: O.step(m, p1, w.x0, w.v0, w.v0, w.tet_E))
+    res.update(value=free * iters / dt, unit="vertex-updates/s", cores=threads, kind="oracle",
+               sample=f"65^3 cube, 1 frame x {iters} iterations, FP64, {threads} threads, "
+                      f"{dt:.1f} s; single thread: 1 frame x 1 iteration, {dt1:.1f} s",
+               single_thread=free / dt1, cpu_model=cpu_model(),
+               host_cpus=os.cpu_count())
+    del m
+    O.set_threads(threads)
+    # the batch: 8 seeded sample meshes of the 512, one frame of 40 iterations
+    wb = W.config_batch(frames=1, coloring="smallest_last")
+    import numpy as np
+    ids = sorted(np.random.default_rng(3).choice(wb.n_meshes, 8, replace=False).tolist())
+    sub = W.subset_meshes(wb, ids)
+    ms = O.Model.from_workload(sub)
+    dtb = timed(lambda: O.step(ms, sub.params, sub.x0, sub.v0, sub.v0, sub.tet_E))
+    res["batch_8_meshes"] = dict(value=sub.n_verts * sub.params.n_iters / dtb, unit="vertex-updates/s",
+                                 seconds=dtb, sample=f"8 of the 512 meshes ({sub.n_verts} vertices), "
+                                                     f"1 frame x {sub.params.n_iters} iterations")
+    # the differentiable cube: one frame of 5 iterations forward and its adjoint
+    wd = W.config_differentiable(coloring="smallest_last")
+    wd = dataclasses.replace(wd, params=dataclasses.replace(wd.params, n_iters=5))
+    md = O.Model.from_workload(wd)
+    st = {}
+
+    def fwd():
+        st["x"] = O.step(md, wd.params, wd.x0, wd.v0, wd.v0, wd.tet_E)[0]
+    dtf = timed(fwd)
+    g = np.ones_like(wd.x0) * 1e-3
+    dtg = timed(lambda: O.step_backward(md, wd.params, wd.x0, wd.v0, wd.v0, wd.tet_E, g, g * 0, g * 0))
+    freed = int((wd.pinned == 0).sum())
+    res["adjoint_one_frame"] = dict(forward_s=dtf, backward_s=dtg,
+                                    updates_per_s_forward_backward=freed * wd.params.n_iters / (dtf + dtg),
+                                    sample=f"33^3 cube, 1 frame x {wd.params.n_iters} iterations, "
+                                           "forward then adjoint")
+    return res
 
 
 def main():
@@ -225,6 +336,13 @@ def main():
     log(f"[bench] solve kernel: {roof['avg_ms'] * 1e3:.1f} us/launch, "
         f"{roof['avg_bytes'] / 1e6:.2f} MB/launch, {roof['achieved_gbs']:.0f} GB/s")
     traffic = kernel_traffic()
+    read_gbs = read_probe(dev)
+    # the cache-ideal byte model (every array once per iteration: 60 B per tet,
+    # 4 B per tet-vertex pair, 52 B per vertex), shared by the iteration's
+    # color phases
+    model_a = (60.0 * w.n_tets + 4.0 * 4 * w.n_tets + 52.0 * w.n_verts) / topo.n_colors
+    log(f"[bench] read probe {read_gbs:.0f} GB/s; cache-ideal model {model_a / 1e6:.2f} MB/launch "
+        f"-> {model_a / (roof['avg_ms'] * 1e-3) / 1e9:.0f} GB/s")
 
     out = {
         "metric": "VBD vertex-updates/s + HBM GB/s, 64³ tet cube; batched & adjoint vs plain",
@@ -249,7 +367,12 @@ def main():
                      "unit": "GB/s", "frac": roof["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_solve<tets> (one color phase per launch)",
                      "avg_launch_us": roof["avg_ms"] * 1e3,
-                     "algorithmic_bytes_per_launch": roof["avg_bytes"]},
+                     "algorithmic_bytes_per_launch": roof["avg_bytes"],
+                     "read_probe_gbs": read_gbs, "frac_of_read_probe": roof["achieved_gbs"] / read_gbs,
+                     "cache_ideal_bytes_per_launch": model_a,
+                     "cache_ideal_frac": model_a / (roof["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "measured_traffic_frac": (None if traffic is None else
+                                               traffic / (roof["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)},
     }
     del topo
     torch.cuda.empty_cache()
@@ -291,7 +414,7 @@ def main():
     out["extra"] = extra
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(W.config_large_cube(coloring="smallest_last"), args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(W, args.cpu_iters)
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} v-upd/s ({out['cpu_baseline']['sample']})")
     print(json.dumps(out))
 
@@ -367,13 +490,28 @@ def extras(dev, W, Topology):
         td.step(x, v, vp, E2, wd.params, MODES["plain"])
     b.record(); torch.cuda.synchronize()
     ms_fwd = a.elapsed_time(b)
+    # the reverse color phases alone (plain launches, HIP events around the
+    # sweep) against the forward color phases of the same topology
+    adj = adjoint_phases(td, wd, dev)
+    fwd_k = kernel_roofline(td, wd, dev, frames=2)
     res["adjoint"] = dict(forward_backward_ms=ms, forward_only_ms=ms_fwd,
                           updates_per_s_forward_backward=upd / (ms * 1e-3),
                           updates_per_s_forward=upd / (ms_fwd * 1e-3),
+                          reverse_phase=dict(avg_launch_us=adj["avg_ms"] * 1e3,
+                                             algorithmic_bytes_per_launch=adj["avg_bytes"],
+                                             achieved_gbs=adj["achieved_gbs"],
+                                             frac=adj["achieved_gbs"] / HBM_PEAK_GBS),
+                          forward_phase=dict(avg_launch_us=fwd_k["avg_ms"] * 1e3,
+                                             algorithmic_bytes_per_launch=fwd_k["avg_bytes"],
+                                             achieved_gbs=fwd_k["achieved_gbs"],
+                                             frac=fwd_k["achieved_gbs"] / HBM_PEAK_GBS),
+                          reverse_over_forward_phase=adj["avg_ms"] / fwd_k["avg_ms"],
                           workload="33^3 cube, 30 frames x 20 iterations, loss on final centroid, "
                                    f"smallest-last coloring ({td.n_colors} colors)",
                           config=td.launch_config)
-    log(f"[bench] adjoint fwd+bwd {ms:.1f} ms, forward {ms_fwd:.1f} ms")
+    log(f"[bench] adjoint fwd+bwd {ms:.1f} ms, forward {ms_fwd:.1f} ms; reverse phase "
+        f"{adj['avg_ms'] * 1e3:.2f} us ({adj['achieved_gbs']:.0f} GB/s), forward phase "
+        f"{fwd_k['avg_ms'] * 1e3:.2f} us ({fwd_k['achieved_gbs']:.0f} GB/s)")
     del td
     # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, graph launches
     ws = W.config_block_stack(cols=8, levels=4, n=9, coloring="smallest_last")

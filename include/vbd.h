@@ -169,11 +169,15 @@ enum {
                                ordered so (b - a) x (c - a) points out of the mesh;
                                sorted by their ascending vertex-id triples */
     VBD_Q_SURFACE_COUNTS = 15, /* int64[2]: n_surf_tris, n_surf_verts */
-    VBD_Q_SNAPSHOT_REGION = 16 /* int64[3]: byte offset of the iterate snapshots in the bound
+    VBD_Q_SNAPSHOT_REGION = 16,/* int64[3]: byte offset of the iterate snapshots in the bound
                                   workspace (-1 when max_backward_iters is 0), bytes per
                                   snapshot (n_verts float4 in slot order), snapshot count - 1
                                   (max_backward_iters); a step of n_iters iterations uses the
                                   first (n_iters + 1) snapshots */
+    VBD_Q_ADJ_PHASE_BYTES = 17,/* double[n_colors]: algorithmic HBM bytes of one reverse color
+                                  phase of vbd_step_backward */
+    VBD_Q_PHASE_COUNTS = 18    /* int64[n_colors][4]: tet pairs, spring entries, distinct
+                                  neighbour vertices and free vertices of each color */
 };
 vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
 vbd_status vbd_topology_destroy(vbd_topology topo);
@@ -335,7 +339,9 @@ vbd_status vbd_autotune(vbd_topology topo, const vbd_step_params *params, const 
 /* Timing of the hot kernel (hipEvents on the launch stream).  When enabled,
  * vbd_step runs its plain launch sequence and records one event pair around
  * the step's back-to-back color-solve launches (or around the persistent
- * kernel); total_ms / n_launches is the average launch duration.
+ * kernel), and vbd_step_backward (plain launches) one around its reverse
+ * sweep's adjoint color phases, with VBD_Q_ADJ_PHASE_BYTES as their bytes;
+ * total_ms / n_launches is the average launch duration.
  * vbd_profile_read synchronizes and reports totals since the last reset. */
 typedef struct {
     int64_t n_launches;        /* timed hot-kernel launches */
@@ -371,6 +377,14 @@ vbd_status vbd_read_counters(vbd_topology topo, vbd_counters *out, int32_t reset
  * the library's own streaming kernel; used to measure achievable HBM
  * bandwidth and to calibrate traffic counters. */
 vbd_status vbd_probe_copy(void *dst, const void *src, size_t n_bytes, void *stream);
+
+/* Device read probe: n_blocks (1..65535) blocks of 256 threads read n_bytes
+ * (multiple of 16) from src, 8 loads of 16 B in flight per thread, and write
+ * one partial sum per block into partials (device float[n_blocks]); the
+ * achievable read-dominant HBM bandwidth that the solve kernels, whose traffic
+ * is almost all reads, are quoted against. */
+vbd_status vbd_probe_read(const void *src, size_t n_bytes, float *partials, int32_t n_blocks,
+                          void *stream);
 
 const char *vbd_last_error(void);
 

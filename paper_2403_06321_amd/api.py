@@ -146,7 +146,9 @@ class Topology:
                 N.Q_PHASE_BYTES: (np.float64, c["n_colors"]),
                 N.Q_TET_ORDER: (np.int32, c["n_tets"]),
                 N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"]),
-                N.Q_SURFACE_COUNTS: (np.int64, 2), N.Q_SNAPSHOT_REGION: (np.int64, 3)}
+                N.Q_SURFACE_COUNTS: (np.int64, 2), N.Q_SNAPSHOT_REGION: (np.int64, 3),
+                N.Q_ADJ_PHASE_BYTES: (np.float64, c["n_colors"]),
+                N.Q_PHASE_COUNTS: (np.int64, 4 * c["n_colors"])}
         if what == N.Q_SURFACE:
             n_tri = int(self.query(N.Q_SURFACE_COUNTS)[0])
             out = np.zeros((n_tri, 3), np.int32)
@@ -283,6 +285,15 @@ class Topology:
             except Exception:
                 pass
             self._h = None
+
+
+def probe_read(src: torch.Tensor, partials: torch.Tensor, stream=None):
+    """Read-only streaming probe over src; partials: float32 CUDA tensor, one
+    entry per block (its length sets the grid)."""
+    if not (partials.is_cuda and partials.dtype == torch.float32 and partials.is_contiguous()):
+        raise ValueError("partials must be a contiguous float32 CUDA tensor")
+    N.check(N.lib().vbd_probe_read(_t_ptr(src), src.numel() * src.element_size(), _t_ptr(partials),
+                                   partials.numel(), _stream_handle(stream)))
 
 
 def probe_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):

@@ -121,6 +121,7 @@ struct vbd_topology_s {
     size_t spr_total = 0;
     std::vector<float> spr_len;
     std::vector<double> phase_bytes;            // for the current launch configuration
+    std::vector<double> adj_phase_bytes;        // one reverse color phase (vbd_step_backward)
     std::vector<std::array<int64_t, 3>> phase_cnt;  // per color: pairs, spring entries,
                                                     // distinct neighbours
     std::vector<int64_t> phase_updates;
@@ -168,10 +169,18 @@ void update_phase_bytes(vbd_topology_s &T)
 {
     const double rec = T.cfg.compact ? 32.0 : 36.0;
     T.phase_bytes.assign(T.phase_cnt.size(), 0.0);
+    T.adj_phase_bytes.assign(T.phase_cnt.size(), 0.0);
     for (size_t c = 0; c < T.phase_cnt.size(); ++c) {
         const auto &n = T.phase_cnt[c];
         T.phase_bytes[c] = rec * (double)n[0] + 8.0 * (double)n[1] + 48.0 * (double)T.phase_updates[c] +
                            16.0 * (double)n[2];
+        // reverse phase: per tet pair the 16-B (tet, slot, others) entry, the
+        // 16-B E-free record, V lam (4 B), the tet's four 12-B contribution
+        // cells read and written, its volume, and its Ebar read and written;
+        // per vertex its snapshot, xbar and ybar read and written and y read
+        // (96 B); 16 B per distinct neighbour position
+        T.adj_phase_bytes[c] = (16.0 + 16.0 + 4.0 + 96.0 + 4.0 + 8.0) * (double)n[0] +
+                               96.0 * (double)T.phase_updates[c] + 16.0 * (double)n[2];
     }
 }
 
@@ -1001,7 +1010,8 @@ vbd_status enqueue_record(vbd_topology_s &T, const vbd_step_params *p, const Ste
 vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
                             const float *x_t, const float *v_t, const float *v_prev, const float *E,
                             const float *gx_out, const float *gv_out, const float *gvp_out,
-                            float *gx_in, float *gv_in, float *gvp_in, float *g_E, hipStream_t s)
+                            float *gx_in, float *gv_in, float *gvp_in, float *g_E, hipStream_t s,
+                            bool in_capture)
 {
     const size_t nv = (size_t)T.nv;
     DevTopo D = T.dev;
@@ -1022,11 +1032,28 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
         HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 12 * (long long)T.nt, s));
         HIP_TRY(launch_zero_u32((unsigned *)D.ebar, T.nt, s));
     }
+    // profiling: one event pair around the reverse sweep's adjoint launches
+    ProfileEvent ev{};
+    const bool prof = T.profiling && !in_capture;
+    if (prof) {
+        vbd_status st = prof_begin(T, s, ev);
+        if (st) return st;
+    }
     for (int it = p->n_iters; it >= 1; --it) {
         const float4 *Sn = T.dev.snaps + nv * it, *Sp = Sn - nv;
-        for (int c = T.n_colors - 1; c >= 0; --c)
+        for (int c = T.n_colors - 1; c >= 0; --c) {
             HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T.color_off[c], T.color_off[c + 1], T.ell_info[c],
                                          T.cfg, s));
+            if (T.color_off[c + 1] > T.color_off[c]) {
+                ++ev.launches;
+                ev.bytes += T.adj_phase_bytes[c];
+                ev.updates += T.phase_updates[c];
+            }
+        }
+    }
+    if (prof) {
+        HIP_TRY(hipEventRecord(ev.b, s));
+        T.events.push_back(ev);
     }
     HIP_TRY(launch_bwd_fold(D, s));
     HIP_TRY(launch_bwd_final(D, v_t, v_prev, gx_in, gv_in, gvp_in, g_E, K, s));
@@ -1421,6 +1448,17 @@ vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t by
     case VBD_Q_SPRING_ROWS: return give(T->spr_row.data(), 4 * T->spr_row.size());
     case VBD_Q_SPRING_NBRS: return give(T->spr_nbr_orig.data(), 4 * T->spr_nbr_orig.size());
     case VBD_Q_PHASE_BYTES: return give(T->phase_bytes.data(), 8 * T->phase_bytes.size());
+    case VBD_Q_ADJ_PHASE_BYTES: return give(T->adj_phase_bytes.data(), 8 * T->adj_phase_bytes.size());
+    case VBD_Q_PHASE_COUNTS: {
+        std::vector<int64_t> q(4 * (size_t)T->n_colors);
+        for (int c = 0; c < T->n_colors; ++c) {
+            q[4 * c] = T->phase_cnt[c][0];
+            q[4 * c + 1] = T->phase_cnt[c][1];
+            q[4 * c + 2] = T->phase_cnt[c][2];
+            q[4 * c + 3] = T->phase_updates[c];
+        }
+        return give(q.data(), 8 * q.size());
+    }
     case VBD_Q_TET_ORDER: return give(T->tet_order.data(), 4 * T->tet_order.size());
     case VBD_Q_SURFACE: return give(T->surf.data(), 4 * T->surf.size());
     case VBD_Q_SURFACE_COUNTS: {
@@ -1576,16 +1614,16 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
         return fail(VBD_E_INVALID_ARG, "NULL array");
     const StepConsts K = make_consts(*T, p);
     hipStream_t s = (hipStream_t)stream;
-    auto enqueue = [&](hipStream_t q) {
+    auto enqueue = [&](hipStream_t q, bool in_capture) {
         return enqueue_backward(*T, p, K, x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in,
-                                gvp_in, g_E, q);
+                                gvp_in, g_E, q, in_capture);
     };
     if (p->launch_mode == VBD_LAUNCH_PLAIN || p->launch_mode == VBD_LAUNCH_PERSISTENT || T->profiling)
-        return enqueue(s);
+        return enqueue(s, false);
     return run_graph(*T, T->bwd_graph,
                      make_key(p, {x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in, gvp_in, g_E},
                               stream),
-                     s, enqueue);
+                     s, [&](hipStream_t q) { return enqueue(q, true); });
 }
 
 vbd_status vbd_detect_contacts(vbd_topology T, const vbd_step_params *p, const float *x,
@@ -1822,6 +1860,16 @@ vbd_status vbd_probe_copy(void *dst, const void *src, size_t n_bytes, void *stre
     if (!dst || !src || n_bytes % 16) return fail(VBD_E_INVALID_ARG, "bad copy arguments");
     if (n_bytes / 16 > (size_t)INT32_MAX) return fail(VBD_E_INVALID_ARG, "copy too large");
     HIP_TRY(launch_copy4((float4 *)dst, (const float4 *)src, (int)(n_bytes / 16), (hipStream_t)stream));
+    return VBD_OK;
+}
+
+vbd_status vbd_probe_read(const void *src, size_t n_bytes, float *partials, int32_t n_blocks,
+                          void *stream)
+{
+    if (!src || !partials || n_bytes % 16 || n_blocks < 1 || n_blocks > 65535)
+        return fail(VBD_E_INVALID_ARG, "bad read-probe arguments");
+    HIP_TRY(launch_read4((const float4 *)src, (long long)(n_bytes / 16), partials, n_blocks,
+                         (hipStream_t)stream));
     return VBD_OK;
 }
 

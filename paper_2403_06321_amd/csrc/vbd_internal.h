@@ -170,6 +170,9 @@ hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters,
                              bool springs, const LaunchCfg &cfg, int n_cu, bool cooperative,
                              hipStream_t s, int *grid_out);
 hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s);
+// Read-only streaming probe: `blocks` blocks of 256 threads sum src[0..n) and
+// write one partial sum per block into out[0..blocks).
+hipError_t launch_read4(const float4 *src, long long n, float *out, int blocks, hipStream_t s);
 hipError_t launch_zero_u32(unsigned *p, long long n, hipStream_t s);
 // Non-finite values among a[0..n) and b[0..n) into the flag counters.
 hipError_t launch_check_finite(const float *a, const float *b, long long n, unsigned *flags,

@@ -664,6 +664,35 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
 }
 
 // Streaming copy: each thread keeps four independent 16-B loads in flight.
+// Read-only streaming probe: every thread keeps 8 loads of 16 B in flight
+// (grid-stride), sums them, and its block writes one partial sum.
+__global__ __launch_bounds__(256) void k_read4(const float4 *src, long long n, float *out)
+{
+    __shared__ float part[256 / 64];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    float acc = 0.f;
+    for (; i + 7 * stride < n; i += 8 * stride) {
+        float4 r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = src[i + j * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += (r[j].x + r[j].y) + (r[j].z + r[j].w);
+    }
+    for (; i < n; i += stride) {
+        const float4 r = src[i];
+        acc += (r.x + r.y) + (r.z + r.w);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
+        out[blockIdx.x] = s;
+    }
+}
+
 __global__ void k_copy4(float4 *dst, const float4 *src, int n)
 {
     const int stride = gridDim.x * blockDim.x;
@@ -1272,6 +1301,13 @@ hipError_t launch_persistent(const DevTopo &T, const StepConsts &K, int n_iters,
     case 32: return persistent_unroll<32>(T, K, n_iters, tets, springs, cfg, n_cu, coop, s, grid_out);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_read4(const float4 *src, long long n, float *out, int blocks, hipStream_t s)
+{
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_read4, dim3(blocks), dim3(256), 0, s, src, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy4(float4 *dst, const float4 *src, int n, hipStream_t s)

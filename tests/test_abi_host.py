@@ -207,6 +207,26 @@ def test_phase_bytes_model():
         assert pb[c] <= 36 * pairs + 48 * nvc + 16 * w.n_verts
 
 
+def test_phase_counts_and_adjoint_bytes_model():
+    """Per color: tet pairs, spring entries, distinct neighbours (brute force
+    over the tets) and free vertices; the reverse phase's bytes follow them."""
+    w = W.tet_cube(5, 0)
+    t = Topology.from_workload(w, bind=False)
+    q = t.query(N.Q_PHASE_COUNTS).reshape(-1, 4)
+    ab = t.query(N.Q_ADJ_PHASE_BYTES)
+    colors = t.query(N.Q_COLORS)
+    free = w.pinned == 0
+    for c in range(t.n_colors):
+        verts = np.flatnonzero((colors == c) & free)
+        inc = [tt for tt in w.tets if np.any(np.isin(tt, verts))]
+        nbrs = set()
+        for tt in inc:
+            nbrs.update(int(u) for u in tt if u not in set(verts.tolist()))
+        assert q[c, 0] == len(inc) and q[c, 1] == 0 and q[c, 3] == len(verts)
+        assert q[c, 2] == len(nbrs)
+        assert ab[c] == 144 * q[c, 0] + 96 * q[c, 3] + 16 * q[c, 2]
+
+
 def test_phase_bytes_follow_the_record_layout():
     """Compact pair records are 32 B, full ones 36 B; nothing else changes."""
     w = W.tet_cube(4, 0)
