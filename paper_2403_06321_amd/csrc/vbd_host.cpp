@@ -55,7 +55,7 @@ struct Layout {
     size_t vol, tet_perm, tet_row, tet_ent, ell, pa, pw, pb, pws, pair_tet, ell_info, spr_ell,
         spr_info, perm, mass, color_off;
     size_t x, xt, y, prev1, prev2, collided, flags;
-    size_t snaps, xbar, ybar, xtbar, vbar, contrib, ebar;
+    size_t snaps, xbar, ybar, xtbar, vbar, contrib, cin, tgt, ebar_pair, tet_pairs;
     // mesh-mesh contacts (only when the topology has a surface)
     size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam, s_gmax;
     size_t s_hcount, s_hstart, s_scan, s_hitems, s_tsph, s_ctri, s_ccount, s_crow, s_cent, s_xsnap;
@@ -174,12 +174,12 @@ void update_phase_bytes(vbd_topology_s &T)
         const auto &n = T.phase_cnt[c];
         T.phase_bytes[c] = rec * (double)n[0] + 8.0 * (double)n[1] + 48.0 * (double)T.phase_updates[c] +
                            16.0 * (double)n[2];
-        // reverse phase: per tet pair the 16-B (tet, slot, others) entry, the
-        // 16-B E-free record, V lam (4 B), the tet's four 12-B contribution
-        // cells read and written, its volume, and its Ebar read and written;
-        // per vertex its snapshot, xbar and ybar read and written and y read
+        // reverse phase: per tet pair the 16-B pair record, the 16-B E-free
+        // record, the 12-B targets, its three 12-B incoming cells read, three
+        // 12-B outgoing cells written and its Ebar share read and written; per
+        // vertex its snapshot, xbar and ybar read and written and y read
         // (96 B); 16 B per distinct neighbour position
-        T.adj_phase_bytes[c] = (16.0 + 16.0 + 4.0 + 96.0 + 4.0 + 8.0) * (double)n[0] +
+        T.adj_phase_bytes[c] = (16.0 + 16.0 + 12.0 + 36.0 + 36.0 + 8.0) * (double)n[0] +
                                96.0 * (double)T.phase_updates[c] + 16.0 * (double)n[2];
     }
 }
@@ -222,7 +222,10 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.xtbar = take(sizeof(float4) * nv);
         L.vbar = take(sizeof(float4) * nv);
         L.contrib = take(sizeof(float3) * 4 * (size_t)T.nt);
-        L.ebar = take(sizeof(float) * (size_t)T.nt);
+        L.cin = take(sizeof(float3) * 3 * T.ell_total);
+        L.tgt = take(sizeof(int3) * T.ell_total);
+        L.ebar_pair = take(sizeof(float) * T.ell_total);
+        L.tet_pairs = take(sizeof(int4) * (size_t)T.nt);
     }
     const size_t ntri = T.surf.size() / 3, nsv = T.sv_slot.size();
     if (ntri > 0) {
@@ -290,7 +293,10 @@ void set_dev_pointers(vbd_topology_s &T)
     D.xtbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xtbar) : nullptr;
     D.vbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.vbar) : nullptr;
     D.contrib = L.max_bwd_iters > 0 ? (float3 *)(b + L.contrib) : nullptr;
-    D.ebar = L.max_bwd_iters > 0 ? (float *)(b + L.ebar) : nullptr;
+    D.cin = L.max_bwd_iters > 0 ? (float3 *)(b + L.cin) : nullptr;
+    D.tgt = L.max_bwd_iters > 0 ? (const int3 *)(b + L.tgt) : nullptr;
+    D.ebar_pair = L.max_bwd_iters > 0 ? (float *)(b + L.ebar_pair) : nullptr;
+    D.tet_pairs = L.max_bwd_iters > 0 ? (const int4 *)(b + L.tet_pairs) : nullptr;
     D.n_verts = T.nv;
     D.n_tets = T.nt;
     D.n_free = T.n_free;
@@ -1030,7 +1036,8 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
     if (T.nt > 0) {
         HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 12 * (long long)T.nt, s));
-        HIP_TRY(launch_zero_u32((unsigned *)D.ebar, T.nt, s));
+        HIP_TRY(launch_zero_u32((unsigned *)D.cin, 9 * (long long)T.ell_total, s));
+        HIP_TRY(launch_zero_u32((unsigned *)D.ebar_pair, (long long)T.ell_total, s));
     }
     // profiling: one event pair around the reverse sweep's adjoint launches
     ProfileEvent ev{};
@@ -1283,6 +1290,8 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         const size_t snap = sizeof(float4) * (size_t)T->nv;
         if (bytes >= L1.total) nb = 2 + (int)std::min<size_t>((bytes - L1.total) / (snap ? snap : 1), 1 << 20);
         while (nb > 0 && make_layout(*T, nb).total > bytes) --nb;
+        // the reverse sweep addresses cells by (entry << 2) | index
+        if (T->ell_total >= ((size_t)1 << 29)) nb = 0;
     }
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
@@ -1383,6 +1392,43 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         HIP_TRY(up(T->lay.pb, pb.data(), sizeof(float) * pb.size()));
         HIP_TRY(up(T->lay.pair_tet, ptet.data(), 4 * ptet.size()));
         HIP_TRY(up(T->lay.ell_info, T->ell_info.data(), sizeof(int2) * T->ell_info.size()));
+        if (T->lay.max_bwd_iters > 0) {
+            // the reverse sweep's contribution cells, addressed by the pair of
+            // the receiving vertex: pos_of[t*4 + k] = padded entry of (slot k's
+            // vertex, t) or -1 for a pinned vertex
+            std::vector<int32_t> pos_of(4 * (size_t)T->nt, -1);
+            for (int c = 0; c < T->n_colors; ++c) {
+                const int2 info = T->ell_info[c];
+                for (int sl = T->color_off[c]; sl < T->color_off[c + 1]; ++sl) {
+                    const size_t base = (size_t)info.x + (size_t)(sl - T->color_off[c]) * (size_t)info.y;
+                    for (int e = T->tet_row[sl]; e < T->tet_row[sl + 1]; ++e)
+                        pos_of[T->tet_ent[e]] = (int32_t)(base + (size_t)(e - T->tet_row[sl]));
+                }
+            }
+            // per pair (slot k of tet t) and each other slot q in ascending
+            // order: (entry of (q, t) << 2) | index of k among q's other slots,
+            // or -1 - (stored tet * 4 + q) when q's vertex is pinned
+            std::vector<int3> tgt(T->ell_total, make_int3(0, 0, 0));
+            for (int t = 0; t < T->nt; ++t)
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t e = pos_of[4 * (size_t)t + k];
+                    if (e < 0) continue;
+                    int32_t o[3], n = 0;
+                    for (int q = 0; q < 4; ++q) {
+                        if (q == k) continue;
+                        const int32_t eq = pos_of[4 * (size_t)t + q];
+                        o[n++] = eq >= 0 ? (eq << 2) | (k < q ? k : k - 1) : -1 - (T->tet_rank[t] * 4 + q);
+                    }
+                    tgt[e] = make_int3(o[0], o[1], o[2]);
+                }
+            std::vector<int4> tpairs(T->nt);
+            for (int t = 0; t < T->nt; ++t) {
+                const int32_t *q = &pos_of[4 * (size_t)t];
+                tpairs[T->tet_rank[t]] = make_int4(q[0], q[1], q[2], q[3]);
+            }
+            HIP_TRY(up(T->lay.tgt, tgt.data(), sizeof(int3) * tgt.size()));
+            HIP_TRY(up(T->lay.tet_pairs, tpairs.data(), sizeof(int4) * tpairs.size()));
+        }
     }
     HIP_TRY(up(T->lay.spr_ell, spr.data(), sizeof(int2) * spr.size()));
     HIP_TRY(up(T->lay.spr_info, T->spr_info.data(), sizeof(int2) * T->spr_info.size()));

@@ -94,8 +94,17 @@ struct DevTopo {
     unsigned *flags;                   // see kFlag* above
     float4 *snaps;                     // backward: (n_iters + 1) iterates
     float4 *xbar, *ybar, *xtbar, *vbar;
-    float3 *contrib;                   // backward: [n_tets][4] pending neighbour adjoints (12 B)
-    float *ebar;                       // backward: [n_tets] Ebar of this step, stored order
+    float3 *contrib;                   // backward: [n_tets][4] pending adjoints of pinned
+                                       // vertices (12 B), by (stored tet, slot)
+    // backward, per padded pair entry of a receiving vertex: its three incoming
+    // contribution cells (cin + j * n_pairs holds the one from the j-th other
+    // vertex of the tet in slot order), the targets of its own outgoing
+    // contributions ((entry << 2) | j of each other slot in slot order, or
+    // -1 - (stored tet * 4 + slot) for a pinned vertex) and its share of Ebar
+    float3 *cin;
+    const int3 *tgt;
+    float *ebar_pair;
+    const int4 *tet_pairs;             // [n_tets] stored order: entry of each slot or -1
     int n_verts, n_tets, n_free, n_colors;
 };
 
@@ -185,7 +194,7 @@ hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const flo
                                 const float4 *Sp, int v_begin, int v_end, int2 ell,
                                 const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s);
-// Also adds T.ebar into g_tet_E (caller's tet order).
+// Also adds the per-pair Ebar shares into g_tet_E (caller's tet order).
 hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev,
                             float *gx_in, float *gv_in, float *gvp_in, float *g_tet_E,
                             const StepConsts &K, hipStream_t s);

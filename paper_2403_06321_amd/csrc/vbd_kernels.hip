@@ -759,11 +759,17 @@ __global__ void k_bwd_init(DevTopo T, const float *gx, const float *gv, const fl
 //   c_q = dJ/dx_q = sigma {e2 x e3, e3 x e1, e1 x e2},
 //   g_q = d(n . w)/dx_q = sigma {w x (x_c - x_b), (x_c - x_a) x w, w x (x_b - x_a)}.
 // H_i = V mu |m|^2 I + V lam n n^T as in the forward solve (|m|^2 = -(w0 + w1 + w2)).
-// Neighbour adjoints go to per-(tet, slot) cells instead of the neighbours
-// themselves: in a color phase a tet has at most one vertex of that color, so
-// its cells are written by one thread only (no atomics, deterministic).  A
-// vertex folds (reads and clears) its own cells when its color is processed,
-// and k_bwd_fold folds what is left at the end of the sweep.
+// Neighbour adjoints travel through cells addressed by the receiving
+// vertex's pair entry (DevTopo::cin): in a color phase a tet has at most one
+// vertex of that color, so each cell has one writer per phase, and between
+// two phases of a vertex every other color runs exactly once, so each of its
+// three incoming cells per tet holds the latest contribution of its writer
+// (all cells start at zero, which covers the colors not yet run in the first
+// reverse iteration).  Writes only, no read-modify-write, and the receiver
+// reads its cells with its own entries.  Pinned vertices are never updated:
+// their contributions accumulate per (tet, slot) in DevTopo::contrib.  At the
+// end of the sweep k_bwd_fold adds the cells written after each vertex's
+// last update.  Ebar accumulates per pair entry (DevTopo::ebar_pair).
 // Position of a neighbour q in the state right after the update of the
 // phase's vertex: colors <= c (slots < c_end) from iteration n, the others
 // from iteration n - 1.
@@ -815,139 +821,70 @@ __device__ __forceinline__ float adj_pair(float3 xi, float4 qa, float4 qb, float
     return K.k_mu * wF - K.k_lam * (J - K.alpha) * nw;
 }
 
-// The entries come from the same per-color padded incidence as the forward
-// solve (the (tet, slot) entries for the cells, the pair records for
-// the frame quantities); each lane handles KU entries at a time with their
-// loads issued together (records, neighbour positions and contribution cells).
-template <int L, int KU>
-__global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K,
-                                                             const float4 *Sn, const float4 *Sp,
-                                                             int v_begin, int v_end, int2 ell,
-                                                             int remap)
+// Sends one outgoing contribution (see DevTopo::tgt): into the receiving
+// entry's cell, or added to a pinned vertex's (tet, slot) cell.
+__device__ __forceinline__ void adj_send(const DevTopo &T, int tg, float3 c)
 {
-    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int gid = b * blockDim.x + threadIdx.x;
-    const int p = v_begin + gid / L;
-    const int lane = threadIdx.x & (L - 1);
-    const bool active = p < v_end;
-    const int c_end = v_end;   // permuted slots < c_end have color <= c
-    const int D = active ? ell.y : 0;
-    const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
-    const PairEnt *E = T.ell + e0;
-    const float mu_lam = K.k_mu / K.k_lam;
-    Acc a;
-    acc_zero(a);
-    float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
-    float wm = 0.f;
-    if (active) {
-        own = Sn[p];
-        xb4 = T.xbar[p];
-        wm = T.y[p].w;
-    }
-    const float3 xi = xyz(own);
-    // pass 1: H_i at the post-update state, and this vertex's pending cells
-    for (int base = lane; base < D; base += L * KU) {
-        PairEnt ent[KU];
-#pragma unroll
-        for (int j = 0; j < KU; ++j) {
-            const int e = base + j * L;
-            ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
-        }
-        float4 qa[KU], qb[KU], qc[KU];
-        float3 g[KU];
-        float hmu[KU], vlam[KU], sig[KU];
-#pragma unroll
-        for (int j = 0; j < KU; ++j)
-            if (ent[j].x >= 0) {
-                const size_t e = e0 + base + j * L;
-                const float4 ws = T.pws[e];
-                vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e)[3]);
-                hmu[j] = -(ws.x + ws.y + ws.z) * (vlam[j] * mu_lam);
-                sig[j] = ws.w;
-                qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
-                qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
-                qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
-                g[j] = T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)];
-            }
-#pragma unroll
-        for (int j = 0; j < KU; ++j)
-            if (ent[j].x >= 0) {
-                adj_hess(qa[j], qb[j], qc[j], hmu[j], vlam[j], sig[j], a);
-                a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
-                T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float3(0.f, 0.f, 0.f);
-            }
-    }
-    acc_reduce<L>(a);
-    if (!active) return;
-    a.hxx += wm; a.hyy += wm; a.hzz += wm;
-    a.fx += xb4.x; a.fy += xb4.y; a.fz += xb4.z;
-    float3 w;
-    if (!solve_sym3(a, K.det_eps_rel, w)) {
-        // skipped update: the adjoint passes through (with the folded cells)
-        if (lane == 0) T.xbar[p] = make_float4(a.fx, a.fy, a.fz, 0.f);
-        return;
-    }
-    if (lane == 0) {
-        T.xbar[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 yb = T.ybar[p];
-        yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
-        T.ybar[p] = yb;
-    }
-    // pass 2: -d(w . grad_i Psi)/dx_q into the cells of the other three slots,
-    // and Ebar (in stored tet order; k_bwd_final scatters it to the caller's
-    // order).  All loads of KU entries, their cells included, are issued
-    // before the stores, which would otherwise order every cell's read after
-    // the previous cell's write.
-    for (int base = lane; base < D; base += L * KU) {
-        PairEnt ent[KU];
-#pragma unroll
-        for (int j = 0; j < KU; ++j) {
-            const int e = base + j * L;
-            ent[j] = (e < D) ? E[e] : make_int4(-1, 0, 0, 0);
-        }
-        float4 qa[KU], qb[KU], qc[KU], ws[KU];
-        float3 c0[KU], c1[KU], c2[KU];
-        float vol[KU], eb[KU], vlam[KU], sig[KU];
-#pragma unroll
-        for (int j = 0; j < KU; ++j)
-            if (ent[j].x >= 0) {
-                const int t = ent[j].x >> 2, k = ent[j].x & 3;
-                const size_t e = e0 + base + j * L;
-                ws[j] = T.pws[e];
-                vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e)[3]);
-                sig[j] = ws[j].w;
-                qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
-                qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
-                qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
-                vol[j] = T.vol[t];
-                eb[j] = T.ebar[t];
-                // the cells of the other slots in ascending slot order
-                const float3 *cell = T.contrib + 4 * (size_t)t;
-                c0[j] = cell[k == 0 ? 1 : 0];
-                c1[j] = cell[k <= 1 ? 2 : 1];
-                c2[j] = cell[k <= 2 ? 3 : 2];
-            }
-#pragma unroll
-        for (int j = 0; j < KU; ++j)
-            if (ent[j].x >= 0) {
-                const int t = ent[j].x >> 2, k = ent[j].x & 3;
-                const float r = adj_pair(xi, qa[j], qb[j], qc[j], ws[j], vlam[j], sig[j], w, mu_lam, K,
-                                         c0[j], c1[j], c2[j]);
-                float3 *cell = T.contrib + 4 * (size_t)t;
-                cell[k == 0 ? 1 : 0] = c0[j];
-                cell[k <= 1 ? 2 : 1] = c1[j];
-                cell[k <= 2 ? 3 : 2] = c2[j];
-                T.ebar[t] = eb[j] - vol[j] * r;
-            }
+    if (tg >= 0) {
+        T.cin[(size_t)(tg & 3) * (size_t)T.n_pairs + (size_t)(tg >> 2)] = c;
+    } else {
+        float3 *cell = T.contrib + (size_t)(-1 - tg);
+        const float3 o = *cell;
+        *cell = make_float3(o.x + c.x, o.y + c.y, o.z + c.z);
     }
 }
 
-// Single-batch form of k_adjoint_color for D <= L * KU: every load of the
-// phase's vertex (its entries and pair records, then the neighbour positions,
-// all four cells of each tet, volumes and Ebar) is issued before any
-// arithmetic, so a vertex costs two dependent memory round trips instead of
-// four.  A tet has one vertex of the phase's color, so no other thread
-// touches its cells or its Ebar during the phase.
+// One entry's loads: pair record (other vertices, V lam), the E-free record
+// (w, sigma; sigma = 0 marks padding), targets, incoming cells, Ebar share.
+struct AdjEnt {
+    int4 pa;
+    float4 ws;
+    int3 tg;
+    float3 g0, g1, g2;
+    float eb;
+};
+
+__device__ __forceinline__ void adj_load(const DevTopo &T, size_t e, AdjEnt &r)
+{
+    const size_t np = (size_t)T.n_pairs;
+    r.pa = T.pa[e];
+    r.ws = T.pws[e];
+    r.tg = T.tgt[e];
+    r.g0 = T.cin[e];
+    r.g1 = T.cin[np + e];
+    r.g2 = T.cin[2 * np + e];
+    r.eb = T.ebar_pair[e];
+}
+
+// The second pass on one entry: outgoing contributions and the Ebar share
+// (V = 1 / (6 |sigma|): sigma = det S = 1 / det D_m' with D_m' = Q R, Q proper).
+__device__ __forceinline__ void adj_emit(const DevTopo &T, const StepConsts &K, size_t e,
+                                         const AdjEnt &r, float3 xi, float4 qa, float4 qb, float4 qc,
+                                         float3 w, float mu_lam)
+{
+    float3 c0 = make_float3(0.f, 0.f, 0.f), c1 = c0, c2 = c0;
+    const float vlam = __int_as_float(r.pa.w);
+    const float sg = r.ws.w;
+    const float rr = adj_pair(xi, qa, qb, qc, r.ws, vlam, sg, w, mu_lam, K, c0, c1, c2);
+    adj_send(T, r.tg.x, c0);
+    adj_send(T, r.tg.y, c1);
+    adj_send(T, r.tg.z, c2);
+    T.ebar_pair[e] = r.eb - rr / (6.f * fabsf(sg));
+}
+
+// A skipped update sends nothing: its receivers' cells are cleared.
+__device__ __forceinline__ void adj_clear(const DevTopo &T, const AdjEnt &r)
+{
+    const float3 z = make_float3(0.f, 0.f, 0.f);
+    if (r.tg.x >= 0) adj_send(T, r.tg.x, z);
+    if (r.tg.y >= 0) adj_send(T, r.tg.y, z);
+    if (r.tg.z >= 0) adj_send(T, r.tg.z, z);
+}
+
+// Reverse of one color phase, every entry of the vertex in registers
+// (D <= L * KU): all loads of the phase's vertex are issued before any
+// arithmetic (two dependent memory round trips: the entries, then the
+// neighbour positions).
 template <int L, int KU>
 __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts K,
                                                            const float4 *Sn, const float4 *Sp,
@@ -963,22 +900,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
     const int D = active ? ell.y : 0;
     const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
     const float mu_lam = K.k_mu / K.k_lam;
-    PairEnt ent[KU];
-    float4 ws[KU];
-    float hmu[KU], vlam[KU], sig[KU];
+    AdjEnt r[KU];
+    bool ok[KU];
 #pragma unroll
     for (int j = 0; j < KU; ++j) {
         const int e = lane + j * L;
-        if (e < D) {
-            ent[j] = T.ell[e0 + e];
-            ws[j] = T.pws[e0 + e];
-            vlam[j] = __int_as_float(reinterpret_cast<const int *>(T.pa + e0 + e)[3]);
-            // V mu |m|^2 = -V lam (k_mu / k_lam) (w0 + w1 + w2)
-            hmu[j] = -(ws[j].x + ws[j].y + ws[j].z) * (vlam[j] * mu_lam);
-            sig[j] = ws[j].w;
-        } else {
-            ent[j] = make_int4(-1, 0, 0, 0);
-        }
+        ok[j] = e < D;
+        if (ok[j]) adj_load(T, e0 + e, r[j]);
     }
     float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
     float wm = 0.f;
@@ -988,32 +916,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
         wm = T.y[p].w;
     }
     float4 qa[KU], qb[KU], qc[KU];
-    float3 g[KU], c0[KU], c1[KU], c2[KU];
-    float vol[KU], eb[KU];
 #pragma unroll
-    for (int j = 0; j < KU; ++j)
-        if (ent[j].x >= 0) {
-            const int t = ent[j].x >> 2, k = ent[j].x & 3;
-            qa[j] = adj_pos(Sn, Sp, ent[j].y, c_end);
-            qb[j] = adj_pos(Sn, Sp, ent[j].z, c_end);
-            qc[j] = adj_pos(Sn, Sp, ent[j].w, c_end);
-            const float3 *cell = T.contrib + 4 * (size_t)t;
-            g[j] = cell[k];
-            c0[j] = cell[k == 0 ? 1 : 0];
-            c1[j] = cell[k <= 1 ? 2 : 1];
-            c2[j] = cell[k <= 2 ? 3 : 2];
-            vol[j] = T.vol[t];
-            eb[j] = T.ebar[t];
+    for (int j = 0; j < KU; ++j) {
+        ok[j] = ok[j] && r[j].ws.w != 0.f;
+        if (ok[j]) {
+            qa[j] = adj_pos(Sn, Sp, r[j].pa.x, c_end);
+            qb[j] = adj_pos(Sn, Sp, r[j].pa.y, c_end);
+            qc[j] = adj_pos(Sn, Sp, r[j].pa.z, c_end);
         }
-    // pass 1: H_i at the post-update state; this vertex's pending cells fold in
+    }
+    // pass 1: H_i at the post-update state; the incoming cells fold in
     Acc a;
     acc_zero(a);
 #pragma unroll
     for (int j = 0; j < KU; ++j)
-        if (ent[j].x >= 0) {
-            adj_hess(qa[j], qb[j], qc[j], hmu[j], vlam[j], sig[j], a);
-            a.fx += g[j].x; a.fy += g[j].y; a.fz += g[j].z;
-            T.contrib[4 * (size_t)(ent[j].x >> 2) + (ent[j].x & 3)] = make_float3(0.f, 0.f, 0.f);
+        if (ok[j]) {
+            const float vlam = __int_as_float(r[j].pa.w);
+            const float hmu = -(r[j].ws.x + r[j].ws.y + r[j].ws.z) * (vlam * mu_lam);
+            adj_hess(qa[j], qb[j], qc[j], hmu, vlam, r[j].ws.w, a);
+            a.fx += r[j].g0.x + r[j].g1.x + r[j].g2.x;
+            a.fy += r[j].g0.y + r[j].g1.y + r[j].g2.y;
+            a.fz += r[j].g0.z + r[j].g1.z + r[j].g2.z;
         }
     acc_reduce<L>(a);
     if (!active) return;
@@ -1021,7 +944,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
     a.fx += xb4.x; a.fy += xb4.y; a.fz += xb4.z;
     float3 w;
     if (!solve_sym3(a, K.det_eps_rel, w)) {
+        // skipped update: the adjoint passes through (with the incoming cells)
         if (lane == 0) T.xbar[p] = make_float4(a.fx, a.fy, a.fz, 0.f);
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ok[j]) adj_clear(T, r[j]);
         return;
     }
     if (lane == 0) {
@@ -1034,29 +961,133 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_one(DevTopo T, StepConsts
     const float3 xi = xyz(own);
 #pragma unroll
     for (int j = 0; j < KU; ++j)
-        if (ent[j].x >= 0) {
-            const int t = ent[j].x >> 2, k = ent[j].x & 3;
-            const float r = adj_pair(xi, qa[j], qb[j], qc[j], ws[j], vlam[j], sig[j], w, mu_lam, K, c0[j],
-                                     c1[j], c2[j]);
-            float3 *cell = T.contrib + 4 * (size_t)t;
-            cell[k == 0 ? 1 : 0] = c0[j];
-            cell[k <= 1 ? 2 : 1] = c1[j];
-            cell[k <= 2 ? 3 : 2] = c2[j];
-            T.ebar[t] = eb[j] - vol[j] * r;
-        }
+        if (ok[j]) adj_emit(T, K, e0 + lane + j * L, r[j], xi, qa[j], qb[j], qc[j], w, mu_lam);
 }
 
-// End of the reverse sweep: every vertex (pinned ones included) folds the
-// cells of its incident tets into its adjoint.
+// The general form for any padded degree: the vertex's entries in batches of
+// L * KU, loaded again in the second pass.
+template <int L, int KU>
+__global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepConsts K,
+                                                             const float4 *Sn, const float4 *Sp,
+                                                             int v_begin, int v_end, int2 ell,
+                                                             int remap)
+{
+    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int gid = b * blockDim.x + threadIdx.x;
+    const int p = v_begin + gid / L;
+    const int lane = threadIdx.x & (L - 1);
+    const bool active = p < v_end;
+    const int c_end = v_end;
+    const int D = active ? ell.y : 0;
+    const size_t e0 = (size_t)ell.x + (size_t)(active ? p - v_begin : 0) * ell.y;
+    const float mu_lam = K.k_mu / K.k_lam;
+    Acc a;
+    acc_zero(a);
+    float4 own = make_float4(0.f, 0.f, 0.f, 0.f), xb4 = own;
+    float wm = 0.f;
+    if (active) {
+        own = Sn[p];
+        xb4 = T.xbar[p];
+        wm = T.y[p].w;
+    }
+    for (int base = lane; base < D; base += L * KU) {
+        AdjEnt r[KU];
+        bool ok[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j) {
+            const int e = base + j * L;
+            ok[j] = e < D;
+            if (ok[j]) adj_load(T, e0 + e, r[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ok[j] && r[j].ws.w != 0.f) {
+                const float4 qa = adj_pos(Sn, Sp, r[j].pa.x, c_end);
+                const float4 qb = adj_pos(Sn, Sp, r[j].pa.y, c_end);
+                const float4 qc = adj_pos(Sn, Sp, r[j].pa.z, c_end);
+                const float vlam = __int_as_float(r[j].pa.w);
+                const float hmu = -(r[j].ws.x + r[j].ws.y + r[j].ws.z) * (vlam * mu_lam);
+                adj_hess(qa, qb, qc, hmu, vlam, r[j].ws.w, a);
+                a.fx += r[j].g0.x + r[j].g1.x + r[j].g2.x;
+                a.fy += r[j].g0.y + r[j].g1.y + r[j].g2.y;
+                a.fz += r[j].g0.z + r[j].g1.z + r[j].g2.z;
+            }
+    }
+    acc_reduce<L>(a);
+    if (!active) return;
+    a.hxx += wm; a.hyy += wm; a.hzz += wm;
+    a.fx += xb4.x; a.fy += xb4.y; a.fz += xb4.z;
+    float3 w;
+    const bool solved = solve_sym3(a, K.det_eps_rel, w);
+    if (lane == 0) {
+        if (!solved) {
+            T.xbar[p] = make_float4(a.fx, a.fy, a.fz, 0.f);
+        } else {
+            T.xbar[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 yb = T.ybar[p];
+            yb.x += wm * w.x; yb.y += wm * w.y; yb.z += wm * w.z;
+            T.ybar[p] = yb;
+        }
+    }
+    const float3 xi = xyz(own);
+    for (int base = lane; base < D; base += L * KU) {
+        AdjEnt r[KU];
+        bool ok[KU];
+#pragma unroll
+        for (int j = 0; j < KU; ++j) {
+            const int e = base + j * L;
+            ok[j] = e < D;
+            if (ok[j]) adj_load(T, e0 + e, r[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+            if (ok[j] && r[j].ws.w != 0.f) {
+                if (!solved) {
+                    adj_clear(T, r[j]);
+                    continue;
+                }
+                const float4 qa = adj_pos(Sn, Sp, r[j].pa.x, c_end);
+                const float4 qb = adj_pos(Sn, Sp, r[j].pa.y, c_end);
+                const float4 qc = adj_pos(Sn, Sp, r[j].pa.z, c_end);
+                adj_emit(T, K, e0 + base + j * L, r[j], xi, qa, qb, qc, w, mu_lam);
+            }
+    }
+}
+
+// End of the reverse sweep: each vertex adds the contributions written after
+// its last update: a free vertex the incoming cells from colors below its own
+// (its entries' other vertices with smaller slots), a pinned vertex all of
+// its (tet, slot) cells.
 __global__ void k_bwd_fold(DevTopo T)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= T.n_verts) return;
     float4 xb = T.xbar[p];
-    for (int e = T.tet_row[p]; e < T.tet_row[p + 1]; ++e) {
-        const int ent = T.tet_ent[e].x;
-        const float3 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
-        xb.x += g.x; xb.y += g.y; xb.z += g.z;
+    if (p < T.n_free) {
+        int c = 0;
+        while (c + 1 < T.n_colors && T.color_off[c + 1] <= p) ++c;
+        const int lo = T.color_off[c];
+        const int2 info = T.ell_info[c];
+        const size_t e0 = (size_t)info.x + (size_t)(p - lo) * (size_t)info.y;
+        const size_t np = (size_t)T.n_pairs;
+        for (int e = 0; e < info.y; ++e) {
+            const size_t i = e0 + e;
+            if (T.pws[i].w == 0.f) continue;   // padding
+            const int4 pa = T.pa[i];
+            const int src[3] = {pa.x, pa.y, pa.z};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                if (src[j] < lo) {
+                    const float3 g = T.cin[(size_t)j * np + i];
+                    xb.x += g.x; xb.y += g.y; xb.z += g.z;
+                }
+        }
+    } else {
+        for (int e = T.tet_row[p]; e < T.tet_row[p + 1]; ++e) {
+            const int ent = T.tet_ent[e].x;
+            const float3 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
+            xb.x += g.x; xb.y += g.y; xb.z += g.z;
+        }
     }
     T.xbar[p] = xb;
 }
@@ -1066,8 +1097,16 @@ __global__ void k_bwd_final(DevTopo T, const float *v_t, const float *v_prev, fl
                             float *gv_in, float *gvp_in, float *gE, StepConsts K)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    // Ebar, accumulated in stored tet order, added into the caller's order
-    for (int t = p; t < T.n_tets; t += gridDim.x * blockDim.x) gE[T.tet_perm[t]] += T.ebar[t];
+    // Ebar: the shares of the tet's free vertices, added into the caller's order
+    for (int t = p; t < T.n_tets; t += gridDim.x * blockDim.x) {
+        const int4 q = T.tet_pairs[t];
+        float eb = 0.f;
+        if (q.x >= 0) eb += T.ebar_pair[q.x];
+        if (q.y >= 0) eb += T.ebar_pair[q.y];
+        if (q.z >= 0) eb += T.ebar_pair[q.z];
+        if (q.w >= 0) eb += T.ebar_pair[q.w];
+        gE[T.tet_perm[t]] += eb;
+    }
     if (p >= T.n_verts) return;
     const int o = T.perm[p];
     const float3 xb = xyz(T.xbar[p]);
@@ -1367,12 +1406,17 @@ hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const flo
 {
     if (ve <= vb) return hipSuccess;
     // at least 16 lanes per vertex: a phase has few vertices on small meshes
-    // and the reverse work per vertex is about three times the forward's
+    // and the reverse work per vertex is about three times the forward's; one
+    // entry per lane when the padded degree allows (measured faster on the
+    // 33^3 cube, degree 24, than 16 lanes with two entries each)
     switch (cfg.lanes) {
     case 2:
     case 4:
     case 8:
-    case 16: adjoint_go<16>(T, K, Sn, Sp, vb, ve, ell, cfg, s); break;
+    case 16:
+        if (ell.y > 16) adjoint_go<32>(T, K, Sn, Sp, vb, ve, ell, cfg, s);
+        else adjoint_go<16>(T, K, Sn, Sp, vb, ve, ell, cfg, s);
+        break;
     case 32: adjoint_go<32>(T, K, Sn, Sp, vb, ve, ell, cfg, s); break;
     default: return hipErrorInvalidValue;
     }

@@ -224,7 +224,7 @@ def test_phase_counts_and_adjoint_bytes_model():
             nbrs.update(int(u) for u in tt if u not in set(verts.tolist()))
         assert q[c, 0] == len(inc) and q[c, 1] == 0 and q[c, 3] == len(verts)
         assert q[c, 2] == len(nbrs)
-        assert ab[c] == 144 * q[c, 0] + 96 * q[c, 3] + 16 * q[c, 2]
+        assert ab[c] == 124 * q[c, 0] + 96 * q[c, 3] + 16 * q[c, 2]
 
 
 def test_phase_bytes_follow_the_record_layout():
