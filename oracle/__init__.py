@@ -58,6 +58,12 @@ def lib():
         L.oracle_closest_point_triangle.argtypes = [p, p, p, p, p, p]
         L.oracle_detect_contacts.argtypes = [p, p, p, p]
         L.oracle_winding_number.argtypes = [p, C.c_int32, p, p]
+        L.oracle_segment_closest.argtypes = [p, p, p, p, p, p]
+        L.oracle_segment_closest.restype = d
+        L.oracle_detect_edges.argtypes = [p, p, p, p, i32, p, p]
+        L.oracle_detect_edges.restype = i32
+        L.oracle_edge_element.argtypes = [p, p, d, d, p]
+        L.oracle_edge_element.restype = d
         L.oracle_winding_number.restype = C.c_double
         _lib = L
     return _lib
@@ -73,7 +79,8 @@ class _Model(C.Structure):
                 ("Dminv", C.c_void_p), ("vol", C.c_void_p), ("spring_rest", C.c_void_p),
                 ("mass", C.c_void_p), ("pinned", C.c_void_p), ("colors", C.c_void_p),
                 ("nu", C.c_double), ("spring_k", C.c_double),
-                ("n_surf_tris", C.c_int32), ("surf_tris", C.c_void_p), ("vert_mesh", C.c_void_p)]
+                ("n_surf_tris", C.c_int32), ("surf_tris", C.c_void_p), ("vert_mesh", C.c_void_p),
+                ("rest_pos", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -85,7 +92,9 @@ class _Params(C.Structure):
                 ("kd", C.c_double), ("cheb_rho", C.c_double),
                 ("friction_mu", C.c_double), ("friction_eps_v", C.c_double),
                 ("spring_psd", C.c_int32), ("mesh_contacts", C.c_int32),
-                ("collision_radius", C.c_double), ("n_col", C.c_int32)]
+                ("collision_radius", C.c_double), ("n_col", C.c_int32),
+                ("self_contact", C.c_int32), ("self_exclusion", C.c_double),
+                ("edge_contacts", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -224,7 +233,7 @@ class Model:
                          _ptr(self.tets), _ptr(self.springs), _ptr(self.Dminv), _ptr(self.vol),
                          _ptr(self.spring_rest), _ptr(self.mass), _ptr(self.pinned),
                          _ptr(self.colors), self.nu, self.spring_k, self.surf_tris.shape[0],
-                         _ptr(self.surf_tris), _ptr(self.vert_mesh))
+                         _ptr(self.surf_tris), _ptr(self.vert_mesh), _ptr(self.rest))
 
     @classmethod
     def from_workload(cls, w):
@@ -252,7 +261,8 @@ def _params(p):
                 0 if pl is None else pl.shape[0], _ptr(pl), float(p.kd), float(p.cheb_rho),
                 float(p.friction_mu), float(p.friction_eps_v), int(bool(getattr(p, "spring_psd", False))),
                 int(bool(getattr(p, "mesh_contacts", False))), float(getattr(p, "collision_radius", 0.0)),
-                int(getattr(p, "n_col", 0)))
+                int(getattr(p, "n_col", 0)), int(bool(getattr(p, "self_contact", False))),
+                float(getattr(p, "self_exclusion", 0.0)), int(bool(getattr(p, "edge_contacts", False))))
     return s, (sph, pl)
 
 
@@ -297,6 +307,35 @@ def detect_contacts(model: Model, params, x):
     ps, keep = _params(params)
     lib().oracle_detect_contacts(C.byref(model._s), C.byref(ps), _ptr(x), _ptr(out))
     return out
+
+
+def segment_closest(p0, p1, q0, q1):
+    """(distance, s, u) of the closest points p0 + s (p1 - p0), q0 + u (q1 - q0)."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (p0, p1, q0, q1)]
+    s, u = C.c_double(), C.c_double()
+    dist = lib().oracle_segment_closest(*[_ptr(v) for v in a], C.byref(s), C.byref(u))
+    return dist, s.value, u.value
+
+
+def detect_edges(model: Model, params, x, xt=None):
+    """Edge-edge elements on positions x (normals from xt, default x):
+    int32 [n, 4] vertex ids (first edge, second edge) and float64 [n, 3] normals."""
+    x = np.ascontiguousarray(x, np.float64)
+    xt = x if xt is None else np.ascontiguousarray(xt, np.float64)
+    cap = 4 * max(1, model.surf_tris.shape[0])
+    ov = np.zeros((cap, 4), np.int32); on = np.zeros((cap, 3))
+    ps, keep = _params(params)
+    n = lib().oracle_detect_edges(C.byref(model._s), C.byref(ps), _ptr(x), _ptr(xt), cap, _ptr(ov), _ptr(on))
+    return ov[:n].copy(), on[:n].copy()
+
+
+def edge_element(x4, n, k, delta):
+    """(d, grad [4, 3]) of one edge-edge element at positions x4 [4, 3]."""
+    x4 = np.ascontiguousarray(x4, np.float64).reshape(12)
+    nn = np.ascontiguousarray(n, np.float64)
+    g = np.zeros(12)
+    d = lib().oracle_edge_element(_ptr(x4), _ptr(nn), float(k), float(delta), _ptr(g))
+    return d, g.reshape(4, 3)
 
 
 def winding_number(model: Model, mesh, p, x):

@@ -341,10 +341,139 @@ static void tri_normal_R(const R a[3], const R b[3], const R c[3], R n[3])
     for (int k = 0; k < 3; ++k) n[k] /= l;
 }
 
+/* Closest points of the segments p0 + s (p1 - p0) and q0 + u (q1 - q0),
+ * s, u in [0, 1]: the minimum of |p0 - q0 + s d1 - u d2|^2 over the unit
+ * square is its stationary point when that lies inside and the segments are
+ * not parallel, else it lies on one of the square's four sides, where the
+ * minimisation is one-dimensional (solve, then clamp to [0, 1]).  Every
+ * candidate is evaluated and the smallest distance wins (ties: the first in
+ * the order interior, s = 0, s = 1, u = 0, u = 1).  Decisions on real parts. */
+static double segment_closest_R(const R p0[3], const R p1[3], const R q0[3], const R q1[3], R *s_out,
+                                R *u_out)
+{
+    R d1[3], d2[3], r[3];
+    for (int k = 0; k < 3; ++k) { d1[k] = p1[k] - p0[k]; d2[k] = q1[k] - q0[k]; r[k] = p0[k] - q0[k]; }
+    R a = 0, b = 0, c = 0, d = 0, e = 0;
+    for (int k = 0; k < 3; ++k) {
+        a += d1[k] * d1[k]; b += d1[k] * d2[k]; c += d2[k] * d2[k];
+        d += d1[k] * r[k]; e += d2[k] * r[k];
+    }
+    R cs[5], cu[5];
+    int nc = 0;
+    const R den = a * c - b * b;
+    if (RE(den) > 1e-14 * RE(a) * RE(c)) {
+        const R s = (b * e - c * d) / den, u = (a * e - b * d) / den;
+        if (RE(s) >= 0.0 && RE(s) <= 1.0 && RE(u) >= 0.0 && RE(u) <= 1.0) { cs[nc] = s; cu[nc] = u; ++nc; }
+    }
+    for (int side = 0; side < 2; ++side) {       /* s fixed at 0 or 1 */
+        R u = (b * (double)side + e) / c;
+        if (RE(u) < 0.0) u = 0.0;
+        if (RE(u) > 1.0) u = 1.0;
+        cs[nc] = (double)side; cu[nc] = u; ++nc;
+    }
+    for (int side = 0; side < 2; ++side) {       /* u fixed at 0 or 1 */
+        R s = (b * (double)side - d) / a;
+        if (RE(s) < 0.0) s = 0.0;
+        if (RE(s) > 1.0) s = 1.0;
+        cs[nc] = s; cu[nc] = (double)side; ++nc;
+    }
+    double best = -1.0;
+    for (int k = 0; k < nc; ++k) {
+        double dd = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double w = RE(r[j]) + RE(cs[k]) * RE(d1[j]) - RE(cu[k]) * RE(d2[j]);
+            dd += w * w;
+        }
+        if (best < 0.0 || dd < best) { best = dd; *s_out = cs[k]; *u_out = cu[k]; }
+    }
+    return sqrt(best);
+}
+
+/* Edge-edge pairs (Sec. 3.5, Fig. CollisionPotential) are kept only when the
+ * closest points are interior to both segments (at an end point the pair is
+ * a vertex-triangle contact of that end point) and the edges are not nearly
+ * parallel (sine of their angle at least EE_MIN_SIN: for parallel edges the
+ * closest points are not unique). */
+#define EE_MIN_SIN 0.1
+
 typedef struct {
     int32_t *tri;          /* [n_verts] contact triangle of a surface vertex or -1 */
     int32_t *crow, *cent;  /* corner incidence: vertices whose contact triangle uses v */
+    int32_t n_ee;          /* edge-edge elements */
+    int32_t *ee;           /* [n_ee*4]: first edge a, b, second edge a, b */
+    double *ee_n;          /* [n_ee*3]: fixed normal, from the second edge to the first */
+    int32_t *erow, *eent;  /* per vertex: the elements it belongs to (ascending) */
 } Contacts;
+
+static int cmp_i64(const void *a, const void *b)
+{
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Surface edges: the distinct vertex pairs (a < b) of the surface triangles,
+ * in ascending (a, b) order.  Returns the count; *out holds 2 ids per edge. */
+static int surface_edges(const oracle_model *M, int32_t **out)
+{
+    const int nt = M->n_surf_tris;
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (3 * (size_t)nt + 1));
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            int64_t a = M->surf_tris[3 * t + k], b = M->surf_tris[3 * t + (k + 1) % 3];
+            if (a > b) { int64_t w = a; a = b; b = w; }
+            key[3 * t + k] = (a << 32) | b;
+        }
+    qsort(key, 3 * (size_t)nt, sizeof(int64_t), cmp_i64);
+    int n = 0;
+    for (int i = 0; i < 3 * nt; ++i)
+        if (i == 0 || key[i] != key[i - 1]) key[n++] = key[i];
+    *out = (int32_t *)malloc(sizeof(int32_t) * (2 * (size_t)n + 1));
+    for (int i = 0; i < n; ++i) {
+        (*out)[2 * i] = (int32_t)(key[i] >> 32);
+        (*out)[2 * i + 1] = (int32_t)(key[i] & 0xffffffff);
+    }
+    free(key);
+    return n;
+}
+
+static int mesh_of(const oracle_model *M, int v) { return M->vert_mesh ? M->vert_mesh[v] : 0; }
+
+/* Self-contact eligibility (Sec. 3.5 self-collisions): two primitives of one
+ * mesh may collide when they share no vertex and lie farther apart than
+ * self_exclusion in the rest shape (closer ones are neighbours of the
+ * material, not contacts). */
+static int self_pair_vt(const oracle_model *M, const oracle_params *P, int v, const int32_t *T)
+{
+    if (!P->self_contact || !M->rest_pos) return 0;
+    if (T[0] == v || T[1] == v || T[2] == v) return 0;
+    R pv[3], a[3], b[3], c[3], q[3], bary[3];
+    for (int k = 0; k < 3; ++k) {
+        pv[k] = M->rest_pos[3 * v + k];
+        a[k] = M->rest_pos[3 * T[0] + k];
+        b[k] = M->rest_pos[3 * T[1] + k];
+        c[k] = M->rest_pos[3 * T[2] + k];
+    }
+    closest_point_R(pv, a, b, c, q, bary);
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) d2 += RE(pv[k] - q[k]) * RE(pv[k] - q[k]);
+    return sqrt(d2) > P->self_exclusion;
+}
+
+static int self_pair_ee(const oracle_model *M, const oracle_params *P, const int32_t *e1,
+                        const int32_t *e2)
+{
+    if (!P->self_contact || !M->rest_pos) return 0;
+    if (e1[0] == e2[0] || e1[0] == e2[1] || e1[1] == e2[0] || e1[1] == e2[1]) return 0;
+    R a0[3], a1[3], b0[3], b1[3], s, u;
+    for (int k = 0; k < 3; ++k) {
+        a0[k] = M->rest_pos[3 * e1[0] + k];
+        a1[k] = M->rest_pos[3 * e1[1] + k];
+        b0[k] = M->rest_pos[3 * e2[0] + k];
+        b1[k] = M->rest_pos[3 * e2[1] + k];
+    }
+    return segment_closest_R(a0, a1, b0, b1, &s, &u) > P->self_exclusion;
+}
+
 
 /* detection: for each surface vertex, the closest surface triangle of another
  * mesh within collision_radius whose outward side is closer than delta */
@@ -378,9 +507,11 @@ static double winding_number(const oracle_model *M, int mesh, const double p[3],
 }
 
 /* discrete detection (Sec. 3.5): for each surface vertex, the closest surface
- * triangle of any other mesh within collision_radius (ties: lower index); the
- * pair is a contact when the vertex has penetrated that mesh (winding number
- * above 1/2) or lies closer than the contact thickness to its surface. */
+ * triangle of any other mesh (and, with self-contact, of its own mesh when
+ * eligible) within collision_radius (ties: lower index); the pair is a
+ * contact when the vertex has penetrated that other mesh (winding number
+ * above 1/2) or lies closer than the contact thickness to its surface; for a
+ * triangle of its own mesh, when the element is active (d > 0). */
 static void detect_R(const oracle_model *M, const oracle_params *P, const R *x, int32_t *tri_out)
 {
     const int nv = M->n_verts;
@@ -395,7 +526,7 @@ static void detect_R(const oracle_model *M, const oracle_params *P, const R *x, 
         int bt = -1;
         for (int t = 0; t < M->n_surf_tris; ++t) {
             const int32_t *T = M->surf_tris + 3 * t;
-            if ((M->vert_mesh ? M->vert_mesh[T[0]] : 0) == mv) continue;
+            if (mesh_of(M, T[0]) == mv && !self_pair_vt(M, P, v, T)) continue;
             R q[3], bary[3];
             closest_point_R(x + 3 * v, x + 3 * T[0], x + 3 * T[1], x + 3 * T[2], q, bary);
             double dist = 0.0;
@@ -406,8 +537,20 @@ static void detect_R(const oracle_model *M, const oracle_params *P, const R *x, 
         }
         if (bt < 0) continue;
         const double p[3] = {RE(x[3 * v]), RE(x[3 * v + 1]), RE(x[3 * v + 2])};
-        const int mb = M->vert_mesh ? M->vert_mesh[M->surf_tris[3 * bt]] : 0;
-        if (best < P->contact_thickness || winding_number(M, mb, p, x) > 0.5) tri_out[v] = bt;
+        const int32_t *B = M->surf_tris + 3 * bt;
+        const int mb = mesh_of(M, B[0]);
+        if (mb != mv) {
+            if (best < P->contact_thickness || winding_number(M, mb, p, x) > 0.5) tri_out[v] = bt;
+        } else {
+            /* own mesh: the element's own activity test, d = delta - (p - q).n > 0
+             * (closer than delta in front of the triangle, or behind it) */
+            R q[3], bary[3], n[3];
+            closest_point_R(x + 3 * v, x + 3 * B[0], x + 3 * B[1], x + 3 * B[2], q, bary);
+            tri_normal_R(x + 3 * B[0], x + 3 * B[1], x + 3 * B[2], n);
+            double dn = 0.0;
+            for (int k = 0; k < 3; ++k) dn += (p[k] - RE(q[k])) * RE(n[k]);
+            if (P->contact_thickness - dn > 0.0) tri_out[v] = bt;
+        }
     }
     free(on_surf);
 }
@@ -430,6 +573,159 @@ static void contacts_index(const oracle_model *M, Contacts *C)
                 C->cent[C->crow[c] + fill[c]++] = v;
             }
     free(fill);
+}
+
+/* Edge-edge detection (Sec. 3.5): for each surface edge e1, the closest
+ * eligible surface edge e2 (another mesh, or its own mesh under the
+ * self-contact rule) within collision_radius (ties: lower index).  The pair
+ * becomes an element when its closest points are interior to both edges, the
+ * edges are not nearly parallel (EE_MIN_SIN) and the element is active,
+ * d = delta - (x_a - x_b).n > 0, with n the unit direction from x_b to x_a at
+ * x^t (closest-point parameters of x, positions of x^t: the side each edge
+ * was on before the step's motion; the paper's edge-edge normal is the
+ * direction between the two contact points).  A pair found from both of its
+ * edges is kept once, from the edge with the lower index. */
+static void detect_ee(const oracle_model *M, const oracle_params *P, const R *x, const R *xt,
+                      Contacts *C)
+{
+    free(C->ee); free(C->ee_n);
+    C->ee = NULL; C->ee_n = NULL; C->n_ee = 0;
+    int32_t *E = NULL;
+    const int ne = surface_edges(M, &E);
+    int32_t *best = (int32_t *)malloc(sizeof(int32_t) * ((size_t)ne + 1));
+    double *bn = (double *)malloc(sizeof(double) * (3 * (size_t)ne + 1));
+    for (int e1 = 0; e1 < ne; ++e1) {
+        best[e1] = -1;
+        const int32_t *A = E + 2 * e1;
+        const int ma = mesh_of(M, A[0]);
+        double bd = 0.0;
+        int b = -1;
+        for (int e2 = 0; e2 < ne; ++e2) {
+            if (e2 == e1) continue;
+            const int32_t *B = E + 2 * e2;
+            if (mesh_of(M, B[0]) == ma && !self_pair_ee(M, P, A, B)) continue;
+            R s, u;
+            const double dist = segment_closest_R(x + 3 * A[0], x + 3 * A[1], x + 3 * B[0], x + 3 * B[1], &s, &u);
+            if (!(dist < P->collision_radius)) continue;
+            if (b < 0 || dist < bd) { bd = dist; b = e2; }
+        }
+        if (b < 0) continue;
+        const int32_t *B = E + 2 * b;
+        R s, u;
+        segment_closest_R(x + 3 * A[0], x + 3 * A[1], x + 3 * B[0], x + 3 * B[1], &s, &u);
+        if (!(RE(s) > 0.0 && RE(s) < 1.0 && RE(u) > 0.0 && RE(u) < 1.0)) continue;
+        double d1[3], d2[3];
+        for (int k = 0; k < 3; ++k) {
+            d1[k] = RE(x[3 * A[1] + k] - x[3 * A[0] + k]);
+            d2[k] = RE(x[3 * B[1] + k] - x[3 * B[0] + k]);
+        }
+        const double cr[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2],
+                              d1[0] * d2[1] - d1[1] * d2[0]};
+        const double l1 = sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
+        const double l2 = sqrt(d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
+        if (!(sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]) >= EE_MIN_SIN * l1 * l2)) continue;
+        double w[3], wl = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double xa = RE(xt[3 * A[0] + k]) + RE(s) * RE(xt[3 * A[1] + k] - xt[3 * A[0] + k]);
+            const double xb = RE(xt[3 * B[0] + k]) + RE(u) * RE(xt[3 * B[1] + k] - xt[3 * B[0] + k]);
+            w[k] = xa - xb;
+            wl += w[k] * w[k];
+        }
+        wl = sqrt(wl);
+        if (!(wl > 0.0)) continue;
+        double gap = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double xa = RE(x[3 * A[0] + k] + s * (x[3 * A[1] + k] - x[3 * A[0] + k]));
+            const double xb = RE(x[3 * B[0] + k] + u * (x[3 * B[1] + k] - x[3 * B[0] + k]));
+            gap += (xa - xb) * w[k] / wl;
+        }
+        if (!(P->contact_thickness - gap > 0.0)) continue;
+        best[e1] = b;
+        for (int k = 0; k < 3; ++k) bn[3 * e1 + k] = w[k] / wl;
+    }
+    int n = 0;
+    for (int e1 = 0; e1 < ne; ++e1)
+        if (best[e1] >= 0 && !(best[best[e1]] == e1 && best[e1] < e1)) ++n;
+    C->ee = (int32_t *)malloc(sizeof(int32_t) * (4 * (size_t)n + 1));
+    C->ee_n = (double *)malloc(sizeof(double) * (3 * (size_t)n + 1));
+    n = 0;
+    for (int e1 = 0; e1 < ne; ++e1) {
+        const int e2 = best[e1];
+        if (e2 < 0 || (best[e2] == e1 && e2 < e1)) continue;
+        C->ee[4 * n] = E[2 * e1];
+        C->ee[4 * n + 1] = E[2 * e1 + 1];
+        C->ee[4 * n + 2] = E[2 * e2];
+        C->ee[4 * n + 3] = E[2 * e2 + 1];
+        for (int k = 0; k < 3; ++k) C->ee_n[3 * n + k] = bn[3 * e1 + k];
+        ++n;
+    }
+    C->n_ee = n;
+    free(best); free(bn); free(E);
+}
+
+/* per vertex, the edge-edge elements it belongs to, ascending */
+static void ee_index(const oracle_model *M, Contacts *C)
+{
+    const int nv = M->n_verts;
+    free(C->erow); free(C->eent);
+    C->erow = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int e = 0; e < C->n_ee; ++e)
+        for (int k = 0; k < 4; ++k) C->erow[C->ee[4 * e + k] + 1]++;
+    for (int v = 0; v < nv; ++v) C->erow[v + 1] += C->erow[v];
+    C->eent = (int32_t *)malloc(sizeof(int32_t) * ((size_t)C->erow[nv] + 1));
+    int32_t *fill = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int e = 0; e < C->n_ee; ++e)
+        for (int k = 0; k < 4; ++k) {
+            const int v = C->ee[4 * e + k];
+            C->eent[C->erow[v] + fill[v]++] = e;
+        }
+    free(fill);
+}
+
+/* one edge-edge element seen from its vertex `role` (0, 1: the first edge's
+ * ends, 2, 3: the second's).  E = 1/2 k_c d^2 with d = delta - (x_a - x_b).n,
+ * x_a = x0 + s (x1 - x0), x_b = x2 + u (x3 - x2) at the closest points of the
+ * current positions, n fixed (Sec. 3.5); s, u and n held fixed in the
+ * derivatives: dd/dx0 = -(1 - s) n, dd/dx1 = -s n, dd/dx2 = (1 - u) n,
+ * dd/dx3 = u n.  IPC-style friction on (x_a - x_a^t) - (x_b - x_b^t) with the
+ * same weights (Sec. 3.6). */
+static int ee_contact(const oracle_params *P, const R *xv[4], const R *xvt[4], const double n[3],
+                      int role, R f[3], R H[3][3])
+{
+    R s, u;
+    segment_closest_R(xv[0], xv[1], xv[2], xv[3], &s, &u);
+    R xa[3], xb[3];
+    for (int k = 0; k < 3; ++k) {
+        xa[k] = xv[0][k] + s * (xv[1][k] - xv[0][k]);
+        xb[k] = xv[2][k] + u * (xv[3][k] - xv[2][k]);
+    }
+    R d = P->contact_thickness;
+    for (int k = 0; k < 3; ++k) d -= (xa[k] - xb[k]) * n[k];
+    if (!(RE(d) > 0.0)) return 0;
+    const R g = role == 0 ? -(1.0 - s) : (role == 1 ? -s : (role == 2 ? 1.0 - u : u));
+    for (int a = 0; a < 3; ++a) {
+        f[a] -= P->contact_k * d * g * n[a];
+        for (int b = 0; b < 3; ++b) H[a][b] += P->contact_k * g * g * n[a] * n[b];
+    }
+    if (P->friction_mu > 0.0) {
+        R dx[3];
+        for (int a = 0; a < 3; ++a) {
+            const R xat = xvt[0][a] + s * (xvt[1][a] - xvt[0][a]);
+            const R xbt = xvt[2][a] + u * (xvt[3][a] - xvt[2][a]);
+            dx[a] = (xa[a] - xat) - (xb[a] - xbt);
+        }
+        R dn = dx[0] * n[0] + dx[1] * n[1] + dx[2] * n[2];
+        R uu[3] = {dx[0] - dn * n[0], dx[1] - dn * n[1], dx[2] - dn * n[2]};
+        R un = RSQRT(uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]);
+        double hev = P->h * P->friction_eps_v;
+        R f1u = (RE(un) < hev) ? (2.0 / hev - un / (hev * hev)) : (1.0 / un);
+        R sf = P->friction_mu * P->contact_k * d * f1u;
+        for (int a = 0; a < 3; ++a) {
+            f[a] += sf * g * uu[a];
+            for (int b = 0; b < 3; ++b) H[a][b] += sf * g * g * ((a == b ? 1.0 : 0.0) - n[a] * n[b]);
+        }
+    }
+    return 1;
 }
 
 /* one vertex-triangle element seen from vertex `role` (-1: the colliding
@@ -559,6 +855,18 @@ static void local_system(const oracle_model *M, const oracle_params *P, const In
                 xct[k] = xt + 3 * T[k];
             }
             if (vt_contact(P, x + 3 * a, xc, xt + 3 * a, xct, role, f, H)) *in_contact = 1;
+        }
+        for (int e = CT->erow ? CT->erow[i] : 0; CT->erow && e < CT->erow[i + 1]; ++e) {
+            const int el = CT->eent[e];
+            const int32_t *V4 = CT->ee + 4 * el;
+            const R *xv[4], *xvt[4];
+            int role = 0;
+            for (int k = 0; k < 4; ++k) {
+                if (V4[k] == i) role = k;
+                xv[k] = (V4[k] == i) ? xi : x + 3 * V4[k];
+                xvt[k] = xt + 3 * V4[k];
+            }
+            if (ee_contact(P, xv, xvt, CT->ee_n + 3 * el, role, f, H)) *in_contact = 1;
         }
     }
     /* contacts against analytic spheres and planes, at the current iterate */
@@ -816,13 +1124,17 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
     }
     int64_t n_upd = 0, n_skip = 0, n_con = 0;
     double max_lg = 0.0, omega = 1.0;
-    Contacts CTs = {NULL, NULL, NULL};
+    Contacts CTs = {NULL, NULL, NULL, 0, NULL, NULL, NULL, NULL};
     const Contacts *CT = NULL;
     if (P->mesh_contacts && M->n_surf_tris > 0) {
         /* discrete detection at x^t (Sec. 3.5, Alg. 1) */
         CTs.tri = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nv + 1));
         detect_R(M, P, xt, CTs.tri);
         contacts_index(M, &CTs);
+        if (P->edge_contacts) {
+            detect_ee(M, P, xt, xt, &CTs);
+            ee_index(M, &CTs);
+        }
         CT = &CTs;
     }
 
@@ -833,6 +1145,10 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
         if (CT && P->n_col > 0 && (it - 1) % P->n_col == 0) {
             detect_R(M, P, x, CTs.tri);
             contacts_index(M, &CTs);
+            if (P->edge_contacts) {
+                detect_ee(M, P, x, xt, &CTs);
+                ee_index(M, &CTs);
+            }
         }
         for (int c = 0; c < C; ++c) {
             const int cb = crow[c], ce = crow[c + 1];
@@ -899,6 +1215,7 @@ int32_t FN(oracle_step)(const oracle_model *M, const oracle_params *P, R *x, R *
     free(xt); free(y); free(xnew); free(pr1); free(pr2); free(collided);
     free(crow); free(clist);
     free(CTs.tri); free(CTs.crow); free(CTs.cent);
+    free(CTs.ee); free(CTs.ee_n); free(CTs.erow); free(CTs.eent);
     inc_free(&inc);
     return 0;
 }
@@ -981,6 +1298,46 @@ void oracle_detect_contacts(const oracle_model *M, const oracle_params *P, const
                             int32_t *tri_of_vertex)
 {
     detect_R(M, P, x, tri_of_vertex);
+}
+
+double oracle_segment_closest(const double p0[3], const double p1[3], const double q0[3],
+                              const double q1[3], double *s, double *u)
+{
+    return segment_closest_R(p0, p1, q0, q1, s, u);
+}
+
+int32_t oracle_detect_edges(const oracle_model *M, const oracle_params *P, const double *x,
+                            const double *xt, int32_t max_out, int32_t *out_v, double *out_n)
+{
+    Contacts C = {NULL, NULL, NULL, 0, NULL, NULL, NULL, NULL};
+    detect_ee(M, P, x, xt, &C);
+    const int n = C.n_ee;
+    for (int e = 0; e < n && e < max_out; ++e) {
+        for (int k = 0; k < 4; ++k) out_v[4 * e + k] = C.ee[4 * e + k];
+        for (int k = 0; k < 3; ++k) out_n[3 * e + k] = C.ee_n[3 * e + k];
+    }
+    free(C.ee); free(C.ee_n);
+    return n;
+}
+
+double oracle_edge_element(const double x[12], const double n[3], double k, double delta,
+                           double grad[12])
+{
+    oracle_params P;
+    memset(&P, 0, sizeof(P));
+    P.contact_k = k;
+    P.contact_thickness = delta;
+    const double *xv[4] = {x, x + 3, x + 6, x + 9};
+    double s, u, d = delta;
+    segment_closest_R(xv[0], xv[1], xv[2], xv[3], &s, &u);
+    for (int a = 0; a < 3; ++a)
+        d -= (xv[0][a] + s * (xv[1][a] - xv[0][a]) - xv[2][a] - u * (xv[3][a] - xv[2][a])) * n[a];
+    for (int role = 0; role < 4; ++role) {
+        double f[3] = {0, 0, 0}, H[3][3] = {{0}};
+        ee_contact(&P, xv, xv, n, role, f, H);
+        for (int a = 0; a < 3; ++a) grad[3 * role + a] = -f[a];
+    }
+    return d;
 }
 
 double oracle_winding_number(const oracle_model *M, int32_t mesh, const double p[3], const double *x)

@@ -37,6 +37,7 @@ typedef struct {
     int32_t n_surf_tris;        /* surface triangles for mesh-mesh contacts (0 = none) */
     const int32_t *surf_tris;   /* [n_surf_tris*3], outward oriented */
     const int32_t *vert_mesh;   /* [n_verts] mesh id of each vertex, or NULL (one mesh) */
+    const double  *rest_pos;    /* [n_verts*3] rest positions (self-contact exclusion), or NULL */
 } oracle_model;
 
 typedef struct {
@@ -55,6 +56,9 @@ typedef struct {
     int32_t mesh_contacts;     /* 1: vertex-triangle contacts between different meshes */
     double collision_radius;   /* detection radius for mesh-mesh contacts */
     int32_t n_col;             /* re-detect every n_col iterations (0 = only at x^t) */
+    int32_t self_contact;      /* 1: contacts within one mesh too (Sec. 3.5, self-collisions) */
+    double self_exclusion;     /* same-mesh primitives closer than this at rest never collide */
+    int32_t edge_contacts;     /* 1: edge-edge elements (Sec. 3.5, Fig. CollisionPotential) */
 } oracle_params;
 
 typedef struct {
@@ -100,6 +104,22 @@ void oracle_closest_point_triangle(const double p[3], const double a[3], const d
  * surface (-1 if none). */
 void oracle_detect_contacts(const oracle_model *M, const oracle_params *P, const double *x,
                             int32_t *tri_of_vertex);
+/* Closest points of segments [p0, p1] and [q0, q1]: parameters s, u in
+ * [0, 1] of p0 + s (p1 - p0) and q0 + u (q1 - q0); returns the distance. */
+double oracle_segment_closest(const double p0[3], const double p1[3], const double q0[3],
+                              const double q1[3], double *s, double *u);
+/* Edge-edge contact elements the step would detect on positions x (with x^t
+ * = xt for the normals): up to max_out elements, each {e1 a, e1 b, e2 a,
+ * e2 b} vertex ids into out_v and its fixed normal into out_n.  Returns the
+ * number of elements. */
+int32_t oracle_detect_edges(const oracle_model *M, const oracle_params *P, const double *x,
+                            const double *xt, int32_t max_out, int32_t *out_v, double *out_n);
+/* One edge-edge element (Sec. 3.5): E = k/2 d^2, d = delta - (x_a - x_b).n,
+ * x_a on [x0, x1], x_b on [x2, x3] at their closest points (held fixed with
+ * n in the derivatives).  grad[12] = dE/dx of the four vertices; returns d
+ * (the element is active when d > 0; grad is zero otherwise). */
+double oracle_edge_element(const double x[12], const double n[3], double k, double delta,
+                           double grad[12]);
 /* Generalized winding number of mesh `mesh`'s surface at p (positions x). */
 double oracle_winding_number(const oracle_model *M, int32_t mesh, const double p[3], const double *x);
 

@@ -61,6 +61,9 @@ class StepParams:
     mesh_contacts: bool = False            # vertex-triangle contacts between meshes
     collision_radius: float = 0.0          # detection radius for mesh contacts
     n_col: int = 0                         # re-detect every n_col iterations (0: only at x^t)
+    self_contact: bool = False             # contacts within one mesh too
+    self_exclusion: float = 0.0            # same-mesh primitives closer at rest never collide
+    edge_contacts: bool = False            # edge-edge elements
 
 
 @dataclasses.dataclass
@@ -340,6 +343,90 @@ def config_block_stack(cols: int = 2, levels: int = 3, n: int = 5, seed: int = 5
                     tet_E=np.concatenate(Es), vert_offsets=np.array(vo, np.int64),
                     tet_offsets=np.array(to, np.int64), params=params, frames=frames,
                     coloring=coloring)
+
+
+def masked_lattice(mask: np.ndarray, edge: float = EDGE):
+    """Kuhn-split lattice of the cells where mask[i, j, k] is true (the
+    neighbouring cells' splits agree on every shared face); unused vertices
+    are dropped and the rest renumbered in lattice order.  Returns
+    (rest [nv, 3] f64 with the lattice origin at 0, tets [nt, 4] int32)."""
+    cx, cy, cz = mask.shape
+    rest, tets = cube_lattice(cx + 1, cy + 1, cz + 1, edge)
+    # cube_lattice emits 6 tets per cell, cells in (k, j, i) order
+    keep_cell = mask.transpose(2, 1, 0).ravel()
+    tets = tets.reshape(-1, 6, 4)[keep_cell].reshape(-1, 4)
+    used = np.zeros(rest.shape[0], bool)
+    used[tets.ravel()] = True
+    new_id = np.cumsum(used) - 1
+    rest = rest[used] - rest.min(axis=0)
+    return rest, new_id[tets].astype(np.int32)
+
+
+def _rotate(rest, axis: int, angle: float):
+    c, s = np.cos(angle), np.sin(angle)
+    i, j = [a for a in range(3) if a != axis]
+    out = rest.copy()
+    out[:, i] = c * rest[:, i] - s * rest[:, j]
+    out[:, j] = s * rest[:, i] + c * rest[:, j]
+    return out
+
+
+def config_crossed_bars(n: int = 4, gap: float = 0.5 * 5e-3, density: float = 100.0,
+                        E: float = 1e6, frames: int = 12, n_iters: int = 20,
+                        contact_k: float = 1e4, coloring: str = "id") -> Workload:
+    """Edge-on-edge contact: two n^3 lattice cubes turned 45 degrees, the
+    lower one about y (its top is an edge along y), the upper one about x
+    (its bottom is an edge along x), the upper edge `gap` above the lower one
+    and crossing it at both edges' midpoints (odd segment counts: the
+    crossing is interior to a segment of each edge).  The lower cube's lowest
+    vertices are pinned.  Only edge-edge elements can hold the upper cube:
+    every vertex is farther from the other cube than the detection radius."""
+    if n % 2:
+        raise ValueError("n must be even: the crossing must be interior to a segment")
+    side = (n - 1) * EDGE
+    r0, t0 = cube_lattice(n, n, n)
+    r0 = r0 - r0.mean(axis=0)
+    lower = _rotate(r0, 1, np.pi / 4)
+    lower[:, 2] -= lower[:, 2].max()
+    upper = _rotate(r0, 0, np.pi / 4)
+    upper[:, 2] += gap - upper[:, 2].min()
+    rest = np.concatenate([lower, upper])
+    tets = np.concatenate([t0, t0 + r0.shape[0]]).astype(np.int32)
+    pinned = np.zeros(rest.shape[0], np.uint8)
+    pinned[:r0.shape[0]][lower[:, 2] < lower[:, 2].min() + 0.3 * side] = 1
+    nv = rest.shape[0]
+    params = StepParams(n_iters=n_iters, contact_k=contact_k, contact_thickness=5e-3,
+                        mesh_contacts=True, collision_radius=0.2 * EDGE, edge_contacts=True)
+    vo = np.array([0, r0.shape[0], nv], np.int64)
+    to = np.array([0, t0.shape[0], 2 * t0.shape[0]], np.int64)
+    return Workload(name=f"crossed bars {n}^3", rest=rest, tets=tets, pinned=pinned,
+                    x0=rest.copy(), v0=np.zeros((nv, 3)), tet_E=np.full(tets.shape[0], E),
+                    density=density, vert_offsets=vo, tet_offsets=to, params=params,
+                    frames=frames, coloring=coloring)
+
+
+def config_folding_c(length: int = 7, width: int = 2, slab: int = 1, gap: int = 1,
+                     E: float = 3e4, frames: int = 24, n_iters: int = 20,
+                     contact_k: float = 1e4, coloring: str = "id") -> Workload:
+    """Self-contact: one mesh shaped like a C lying on its side, a lower and
+    an upper slab (`slab` cells thick, `length` cells long, `width` deep)
+    joined by a wall at x = 0, `gap` cells apart.  The lower slab's bottom is
+    pinned; the soft upper slab sags onto the lower one, so its bottom face
+    meets the lower slab's top face: surfaces of the same mesh that are a gap
+    apart in the rest shape (the self-contact exclusion distance is half of
+    it)."""
+    nz = 2 * slab + gap
+    mask = np.ones((length, width, nz), bool)
+    mask[1:, :, slab:slab + gap] = False
+    rest, tets = masked_lattice(mask)
+    pinned = (rest[:, 2] < 1e-12).astype(np.uint8)
+    nv = rest.shape[0]
+    params = StepParams(n_iters=n_iters, contact_k=contact_k, contact_thickness=5e-3,
+                        mesh_contacts=True, collision_radius=0.2 * EDGE, edge_contacts=True,
+                        self_contact=True, self_exclusion=0.5 * gap * EDGE, n_col=10)
+    return Workload(name=f"folding C {length}x{width}", rest=rest, tets=tets, pinned=pinned,
+                    x0=rest.copy(), v0=np.zeros((nv, 3)), tet_E=np.full(tets.shape[0], E),
+                    params=params, frames=frames, coloring=coloring)
 
 
 def config_differentiable(n: int = 33, seed: int = 4, frames: int = 30, n_iters: int = 20,
