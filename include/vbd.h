@@ -165,10 +165,10 @@ enum {
     VBD_Q_REST_FRAME = 13,  /* double[n_tets][6]: upper triangle of R^{-1}, D_m = Q R with
                                Q a proper rotation (caller's tet order) */
     VBD_Q_SURFACE = 14,     /* int32[n_surf_tris][3]: surface triangles (faces of exactly
-                               one tet; extracted when n_meshes > 1), original vertex ids,
-                               ordered so (b - a) x (c - a) points out of the mesh;
-                               sorted by their ascending vertex-id triples */
-    VBD_Q_SURFACE_COUNTS = 15, /* int64[2]: n_surf_tris, n_surf_verts */
+                               one tet), original vertex ids, ordered so (b - a) x (c - a)
+                               points out of the mesh; sorted by their ascending vertex-id
+                               triples */
+    VBD_Q_SURFACE_COUNTS = 15, /* int64[3]: n_surf_tris, n_surf_verts, n_surf_edges */
     VBD_Q_SNAPSHOT_REGION = 16,/* int64[3]: byte offset of the iterate snapshots in the bound
                                   workspace (-1 when max_backward_iters is 0), bytes per
                                   snapshot (n_verts float4 in slot order), snapshot count - 1
@@ -176,8 +176,10 @@ enum {
                                   first (n_iters + 1) snapshots */
     VBD_Q_ADJ_PHASE_BYTES = 17,/* double[n_colors]: algorithmic HBM bytes of one reverse color
                                   phase of vbd_step_backward */
-    VBD_Q_PHASE_COUNTS = 18    /* int64[n_colors][4]: tet pairs, spring entries, distinct
+    VBD_Q_PHASE_COUNTS = 18,   /* int64[n_colors][4]: tet pairs, spring entries, distinct
                                   neighbour vertices and free vertices of each color */
+    VBD_Q_SURFACE_EDGES = 19   /* int32[n_surf_edges][2]: the distinct edges of the surface
+                                  triangles, original ids a < b, ascending (a, b) */
 };
 vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
 vbd_status vbd_topology_destroy(vbd_topology topo);
@@ -205,7 +207,8 @@ typedef struct {
                                       the exact PSD projection of a spring block */
     int32_t launch_mode;           /* VBD_LAUNCH_* */
     /* Mesh-mesh vertex-triangle contacts (Sec. 3.5, 3.9), between different
-     * meshes of a batched topology (no self-contact).  Detection at x^t: each
+     * meshes of a batched topology (and within one mesh with self_contact,
+     * below).  Detection at x^t: each
      * surface vertex takes the closest surface triangle of another mesh within
      * collision_radius; the pair is a contact element when the vertex is inside
      * that mesh or closer than contact_thickness to its surface.  Detection is
@@ -227,6 +230,28 @@ typedef struct {
      * on the device (one extra pass over them); vbd_check then returns
      * VBD_E_NONFINITE when any was found.  0 = no check. */
     int32_t check_finite;
+    /* Self-contact (Sec. 3.5 self-collisions), with mesh_contacts only: the
+     * detection also pairs primitives of one mesh that share no vertex and
+     * lie farther apart than self_exclusion in the rest shape; such a
+     * vertex-triangle pair is a contact element when the element is active
+     * (d > 0, closer than the contact thickness in front of the triangle or
+     * behind it).  Else VBD_E_INVALID_ARG. */
+    int32_t self_contact;          /* 1 = on */
+    float self_exclusion;          /* >= 0, rest-shape distance */
+    /* Edge-edge elements (Sec. 3.5, Fig. CollisionPotential), with
+     * mesh_contacts only: at every detection each surface edge takes the
+     * closest eligible surface edge (another mesh, or its own under the
+     * self-contact rule) within collision_radius; the pair is an element when
+     * its closest points are interior to both edges, the edges are not nearly
+     * parallel (sine of their angle >= 0.1; parallel pairs are left to the
+     * vertex-triangle elements of their end points) and the element is
+     * active.  Energy k_c/2 d^2, d = delta - (x_a - x_b).n, x_a, x_b the
+     * closest points (recomputed at every evaluation), n the unit direction
+     * from x_b to x_a at x^t (held fixed); a pair found from both edges is
+     * kept once (the lower edge index's).  Friction as for vertex-triangle
+     * elements.  Up to two same-color vertex pairs per element read the
+     * positions from before their color (x_new buffer, Sec. 3.9). */
+    int32_t edge_contacts;         /* 1 = on */
 } vbd_step_params;
 
 /* One implicit-Euler time step of every mesh (Alg. 1):
@@ -299,6 +324,17 @@ vbd_status vbd_step_backward(vbd_topology topo, const vbd_step_params *params,
  * and stream stay the same).  Errors: as vbd_step_backward. */
 vbd_status vbd_step_record(vbd_topology topo, const vbd_step_params *params, float *x, float *v,
                            float *v_prev, const float *tet_E, void *stream);
+
+/* Runs the edge-edge detection that vbd_step does (params: mesh_contacts and
+ * edge_contacts must be 1) with closest points on x and normals from x_t
+ * (device float [n_verts][3] each, original order; x = x_t is the detection
+ * at the start of a step) and writes, for every surface edge in
+ * VBD_Q_SURFACE_EDGES order, the second edge of the element kept from it
+ * (the elements are the pairs (e, partner_out[e]) with partner_out[e] >= 0),
+ * or -1 (partner_out: device int32 [n_surf_edges]).  Uses the library's
+ * internal state buffers.  Errors as vbd_detect_contacts. */
+vbd_status vbd_detect_edges(vbd_topology topo, const vbd_step_params *params, const float *x,
+                            const float *x_t, int32_t *partner_out, void *stream);
 
 /* Runs the mesh-mesh contact detection that vbd_step does at x^t (params:
  * mesh_contacts must be 1; collision_radius and contact_thickness are used) on

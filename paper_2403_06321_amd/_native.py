@@ -16,14 +16,14 @@ COLOR_ID_ORDER, COLOR_SMALLEST_LAST, COLOR_DSATUR = 0, 1, 2
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
  Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME, Q_SURFACE,
- Q_SURFACE_COUNTS, Q_SNAPSHOT_REGION, Q_ADJ_PHASE_BYTES, Q_PHASE_COUNTS) = range(19)
+ Q_SURFACE_COUNTS, Q_SNAPSHOT_REGION, Q_ADJ_PHASE_BYTES, Q_PHASE_COUNTS, Q_SURFACE_EDGES) = range(20)
 
 # every symbol include/vbd.h declares
 EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_color_greedy", "vbd_color_given", "vbd_workspace_size", "vbd_bind_workspace",
            "vbd_topology_query", "vbd_topology_destroy", "vbd_step", "vbd_step_static", "vbd_step_record", "vbd_step_backward",
            "vbd_get_launch_config", "vbd_set_launch_config", "vbd_autotune",
            "vbd_profile_enable", "vbd_profile_read", "vbd_check", "vbd_probe_copy", "vbd_probe_read",
-           "vbd_detect_contacts", "vbd_read_counters", "vbd_last_error"]
+           "vbd_detect_contacts", "vbd_detect_edges", "vbd_read_counters", "vbd_last_error"]
 
 
 class MeshDesc(C.Structure):
@@ -42,7 +42,9 @@ class StepParamsC(C.Structure):
                 ("cheb_rho", C.c_float), ("friction_mu", C.c_float), ("friction_eps_v", C.c_float),
                 ("spring_psd", C.c_int32), ("launch_mode", C.c_int32),
                 ("mesh_contacts", C.c_int32), ("collision_radius", C.c_float), ("n_col", C.c_int32),
-                ("backward_recorded", C.c_int32), ("check_finite", C.c_int32)]
+                ("backward_recorded", C.c_int32), ("check_finite", C.c_int32),
+                ("self_contact", C.c_int32), ("self_exclusion", C.c_float),
+                ("edge_contacts", C.c_int32)]
 
 
 class LaunchConfig(C.Structure):
@@ -100,6 +102,7 @@ def lib():
     L.vbd_probe_copy.argtypes = [p, p, sz, p]
     L.vbd_probe_read.argtypes = [p, sz, p, i32, p]
     L.vbd_detect_contacts.argtypes = [p, C.POINTER(StepParamsC), p, p, p]
+    L.vbd_detect_edges.argtypes = [p, C.POINTER(StepParamsC), p, p, p, p]
     L.vbd_read_counters.argtypes = [p, C.POINTER(Counters), i32, p]
     L.vbd_last_error.argtypes = []
     L.vbd_last_error.restype = C.c_char_p

@@ -41,7 +41,9 @@ def params_struct(p: StepParams, launch_mode: int = N.LAUNCH_PLAIN, backward_rec
                       int(bool(getattr(p, "spring_psd", False))), int(launch_mode),
                       int(bool(getattr(p, "mesh_contacts", False))),
                       float(getattr(p, "collision_radius", 0.0)), int(getattr(p, "n_col", 0)),
-                      1 if backward_recorded else 0, 1 if check_finite else 0)
+                      1 if backward_recorded else 0, 1 if check_finite else 0,
+                      int(bool(getattr(p, "self_contact", False))), float(getattr(p, "self_exclusion", 0.0)),
+                      int(bool(getattr(p, "edge_contacts", False))))
     return s, (sph, pl)
 
 
@@ -146,12 +148,17 @@ class Topology:
                 N.Q_PHASE_BYTES: (np.float64, c["n_colors"]),
                 N.Q_TET_ORDER: (np.int32, c["n_tets"]),
                 N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"]),
-                N.Q_SURFACE_COUNTS: (np.int64, 2), N.Q_SNAPSHOT_REGION: (np.int64, 3),
+                N.Q_SURFACE_COUNTS: (np.int64, 3), N.Q_SNAPSHOT_REGION: (np.int64, 3),
                 N.Q_ADJ_PHASE_BYTES: (np.float64, c["n_colors"]),
                 N.Q_PHASE_COUNTS: (np.int64, 4 * c["n_colors"])}
         if what == N.Q_SURFACE:
             n_tri = int(self.query(N.Q_SURFACE_COUNTS)[0])
             out = np.zeros((n_tri, 3), np.int32)
+            N.check(N.lib().vbd_topology_query(self._h, what, _np_ptr(out), out.nbytes))
+            return out
+        if what == N.Q_SURFACE_EDGES:
+            n_edge = int(self.query(N.Q_SURFACE_COUNTS)[2])
+            out = np.zeros((n_edge, 2), np.int32)
             N.check(N.lib().vbd_topology_query(self._h, what, _np_ptr(out), out.nbytes))
             return out
         spec = spec[what]
@@ -169,6 +176,20 @@ class Topology:
         N.check(N.lib().vbd_detect_contacts(self._h, C.byref(ps), _t_ptr(x), _t_ptr(out),
                                             _stream_handle(stream)))
         return out
+
+    def detect_edges(self, x, params: StepParams, x_t=None, stream=None):
+        """Edge-edge detection with closest points on x and normals from x_t
+        (default x), device float32 [n_verts, 3]: int32 [n_surf_edges], for
+        each surface edge the second edge of the element kept from it, or -1."""
+        _check_state(x, self.n_verts, "x")
+        xt = x if x_t is None else x_t
+        _check_state(xt, self.n_verts, "x_t")
+        n_edge = int(self.query(N.Q_SURFACE_COUNTS)[2])
+        out = torch.empty(max(n_edge, 1), dtype=torch.int32, device=x.device)
+        ps, keep = params_struct(params)
+        N.check(N.lib().vbd_detect_edges(self._h, C.byref(ps), _t_ptr(x), _t_ptr(xt), _t_ptr(out),
+                                         _stream_handle(stream)))
+        return out[:n_edge]
 
     def step(self, x, v, v_prev, tet_E, params: StepParams, launch_mode: int = N.LAUNCH_PLAIN,
              stream=None, check_finite: bool = False):

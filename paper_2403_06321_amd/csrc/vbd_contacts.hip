@@ -24,6 +24,18 @@
 // The corner incidence (for each vertex, the colliding vertices whose
 // contact triangle has it as a corner) is built the same way and each row is
 // sorted, so the solve visits the elements in a fixed order.
+//
+// Self-contact: triangles of the vertex's own mesh are candidates when they
+// share no vertex with it and lie farther than the exclusion distance from it
+// in the rest shape; such a pair is kept when its element is active.
+//
+// Edge-edge elements: edge midpoints binned the same way (cell size r +
+// 2 L_max, L_max the largest half edge length), every surface edge takes the
+// closest eligible edge within r (minimum of (distance, edge index)), and the
+// pair is kept when its closest points are interior to both edges, the edges
+// are not nearly parallel and the element, with its normal taken from the
+// contact points at x^t, is active; a pair found from both edges is kept from
+// the lower index.  Each vertex's elements form a sorted incidence row.
 #include "vbd_device.h"
 
 namespace vbd {
@@ -190,17 +202,18 @@ __global__ __launch_bounds__(256) void k_tri_prep(DevSurf S, const float4 *X)
         S.gmax[blockIdx.x] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
 }
 
-// One block: gparam[0] = float bits of the largest triangle radius.
-__global__ __launch_bounds__(256) void k_max_radius(DevSurf S, int nb)
+// One block: *out = float bits of the largest of the nb per-block maxima
+// (gparam[0]: triangle radius, gparam[1]: half edge length).
+__global__ __launch_bounds__(256) void k_max_radius(const float *gmax, int nb, unsigned *out)
 {
     __shared__ float wmax[4];
     float R = 0.f;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) R = fmaxf(R, S.gmax[i]);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) R = fmaxf(R, gmax[i]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) R = fmaxf(R, __shfl_xor(R, off, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = R;
     __syncthreads();
-    if (threadIdx.x == 0) S.gparam[0] = __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
+    if (threadIdx.x == 0) *out = __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
 }
 
 // Angle-weighted pseudonormal of every surface vertex.
@@ -265,6 +278,24 @@ __device__ __forceinline__ float3 feature_normal(const DevSurf &S, int t, int fe
     return o >= 0 ? nt + xyz(S.tnorm[o]) : nt;
 }
 
+// Self-contact eligibility: no shared vertex, farther apart than the
+// exclusion distance in the rest shape.
+__device__ __forceinline__ bool self_vt_ok(const DevSurf &S, const StepConsts &K, int slot, int4 tr)
+{
+    if (tr.x == slot || tr.y == slot || tr.z == slot) return false;
+    const float3 p = xyz(S.srest[slot]);
+    const ClosestPt cp = closest_on_triangle(p, xyz(S.srest[tr.x]), xyz(S.srest[tr.y]), xyz(S.srest[tr.z]));
+    const float3 d = p - cp.q;
+    return sqrtf(dot3(d, d)) > K.self_excl;
+}
+
+__device__ __forceinline__ bool self_ee_ok(const DevSurf &S, const StepConsts &K, int4 A, int4 B)
+{
+    if (A.x == B.x || A.x == B.y || A.y == B.x || A.y == B.y) return false;
+    const SegPt sp = seg_closest(xyz(S.srest[A.x]), xyz(S.srest[A.y]), xyz(S.srest[B.x]), xyz(S.srest[B.y]));
+    return sqrtf(sp.d2) > K.self_excl;
+}
+
 // One surface vertex per group of kDetLanes lanes: lane l < 27 scans the
 // bucket of neighbouring cell l, then the group reduces the (distance^2,
 // triangle) minimum with shuffles; the group's first lane decides the contact.
@@ -291,8 +322,8 @@ __global__ __launch_bounds__(256) void k_detect(DevSurf S, const float4 *X, Step
         const unsigned e1 = S.hstart[h + 1];
         for (unsigned e = S.hstart[h]; e < e1; ++e) {
             const int2 item = S.hitems[e];
-            if (item.y == sv.y) continue;              // own mesh
             const int t = item.x;
+            if (item.y == sv.y && !(K.self_contact && self_vt_ok(S, K, sv.x, S.tri[t]))) continue;
             // every point of the triangle lies within R of its centroid; the
             // margin keeps rounding of the bound from deciding a tie
             const float4 sph = S.tsph[t];
@@ -324,8 +355,12 @@ __global__ __launch_bounds__(256) void k_detect(DevSurf S, const float4 *X, Step
     if (best >= 0) {
         const int4 tr = S.tri[best];
         const ClosestPt cp = closest_on_triangle(p, xyz(X[tr.x]), xyz(X[tr.y]), xyz(X[tr.z]));
-        const bool inside = dot3(p - cp.q, feature_normal(S, best, cp.feature)) < 0.f;
-        if (sqrtf(best_d2) < K.delta || inside) hit = best;
+        if (tr.w != sv.y) {
+            const bool inside = dot3(p - cp.q, feature_normal(S, best, cp.feature)) < 0.f;
+            if (sqrtf(best_d2) < K.delta || inside) hit = best;
+        } else if (K.delta - dot3(p - cp.q, xyz(S.tnorm[best])) > 0.f) {
+            hit = best;   // own mesh: the element's own activity test
+        }
     }
     S.ctri[sv.x] = hit;
     if (hit >= 0) {
@@ -369,6 +404,188 @@ __global__ void k_corner_sort(DevSurf S, int n_verts)
     }
 }
 
+// ---------------------------------------------------------- edge-edge --
+// Midpoints and half lengths of the surface edges, and per block the largest
+// half length (reduced into gparam[1]).
+__global__ __launch_bounds__(256) void k_edge_prep(DevSurf S, const float4 *X)
+{
+    __shared__ float wmax[4];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    float R = 0.f;
+    if (e < S.n_edge) {
+        const int4 ed = S.edge[e];
+        const float3 a = xyz(X[ed.x]), b = xyz(X[ed.y]);
+        const float3 m = (a + b) * 0.5f, h = (b - a) * 0.5f;
+        R = sqrtf(dot3(h, h));
+        S.emid[e] = make_float4(m.x, m.y, m.z, R);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) R = fmaxf(R, __shfl_xor(R, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = R;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        S.egmax[blockIdx.x] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+}
+
+__device__ __forceinline__ float edge_cell_size(const DevSurf &S, const StepConsts &K)
+{
+    const float s = K.col_radius + 2.f * __uint_as_float(S.gparam[1]);
+    return s > 0.f ? s : 1.f;
+}
+
+__global__ void k_egrid_count(DevSurf S, StepConsts K)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S.n_edge) return;
+    const float4 m = S.emid[e];
+    const float inv_s = 1.0f / edge_cell_size(S, K);
+    const unsigned h = cell_hash(cell_coord(m.x, inv_s), cell_coord(m.y, inv_s), cell_coord(m.z, inv_s), S.ehmask);
+    atomicAdd(&S.ehcount[h], 1u);
+}
+
+__global__ void k_egrid_fill(DevSurf S, StepConsts K)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S.n_edge) return;
+    const float4 m = S.emid[e];
+    const float inv_s = 1.0f / edge_cell_size(S, K);
+    const unsigned h = cell_hash(cell_coord(m.x, inv_s), cell_coord(m.y, inv_s), cell_coord(m.z, inv_s), S.ehmask);
+    const unsigned pos = S.ehstart[h] + atomicAdd(&S.ehcount[h], 1u);
+    S.ehitems[pos] = make_int2(e, S.edge[e].z);
+}
+
+// One surface edge per group of kDetLanes lanes (as k_detect): the closest
+// eligible edge within r, then the element tests on the group's first lane.
+// A point of an edge lies within its half length of the midpoint, so a pair
+// within r has midpoints within r + 2 L_max: the 27 cells hold them all.
+__global__ __launch_bounds__(256) void k_detect_ee(DevSurf S, const float4 *X, const float4 *Xt,
+                                                   StepConsts K)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e1 = gid / kDetLanes, lane = threadIdx.x & (kDetLanes - 1);
+    const bool active = e1 < S.n_edge;
+    int4 A = make_int4(0, 0, -1, 0);
+    float3 a0 = make_float3(0.f, 0.f, 0.f), a1 = a0;
+    float4 m1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float best_d2 = K.col_radius * K.col_radius;
+    int best = -1;
+    if (active) {
+        A = S.edge[e1];
+        a0 = xyz(X[A.x]);
+        a1 = xyz(X[A.y]);
+        m1 = S.emid[e1];
+    }
+    if (active && lane < 27) {
+        const float inv_s = 1.0f / edge_cell_size(S, K);
+        const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+        const unsigned h = cell_hash(cell_coord(m1.x, inv_s) + dx, cell_coord(m1.y, inv_s) + dy,
+                                     cell_coord(m1.z, inv_s) + dz, S.ehmask);
+        const unsigned c1 = S.ehstart[h + 1];
+        for (unsigned c = S.ehstart[h]; c < c1; ++c) {
+            const int2 item = S.ehitems[c];
+            const int e2 = item.x;
+            if (e2 == e1) continue;
+            const int4 B = S.edge[e2];
+            if (item.y == A.z && !(K.self_contact && self_ee_ok(S, K, A, B))) continue;
+            const float4 m2 = S.emid[e2];
+            const float3 dm = make_float3(m1.x - m2.x, m1.y - m2.y, m1.z - m2.z);
+            const float lb = sqrtf(dot3(dm, dm)) - m1.w - m2.w;
+            if (lb > 0.f && lb * lb > 1.001f * best_d2) continue;
+            const SegPt sp = seg_closest(a0, a1, xyz(X[B.x]), xyz(X[B.y]));
+            if (sp.d2 < best_d2 || (sp.d2 == best_d2 && best >= 0 && e2 < best)) {
+                best_d2 = sp.d2;
+                best = e2;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = kDetLanes / 2; off > 0; off >>= 1) {
+        const float od2 = __shfl_xor(best_d2, off, kDetLanes);
+        const int oe = __shfl_xor(best, off, kDetLanes);
+        if (oe >= 0 && (best < 0 || od2 < best_d2 || (od2 == best_d2 && oe < best))) {
+            best_d2 = od2;
+            best = oe;
+        }
+    }
+    if (!active || lane != 0) return;
+    int keep = -1;
+    float3 n = make_float3(0.f, 0.f, 0.f);
+    if (best >= 0) {
+        const int4 B = S.edge[best];
+        const float3 b0 = xyz(X[B.x]), b1 = xyz(X[B.y]);
+        const SegPt sp = seg_closest(a0, a1, b0, b1);
+        const float3 d1 = a1 - a0, d2 = b1 - b0;
+        const float3 cr = cross3(d1, d2);
+        const bool interior = sp.s > 0.f && sp.s < 1.f && sp.u > 0.f && sp.u < 1.f;
+        const bool crossing = sqrtf(dot3(cr, cr)) >= 0.1f * sqrtf(dot3(d1, d1)) * sqrtf(dot3(d2, d2));
+        const float3 ta0 = xyz(Xt[A.x]), ta1 = xyz(Xt[A.y]), tb0 = xyz(Xt[B.x]), tb1 = xyz(Xt[B.y]);
+        const float3 w = (ta0 + (ta1 - ta0) * sp.s) - (tb0 + (tb1 - tb0) * sp.u);
+        const float wl = sqrtf(dot3(w, w));
+        if (interior && crossing && wl > 0.f) {
+            n = w * (1.0f / wl);
+            const float3 xa = a0 + d1 * sp.s, xb = b0 + d2 * sp.u;
+            if (K.delta - dot3(xa - xb, n) > 0.f) keep = best;
+        }
+    }
+    S.eb[e1] = keep;
+    S.en[e1] = make_float4(n.x, n.y, n.z, 0.f);
+}
+
+// A pair found from both of its edges is kept from the lower index.
+__device__ __forceinline__ bool ee_kept(const DevSurf &S, int e1)
+{
+    const int e2 = S.eb[e1];
+    return e2 >= 0 && !(S.eb[e2] == e1 && e2 < e1);
+}
+
+__global__ void k_ee_count(DevSurf S)
+{
+    const int e1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e1 >= S.n_edge || !ee_kept(S, e1)) return;
+    const int4 A = S.edge[e1], B = S.edge[S.eb[e1]];
+    atomicAdd(&S.ecount[A.x], 1u);
+    atomicAdd(&S.ecount[A.y], 1u);
+    atomicAdd(&S.ecount[B.x], 1u);
+    atomicAdd(&S.ecount[B.y], 1u);
+}
+
+__global__ void k_ee_fill(DevSurf S)
+{
+    const int e1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e1 >= S.n_edge || !ee_kept(S, e1)) return;
+    const int4 A = S.edge[e1], B = S.edge[S.eb[e1]];
+    const int v[4] = {A.x, A.y, B.x, B.y};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned pos = S.erow[v[k]] + atomicAdd(&S.ecount[v[k]], 1u);
+        S.eent[pos] = e1;
+    }
+}
+
+// Insertion sort of every element row (a handful of entries each).
+__global__ void k_ee_sort(DevSurf S, int n_verts)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_verts) return;
+    const int b = (int)S.erow[p], e = (int)S.erow[p + 1];
+    for (int i = b + 1; i < e; ++i) {
+        const int key = S.eent[i];
+        int j = i - 1;
+        while (j >= b && S.eent[j] > key) {
+            S.eent[j + 1] = S.eent[j];
+            --j;
+        }
+        S.eent[j + 1] = key;
+    }
+}
+
+__global__ void k_store_partners(DevSurf S, int *out)
+{
+    const int e1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e1 >= S.n_edge) return;
+    out[e1] = ee_kept(S, e1) ? S.eb[e1] : -1;
+}
+
 __global__ void k_load_x(DevTopo T, const float *x)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -395,7 +612,7 @@ hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X, co
     if ((e = fill_u32(S.ccount, T.n_verts, 0u, s)) != hipSuccess) return e;
     const int nb_tri = cdiv(S.n_tri, 256);
     hipLaunchKernelGGL(k_tri_prep, dim3(nb_tri), dim3(256), 0, s, S, X);
-    hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(256), 0, s, S, nb_tri);
+    hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(256), 0, s, S.gmax, nb_tri, S.gparam);
     hipLaunchKernelGGL(k_vert_normals, dim3(cdiv(S.n_sv, 256)), dim3(256), 0, s, S, X);
     hipLaunchKernelGGL(k_grid_count, dim3(cdiv(S.n_tri, 256)), dim3(256), 0, s, S, X, K);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -408,6 +625,35 @@ hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X, co
     if ((e = fill_u32(S.ccount, T.n_verts, 0u, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_corner_fill, dim3(cdiv(S.n_sv, 256)), dim3(256), 0, s, S);
     hipLaunchKernelGGL(k_corner_sort, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, S, T.n_verts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!K.edge_contacts || S.n_edge == 0) return hipSuccess;
+    // edge-edge elements, normals from x^t
+    const int HE = S.ehmask + 1;
+    const int nb_e = cdiv(S.n_edge, 256);
+    if ((e = fill_u32(S.ehcount, HE, 0u, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.ecount, T.n_verts, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_edge_prep, dim3(nb_e), dim3(256), 0, s, S, X);
+    hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(256), 0, s, S.egmax, nb_e, S.gparam + 1);
+    hipLaunchKernelGGL(k_egrid_count, dim3(nb_e), dim3(256), 0, s, S, K);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive(S.ehcount, S.ehstart, S.scan_tmp, HE, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.ehcount, HE, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_egrid_fill, dim3(nb_e), dim3(256), 0, s, S, K);
+    hipLaunchKernelGGL(k_detect_ee, dim3(cdiv((long)S.n_edge * kDetLanes, 256)), dim3(256), 0, s, S, X,
+                       (const float4 *)T.xt, K);
+    hipLaunchKernelGGL(k_ee_count, dim3(nb_e), dim3(256), 0, s, S);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive(S.ecount, S.erow, S.scan_tmp, T.n_verts, s)) != hipSuccess) return e;
+    if ((e = fill_u32(S.ecount, T.n_verts, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ee_fill, dim3(nb_e), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_ee_sort, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, S, T.n_verts);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_edge_partners(const DevSurf &S, int *partner_out, hipStream_t s)
+{
+    if (S.n_edge == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_store_partners, dim3(cdiv(S.n_edge, 256)), dim3(256), 0, s, S, partner_out);
     return hipGetLastError();
 }
 

@@ -81,4 +81,37 @@ __device__ __forceinline__ ClosestPt closest_on_triangle(float3 p, float3 a, flo
     return r;
 }
 
+
+// Closest points of the segments p0 + s (p1 - p0) and q0 + u (q1 - q0), s, u
+// in [0, 1], and their squared distance: the clamped solve of Ericson,
+// Real-Time Collision Detection (2005), Sec. 5.1.9 (s from the unconstrained
+// minimum clamped to [0, 1], u for that s; when u leaves [0, 1] it is clamped
+// and s solved again).  Edges have positive length.
+struct SegPt {
+    float s, u, d2;
+};
+
+__device__ __forceinline__ SegPt seg_closest(float3 p0, float3 p1, float3 q0, float3 q1)
+{
+    const float3 d1 = p1 - p0, d2 = q1 - q0, r = p0 - q0;
+    const float a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+    const float c = dot3(d1, r), b = dot3(d1, d2);
+    const float den = a * e - b * b;
+    float s = den > 0.f ? fminf(fmaxf((b * f - c * e) / den, 0.f), 1.f) : 0.f;
+    float u = (b * s + f) / e;
+    if (u < 0.f) {
+        u = 0.f;
+        s = fminf(fmaxf(-c / a, 0.f), 1.f);
+    } else if (u > 1.f) {
+        u = 1.f;
+        s = fminf(fmaxf((b - c) / a, 0.f), 1.f);
+    }
+    const float3 w = r + d1 * s - d2 * u;
+    SegPt out;
+    out.s = s;
+    out.u = u;
+    out.d2 = dot3(w, w);
+    return out;
+}
+
 }  // namespace vbd

@@ -59,7 +59,9 @@ struct Layout {
     // mesh-mesh contacts (only when the topology has a surface)
     size_t s_tri, s_tadj, s_svert, s_svidx, s_sv_row, s_sv_tri, s_tnorm, s_vnorm, s_gparam, s_gmax;
     size_t s_hcount, s_hstart, s_scan, s_hitems, s_tsph, s_ctri, s_ccount, s_crow, s_cent, s_xsnap;
-    int hsize;
+    size_t s_rest, s_edge, s_emid, s_egmax, s_ehcount, s_ehstart, s_ehitems, s_eb, s_en, s_ecount,
+        s_erow, s_eent;
+    int hsize, ehsize;
     size_t total;
     int max_bwd_iters;
 };
@@ -131,6 +133,7 @@ struct vbd_topology_s {
     std::vector<int32_t> vert_mesh;     // [nv]
     std::vector<int32_t> sv_slot;       // surface vertices as permuted slots, ascending
     std::vector<int32_t> sv_row, sv_tri;
+    std::vector<int32_t> sedge;         // [n_edge][2] surface edges, a < b (original ids), ascending
     DevSurf surf_dev{};
     // device
     char *ws = nullptr;
@@ -244,7 +247,11 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.s_gmax = take(sizeof(float) * (ntri / 256 + 1));
         L.s_hcount = take(sizeof(uint32_t) * (size_t)H);
         L.s_hstart = take(sizeof(uint32_t) * ((size_t)H + 1));
-        const size_t big = std::max<size_t>((size_t)H, nv + 1);
+        const size_t ne = T.sedge.size() / 2;
+        int HE = 1024;
+        while ((size_t)HE < 2 * ne) HE <<= 1;
+        L.ehsize = HE;
+        const size_t big = std::max<size_t>(std::max<size_t>((size_t)H, (size_t)HE), nv + 1);
         L.s_scan = take(sizeof(uint32_t) * (big / 2048 + 2));
         L.s_hitems = take(sizeof(int2) * ntri);
         L.s_tsph = take(sizeof(float4) * ntri);
@@ -253,6 +260,18 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
         L.s_crow = take(sizeof(uint32_t) * (nv + 1));
         L.s_cent = take(sizeof(int32_t) * 3 * nsv);
         L.s_xsnap = take(sizeof(float4) * nv);
+        L.s_rest = take(sizeof(float4) * nv);
+        L.s_edge = take(sizeof(int4) * ne);
+        L.s_emid = take(sizeof(float4) * ne);
+        L.s_egmax = take(sizeof(float) * (ne / 256 + 1));
+        L.s_ehcount = take(sizeof(uint32_t) * (size_t)HE);
+        L.s_ehstart = take(sizeof(uint32_t) * ((size_t)HE + 1));
+        L.s_ehitems = take(sizeof(int2) * ne);
+        L.s_eb = take(sizeof(int32_t) * ne);
+        L.s_en = take(sizeof(float4) * ne);
+        L.s_ecount = take(sizeof(uint32_t) * nv);
+        L.s_erow = take(sizeof(uint32_t) * (nv + 1));
+        L.s_eent = take(sizeof(int32_t) * 4 * ne);
     }
     L.total = off;
     return L;
@@ -326,6 +345,20 @@ void set_dev_pointers(vbd_topology_s &T)
         S.crow = (unsigned *)(b + L.s_crow);
         S.cent = (int *)(b + L.s_cent);
         S.xsnap = (float4 *)(b + L.s_xsnap);
+        S.srest = (const float4 *)(b + L.s_rest);
+        S.edge = (const int4 *)(b + L.s_edge);
+        S.emid = (float4 *)(b + L.s_emid);
+        S.egmax = (float *)(b + L.s_egmax);
+        S.ehcount = (unsigned *)(b + L.s_ehcount);
+        S.ehstart = (unsigned *)(b + L.s_ehstart);
+        S.ehitems = (int2 *)(b + L.s_ehitems);
+        S.eb = (int *)(b + L.s_eb);
+        S.en = (float4 *)(b + L.s_en);
+        S.ecount = (unsigned *)(b + L.s_ecount);
+        S.erow = (unsigned *)(b + L.s_erow);
+        S.eent = (int *)(b + L.s_eent);
+        S.n_edge = (int)(T.sedge.size() / 2);
+        S.ehmask = L.ehsize - 1;
         S.hmask = L.hsize - 1;
     }
 }
@@ -354,6 +387,10 @@ vbd_status validate_params(const vbd_topology_s &T, const vbd_step_params *p)
         if (p->n_col < 0) return fail(VBD_E_INVALID_ARG, "n_col must be >= 0");
         if (p->launch_mode == VBD_LAUNCH_PERSISTENT || p->launch_mode == VBD_LAUNCH_PERSISTENT_GRAPH)
             return fail(VBD_E_UNSUPPORTED, "mesh contacts need launch_mode PLAIN or GRAPH");
+        if (p->self_contact && (!(p->self_exclusion >= 0.f) || !std::isfinite(p->self_exclusion)))
+            return fail(VBD_E_INVALID_ARG, "self_exclusion must be finite and >= 0");
+    } else if (p->self_contact || p->edge_contacts) {
+        return fail(VBD_E_INVALID_ARG, "self_contact and edge_contacts need mesh_contacts");
     }
     (void)T;
     return VBD_OK;
@@ -394,6 +431,9 @@ StepConsts make_consts(const vbd_topology_s &T, const vbd_step_params *p)
         K.planes[i] = make_float4(q[0] * s, q[1] * s, q[2] * s, q[3] * s);
     }
     K.col_radius = p->mesh_contacts ? p->collision_radius : 0.f;
+    K.self_contact = p->mesh_contacts && p->self_contact ? 1 : 0;
+    K.self_excl = p->self_exclusion;
+    K.edge_contacts = p->mesh_contacts && p->edge_contacts ? 1 : 0;
     return K;
 }
 
@@ -745,7 +785,8 @@ void build_surface(vbd_topology_s &T)
     T.vert_mesh.assign(T.nv, 0);
     for (int m = 0; m < T.n_meshes; ++m)
         for (int64_t v = T.vert_off[m]; v < T.vert_off[m + 1]; ++v) T.vert_mesh[v] = m;
-    if (T.n_meshes < 2 || T.nt == 0) return;
+    T.sedge.clear();
+    if (T.nt == 0) return;
     // faces bucketed by their smallest vertex id (counting sort), then each
     // bucket sorted by the other two ids: the output is in ascending order of
     // the sorted id triples, linear in the number of faces
@@ -814,6 +855,9 @@ void build_surface(vbd_topology_s &T)
             ed.push_back({std::min(a, b), std::max(a, b), t, k});
         }
     std::sort(ed.begin(), ed.end());
+    for (size_t i = 0; i < ed.size(); ++i)
+        if (i == 0 || ed[i][0] != ed[i - 1][0] || ed[i][1] != ed[i - 1][1])
+            T.sedge.insert(T.sedge.end(), {ed[i][0], ed[i][1]});
     T.surf_adj.assign(3 * (size_t)ntri, -1);
     for (size_t i = 0; i < ed.size();) {
         size_t j = i + 1;
@@ -959,6 +1003,7 @@ GraphKey make_key(const vbd_step_params *p, std::vector<const void *> ptrs, void
     push(&p->mesh_contacts, 4); push(&p->collision_radius, 4); push(&p->n_col, 4);
     push(&p->backward_recorded, 4);
     push(&p->check_finite, 4);
+    push(&p->self_contact, 4); push(&p->self_exclusion, 4); push(&p->edge_contacts, 4);
     return k;
 }
 
@@ -1458,6 +1503,24 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         HIP_TRY(up(T->lay.s_sv_tri, T->sv_tri.data(), 4 * T->sv_tri.size()));
         HIP_TRY(up(T->lay.s_ctri, ctri.data(), 4 * ctri.size()));
         HIP_TRY(launch_zero_u32((unsigned *)(T->ws + T->lay.s_crow), T->nv + 1, s));
+        // rest positions (self-contact exclusion) and surface edges as
+        // {permuted a, permuted b, mesh, 0} in ascending original-id order
+        std::vector<float4> srest(T->nv);
+        for (int sl = 0; sl < T->nv; ++sl) {
+            const double *r = &T->rest[3 * (size_t)T->perm[sl]];
+            srest[sl] = make_float4((float)r[0], (float)r[1], (float)r[2], 0.f);
+        }
+        const size_t ne = T->sedge.size() / 2;
+        std::vector<int4> sedge(ne);
+        for (size_t e = 0; e < ne; ++e) {
+            const int32_t a = T->sedge[2 * e], b = T->sedge[2 * e + 1];
+            sedge[e] = make_int4(T->iperm[a], T->iperm[b], T->vert_mesh[a], 0);
+        }
+        HIP_TRY(up(T->lay.s_rest, srest.data(), sizeof(float4) * srest.size()));
+        HIP_TRY(up(T->lay.s_edge, sedge.data(), sizeof(int4) * sedge.size()));
+        HIP_TRY(launch_zero_u32((unsigned *)(T->ws + T->lay.s_erow), T->nv + 1, s));
+        std::vector<int32_t> no_partner(ne, -1);
+        HIP_TRY(up(T->lay.s_eb, no_partner.data(), 4 * no_partner.size()));
     }
     HIP_TRY(launch_zero_u32(T->dev.flags, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1507,8 +1570,10 @@ vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t by
     }
     case VBD_Q_TET_ORDER: return give(T->tet_order.data(), 4 * T->tet_order.size());
     case VBD_Q_SURFACE: return give(T->surf.data(), 4 * T->surf.size());
+    case VBD_Q_SURFACE_EDGES: return give(T->sedge.data(), 4 * T->sedge.size());
     case VBD_Q_SURFACE_COUNTS: {
-        int64_t c[2] = {(int64_t)(T->surf.size() / 3), (int64_t)T->sv_slot.size()};
+        int64_t c[3] = {(int64_t)(T->surf.size() / 3), (int64_t)T->sv_slot.size(),
+                        (int64_t)(T->sedge.size() / 2)};
         return give(c, sizeof(c));
     }
     case VBD_Q_SNAPSHOT_REGION: {
@@ -1670,6 +1735,28 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
                      make_key(p, {x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in, gvp_in, g_E},
                               stream),
                      s, [&](hipStream_t q) { return enqueue(q, true); });
+}
+
+vbd_status vbd_detect_edges(vbd_topology T, const vbd_step_params *p, const float *x,
+                            const float *x_t, int32_t *partner_out, void *stream)
+{
+    vbd_status st = check_ready(T);
+    if (st) return st;
+    if ((st = validate_params(*T, p))) return st;
+    if (!p->mesh_contacts || !p->edge_contacts)
+        return fail(VBD_E_INVALID_ARG, "params->mesh_contacts and edge_contacts must be 1");
+    if (T->nv > 0 && (!x || !x_t || (!partner_out && !T->sedge.empty())))
+        return fail(VBD_E_INVALID_ARG, "NULL device pointer");
+    if (T->nv == 0 || T->sedge.empty()) return VBD_OK;
+    const StepConsts K = make_consts(*T, p);
+    hipStream_t s = (hipStream_t)stream;
+    DevTopo Dt = T->dev;
+    Dt.x = T->dev.xt;
+    HIP_TRY(launch_load_x(Dt, x_t, s));
+    HIP_TRY(launch_load_x(T->dev, x, s));
+    HIP_TRY(launch_detect(T->dev, T->surf_dev, T->dev.x, K, s));
+    HIP_TRY(launch_store_edge_partners(T->surf_dev, partner_out, s));
+    return VBD_OK;
 }
 
 vbd_status vbd_detect_contacts(vbd_topology T, const vbd_step_params *p, const float *x,

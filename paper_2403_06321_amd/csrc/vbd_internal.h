@@ -45,6 +45,9 @@ struct StepConsts {
     float4 spheres[kMaxObstacles]; // cx, cy, cz, R
     float4 planes[kMaxObstacles];  // unit normal, offset
     float col_radius;              // mesh-mesh detection radius
+    int self_contact;              // pairs within one mesh (rest distance > self_excl)
+    float self_excl;
+    int edge_contacts;             // edge-edge elements
 };
 
 // Device-side view of a bound workspace.
@@ -132,7 +135,20 @@ struct DevSurf {
     int *cent;             // [3 n_sv] colliding vertex of each corner entry
     float4 *xsnap;         // [n_verts] positions of each color as of the start of its
                            // phase (read for same-color contact partners)
-    int n_tri, n_sv, hmask;
+    const float4 *srest;   // [n_verts] rest positions (self-contact exclusion)
+    // edge-edge elements
+    const int4 *edge;      // [n_edge] {a, b, mesh, 0} permuted ids, ascending original (a, b)
+    float4 *emid;          // [n_edge] midpoint and half length
+    float *egmax;          // [ceil(n_edge / 256)] per-block maximum half length
+    unsigned *ehcount;     // [HE] bucket sizes, then fill cursors
+    unsigned *ehstart;     // [HE + 1]
+    int2 *ehitems;         // [n_edge] {edge, its mesh} grouped by bucket
+    int *eb;               // [n_edge] partner edge of the element found from this edge, or -1
+    float4 *en;            // [n_edge] the element's fixed normal
+    unsigned *ecount;      // [n_verts] element entries per slot, then fill cursors
+    unsigned *erow;        // [n_verts + 1]
+    int *eent;             // [4 n_edge] kept elements (their first edge) of each slot, ascending
+    int n_tri, n_sv, hmask, n_edge, ehmask;
 };
 
 struct LaunchCfg {
@@ -165,6 +181,8 @@ hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepC
 // corner CSR (S.crow, S.cent).
 hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X,
                          const StepConsts &K, hipStream_t s);
+// Edge partners of the kept elements (S.eb filtered) -> partner_out.
+hipError_t launch_store_edge_partners(const DevSurf &S, int *partner_out, hipStream_t s);
 // x (original order) -> T.x, and S.ctri -> tri_out (original order, or -1).
 hipError_t launch_load_x(const DevTopo &T, const float *x, hipStream_t s);
 hipError_t launch_store_ctri(const DevTopo &T, const DevSurf &S, int *tri_out, hipStream_t s);

@@ -341,6 +341,41 @@ __device__ __forceinline__ bool vt_term(const StepConsts &K, const float4 *Xt, f
 }
 
 // Position of a contact partner q during the phase over slots [vb, ve).
+// Edge-edge contact element (Sec. 3.5) seen from one of its four vertices:
+// role 0, 1 the first edge's ends (x0, x1), 2, 3 the second's (x2, x3).
+// E = k_c/2 d^2, d = delta - (x_a - x_b).n with x_a, x_b the closest points
+// (recomputed here) and n fixed; with s, u and n held fixed,
+// dd/dx0 = -(1 - s) n, dd/dx1 = -s n, dd/dx2 = (1 - u) n, dd/dx3 = u n.
+// Friction (Sec. 3.6) on (x_a - x_a^t) - (x_b - x_b^t) with the same weights.
+__device__ __forceinline__ bool ee_term(const StepConsts &K, const float4 *Xt, float3 x0, float3 x1,
+                                        float3 x2, float3 x3, int4 A, int4 B, float3 n, int role,
+                                        Acc &a)
+{
+    const SegPt sp = seg_closest(x0, x1, x2, x3);
+    const float3 xa = x0 + (x1 - x0) * sp.s, xb = x2 + (x3 - x2) * sp.u;
+    const float d = K.delta - dot3(xa - xb, n);
+    if (!(d > 0.f)) return false;
+    const float g = role == 0 ? -(1.f - sp.s) : (role == 1 ? -sp.s : (role == 2 ? 1.f - sp.u : sp.u));
+    const float kd = K.kc * d * g, kh = K.kc * g * g;
+    a.fx -= kd * n.x; a.fy -= kd * n.y; a.fz -= kd * n.z;
+    a.hxx += kh * n.x * n.x; a.hxy += kh * n.x * n.y; a.hxz += kh * n.x * n.z;
+    a.hyy += kh * n.y * n.y; a.hyz += kh * n.y * n.z; a.hzz += kh * n.z * n.z;
+    if (K.fric_mu > 0.f) {
+        const float3 ta0 = xyz(Xt[A.x]), ta1 = xyz(Xt[A.y]), tb0 = xyz(Xt[B.x]), tb1 = xyz(Xt[B.y]);
+        const float3 dx = (xa - (ta0 + (ta1 - ta0) * sp.s)) - (xb - (tb0 + (tb1 - tb0) * sp.u));
+        const float3 u = dx - n * dot3(dx, n);
+        const float un = sqrtf(dot3(u, u));
+        const float hev = K.fric_hev;
+        const float f1u = (un < hev) ? (2.0f / hev - un / (hev * hev)) : (1.0f / un);
+        const float sf = K.fric_mu * K.kc * d * f1u;
+        const float sg = sf * g, sg2 = sf * g * g;
+        a.fx += sg * u.x; a.fy += sg * u.y; a.fz += sg * u.z;
+        a.hxx += sg2 * (1.f - n.x * n.x); a.hxy -= sg2 * n.x * n.y; a.hxz -= sg2 * n.x * n.z;
+        a.hyy += sg2 * (1.f - n.y * n.y); a.hyz -= sg2 * n.y * n.z; a.hzz += sg2 * (1.f - n.z * n.z);
+    }
+    return true;
+}
+
 __device__ __forceinline__ float3 phase_pos(const float4 *X, const float4 *Xs, int q, int vb, int ve)
 {
     return xyz((q >= vb && q < ve) ? Xs[q] : X[q]);
@@ -376,6 +411,19 @@ __device__ __forceinline__ float contact_terms(const DevTopo &T, const DevSurf &
         const float3 c1 = role == 1 ? xi : phase_pos(X, Xs, tr.y, vb, ve);
         const float3 c2 = role == 2 ? xi : phase_pos(X, Xs, tr.z, vb, ve);
         if (vt_term(K, T.xt, phase_pos(X, Xs, va, vb, ve), va, c0, c1, c2, tr, role, a)) nc += 1.f;
+    }
+    if (K.edge_contacts) {
+        const int r1 = (int)S.erow[p + 1];
+        for (int e = (int)S.erow[p] + lane; e < r1; e += L) {
+            const int el = S.eent[e];
+            const int4 A = S.edge[el], B = S.edge[S.eb[el]];
+            const int role = A.x == p ? 0 : (A.y == p ? 1 : (B.x == p ? 2 : 3));
+            const float3 x0 = role == 0 ? xi : phase_pos(X, Xs, A.x, vb, ve);
+            const float3 x1 = role == 1 ? xi : phase_pos(X, Xs, A.y, vb, ve);
+            const float3 x2 = role == 2 ? xi : phase_pos(X, Xs, B.x, vb, ve);
+            const float3 x3 = role == 3 ? xi : phase_pos(X, Xs, B.y, vb, ve);
+            if (ee_term(K, T.xt, x0, x1, x2, x3, A, B, xyz(S.en[el]), role, a)) nc += 1.f;
+        }
     }
     return nc;
 }

@@ -350,7 +350,7 @@ def test_surface_matches_oracle_with_outward_orientation():
     w = W.config_block_stack(cols=2, levels=2, n=4)
     t = Topology.from_workload(w, bind=False)
     surf = t.query(N.Q_SURFACE)
-    n_tri, n_sv = t.query(N.Q_SURFACE_COUNTS)
+    n_tri, n_sv, n_edge = t.query(N.Q_SURFACE_COUNTS)
     m = O.Model.from_workload(w)
     assert n_tri == surf.shape[0] == m.surf_tris.shape[0] == w.n_meshes * 2 * 6 * 3 ** 2
     assert n_sv == np.unique(surf).size
@@ -361,9 +361,18 @@ def test_surface_matches_oracle_with_outward_orientation():
     for tri in surf:
         k = int(np.argmin(tri))
         assert tuple(np.roll(tri, -k)) in rot
-    # a single mesh has no surface (contacts are between meshes)
-    t1 = Topology.from_workload(W.tet_cube(4, 0), bind=False)
-    assert tuple(t1.query(N.Q_SURFACE_COUNTS)) == (0, 0)
+    # surface edges: the distinct edges of the surface triangles, ascending
+    edges = t.query(N.Q_SURFACE_EDGES)
+    ref = np.unique(np.sort(np.concatenate([surf[:, [0, 1]], surf[:, [1, 2]], surf[:, [2, 0]]]), axis=1),
+                    axis=0)
+    assert n_edge == edges.shape[0] and np.array_equal(edges, ref)
+    # a single mesh has its surface too (self-contact); springs alone have none
+    w1 = W.tet_cube(4, 0)
+    t1 = Topology.from_workload(w1, bind=False)
+    n_f = 2 * 6 * 3 ** 2                       # closed surface: E = 3F/2, V = E - F + 2
+    assert tuple(t1.query(N.Q_SURFACE_COUNTS)) == (n_f, n_f // 2 + 2, 3 * n_f // 2)
+    t2 = Topology.from_workload(W.spring_net(n=4), bind=False)
+    assert tuple(t2.query(N.Q_SURFACE_COUNTS)) == (0, 0, 0)
 
 
 def test_given_coloring_layout_and_validation():

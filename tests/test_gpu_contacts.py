@@ -104,3 +104,112 @@ def test_graph_replays_match_plain_bitwise_and_persistent_is_refused():
     with pytest.raises(N.VBDError) as e:
         t.step(x, v, vp, E, w.params, N.LAUNCH_PERSISTENT)
     assert e.value.status == -6
+
+
+# ---------------------------------------------------------------- edge-edge --
+def _edge_pairs(edges, partner):
+    return sorted((tuple(edges[e]), tuple(edges[p])) for e, p in enumerate(partner) if p >= 0)
+
+
+def _oracle_pairs(ev):
+    return sorted(((int(a), int(b)), (int(c), int(d))) for a, b, c, d in ev)
+
+
+def _gpu_edges(w, p, x, xt):
+    import torch
+    from paper_2403_06321_amd import _native as N
+    from paper_2403_06321_amd.api import Topology
+    t = Topology.from_workload(w)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda").contiguous()
+    xtd = torch.tensor(xt, dtype=torch.float32, device="cuda").contiguous()
+    partner = t.detect_edges(xd, p, xtd).cpu().numpy()
+    return _edge_pairs(t.query(N.Q_SURFACE_EDGES), partner)
+
+
+def test_edge_detection_matches_oracle_on_crossed_bars():
+    """The crossed cubes at rest and along the oracle's rollout (closest points
+    on each state, normals from the state before it): the same edge-edge
+    element set, compared as integers."""
+    w = W.config_crossed_bars()
+    m = O.Model.from_workload(w)
+    st = oracle_states(w, w.frames)
+    for f in range(0, w.frames, 3):
+        x, xt = st[f + 1][0], st[f][0]
+        ev, _ = O.detect_edges(m, w.params, x, xt)
+        assert ev.shape[0] == 1
+        assert _gpu_edges(w, w.params, x, xt) == _oracle_pairs(ev)
+    say(f"crossed bars: edge elements match over {w.frames} frames")
+
+
+def test_self_contact_detection_matches_oracle():
+    """The folding C with its upper slab lowered into the contact layer and
+    shifted off the lattice lines (no ties between triangles): the same
+    vertex-triangle self-contacts, and none with self-contact off."""
+    w = W.config_folding_c()
+    x = w.x0.copy()
+    up = (w.rest[:, 2] > 1.5 * W.EDGE) & (w.rest[:, 0] > 1.5 * W.EDGE)
+    x[up, 2] -= W.EDGE - 0.5 * w.params.contact_thickness
+    x[up, 0] += 0.33 * W.EDGE * (w.rest[up, 0] - 1.5 * W.EDGE) / w.rest[:, 0].max()
+    x[up, 1] += 0.21 * W.EDGE
+    m = O.Model.from_workload(w)
+    tri_o = O.detect_contacts(m, w.params, x)
+    tri_g, surf_g = _gpu_detect(w, w.params, x)
+    assert (tri_o >= 0).sum() > 10
+    assert _tri_keys(surf_g, tri_g) == _tri_keys(m.surf_tris, tri_o)
+    off = replace(w.params, self_contact=False)
+    tri_g, _ = _gpu_detect(w, off, x)
+    assert not np.any(tri_g >= 0)
+    say(f"folding C lowered: {(tri_o >= 0).sum()} self-contacts match")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_crossed_bars_steps_match_oracle(mode):
+    """Edge-on-edge contact carrying the upper cube, per step from the
+    oracle's state, strict (the oracle's own spread under FP32-size state
+    perturbations is below 3e-8 on every frame)."""
+    w = W.config_crossed_bars()
+    st = oracle_states(w, w.frames)
+    resync_parity(w, st, launch_mode=mode, tol=1e-5, label=f"crossed bars mode {mode}")
+
+
+def test_crossed_bars_with_friction_and_redetection():
+    w = W.config_crossed_bars(frames=6, n_iters=30)
+    p = replace(w.params, friction_mu=0.3, friction_eps_v=1e-2, n_col=10)
+    w.v0[w.vert_offsets[1]:, 1] = 0.2          # the upper cube slides along its edge's cross direction
+    st = oracle_states(w, w.frames, params=p)
+    resync_parity(w, st, params=p, tol=1e-5, label="crossed bars friction, n_col=10")
+
+
+def test_folding_c_self_contact_steps():
+    """The C's upper slab falls onto its lower slab (self-contact: vertex-
+    triangle and edge-edge elements of one mesh).  Per-step parity at 1e-5 on
+    every frame where the oracle itself is stable under a U(+-3e-8 m) state
+    perturbation (three draws); on the impact frames, where contact
+    activation switches the penalty Hessian and the oracle's own step moves by
+    more than 1e-6, the GPU's step stays within twice the oracle's spread."""
+    from gpu_util import bbox_diag, resync_errors
+    w = W.config_folding_c()
+    st = oracle_states(w, w.frames)
+    m = O.Model.from_workload(w)
+    free = (w.pinned == 0)[:, None]
+    spread = []
+    for f in range(w.frames):
+        worst = 0.0
+        for d in range(3):
+            rng = np.random.default_rng(1000 * f + d)
+            x, v, vp = st[f]
+            xo, _, _, _ = O.step(m, w.params, x + rng.uniform(-3e-8, 3e-8, size=x.shape) * free, v, vp,
+                                 w.tet_E)
+            x1 = st[f + 1][0]
+            worst = max(worst, np.linalg.norm(xo - x1, axis=1).max() / bbox_diag(x1))
+        spread.append(worst)
+    errs = resync_errors(w, st, launch_mode=0)
+    n_strict = 0
+    for f, e in enumerate(errs):
+        say(f"folding C frame {f}: GPU max {e.max():.2e}, oracle spread {spread[f]:.1e}")
+        if spread[f] <= 1e-6:
+            assert e.max() <= 1e-5, f"frame {f}: {e.max():.3e}"
+            n_strict += 1
+        else:
+            assert e.max() <= 2 * spread[f], f"frame {f}: {e.max():.3e} vs spread {spread[f]:.3e}"
+    assert n_strict >= w.frames // 2
