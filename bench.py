@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=50)
     ap.add_argument("--profile-only", default="",
-                    help="run only one workload for a profiler: cube|batch|copy|stack|adjoint")
+                    help="run only one workload for a profiler: cube|batch|copy|stack|adjoint|floor")
     ap.add_argument("--lanes", type=int, default=8, help="--profile-only: lanes per vertex")
     ap.add_argument("--block", type=int, default=128, help="--profile-only: block size")
     ap.add_argument("--remap", type=int, default=1, help="--profile-only: XCD remap")
@@ -267,6 +267,10 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 2 * 4 * n}))
         return
 
+    if args.profile_only == "floor":
+        print(json.dumps(phase_floor(dev, W, Topology)))
+        return
+
     if args.profile_only == "stack":
         # mesh-mesh contacts: 4 levels of 8x8 stacked 9^3 cubes, plain launches
         ws = W.config_block_stack(cols=8, levels=4, n=9, coloring="smallest_last")
@@ -419,9 +423,37 @@ def main():
     print(json.dumps(out))
 
 
+def phase_floor(dev, W, Topology):
+    """Cost of one color phase with (almost) no work: a 2x2x2 cube (8 colors
+    of one vertex) stepped with 2000 iterations, per-color kernels replayed
+    from a hipGraph against the persistent kernel's grid barrier (the
+    autotuned grid of the 65^3 cube: the barrier's cost depends on the grid,
+    not on the work)."""
+    import dataclasses
+    import torch
+    w = W.tet_cube(2, 0, n_iters=2000, pin_bottom=False)
+    t = Topology.from_workload(w)
+    res = {}
+    for name, mode, cfg in (("graph_us", MODES["graph"], dict(block_size=64)),
+                            ("persistent_256_blocks_us", MODES["persistent_graph"],
+                             dict(block_size=512, blocks_per_cu=1)),
+                            ("persistent_1024_blocks_us", MODES["persistent_graph"],
+                             dict(block_size=256, blocks_per_cu=4))):
+        t.launch_config = cfg
+        secs, _ = time_frames(t, w, mode, 5, 2, dev, autotune=False)
+        res[name] = secs / 5 / (w.params.n_iters * t.n_colors) * 1e6
+    res["workload"] = (f"2x2x2 cube, {t.n_colors} colors of one vertex, 2000 iterations; "
+                       "per color phase")
+    return res
+
+
 def extras(dev, W, Topology):
     import torch
     res = {}
+    res["phase_floor"] = phase_floor(dev, W, Topology)
+    log(f"[bench] empty color phase: graph {res['phase_floor']['graph_us']:.2f} us, persistent "
+        f"{res['phase_floor']['persistent_256_blocks_us']:.2f} us (256 blocks), "
+        f"{res['phase_floor']['persistent_1024_blocks_us']:.2f} us (1024 blocks)")
     # batched: 512 meshes, persistent hipGraph vs the plain kernel mesh by mesh
     wb = W.config_batch(coloring="smallest_last")
     log(f"[bench] batch: {wb.n_meshes} meshes, {wb.n_verts} verts, {wb.n_tets} tets")

@@ -216,7 +216,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.prev1 = take(sizeof(float4) * nv);
     L.prev2 = take(sizeof(float4) * nv);
     L.collided = take(nv);
-    L.flags = take(sizeof(uint32_t) * 64);
+    L.flags = take(sizeof(uint32_t) * kFlagWords);
     L.max_bwd_iters = max_bwd_iters;
     if (max_bwd_iters > 0) {
         L.snaps = take(sizeof(float4) * nv * (size_t)(max_bwd_iters + 1));
@@ -1522,7 +1522,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         std::vector<int32_t> no_partner(ne, -1);
         HIP_TRY(up(T->lay.s_eb, no_partner.data(), 4 * no_partner.size()));
     }
-    HIP_TRY(launch_zero_u32(T->dev.flags, 64, s));
+    HIP_TRY(launch_zero_u32(T->dev.flags, kFlagWords, s));
     HIP_TRY(hipStreamSynchronize(s));
     T->bound = true;
     T->fwd_graph.reset();

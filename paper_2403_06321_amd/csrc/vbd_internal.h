@@ -18,7 +18,7 @@ using PairEnt = int4;
 
 constexpr int kMaxObstacles = 8;
 
-// Entries of the device flag array (DevTopo::flags, 64 x 32 bit):
+// Entries of the device flag array (DevTopo::flags, kFlagWords x 32 bit):
 //   0 barrier arrivals, 1 barrier abort, 3..5 abort diagnostics (arrivals
 //   seen, target, grid), kFlagNonfinite / kFlagNonfiniteTotal non-finite
 //   output values since the last vbd_check / counter reset, kFlagSkips a
@@ -26,6 +26,17 @@ constexpr int kMaxObstacles = 8;
 constexpr int kFlagNonfinite = 6;
 constexpr int kFlagNonfiniteTotal = 7;
 constexpr int kFlagSkips = 8;
+// The persistent kernel's barrier counters from kFlagBar on, one 128-B line
+// each: kBarGroups group counters (block index mod kBarGroups, the XCD a
+// block runs on under the default round-robin dispatch), then the global one.
+constexpr int kFlagBar = 64;
+constexpr int kBarGroups = 8;
+constexpr int kBarStride = 32;   // 32 x 4 B = 128 B
+constexpr int kFlagWords = kFlagBar + (kBarGroups + 1) * kBarStride;
+// Waves per SIMD that the persistent grid fills: every persistent kernel is
+// compiled for at least this occupancy (amdgpu_waves_per_eu), so the grid is
+// resident by construction (a CPU test reads the compiler's occupancy).
+constexpr int kPersistentWavesPerSimd = 4;
 
 // Per-step constants passed by value to every kernel.
 struct StepConsts {

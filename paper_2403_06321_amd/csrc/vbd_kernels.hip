@@ -519,7 +519,7 @@ __global__ void k_predict(DevTopo T, const float *x, const float *v, const float
                           StepConsts K, int reset_flags, int cheb)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && reset_flags) T.flags[0] = 0u;
+    if (p <= kBarGroups && reset_flags) T.flags[kFlagBar + p * kBarStride] = 0u;
     if (p >= T.n_verts) return;
     const int o = T.perm[p];
     const float3 xt = ld3(x, o), vt = ld3(v, o);
@@ -632,33 +632,46 @@ __global__ void k_finalize(DevTopo T, float *x, float *v, float *vp, float h)
     st3(x, o, xn);
 }
 
-// Device-wide barrier for the persistent kernel.  flags[0] counts arrivals
-// (reset to 0 by k_predict before the launch); barrier number k completes
-// when it reaches k * nblocks.  The wait is bounded: after kSpinLimit polls
-// the block raises flags[1] and every block leaves at its next barrier, so
-// the kernel always terminates.  Returns true when the kernel must stop.
+// Device-wide barrier for the persistent kernel, in two levels: a block
+// arrives at its group's counter (block index mod kBarGroups, one 128-B line
+// per group, so the arrivals of different groups do not serialise on one
+// address), the last arrival of a group arrives at the global counter, and
+// every block waits for the global count.  Counters only grow (reset to 0 by
+// k_predict before the launch): barrier number k completes when the global
+// counter reaches k * (number of groups).  The wait is bounded: after
+// kSpinLimit polls the block raises flags[1] and every block leaves at its
+// next barrier, so the kernel always terminates.  Returns true when the
+// kernel must stop.
 constexpr long kSpinLimit = 1L << 20;
 
-__device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned target)
+__device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned k)
 {
     __shared__ int s_abort;
     __syncthreads();
     if (threadIdx.x == 0) {
         int abort = 0;
+        const unsigned nb = gridDim.x, grp = blockIdx.x % kBarGroups;
+        const unsigned n_groups = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
+        const unsigned in_grp = (nb - grp + kBarGroups - 1) / kBarGroups;
+        unsigned *gc = flags + kFlagBar + grp * kBarStride;
+        unsigned *all = flags + kFlagBar + kBarGroups * kBarStride;
+        const unsigned target = k * n_groups;
         // release this block's writes (all waves passed the barrier above),
-        // arrive, then poll with plain agent-scope loads; one acquire fence
-        // after the wait makes the other blocks' writes visible to the CU
+        // arrive; the group's last arrival passes the group on (its release
+        // covers the group: every earlier arrival released before its add)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(&flags[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == k * in_grp)
+            __hip_atomic_fetch_add(all, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         long spins = 0;
-        while (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 abort = 1;
                 break;
             }
             if (++spins > kSpinLimit) {
                 // record what the waiting block saw, for vbd_check's message
-                const unsigned seen = __hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned seen = __hip_atomic_load(all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_max(&flags[3], seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_max(&flags[4], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&flags[5], gridDim.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -676,8 +689,8 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned target)
 }
 
 template <int L, int KU, bool TETS, bool SPRINGS, bool CR>
-__global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts K, int n_iters,
-                                                          int remap)
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(kPersistentWavesPerSimd)))
+void k_persistent(DevTopo T, StepConsts K, int n_iters, int remap)
 {
     const int nb = gridDim.x;
     const int b = xcd_block(blockIdx.x, nb, remap);
@@ -699,14 +712,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevTopo T, StepConsts 
                 solve_vertex<L, KU, TETS, SPRINGS, false, CR>(T, K, p, lane, p < cend, vb, ve, inc);
             }
             ++nbar;
-            if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
+            if (grid_barrier(T.flags, nbar)) return;
         }
         if (K.cheb_rho > 0.f) {
             const float om = cheb_omega(it, K.cheb_rho);
             for (int p = b * blockDim.x + threadIdx.x; p < T.n_free; p += nb * blockDim.x)
                 cheb_vertex(T, p, om);
             ++nbar;
-            if (grid_barrier(T.flags, nbar * (unsigned)nb)) return;
+            if (grid_barrier(T.flags, nbar)) return;
         }
     }
 }
@@ -1329,11 +1342,11 @@ static hipError_t persistent_go(const DevTopo &T, const StepConsts &K, int n_ite
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, cfg.block, 0);
     if (e != hipSuccess) return e;
     if (per_cu <= 0) return hipErrorInvalidConfiguration;
-    // The occupancy query does not see every residency limit (measured on
-    // gfx950: this kernel's 87 SGPRs allow 7 waves per SIMD where the query
-    // assumes 8), so the persistent grid uses at most 3/4 of what it reports.
-    per_cu = per_cu * 3 / 4;
-    if (per_cu < 1) per_cu = 1;
+    // The occupancy query does not see every residency limit (on gfx950 a
+    // kernel's SGPRs can allow fewer waves than it assumes), so the grid
+    // fills kPersistentWavesPerSimd waves per SIMD (4 SIMDs per CU), an
+    // occupancy every persistent kernel is compiled for.
+    per_cu = std::min(per_cu, std::max(1, kPersistentWavesPerSimd * 4 * 64 / cfg.block));
     if (cfg.blocks_per_cu > 0 && cfg.blocks_per_cu < per_cu) per_cu = cfg.blocks_per_cu;
     const int grid = per_cu * n_cu;
     if (grid_out) *grid_out = grid;
