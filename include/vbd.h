@@ -178,8 +178,10 @@ enum {
                                   phase of vbd_step_backward */
     VBD_Q_PHASE_COUNTS = 18,   /* int64[n_colors][4]: tet pairs, spring entries, distinct
                                   neighbour vertices and free vertices of each color */
-    VBD_Q_SURFACE_EDGES = 19   /* int32[n_surf_edges][2]: the distinct edges of the surface
+    VBD_Q_SURFACE_EDGES = 19,  /* int32[n_surf_edges][2]: the distinct edges of the surface
                                   triangles, original ids a < b, ascending (a, b) */
+    VBD_Q_XCD_SPLIT = 20       /* int32[n_colors][9]: slot boundaries of the 8 parts of each
+                                  color that launch mapping 3 runs on XCDs 0..7 */
 };
 vbd_status vbd_topology_query(vbd_topology topo, int32_t what, void *host_out, size_t bytes);
 vbd_status vbd_topology_destroy(vbd_topology topo);
@@ -353,7 +355,10 @@ typedef struct {
     int32_t xcd_remap;          /* 0: blocks as launched (round-robin over the 8
                                    XCDs), 1: each XCD a contiguous range of blocks,
                                    2: chunks of 16 consecutive blocks dealt to the
-                                   XCDs in turn; other values: VBD_E_INVALID_ARG */
+                                   XCDs in turn, 3: each XCD a contiguous part of the
+                                   color cut at mesh boundaries with about equal work
+                                   (VBD_Q_XCD_SPLIT; the color solve only, elsewhere
+                                   as 1); other values: VBD_E_INVALID_ARG */
     int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */
     int32_t tet_unroll;         /* 1..3 tet entries per lane loaded together */
     int32_t compact_records;    /* 1: 32-B pair records (|m|^2 summed from w in the

@@ -16,7 +16,8 @@ COLOR_ID_ORDER, COLOR_SMALLEST_LAST, COLOR_DSATUR = 0, 1, 2
 
 (Q_COUNTS, Q_COLORS, Q_PERM, Q_COLOR_OFFSETS, Q_TET_ROWS, Q_TET_ENTRIES, Q_SPRING_ROWS,
  Q_SPRING_NBRS, Q_MASS, Q_DMINV, Q_VOLUME, Q_PHASE_BYTES, Q_TET_ORDER, Q_REST_FRAME, Q_SURFACE,
- Q_SURFACE_COUNTS, Q_SNAPSHOT_REGION, Q_ADJ_PHASE_BYTES, Q_PHASE_COUNTS, Q_SURFACE_EDGES) = range(20)
+ Q_SURFACE_COUNTS, Q_SNAPSHOT_REGION, Q_ADJ_PHASE_BYTES, Q_PHASE_COUNTS, Q_SURFACE_EDGES,
+ Q_XCD_SPLIT) = range(21)
 
 # every symbol include/vbd.h declares
 EXPORTS = ["vbd_build_topology", "vbd_color", "vbd_color_greedy", "vbd_color_given", "vbd_workspace_size", "vbd_bind_workspace",

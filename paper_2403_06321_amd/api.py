@@ -150,7 +150,8 @@ class Topology:
                 N.Q_REST_FRAME: (np.float64, 6 * c["n_tets"]),
                 N.Q_SURFACE_COUNTS: (np.int64, 3), N.Q_SNAPSHOT_REGION: (np.int64, 3),
                 N.Q_ADJ_PHASE_BYTES: (np.float64, c["n_colors"]),
-                N.Q_PHASE_COUNTS: (np.int64, 4 * c["n_colors"])}
+                N.Q_PHASE_COUNTS: (np.int64, 4 * c["n_colors"]),
+                N.Q_XCD_SPLIT: (np.int32, 9 * c["n_colors"])}
         if what == N.Q_SURFACE:
             n_tri = int(self.query(N.Q_SURFACE_COUNTS)[0])
             out = np.zeros((n_tri, 3), np.int32)

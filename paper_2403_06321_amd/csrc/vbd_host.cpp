@@ -53,7 +53,7 @@ inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t vol, tet_perm, tet_row, tet_ent, ell, pa, pw, pb, pws, pair_tet, ell_info, spr_ell,
-        spr_info, perm, mass, color_off;
+        spr_info, perm, mass, color_off, xsplit;
     size_t x, xt, y, prev1, prev2, collided, flags;
     size_t snaps, xbar, ybar, xtbar, vbar, contrib, cin, tgt, ebar_pair, tet_pairs;
     // mesh-mesh contacts (only when the topology has a surface)
@@ -134,6 +134,8 @@ struct vbd_topology_s {
     std::vector<int32_t> sv_slot;       // surface vertices as permuted slots, ascending
     std::vector<int32_t> sv_row, sv_tri;
     std::vector<int32_t> sedge;         // [n_edge][2] surface edges, a < b (original ids), ascending
+    std::vector<int32_t> xsplit;        // [n_colors][9] mesh-aligned XCD parts of each color
+    std::vector<int32_t> xsplit_max;    // [n_colors] largest part (vertices)
     DevSurf surf_dev{};
     // device
     char *ws = nullptr;
@@ -210,6 +212,7 @@ Layout make_layout(const vbd_topology_s &T, int max_bwd_iters)
     L.perm = take(sizeof(int32_t) * nv);
     L.mass = take(sizeof(float) * nv);
     L.color_off = take(sizeof(int32_t) * (size_t)(T.n_colors + 1));
+    L.xsplit = take(sizeof(int32_t) * 9 * (size_t)T.n_colors);
     L.x = take(sizeof(float4) * nv);
     L.xt = take(sizeof(float4) * nv);
     L.y = take(sizeof(float4) * nv);
@@ -890,6 +893,61 @@ int4 incidence(const vbd_topology_s &T, int c)
     return make_int4(T.ell_info[c].x, T.ell_info[c].y, T.spr_info[c].x, T.spr_info[c].y);
 }
 
+// Mesh-aligned XCD parts of every color (launch mapping 3): 8 contiguous
+// parts of the color's slot range with about equal work, each cut at the mesh
+// boundary nearest its target unless that is more than 1/16 of the color's
+// work away (large meshes are cut inside), so that the vertices of one mesh
+// and color, which read each other's neighbour positions, mostly run on one
+// XCD and share its L2.  Work = vertices: every vertex of a color walks the
+// color's padded degree.
+void build_xcd_split(vbd_topology_s &T)
+{
+    T.xsplit.assign(9 * (size_t)T.n_colors, 0);
+    T.xsplit_max.assign(T.n_colors, 0);
+    for (int c = 0; c < T.n_colors; ++c) {
+        const int b = T.color_off[c], e = T.color_off[c + 1], n = e - b;
+        std::vector<double> cum((size_t)n + 1, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const int sl = b + i;
+            (void)sl;
+            cum[i + 1] = cum[i] + 1.0;
+        }
+        std::vector<int> bounds{0};
+        for (int i = 1; i < n; ++i)
+            if (T.vert_mesh[T.perm[b + i]] != T.vert_mesh[T.perm[b + i - 1]]) bounds.push_back(i);
+        bounds.push_back(n);
+        int32_t *xs = &T.xsplit[9 * (size_t)c];
+        xs[0] = b;
+        xs[8] = e;
+        int prev = 0;
+        for (int k = 1; k < 8; ++k) {
+            const double target = cum[n] * k / 8.0;
+            // nearest mesh boundary to the target
+            auto it = std::lower_bound(bounds.begin(), bounds.end(), 0, [&](int pos, int) {
+                return cum[pos] < target;
+            });
+            int best = it == bounds.end() ? n : *it;
+            if (it != bounds.begin() && it != bounds.end()) {
+                const int lo = *(it - 1);
+                if (target - cum[lo] < cum[best] - target) best = lo;
+            }
+            if (std::fabs(cum[best] - target) > cum[n] / 16.0) {
+                // cut inside the mesh at the target
+                best = (int)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+            }
+            best = std::max(best, prev);
+            xs[k] = b + best;
+            prev = best;
+        }
+        for (int k = 0; k < 8; ++k) T.xsplit_max[c] = std::max(T.xsplit_max[c], xs[k + 1] - xs[k]);
+    }
+}
+
+XcdSplit xcd_split(const vbd_topology_s &T, int c)
+{
+    return XcdSplit{(const int *)(T.ws + T.lay.xsplit) + 9 * (size_t)c, T.xsplit_max[c]};
+}
+
 // --------------------------------------------------------------- profiling --
 vbd_status prof_begin(vbd_topology_s &T, hipStream_t s, ProfileEvent &ev)
 {
@@ -956,12 +1014,14 @@ vbd_status enqueue_step(vbd_topology_s &T, const DevTopo &D, const vbd_step_para
                 if (mc) {
                     if (T.color_off[c + 1] > T.color_off[c]) {
                         HIP_TRY(launch_solve_contacts(D, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
-                                                      incidence(T, c), pend_b, pend_e, tets, springs, T.cfg, s));
+                                                      incidence(T, c), pend_b, pend_e, tets, springs, T.cfg, s,
+                                                      xcd_split(T, c)));
                         pend_b = T.color_off[c];
                         pend_e = T.color_off[c + 1];
                     }
                 } else
-                    HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), tets, springs, T.cfg, s));
+                    HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), tets, springs,
+                                         T.cfg, s, xcd_split(T, c)));
                 if (T.color_off[c + 1] > T.color_off[c]) {
                     ++launches;
                     ev.bytes += T.phase_bytes[c];
@@ -1053,7 +1113,8 @@ vbd_status enqueue_record(vbd_topology_s &T, const vbd_step_params *p, const Ste
         HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
         D.x = Sn;
         for (int c = 0; c < T.n_colors; ++c)
-            HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), true, false, T.cfg, s));
+            HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), true, false, T.cfg, s,
+                                 xcd_split(T, c)));
     }
     return VBD_OK;
 }
@@ -1271,6 +1332,7 @@ vbd_status vbd_color_greedy(vbd_topology T, int32_t order, int32_t *n_colors_out
         T->color_order = order;
         build_csr(*T);
         build_surface(*T);
+        build_xcd_split(*T);
         T->colored = true;
     }
     if (n_colors_out) *n_colors_out = T->n_colors;
@@ -1303,6 +1365,7 @@ vbd_status vbd_color_given(vbd_topology T, const int32_t *colors)
     T->color_order = -1;
     build_csr(*T);
     build_surface(*T);
+    build_xcd_split(*T);
     T->colored = true;
     return VBD_OK;
 }
@@ -1480,6 +1543,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(up(T->lay.perm, T->perm.data(), 4 * T->perm.size()));
     HIP_TRY(up(T->lay.mass, massp.data(), 4 * massp.size()));
     HIP_TRY(up(T->lay.color_off, T->color_off.data(), 4 * T->color_off.size()));
+    HIP_TRY(up(T->lay.xsplit, T->xsplit.data(), 4 * T->xsplit.size()));
     const int ntri = (int)(T->surf.size() / 3), nsv = (int)T->sv_slot.size();
     std::vector<int4> stri(ntri), sadj(ntri);
     std::vector<int2> svert(nsv);
@@ -1571,6 +1635,7 @@ vbd_status vbd_topology_query(vbd_topology T, int32_t what, void *out, size_t by
     case VBD_Q_TET_ORDER: return give(T->tet_order.data(), 4 * T->tet_order.size());
     case VBD_Q_SURFACE: return give(T->surf.data(), 4 * T->surf.size());
     case VBD_Q_SURFACE_EDGES: return give(T->sedge.data(), 4 * T->sedge.size());
+    case VBD_Q_XCD_SPLIT: return give(T->xsplit.data(), 4 * T->xsplit.size());
     case VBD_Q_SURFACE_COUNTS: {
         int64_t c[3] = {(int64_t)(T->surf.size() / 3), (int64_t)T->sv_slot.size(),
                         (int64_t)(T->sedge.size() / 2)};
@@ -1800,7 +1865,7 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
     if (c->tet_unroll < 1 || c->tet_unroll > 3) return fail(VBD_E_INVALID_ARG, "tet_unroll must be 1, 2 or 3");
     if (c->compact_records != 0 && c->compact_records != 1)
         return fail(VBD_E_INVALID_ARG, "compact_records must be 0 or 1");
-    if (c->xcd_remap < 0 || c->xcd_remap > 2) return fail(VBD_E_INVALID_ARG, "xcd_remap must be 0, 1 or 2");
+    if (c->xcd_remap < 0 || c->xcd_remap > 3) return fail(VBD_E_INVALID_ARG, "xcd_remap must be 0, 1, 2 or 3");
     T->cfg = LaunchCfg{L, c->block_size, c->xcd_remap, c->blocks_per_cu, c->tet_unroll,
                        c->compact_records};
     update_phase_bytes(*T);
@@ -1839,7 +1904,8 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
             for (int U : {1, 2, 3}) {
                 if (!tets && U > 1) continue;
                 for (int B : {64, 128, 256, 512})
-                    for (int rm : {0, 1, 2}) {
+                    for (int rm : {0, 1, 2, 3}) {
+                        if (rm == 3 && (T->n_meshes < 2 || persistent)) continue;
                         if (persistent)
                             for (int bpc : {0, 2, 1}) cands.push_back(LaunchCfg{L, B, rm, bpc, U, cr});
                         else
@@ -1875,7 +1941,8 @@ vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x
             } else {
                 for (int it = 0; it < sweeps; ++it)
                     for (int c = 0; c < T->n_colors; ++c)
-                        HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], incidence(*T, c), tets, springs, cf, s));
+                        HIP_TRY(launch_solve(T->dev, K, T->color_off[c], T->color_off[c + 1], incidence(*T, c), tets,
+                                             springs, cf, s, xcd_split(*T, c)));
             }
             HIP_TRY(hipEventRecord(b, s));
             HIP_TRY(hipEventSynchronize(b));

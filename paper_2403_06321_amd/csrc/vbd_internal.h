@@ -162,10 +162,19 @@ struct DevSurf {
     int n_tri, n_sv, hmask, n_edge, ehmask;
 };
 
+// One color's vertex range split into 8 contiguous parts at mesh boundaries
+// (launch mapping 3: part k runs on XCD k): dev = the 9 boundaries (device),
+// max_size = the largest part in vertices.  dev == nullptr: no split.
+struct XcdSplit {
+    const int *dev;
+    int max_size;
+};
+
 struct LaunchCfg {
     int lanes;        // lanes per vertex
     int block;        // threads per block (<= 512)
-    int xcd_remap;
+    int xcd_remap;    // 0 as launched, 1 contiguous ranges, 2 16-block chunks in turn,
+                      // 3 contiguous ranges split at mesh boundaries (XcdSplit)
     int blocks_per_cu;
     int unroll;       // tet entries per lane whose loads are issued together (1..3)
     int compact;      // 1: 32-B pair records (see DevTopo), 0: 36-B
@@ -180,14 +189,16 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
 // inc: {first tet entry, padded tet degree, first spring entry, padded spring
 // degree} of the color (DevTopo::ell_info, DevTopo::spr_info).
 hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int v_begin, int v_end, int4 inc,
-                        bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
+                        bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s,
+                        XcdSplit xs = XcdSplit{nullptr, 0});
 // Color solve with mesh-mesh contact elements.  Updates T.x in place; contact
 // partners of the same color are read from S.xsnap (their positions before
 // the phase).  [prev_begin, prev_end): the previously solved color, whose
 // snapshot the kernel refreshes from T.x.
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K,
                                  int v_begin, int v_end, int4 inc, int prev_begin, int prev_end,
-                                 bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s);
+                                 bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s,
+                                 XcdSplit xs = XcdSplit{nullptr, 0});
 // Detection on the permuted positions X (T.xt or T.x) into S.ctri and the
 // corner CSR (S.crow, S.cent).
 hipError_t launch_detect(const DevTopo &T, const DevSurf &S, const float4 *X,

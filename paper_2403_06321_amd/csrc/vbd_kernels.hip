@@ -47,6 +47,8 @@ __device__ __forceinline__ float group_sum(float v)
 constexpr int kXcdChunk = 16;
 __device__ __forceinline__ int xcd_block(int b, int nb, int remap)
 {
+    // mapping 3 splits colors at mesh boundaries where the launcher has the
+    // split (XcdSplit); elsewhere it maps as 1
     if (!remap) return b;
     const int x = b & 7;
     if (remap == 2) {
@@ -558,14 +560,32 @@ __global__ void k_predict(DevTopo T, const float *x, const float *v, const float
 
 constexpr int kMaxBlock = 512;
 
+// The vertex slot of this thread's group and whether it is in range: with a
+// mesh-aligned split (xs, launch mapping 3) block b runs part b mod 8 of the
+// color (XCD b mod 8 under round-robin dispatch), else xcd_block's mapping.
+template <int L>
+__device__ __forceinline__ int phase_slot(int v_begin, int v_end, int remap, const int *xs, bool &act)
+{
+    if (xs) {
+        const int x = blockIdx.x & 7;
+        const int lo = xs[x], hi = xs[x + 1];
+        const int p = lo + (int)(((blockIdx.x >> 3) * blockDim.x + threadIdx.x) / L);
+        act = p < hi;
+        return p;
+    }
+    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int p = v_begin + (int)((b * blockDim.x + threadIdx.x) / L);
+    act = p < v_end;
+    return p;
+}
+
 template <int L, int KU, bool TETS, bool SPRINGS, bool CR>
 __global__ __launch_bounds__(kMaxBlock) void k_solve(
-    DevTopo T, StepConsts K, int v_begin, int v_end, int4 inc, int remap)
+    DevTopo T, StepConsts K, int v_begin, int v_end, int4 inc, int remap, const int *xs)
 {
-    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int gid = b * blockDim.x + threadIdx.x;
-    const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS, false, CR>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin, v_end,
+    bool act;
+    const int p = phase_slot<L>(v_begin, v_end, remap, xs, act);
+    solve_vertex<L, KU, TETS, SPRINGS, false, CR>(T, K, p, threadIdx.x & (L - 1), act, v_begin, v_end,
                                                   inc);
 }
 
@@ -575,16 +595,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_solve(
 template <int L, int KU, bool TETS, bool SPRINGS, bool CR>
 __global__ __launch_bounds__(kMaxBlock) void k_solve_mc(DevTopo T, DevSurf S, StepConsts K,
                                                         int v_begin, int v_end, int4 inc,
-                                                        int prev_begin, int prev_end, int remap)
+                                                        int prev_begin, int prev_end, int remap,
+                                                        const int *xs)
 {
     for (int q = prev_begin + blockIdx.x * blockDim.x + threadIdx.x; q < prev_end;
          q += gridDim.x * blockDim.x)
         S.xsnap[q] = T.x[q];
-    const int b = xcd_block(blockIdx.x, gridDim.x, remap);
-    const int gid = b * blockDim.x + threadIdx.x;
-    const int p = v_begin + gid / L;
-    solve_vertex<L, KU, TETS, SPRINGS, true, CR>(T, K, p, threadIdx.x & (L - 1), p < v_end, v_begin,
-                                                 v_end, inc, &S);
+    bool act;
+    const int p = phase_slot<L>(v_begin, v_end, remap, xs, act);
+    solve_vertex<L, KU, TETS, SPRINGS, true, CR>(T, K, p, threadIdx.x & (L - 1), act, v_begin, v_end,
+                                                 inc, &S);
 }
 
 __device__ __forceinline__ float cheb_omega(int it, float rho)
@@ -1220,48 +1240,50 @@ hipError_t launch_predict(const DevTopo &T, const float *x, const float *v, cons
 
 template <int L, int KU>
 static hipError_t solve_dispatch(const DevTopo &T, const StepConsts &K, int vb, int ve, int4 inc,
-                                 bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
+                                 bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s,
+                                 XcdSplit xs)
 {
-    const int grid = cdiv((long)(ve - vb) * L, cfg.block);
+    const int grid = xs.dev ? 8 * cdiv((long)xs.max_size * L, cfg.block) : cdiv((long)(ve - vb) * L, cfg.block);
     const bool cr = cfg.compact != 0;
     if (tets && springs && cr)
-        hipLaunchKernelGGL((k_solve<L, KU, true, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap, xs.dev);
     else if (tets && springs)
-        hipLaunchKernelGGL((k_solve<L, KU, true, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap, xs.dev);
     else if (tets && cr)
-        hipLaunchKernelGGL((k_solve<L, KU, true, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap, xs.dev);
     else if (tets)
-        hipLaunchKernelGGL((k_solve<L, KU, true, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, KU, true, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap, xs.dev);
     else if (springs)
-        hipLaunchKernelGGL((k_solve<L, 1, false, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap, xs.dev);
     else
-        hipLaunchKernelGGL((k_solve<L, 1, false, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve<L, 1, false, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, K, vb, ve, inc, cfg.xcd_remap, xs.dev);
     return hipGetLastError();
 }
 
 template <int L>
 static hipError_t solve_unroll(const DevTopo &T, const StepConsts &K, int vb, int ve, int4 inc,
-                               bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s)
+                               bool tets, bool springs, const LaunchCfg &cfg, hipStream_t s, XcdSplit xs)
 {
     switch (cfg.unroll) {
-    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, inc, tets, springs, cfg, s);
-    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, inc, tets, springs, cfg, s);
-    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 1: return solve_dispatch<L, 1>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
+    case 2: return solve_dispatch<L, 2>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
+    case 3: return solve_dispatch<L, 3>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, int4 inc, bool tets,
-                        bool springs, const LaunchCfg &cfg, hipStream_t s)
+                        bool springs, const LaunchCfg &cfg, hipStream_t s, XcdSplit xs)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
+    if (cfg.xcd_remap != 3) xs = XcdSplit{nullptr, 0};
     switch (cfg.lanes) {
-    case 2: return solve_unroll<2>(T, K, vb, ve, inc, tets, springs, cfg, s);
-    case 4: return solve_unroll<4>(T, K, vb, ve, inc, tets, springs, cfg, s);
-    case 8: return solve_unroll<8>(T, K, vb, ve, inc, tets, springs, cfg, s);
-    case 16: return solve_unroll<16>(T, K, vb, ve, inc, tets, springs, cfg, s);
-    case 32: return solve_unroll<32>(T, K, vb, ve, inc, tets, springs, cfg, s);
+    case 2: return solve_unroll<2>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
+    case 4: return solve_unroll<4>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
+    case 8: return solve_unroll<8>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
+    case 16: return solve_unroll<16>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
+    case 32: return solve_unroll<32>(T, K, vb, ve, inc, tets, springs, cfg, s, xs);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1269,50 +1291,51 @@ hipError_t launch_solve(const DevTopo &T, const StepConsts &K, int vb, int ve, i
 template <int L, int KU>
 static hipError_t solve_mc_dispatch(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
                                     int ve, int4 inc, int pb, int pe, bool tets, bool springs,
-                                    const LaunchCfg &cfg, hipStream_t s)
+                                    const LaunchCfg &cfg, hipStream_t s, XcdSplit xs)
 {
-    const int grid = cdiv((long)(ve - vb) * L, cfg.block);
+    const int grid = xs.dev ? 8 * cdiv((long)xs.max_size * L, cfg.block) : cdiv((long)(ve - vb) * L, cfg.block);
     const bool cr = cfg.compact != 0;
     if (tets && springs && cr)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap, xs.dev);
     else if (tets && springs)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap, xs.dev);
     else if (tets && cr)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false, true>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap, xs.dev);
     else if (tets)
-        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, KU, true, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap, xs.dev);
     else if (springs)
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, true, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap, xs.dev);
     else
-        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap);
+        hipLaunchKernelGGL((k_solve_mc<L, 1, false, false, false>), dim3(grid), dim3(cfg.block), 0, s, T, S, K, vb, ve, inc, pb, pe, cfg.xcd_remap, xs.dev);
     return hipGetLastError();
 }
 
 template <int L>
 static hipError_t solve_mc_unroll(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
                                   int ve, int4 inc, int pb, int pe, bool tets, bool springs,
-                                  const LaunchCfg &cfg, hipStream_t s)
+                                  const LaunchCfg &cfg, hipStream_t s, XcdSplit xs)
 {
     switch (cfg.unroll) {
-    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
-    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
-    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 1: return solve_mc_dispatch<L, 1>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
+    case 2: return solve_mc_dispatch<L, 2>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
+    case 3: return solve_mc_dispatch<L, 3>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_solve_contacts(const DevTopo &T, const DevSurf &S, const StepConsts &K, int vb,
                                  int ve, int4 inc, int pb, int pe, bool tets, bool springs,
-                                 const LaunchCfg &cfg, hipStream_t s)
+                                 const LaunchCfg &cfg, hipStream_t s, XcdSplit xs)
 {
     if (ve <= vb) return hipSuccess;
     if (cfg.block > kMaxBlock) return hipErrorInvalidValue;
+    if (cfg.xcd_remap != 3) xs = XcdSplit{nullptr, 0};
     switch (cfg.lanes) {
-    case 2: return solve_mc_unroll<2>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
-    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
-    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
-    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
-    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s);
+    case 2: return solve_mc_unroll<2>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
+    case 4: return solve_mc_unroll<4>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
+    case 8: return solve_mc_unroll<8>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
+    case 16: return solve_mc_unroll<16>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
+    case 32: return solve_mc_unroll<32>(T, S, K, vb, ve, inc, pb, pe, tets, springs, cfg, s, xs);
     default: return hipErrorInvalidValue;
     }
 }

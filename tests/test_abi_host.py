@@ -259,12 +259,44 @@ def test_launch_config_lanes_validation():
 def test_launch_config_remap_validation():
     w = W.tet_cube(3, 0)
     t = Topology.from_workload(w, bind=False)
-    for rm in (0, 1, 2):
+    for rm in (0, 1, 2, 3):
         t.launch_config = dict(xcd_remap=rm)
         assert t.launch_config["xcd_remap"] == rm
-    for rm in (-1, 3):
+    for rm in (-1, 4):
         with pytest.raises(N.VBDError):
             t.launch_config = dict(xcd_remap=rm)
+
+
+def test_xcd_split_cuts_colors_at_mesh_boundaries():
+    """Launch mapping 3: each color's slot range in 8 contiguous parts that
+    cover it, cut at mesh boundaries where that keeps each part within 1/16 of
+    the color's work of its target (work = vertices: each walks the color's
+    padded degree), else inside a mesh at the target; a single mesh is cut
+    into about equal parts."""
+    w = W.config_batch(n_meshes=40, frames=1, coloring="smallest_last")
+    t = Topology.from_workload(w, bind=False)
+    xs = t.query(N.Q_XCD_SPLIT).reshape(-1, 9)
+    co, perm, rows = t.query(N.Q_COLOR_OFFSETS), t.query(N.Q_PERM), t.query(N.Q_TET_ROWS)
+    mesh = np.searchsorted(w.vert_offsets, perm, side="right") - 1
+    for c in range(t.n_colors):
+        b, e = co[c], co[c + 1]
+        assert xs[c, 0] == b and xs[c, 8] == e and np.all(np.diff(xs[c]) >= 0)
+        work = np.arange(e - b + 1, dtype=np.float64)
+        for k in range(1, 8):
+            cut = xs[c, k] - b
+            target = work[-1] * k / 8
+            at_boundary = cut in (0, e - b) or mesh[b + cut] != mesh[b + cut - 1]
+            assert at_boundary or abs(work[cut] - target) <= 1.0
+            if at_boundary:
+                assert abs(work[cut] - target) <= work[-1] / 16 + 1e-9 or cut == 0 or cut == e - b
+    # one mesh: cut at the work targets, each part within one vertex's work of
+    # an eighth
+    t1 = Topology.from_workload(W.tet_cube(9, 0), bind=False)
+    xs1 = t1.query(N.Q_XCD_SPLIT).reshape(-1, 9)
+    co1, rows1 = t1.query(N.Q_COLOR_OFFSETS), t1.query(N.Q_TET_ROWS)
+    for c in range(t1.n_colors):
+        parts = np.diff(xs1[c])
+        assert np.abs(parts - (co1[c + 1] - co1[c]) / 8).max() <= 1.0
 
 
 def test_tet_order_groups_tets_by_vertex_colors():

@@ -39,14 +39,35 @@ def test_xcd_remaps_bit_identical(lanes, block, unroll):
     of chunks), every remap gives bit-identical positions, i.e. each vertex of
     each color is updated exactly once."""
     w = W.tet_cube(33, 6, E_range=(5e4, 5e5), n_iters=10, frames=2)
-    say(f"33^3 cube, lanes={lanes} block={block}: xcd remap 0 / 1 / 2")
+    say(f"33^3 cube, lanes={lanes} block={block}: xcd remap 0 / 1 / 2 / 3")
     out = []
-    for remap in (0, 1, 2):
+    for remap in (0, 1, 2, 3):
         cfg = dict(lanes_per_vertex=lanes, block_size=block, xcd_remap=remap, tet_unroll=unroll)
         xg, vg, _ = gpu_rollout(w, w.frames, cfg=cfg)
         out.append((xg, vg))
-    for remap, (xg, vg) in zip((1, 2), out[1:]):
+    for remap, (xg, vg) in zip((1, 2, 3), out[1:]):
         assert np.array_equal(xg, out[0][0]) and np.array_equal(vg, out[0][1]), f"remap {remap}"
+
+
+def test_batch_mesh_aligned_xcd_split_bit_identical():
+    """Launch mapping 3 on a ragged batch (parts cut at mesh boundaries, a grid
+    of 8 x the largest part): bit-identical to mapping 1 in the plain and
+    graph modes, with mesh contacts too."""
+    w = W.config_batch(n_meshes=60, frames=2, n_iters=8, coloring="smallest_last")
+    out = []
+    for remap in (1, 3):
+        for mode in (0, 1):
+            xg, vg, _ = gpu_rollout(w, w.frames, launch_mode=mode, cfg=dict(xcd_remap=remap, lanes_per_vertex=8,
+                                                                            block_size=128))
+            out.append((xg[-1], vg[-1]))
+    for xg, vg in out[1:]:
+        assert np.array_equal(xg, out[0][0]) and np.array_equal(vg, out[0][1])
+    ws = W.config_block_stack(cols=2, levels=2, n=5, frames=2)
+    outs = []
+    for remap in (1, 3):
+        xg, _, _ = gpu_rollout(ws, ws.frames, cfg=dict(xcd_remap=remap))
+        outs.append(xg[-1])
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("lanes,block,remap", [(2, 128, 1), (4, 64, 0), (8, 256, 2), (16, 512, 1), (32, 128, 0)])
