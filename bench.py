@@ -156,9 +156,11 @@ def read_probe(dev):
     return best
 
 
-def kernel_traffic():
-    """Measured HBM bytes per launch from committed rocprofv3 counter runs,
-    valid only while the kernel source is unchanged."""
+def kernel_traffic(cfg):
+    """Measured HBM bytes per launch of the color-solve kernel in launch
+    configuration cfg, from committed rocprofv3 counter runs (one record per
+    configuration taken); None when cfg was not measured or the kernel source
+    has changed since."""
     path = os.path.join(ROOT, "profiles", "traffic_solve_tet_cube65.json")
     if not os.path.exists(path):
         return None
@@ -166,7 +168,11 @@ def kernel_traffic():
     src = os.path.join(ROOT, "paper_2403_06321_amd", "csrc", "vbd_kernels.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_sha256"):
         return None
-    return rec.get("bytes_per_launch")
+    keys = ("lanes_per_vertex", "block_size", "xcd_remap", "blocks_per_cu", "tet_unroll", "compact_records")
+    for r in rec.get("configs", []):
+        if all(r["launch_config"].get(k) == cfg.get(k) for k in keys):
+            return r["bytes_per_launch"]
+    return None
 
 
 def host_threads():
@@ -339,7 +345,7 @@ def main():
     roof = kernel_roofline(topo, w, dev)
     log(f"[bench] solve kernel: {roof['avg_ms'] * 1e3:.1f} us/launch, "
         f"{roof['avg_bytes'] / 1e6:.2f} MB/launch, {roof['achieved_gbs']:.0f} GB/s")
-    traffic = kernel_traffic()
+    traffic = kernel_traffic(topo.launch_config)
     read_gbs = read_probe(dev)
     # the cache-ideal byte model (every array once per iteration: 60 B per tet,
     # 4 B per tet-vertex pair, 52 B per vertex), shared by the iteration's
