@@ -377,7 +377,15 @@ vbd_status vbd_set_launch_config(vbd_topology topo, const vbd_launch_config *cfg
 vbd_status vbd_autotune(vbd_topology topo, const vbd_step_params *params, const float *x,
                         const float *v, const float *v_prev, const float *tet_E, void *stream);
 
-/* Timing of the hot kernel (hipEvents on the launch stream).  When enabled,
+/* Marker ranges: vbd_build_topology, vbd_color_greedy (and so vbd_color),
+ * vbd_color_given, vbd_bind_workspace, vbd_step, vbd_step_record,
+ * vbd_step_backward, vbd_detect_edges, vbd_detect_contacts and vbd_autotune
+ * each open a ROCTx range named after the call for its whole duration (host
+ * time: the enqueue, plus the synchronizations the call itself makes), seen
+ * by tools that trace markers (rocprofv3 --marker-trace); vbd_step_static
+ * opens none.  Without such a tool the ranges cost a function call each.
+ *
+ * Timing of the hot kernel (hipEvents on the launch stream).  When enabled,
  * vbd_step runs its plain launch sequence and records one event pair around
  * the step's back-to-back color-solve launches (or around the persistent
  * kernel), and vbd_step_backward (plain launches) one around its reverse

@@ -20,6 +20,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 SOURCES = ["vbd_kernels.hip", "vbd_contacts.hip", "vbd_static.hip", "vbd_host.cpp"]
+# ROCTx: the host entry points open named ranges for marker tracing.
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False) -> str:
@@ -37,7 +39,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}")
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -4,6 +4,7 @@
 // hipGraph / persistent, mesh-contact detection), backward, autotuner and
 // profiling.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <array>
@@ -28,6 +29,16 @@ using namespace vbd;
 namespace {
 
 thread_local std::string g_err;
+
+// A named host-side range for tools that trace ROCTx markers (rocprofv3
+// --marker-trace): the entry points below open one for their whole call, so a
+// trace shows which API call enqueued which kernels.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 vbd_status fail(vbd_status s, const char *fmt, ...)
 {
@@ -1193,6 +1204,7 @@ const char *vbd_last_error(void) { return g_err.c_str(); }
 
 vbd_status vbd_build_topology(const vbd_mesh_desc *d, vbd_topology *out)
 {
+    Range range("vbd_build_topology");
     if (!d || !out) return fail(VBD_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
     if (d->n_verts < 0 || d->n_tets < 0 || d->n_springs < 0 || d->n_meshes < 1)
@@ -1320,6 +1332,7 @@ vbd_status vbd_color(vbd_topology T, int32_t *n_colors_out, int32_t *colors_out)
 
 vbd_status vbd_color_greedy(vbd_topology T, int32_t order, int32_t *n_colors_out, int32_t *colors_out)
 {
+    Range range("vbd_color_greedy");
     if (!T) return fail(VBD_E_INVALID_ARG, "NULL topology");
     if (order != VBD_COLOR_ID_ORDER && order != VBD_COLOR_SMALLEST_LAST && order != VBD_COLOR_DSATUR)
         return fail(VBD_E_INVALID_ARG, "unknown coloring order %d", order);
@@ -1342,6 +1355,7 @@ vbd_status vbd_color_greedy(vbd_topology T, int32_t order, int32_t *n_colors_out
 
 vbd_status vbd_color_given(vbd_topology T, const int32_t *colors)
 {
+    Range range("vbd_color_given");
     if (!T || (!colors && T->nv > 0)) return fail(VBD_E_INVALID_ARG, "NULL argument");
     if (T->bound) return fail(VBD_E_INVALID_ARG, "the topology is bound: color before vbd_bind_workspace");
     int nc = 0;
@@ -1381,6 +1395,7 @@ vbd_status vbd_workspace_size(vbd_topology T, int32_t max_backward_iters, size_t
 
 vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void *stream)
 {
+    Range range("vbd_bind_workspace");
     if (!T || !dev_ptr) return fail(VBD_E_INVALID_ARG, "NULL argument");
     if (!T->colored) return fail(VBD_E_NOT_COLORED, "call vbd_color first");
     if ((uintptr_t)dev_ptr % kAlign) return fail(VBD_E_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -1674,6 +1689,7 @@ static vbd_status check_ready(vbd_topology T)
 vbd_status vbd_step(vbd_topology T, const vbd_step_params *p, float *x, float *v, float *vp,
                     const float *E, void *stream)
 {
+    Range range("vbd_step");
     vbd_status st = check_ready(T);
     if (st) return st;
     if ((st = validate_params(*T, p))) return st;
@@ -1757,6 +1773,7 @@ vbd_status check_differentiable(vbd_topology T, const vbd_step_params *p)
 vbd_status vbd_step_record(vbd_topology T, const vbd_step_params *p, float *x, float *v, float *vp,
                            const float *E, void *stream)
 {
+    Range range("vbd_step_record");
     vbd_status st = check_differentiable(T, p);
     if (st) return st;
     if (T->nv == 0) return VBD_OK;
@@ -1782,6 +1799,7 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
                              const float *gx_out, const float *gv_out, const float *gvp_out,
                              float *gx_in, float *gv_in, float *gvp_in, float *g_E, void *stream)
 {
+    Range range("vbd_step_backward");
     vbd_status st = check_differentiable(T, p);
     if (st) return st;
     if (T->nv == 0) return VBD_OK;
@@ -1805,6 +1823,7 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
 vbd_status vbd_detect_edges(vbd_topology T, const vbd_step_params *p, const float *x,
                             const float *x_t, int32_t *partner_out, void *stream)
 {
+    Range range("vbd_detect_edges");
     vbd_status st = check_ready(T);
     if (st) return st;
     if ((st = validate_params(*T, p))) return st;
@@ -1827,6 +1846,7 @@ vbd_status vbd_detect_edges(vbd_topology T, const vbd_step_params *p, const floa
 vbd_status vbd_detect_contacts(vbd_topology T, const vbd_step_params *p, const float *x,
                                int32_t *tri_out, void *stream)
 {
+    Range range("vbd_detect_contacts");
     vbd_status st = check_ready(T);
     if (st) return st;
     if ((st = validate_params(*T, p))) return st;
@@ -1878,6 +1898,7 @@ vbd_status vbd_set_launch_config(vbd_topology T, const vbd_launch_config *c)
 vbd_status vbd_autotune(vbd_topology T, const vbd_step_params *p, const float *x, const float *v,
                         const float *vp, const float *E, void *stream)
 {
+    Range range("vbd_autotune");
     vbd_status st = check_ready(T);
     if (st) return st;
     if ((st = validate_params(*T, p))) return st;

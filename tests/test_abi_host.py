@@ -27,6 +27,17 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_library_opens_marker_ranges():
+    """The entry points open ROCTx ranges: the library depends on the ROCTx
+    runtime and imports its range push and pop."""
+    import subprocess
+    so = N.lib()._name
+    dyn = subprocess.run(["readelf", "-d", so], capture_output=True, text=True, check=True).stdout
+    assert "librocprofiler-sdk-roctx" in dyn
+    und = subprocess.run(["nm", "-D", "--undefined-only", so], capture_output=True, text=True, check=True).stdout
+    assert "roctxRangePushA" in und and "roctxRangePop" in und
+
+
 @pytest.mark.parametrize("n", [3, 5, 11])
 def test_coloring_matches_oracle_bit_exact(n):
     w = W.tet_cube(n, n)

@@ -54,6 +54,6 @@ def test_host_library_under_address_and_undefined_sanitizers(tmp_path):
     drv = str(tmp_path / "driver.o")
     _run([B.HIPCC, *flags, "-c", os.path.join(HERE, "sanitize", "host_driver.cpp"), "-o", drv])
     exe = str(tmp_path / "host_driver")
-    _run([B.HIPCC, arch, *SAN, "-fno-gpu-sanitize", drv, *objs, "-o", exe])
+    _run([B.HIPCC, arch, *SAN, "-fno-gpu-sanitize", drv, *objs, *B.LIBS, "-o", exe])
     r = _run([exe], env=ENV)
     assert "all calls behaved" in r.stdout
