@@ -339,16 +339,21 @@ class Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x0, v0, tet_E, topo: Topology, params: StepParams, frames: int,
                 record_bytes: int = 1 << 33):
-        x = x0.detach().clone().contiguous()
-        v = v0.detach().clone().contiguous()
-        vp = v.clone()
+        # x, v, v_prev as three views of one buffer: a frame's checkpoint is
+        # one copy
+        xvv = torch.empty((3,) + tuple(x0.shape), dtype=torch.float32, device=x0.device)
+        xvv[0].copy_(x0.detach())
+        xvv[1].copy_(v0.detach())
+        xvv[2].copy_(v0.detach())
+        x, v, vp = xvv[0], xvv[1], xvv[2]
         E = tet_E.detach().contiguous()
-        states, records = [], None
+        states = torch.empty((frames,) + tuple(xvv.shape), dtype=torch.float32, device=x0.device)
+        records = None
         snaps = topo.snapshots(params.n_iters) if topo.max_backward_iters >= params.n_iters else None
         if snaps is not None and frames * snaps.numel() <= record_bytes:
             records = torch.empty((frames, snaps.numel()), dtype=torch.uint8, device=x.device)
         for f in range(frames):
-            states.append((x.clone(), v.clone(), vp.clone()))
+            states[f].copy_(xvv)
             if records is None:
                 topo.step(x, v, vp, E, params, N.LAUNCH_GRAPH)
             else:
@@ -356,27 +361,28 @@ class Rollout(torch.autograd.Function):
                 records[f].copy_(snaps)
         ctx.topo, ctx.params, ctx.states, ctx.records = topo, params, states, records
         ctx.save_for_backward(E)
-        return x, v
+        return x.clone(), v.clone()
 
     @staticmethod
     def backward(ctx, gx, gv):
         (E,) = ctx.saved_tensors
-        topo, params, records = ctx.topo, ctx.params, ctx.records
-        ref = ctx.states[0][0]
-        g_out = [torch.zeros_like(ref) if g is None else g.contiguous().float().clone()
-                 for g in (gx, gv)] + [torch.zeros_like(ref)]
-        g_in = [torch.empty_like(ref) for _ in range(3)]
-        stage = [torch.empty_like(ref) for _ in range(3)]
+        topo, params, records, states = ctx.topo, ctx.params, ctx.records, ctx.states
+        # fixed buffers (one captured graph serves every frame), each set of
+        # three arrays one buffer so that a hand-over is one copy
+        g_out = torch.zeros_like(states[0])
+        for k, g in enumerate((gx, gv)):
+            if g is not None:
+                g_out[k].copy_(g)
+        g_in = torch.empty_like(g_out)
+        stage = torch.empty_like(g_out)
         gE = torch.zeros_like(E)
         snaps = topo.snapshots(params.n_iters) if records is not None else None
-        for f in reversed(range(len(ctx.states))):
-            for dst, src in zip(stage, ctx.states[f]):
-                dst.copy_(src)
+        for f in reversed(range(states.shape[0])):
+            stage.copy_(states[f])
             if records is not None:
                 snaps.copy_(records[f])
             topo.step_backward(*stage, E, *g_out, *g_in, gE, params, N.LAUNCH_GRAPH,
                                recorded=records is not None)
-            for dst, src in zip(g_out, g_in):
-                dst.copy_(src)
+            g_out.copy_(g_in)
         gx0, gv0, gvp0 = g_out
-        return gx0, gv0 + gvp0, gE, None, None, None, None
+        return gx0.clone(), gv0 + gvp0, gE, None, None, None, None

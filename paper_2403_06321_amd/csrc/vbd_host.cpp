@@ -163,6 +163,10 @@ struct vbd_topology_s {
     GraphCache fwd_graph, bwd_graph, rec_graph;
     // profiling
     bool profiling = false;
+    // the reverse sweep's accumulators (contribution cells, pinned cells,
+    // Ebar shares) are zero: after binding and after every enqueued backward,
+    // whose last two kernels clear what they read
+    bool bwd_zero = false;
     std::vector<ProfileEvent> events;
     vbd_profile_stats acc{};
     ~vbd_topology_s()
@@ -321,6 +325,7 @@ void set_dev_pointers(vbd_topology_s &T)
     D.collided = (unsigned char *)(b + L.collided);
     D.flags = (unsigned *)(b + L.flags);
     D.snaps = L.max_bwd_iters > 0 ? (float4 *)(b + L.snaps) : nullptr;
+    D.xnext = nullptr;
     D.xbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xbar) : nullptr;
     D.ybar = L.max_bwd_iters > 0 ? (float4 *)(b + L.ybar) : nullptr;
     D.xtbar = L.max_bwd_iters > 0 ? (float4 *)(b + L.xtbar) : nullptr;
@@ -1119,15 +1124,31 @@ vbd_status enqueue_record(vbd_topology_s &T, const vbd_step_params *p, const Ste
     D.x = D.snaps;
     HIP_TRY(launch_material(D, E, K, T.cfg.compact != 0, s));
     HIP_TRY(launch_predict(D, x_t, v_t, v_prev, K, false, s));
+    // snapshot 1 starts as the initial guess and every snapshot holds the
+    // pinned positions; the updates of iteration n are stored into snapshot
+    // n and, as the start of iteration n + 1, into snapshot n + 1
+    HIP_TRY(launch_seed_snapshots(D, p->n_iters, s));
     for (int it = 1; it <= p->n_iters; ++it) {
         float4 *Sn = T.dev.snaps + nv * it;
-        HIP_TRY(launch_copy4(Sn, Sn - nv, (int)nv, s));
         D.x = Sn;
+        D.xnext = it < p->n_iters ? Sn + nv : nullptr;
         for (int c = 0; c < T.n_colors; ++c)
             HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), true, false, T.cfg, s,
                                  xcd_split(T, c)));
     }
     return VBD_OK;
+}
+
+// Clears the reverse sweep's accumulators: the contribution cells, the pinned
+// vertices' (tet, slot) cells and the Ebar shares.
+hipError_t zero_bwd_accumulators(vbd_topology_s &T, hipStream_t s)
+{
+    if (T.lay.max_bwd_iters <= 0 || T.nt == 0) return hipSuccess;
+    const DevTopo &D = T.dev;
+    hipError_t e = launch_zero_u32((unsigned *)D.contrib, 12 * (long long)T.nt, s);
+    if (e == hipSuccess) e = launch_zero_u32((unsigned *)D.cin, 9 * (long long)T.ell_total, s);
+    if (e == hipSuccess) e = launch_zero_u32((unsigned *)D.ebar_pair, (long long)T.ell_total, s);
+    return e;
 }
 
 vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const StepConsts &K,
@@ -1151,11 +1172,6 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
     D.x = T.dev.snaps;
     // reverse sweep
     HIP_TRY(launch_bwd_init(D, gx_out, gv_out, gvp_out, K, s));
-    if (T.nt > 0) {
-        HIP_TRY(launch_zero_u32((unsigned *)D.contrib, 12 * (long long)T.nt, s));
-        HIP_TRY(launch_zero_u32((unsigned *)D.cin, 9 * (long long)T.ell_total, s));
-        HIP_TRY(launch_zero_u32((unsigned *)D.ebar_pair, (long long)T.ell_total, s));
-    }
     // profiling: one event pair around the reverse sweep's adjoint launches
     ProfileEvent ev{};
     const bool prof = T.profiling && !in_capture;
@@ -1476,8 +1492,11 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
         }
         HIP_TRY(up(T->lay.ell, ell.data(), sizeof(PairEnt) * ell.size()));
         // pair records: from the rest frame S of each (vertex, tet) pair with
-        // the vertex as origin (the other three vertices in slot order), in
-        // double: m = -(rows of S summed), w = S m, sigma = det S
+        // the vertex as origin and the other three vertices in ascending
+        // permuted slot, i.e. ascending color (the reverse sweep's cells are
+        // numbered in the same order, so that one color phase writes one
+        // cell array per receiving color), in double: m = -(rows of S
+        // summed), w = S m, sigma = det S
         std::vector<int4> pa(T->ell_total, make_int4(-1, 0, 0, 0));
         std::vector<float4> pws(T->ell_total, make_float4(0.f, 0.f, 0.f, 0.f));
         std::vector<float> pb(T->ell_total, 0.f);
@@ -1493,6 +1512,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
                     int n = 1;
                     for (int j = 0; j < 4; ++j)
                         if (j != k) ord[n++] = q[j];
+                    std::sort(ord + 1, ord + 4, [&](int32_t a, int32_t b) { return T->iperm[a] < T->iperm[b]; });
                     double S[6];   // S00, S01, S02, S11, S12, S22
                     rest_frame_inverse(T->rest, ord, S);
                     const double m0 = -S[0], m1 = -(S[1] + S[3]), m2 = -(S[2] + S[4] + S[5]);
@@ -1528,22 +1548,32 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
                         pos_of[T->tet_ent[e]] = (int32_t)(base + (size_t)(e - T->tet_row[sl]));
                 }
             }
-            // per pair (slot k of tet t) and each other slot q in ascending
-            // order: (entry of (q, t) << 2) | index of k among q's other slots,
-            // or -1 - (stored tet * 4 + q) when q's vertex is pinned
+            // per pair (slot k of tet t) and each other slot q in the pair
+            // record's order (ascending permuted slot): (entry of (q, t) << 2)
+            // | index of k among q's other vertices in that order, or
+            // -1 - (stored tet * 4 + q) when q's vertex is pinned
             std::vector<int3> tgt(T->ell_total, make_int3(0, 0, 0));
-            for (int t = 0; t < T->nt; ++t)
+            for (int t = 0; t < T->nt; ++t) {
+                const int32_t *qv = &T->tets[4 * (size_t)t];
                 for (int k = 0; k < 4; ++k) {
                     const int32_t e = pos_of[4 * (size_t)t + k];
                     if (e < 0) continue;
-                    int32_t o[3], n = 0;
-                    for (int q = 0; q < 4; ++q) {
-                        if (q == k) continue;
+                    int32_t os[3], n = 0;
+                    for (int q = 0; q < 4; ++q)
+                        if (q != k) os[n++] = q;
+                    std::sort(os, os + 3, [&](int a, int b) { return T->iperm[qv[a]] < T->iperm[qv[b]]; });
+                    int32_t o[3];
+                    for (int j = 0; j < 3; ++j) {
+                        const int q = os[j];
                         const int32_t eq = pos_of[4 * (size_t)t + q];
-                        o[n++] = eq >= 0 ? (eq << 2) | (k < q ? k : k - 1) : -1 - (T->tet_rank[t] * 4 + q);
+                        int rank = 0;   // k among q's others: those of smaller permuted slot
+                        for (int r = 0; r < 4; ++r)
+                            if (r != q && T->iperm[qv[r]] < T->iperm[qv[k]]) ++rank;
+                        o[j] = eq >= 0 ? (eq << 2) | rank : -1 - (T->tet_rank[t] * 4 + q);
                     }
                     tgt[e] = make_int3(o[0], o[1], o[2]);
                 }
+            }
             std::vector<int4> tpairs(T->nt);
             for (int t = 0; t < T->nt; ++t) {
                 const int32_t *q = &pos_of[4 * (size_t)t];
@@ -1604,6 +1634,7 @@ vbd_status vbd_bind_workspace(vbd_topology T, void *dev_ptr, size_t bytes, void 
     HIP_TRY(launch_zero_u32(T->dev.flags, kFlagWords, s));
     HIP_TRY(hipStreamSynchronize(s));
     T->bound = true;
+    T->bwd_zero = false;
     T->fwd_graph.reset();
     T->bwd_graph.reset();
     T->rec_graph.reset();
@@ -1808,16 +1839,26 @@ vbd_status vbd_step_backward(vbd_topology T, const vbd_step_params *p, const flo
         return fail(VBD_E_INVALID_ARG, "NULL array");
     const StepConsts K = make_consts(*T, p);
     hipStream_t s = (hipStream_t)stream;
+    // the sweep starts from zero accumulators; they are left zero by the last
+    // backward unless its enqueue stopped part way
+    if (!T->bwd_zero) {
+        HIP_TRY(zero_bwd_accumulators(*T, s));
+        T->bwd_zero = true;
+    }
     auto enqueue = [&](hipStream_t q, bool in_capture) {
         return enqueue_backward(*T, p, K, x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in,
                                 gvp_in, g_E, q, in_capture);
     };
+    T->bwd_zero = false;
     if (p->launch_mode == VBD_LAUNCH_PLAIN || p->launch_mode == VBD_LAUNCH_PERSISTENT || T->profiling)
-        return enqueue(s, false);
-    return run_graph(*T, T->bwd_graph,
-                     make_key(p, {x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in, gvp_in, g_E},
-                              stream),
-                     s, [&](hipStream_t q) { return enqueue(q, true); });
+        st = enqueue(s, false);
+    else
+        st = run_graph(*T, T->bwd_graph,
+                       make_key(p, {x_t, v_t, v_prev, E, gx_out, gv_out, gvp_out, gx_in, gv_in, gvp_in, g_E},
+                                stream),
+                       s, [&](hipStream_t q) { return enqueue(q, true); });
+    if (st == VBD_OK) T->bwd_zero = true;
+    return st;
 }
 
 vbd_status vbd_detect_edges(vbd_topology T, const vbd_step_params *p, const float *x,

@@ -78,7 +78,7 @@ struct DevTopo {
     //                       F times a rotation), this vertex's shape gradient
     //                       m = -(rows of S summed), w = S m (so that
     //                       w0 + w1 + w2 = -|m|^2) and sigma = det S:
-    //                       pa = {the other three vertices (slot order), float
+    //                       pa = {the other three vertices (ascending slot), float
     //                       bits of V lam}, pw = {V mu w, last}, pb = sigma, in
     //                       two layouts: compact (32 B: last = sigma, pb not
     //                       read, V mu |m|^2 summed from w) or full (36 B:
@@ -103,6 +103,8 @@ struct DevTopo {
     const float *mass;                 // permuted
     const int *color_off;              // [n_colors + 1]
     float4 *x, *xt, *y;                // current iterate, x^t, inertia target (w = m/h^2)
+    float4 *xnext;                     // recording the iterates: each update is also stored
+                                       // here (the next iterate's snapshot); else null
     float4 *prev1, *prev2;             // Chebyshev history
     unsigned char *collided;           // sticky contact flag within a step
     unsigned *flags;                   // see kFlag* above
@@ -112,9 +114,12 @@ struct DevTopo {
                                        // vertices (12 B), by (stored tet, slot)
     // backward, per padded pair entry of a receiving vertex: its three incoming
     // contribution cells (cin + j * n_pairs holds the one from the j-th other
-    // vertex of the tet in slot order), the targets of its own outgoing
-    // contributions ((entry << 2) | j of each other slot in slot order, or
-    // -1 - (stored tet * 4 + slot) for a pinned vertex) and its share of Ebar
+    // vertex of the tet in the pair record's order, ascending permuted slot and
+    // so ascending color: with a tet's vertices in distinct colors, one color
+    // phase writes the cells of one array per receiving color), the targets of
+    // its own outgoing contributions ((entry << 2) | j of each other vertex in
+    // that order, or -1 - (stored tet * 4 + slot) for a pinned vertex) and its
+    // share of Ebar
     float3 *cin;
     const int3 *tgt;
     float *ebar_pair;
@@ -233,6 +238,7 @@ hipError_t launch_bwd_init(const DevTopo &T, const float *gx_out, const float *g
 hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const float4 *Sn,
                                 const float4 *Sp, int v_begin, int v_end, int2 ell,
                                 const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_seed_snapshots(const DevTopo &T, int n_iters, hipStream_t s);
 hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s);
 // Also adds the per-pair Ebar shares into g_tet_E (caller's tet order).
 hipError_t launch_bwd_final(const DevTopo &T, const float *v_t, const float *v_prev,

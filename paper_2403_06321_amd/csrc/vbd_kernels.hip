@@ -488,8 +488,10 @@ __device__ __forceinline__ void solve_vertex(const DevTopo &T, const StepConsts 
     float3 dx;
     const bool ok = solve_sym3(a, K.det_eps_rel, dx);
     if (lane == 0) {
-        if (ok) T.x[p] = make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w);
+        const float4 xo = ok ? make_float4(xi.x + dx.x, xi.y + dx.y, xi.z + dx.z, xi4.w) : xi4;
+        if (ok) T.x[p] = xo;
         else atomicAdd(reinterpret_cast<unsigned long long *>(T.flags + kFlagSkips), 1ull);
+        if (T.xnext) T.xnext[p] = xo;
         if (contact) T.collided[p] = 1;
     }
 }
@@ -871,7 +873,7 @@ __device__ __forceinline__ void adj_hess(float4 qa, float4 qb, float4 qc, float 
 }
 
 // One tet's reverse terms: -d(w . grad_i Psi)/dx_q added to the cells of the
-// other three slots (c0, c1, c2 in slot order); returns (w . grad_i Psi)/(V E).
+// other three vertices (c0, c1, c2 in the pair record's order); returns (w . grad_i Psi)/(V E).
 __device__ __forceinline__ float adj_pair(float3 xi, float4 qa, float4 qb, float4 qc, float4 ws,
                                           float Vlam, float sg, float3 w, float mu_lam,
                                           const StepConsts &K, float3 &c0, float3 &c1, float3 &c2)
@@ -1138,20 +1140,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_adjoint_color(DevTopo T, StepCons
 // End of the reverse sweep: each vertex adds the contributions written after
 // its last update: a free vertex the incoming cells from colors below its own
 // (its entries' other vertices with smaller slots), a pinned vertex all of
-// its (tet, slot) cells.
-__global__ void k_bwd_fold(DevTopo T)
+// its (tet, slot) cells.  A group of kFoldLanes lanes per vertex, over its
+// entries, then a group sum.  The cells it reads are cleared for the next
+// sweep: cells from lower colors are read before they are written in a sweep,
+// the other cells of free senders are written first (a skipped update writes
+// zeros), and cells of pinned senders are never written.
+constexpr int kFoldLanes = 8;
+__global__ __launch_bounds__(256) void k_bwd_fold(DevTopo T)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= T.n_verts) return;
-    float4 xb = T.xbar[p];
-    if (p < T.n_free) {
+    const int L = kFoldLanes;
+    const int p = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) / L);
+    const int lane = threadIdx.x & (L - 1);
+    const bool active = p < T.n_verts;
+    float3 g = make_float3(0.f, 0.f, 0.f);
+    if (active && p < T.n_free) {
         int c = 0;
         while (c + 1 < T.n_colors && T.color_off[c + 1] <= p) ++c;
         const int lo = T.color_off[c];
         const int2 info = T.ell_info[c];
         const size_t e0 = (size_t)info.x + (size_t)(p - lo) * (size_t)info.y;
         const size_t np = (size_t)T.n_pairs;
-        for (int e = 0; e < info.y; ++e) {
+        for (int e = lane; e < info.y; e += L) {
             const size_t i = e0 + e;
             if (T.pws[i].w == 0.f) continue;   // padding
             const int4 pa = T.pa[i];
@@ -1159,18 +1168,41 @@ __global__ void k_bwd_fold(DevTopo T)
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 if (src[j] < lo) {
-                    const float3 g = T.cin[(size_t)j * np + i];
-                    xb.x += g.x; xb.y += g.y; xb.z += g.z;
+                    float3 *cell = T.cin + (size_t)j * np + i;
+                    const float3 cj = *cell;
+                    g.x += cj.x; g.y += cj.y; g.z += cj.z;
+                    *cell = make_float3(0.f, 0.f, 0.f);
                 }
         }
-    } else {
-        for (int e = T.tet_row[p]; e < T.tet_row[p + 1]; ++e) {
+    } else if (active) {
+        for (int e = T.tet_row[p] + lane; e < T.tet_row[p + 1]; e += L) {
             const int ent = T.tet_ent[e].x;
-            const float3 g = T.contrib[4 * (size_t)(ent >> 2) + (ent & 3)];
-            xb.x += g.x; xb.y += g.y; xb.z += g.z;
+            float3 *cell = T.contrib + 4 * (size_t)(ent >> 2) + (ent & 3);
+            const float3 cj = *cell;
+            g.x += cj.x; g.y += cj.y; g.z += cj.z;
+            *cell = make_float3(0.f, 0.f, 0.f);
         }
     }
+    g.x = group_sum<L>(g.x);
+    g.y = group_sum<L>(g.y);
+    g.z = group_sum<L>(g.z);
+    if (!active || lane != 0) return;
+    float4 xb = T.xbar[p];
+    xb.x += g.x; xb.y += g.y; xb.z += g.z;
     T.xbar[p] = xb;
+}
+
+// Start of a recorded step: snapshot 1 = snapshot 0 (the initial guess), and
+// the pinned slots of snapshots 2..n_iters from snapshot 0 (pinned vertices
+// are never updated; the updates of the free ones are stored into the next
+// snapshot by the solve).  blockIdx.y = snapshot - 1.
+__global__ void k_seed_snapshots(float4 *snaps, int nv, int n_free)
+{
+    const int n = (int)blockIdx.y + 1;
+    const int lo = n == 1 ? 0 : n_free;
+    const int p = lo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= nv) return;
+    snaps[(size_t)n * nv + p] = snaps[p];
 }
 
 // Adjoint of the initial guess (Sec. 3.7) and of y, written in original order.
@@ -1178,14 +1210,15 @@ __global__ void k_bwd_final(DevTopo T, const float *v_t, const float *v_prev, fl
                             float *gv_in, float *gvp_in, float *gE, StepConsts K)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    // Ebar: the shares of the tet's free vertices, added into the caller's order
+    // Ebar: the shares of the tet's free vertices, added into the caller's
+    // order; the shares are cleared for the next sweep
     for (int t = p; t < T.n_tets; t += gridDim.x * blockDim.x) {
         const int4 q = T.tet_pairs[t];
         float eb = 0.f;
-        if (q.x >= 0) eb += T.ebar_pair[q.x];
-        if (q.y >= 0) eb += T.ebar_pair[q.y];
-        if (q.z >= 0) eb += T.ebar_pair[q.z];
-        if (q.w >= 0) eb += T.ebar_pair[q.w];
+        if (q.x >= 0) { eb += T.ebar_pair[q.x]; T.ebar_pair[q.x] = 0.f; }
+        if (q.y >= 0) { eb += T.ebar_pair[q.y]; T.ebar_pair[q.y] = 0.f; }
+        if (q.z >= 0) { eb += T.ebar_pair[q.z]; T.ebar_pair[q.z] = 0.f; }
+        if (q.w >= 0) { eb += T.ebar_pair[q.w]; T.ebar_pair[q.w] = 0.f; }
         gE[T.tet_perm[t]] += eb;
     }
     if (p >= T.n_verts) return;
@@ -1509,7 +1542,17 @@ hipError_t launch_adjoint_color(const DevTopo &T, const StepConsts &K, const flo
 
 hipError_t launch_bwd_fold(const DevTopo &T, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bwd_fold, dim3(cdiv(T.n_verts, 256)), dim3(256), 0, s, T);
+    if (T.n_verts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bwd_fold, dim3(cdiv((long)T.n_verts * kFoldLanes, 256)), dim3(256), 0, s, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_snapshots(const DevTopo &T, int n_iters, hipStream_t s)
+{
+    if (T.n_verts <= 0 || n_iters < 1) return hipSuccess;
+    // snapshot 1 covers every slot; later ones only the pinned range
+    hipLaunchKernelGGL(k_seed_snapshots, dim3(cdiv(T.n_verts, 256), n_iters), dim3(256), 0, s, T.snaps,
+                       T.n_verts, T.n_free);
     return hipGetLastError();
 }
 
