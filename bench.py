@@ -342,6 +342,13 @@ def main():
     value = upd * args.steps / secs
     ms_per_step = secs / args.steps * 1e3
     log(f"[bench] headline ({best}): {value:.3e} v-upd/s, {ms_per_step:.3f} ms/frame")
+    # two more runs of the same frames, for the median and minimum of three
+    runs = [value]
+    for _ in range(2):
+        s2, _ = time_frames(topo, w, MODES[best], args.steps, args.warmup, dev, autotune=False)
+        runs.append(upd * args.steps / s2)
+    headline_runs = dict(updates_per_s=runs, median=float(sorted(runs)[1]), min=float(min(runs)))
+    log(f"[bench] three runs: median {headline_runs['median']:.3e}, min {headline_runs['min']:.3e}")
     roof = kernel_roofline(topo, w, dev)
     log(f"[bench] solve kernel: {roof['avg_ms'] * 1e3:.1f} us/launch, "
         f"{roof['avg_bytes'] / 1e6:.2f} MB/launch, {roof['achieved_gbs']:.0f} GB/s")
@@ -387,7 +394,7 @@ def main():
     del topo
     torch.cuda.empty_cache()
 
-    extra = {"cube_modes": per_mode}
+    extra = {"cube_modes": per_mode, "headline_runs": headline_runs}
     if not args.no_extras:
         # the same cube and iterations with other colorings: greedy first fit in
         # vertex-id order (8 colors) and the caller-supplied lattice coloring
