@@ -27,12 +27,15 @@ constexpr int kFlagNonfinite = 6;
 constexpr int kFlagNonfiniteTotal = 7;
 constexpr int kFlagSkips = 8;
 // The persistent kernel's barrier counters from kFlagBar on, one 128-B line
-// each: kBarGroups group counters (block index mod kBarGroups, the XCD a
-// block runs on under the default round-robin dispatch), then the global one.
+// each: kBarGroups group counters (one per XCD, by the XCD a block runs on),
+// then the global one; then the start-of-launch census: the number of blocks
+// on each XCD (one line) and the number counted (one line).
 constexpr int kFlagBar = 64;
 constexpr int kBarGroups = 8;
 constexpr int kBarStride = 32;   // 32 x 4 B = 128 B
-constexpr int kFlagWords = kFlagBar + (kBarGroups + 1) * kBarStride;
+constexpr int kFlagCensus = kFlagBar + (kBarGroups + 1) * kBarStride;
+constexpr int kFlagCensusTotal = kFlagCensus + kBarStride;
+constexpr int kFlagWords = kFlagCensusTotal + kBarStride;
 // Waves per SIMD that the persistent grid fills: every persistent kernel is
 // compiled for at least this occupancy (amdgpu_waves_per_eu), so the grid is
 // resident by construction (a CPU test reads the compiler's occupancy).

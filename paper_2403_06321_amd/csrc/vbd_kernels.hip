@@ -523,7 +523,11 @@ __global__ void k_predict(DevTopo T, const float *x, const float *v, const float
                           StepConsts K, int reset_flags, int cheb)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p <= kBarGroups && reset_flags) T.flags[kFlagBar + p * kBarStride] = 0u;
+    if (reset_flags) {
+        if (p <= kBarGroups) T.flags[kFlagBar + p * kBarStride] = 0u;
+        if (p < kBarGroups) T.flags[kFlagCensus + p] = 0u;
+        if (p == 0) T.flags[kFlagCensusTotal] = 0u;
+    }
     if (p >= T.n_verts) return;
     const int o = T.perm[p];
     const float3 xt = ld3(x, o), vt = ld3(v, o);
@@ -654,55 +658,95 @@ __global__ void k_finalize(DevTopo T, float *x, float *v, float *vp, float h)
     st3(x, o, xn);
 }
 
-// Device-wide barrier for the persistent kernel, in two levels: a block
-// arrives at its group's counter (block index mod kBarGroups, one 128-B line
-// per group, so the arrivals of different groups do not serialise on one
-// address), the last arrival of a group arrives at the global counter, and
-// every block waits for the global count.  Counters only grow (reset to 0 by
-// k_predict before the launch): barrier number k completes when the global
-// counter reaches k * (number of groups).  The wait is bounded: after
-// kSpinLimit polls the block raises flags[1] and every block leaves at its
-// next barrier, so the kernel always terminates.  Returns true when the
-// kernel must stop.
+// Device-wide barrier for the persistent kernel.  The XCDs' L2 caches are not
+// coherent with each other: a block's writes reach other XCDs only after an
+// agent-scope release writes its L2 back, and its reads see other XCDs' writes
+// only after an agent-scope acquire.  A write-back covers the whole L2 of the
+// XCD, so one per XCD suffices: every block waits until its own stores have
+// reached its L2 and arrives at its XCD's counter; the XCD's last arrival
+// writes that L2 back once and arrives at the global counter; every block
+// waits for the global count and then acquires.  Blocks are grouped by the XCD
+// they run on (the hardware XCC_ID register), counted once per launch by
+// barrier_census.  Counters only grow (reset to 0 by k_predict before the
+// launch): barrier k completes when an XCD's counter reaches k * (its blocks)
+// and the global one k * (XCDs in use).  Every wait is bounded: after
+// kSpinLimit polls the block raises flags[1] and every block leaves at its next
+// barrier, so the kernel always terminates.
 constexpr long kSpinLimit = 1L << 20;
 
-__device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned k)
+struct BarGroup {
+    unsigned xcd;        // XCD this block runs on
+    unsigned in_grp;     // blocks of the grid on that XCD
+    unsigned n_groups;   // XCDs with at least one block
+};
+
+// Bounded wait for *ctr >= target; on timeout records what was seen and raises
+// the abort flag.  Returns true when the kernel must stop.
+__device__ __forceinline__ bool bar_wait(unsigned *flags, unsigned *ctr, unsigned target)
+{
+    long spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return true;
+        if (++spins > kSpinLimit) {
+            // record what the waiting block saw, for vbd_check's message
+            const unsigned seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&flags[3], seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&flags[4], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&flags[5], gridDim.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&flags[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return true;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+// Start of a persistent launch: every block counts itself on its XCD, then
+// waits until all blocks are counted.  Returns true when the kernel must stop.
+__device__ __forceinline__ bool barrier_census(unsigned *flags, BarGroup &bg)
 {
     __shared__ int s_abort;
+    __shared__ unsigned s_grp[3];
+    if (threadIdx.x == 0) {
+        // HW_REG_XCC_ID (register 20), bits 3:0
+        const unsigned xcd = __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (kBarGroups - 1);
+        __hip_atomic_fetch_add(&flags[kFlagCensus + xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the XCD count lands before the total that announces it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&flags[kFlagCensusTotal], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int abort = bar_wait(flags, &flags[kFlagCensusTotal], gridDim.x) ? 1 : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        unsigned ng = 0;
+        for (int g = 0; g < kBarGroups; ++g)
+            ng += __hip_atomic_load(&flags[kFlagCensus + g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        s_grp[0] = xcd;
+        s_grp[1] = __hip_atomic_load(&flags[kFlagCensus + xcd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_grp[2] = ng;
+        s_abort = abort;
+    }
+    __syncthreads();
+    bg.xcd = s_grp[0];
+    bg.in_grp = s_grp[1];
+    bg.n_groups = s_grp[2];
+    return s_abort != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(unsigned *flags, unsigned k, const BarGroup &bg)
+{
+    __shared__ int s_abort;
+    // every wave's stores have reached its XCD's L2 (stores count in vmcnt)
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        int abort = 0;
-        const unsigned nb = gridDim.x, grp = blockIdx.x % kBarGroups;
-        const unsigned n_groups = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
-        const unsigned in_grp = (nb - grp + kBarGroups - 1) / kBarGroups;
-        unsigned *gc = flags + kFlagBar + grp * kBarStride;
+        unsigned *gc = flags + kFlagBar + bg.xcd * kBarStride;
         unsigned *all = flags + kFlagBar + kBarGroups * kBarStride;
-        const unsigned target = k * n_groups;
-        // release this block's writes (all waves passed the barrier above),
-        // arrive; the group's last arrival passes the group on (its release
-        // covers the group: every earlier arrival released before its add)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1u == k * in_grp)
-            __hip_atomic_fetch_add(all, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        long spins = 0;
-        while (__hip_atomic_load(all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                abort = 1;
-                break;
-            }
-            if (++spins > kSpinLimit) {
-                // record what the waiting block saw, for vbd_check's message
-                const unsigned seen = __hip_atomic_load(all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_max(&flags[3], seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_max(&flags[4], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&flags[5], gridDim.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&flags[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                abort = 1;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+        const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == k * bg.in_grp) {
+            // the XCD's last arrival: one write-back of this L2 for all its blocks
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(all, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        const int abort = bar_wait(flags, all, k * bg.n_groups) ? 1 : 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_abort = abort;
     }
@@ -718,6 +762,8 @@ void k_persistent(DevTopo T, StepConsts K, int n_iters, int remap)
     const int b = xcd_block(blockIdx.x, nb, remap);
     const int G = blockDim.x / L;   // vertex groups per block
     const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+    BarGroup bg;
+    if (barrier_census(T.flags, bg)) return;
     unsigned nbar = 0;
     for (int it = 1; it <= n_iters; ++it) {
         for (int c = 0; c < T.n_colors; ++c) {
@@ -734,14 +780,14 @@ void k_persistent(DevTopo T, StepConsts K, int n_iters, int remap)
                 solve_vertex<L, KU, TETS, SPRINGS, false, CR>(T, K, p, lane, p < cend, vb, ve, inc);
             }
             ++nbar;
-            if (grid_barrier(T.flags, nbar)) return;
+            if (grid_barrier(T.flags, nbar, bg)) return;
         }
         if (K.cheb_rho > 0.f) {
             const float om = cheb_omega(it, K.cheb_rho);
             for (int p = b * blockDim.x + threadIdx.x; p < T.n_free; p += nb * blockDim.x)
                 cheb_vertex(T, p, om);
             ++nbar;
-            if (grid_barrier(T.flags, nbar)) return;
+            if (grid_barrier(T.flags, nbar, bg)) return;
         }
     }
 }
