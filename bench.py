@@ -302,14 +302,17 @@ def main():
         wd = W.config_differentiable(coloring="smallest_last")
         td = Topology.from_workload(wd, max_backward_iters=wd.params.n_iters)
         x0, v0, _, E = state(wd, dev)
-        td.autotune(x0, v0, v0.clone(), E, wd.params, MODES["graph"])
+        # the launch configuration given (the reverse phases take its block
+        # size and XCD mapping), so that counter runs are reproducible
+        td.launch_config = dict(lanes_per_vertex=args.lanes, block_size=args.block, xcd_remap=args.remap,
+                                blocks_per_cu=0, tet_unroll=args.unroll, compact_records=args.compact)
         v0.requires_grad_(True); E.requires_grad_(True)
         target = torch.tensor(wd.target, dtype=torch.float32, device=dev)
         for _ in range(args.steps):
             xT, _ = Rollout.apply(x0, v0, E, td, wd.params, wd.frames)
             ((xT.mean(0) - target) ** 2).sum().backward()
         torch.cuda.synchronize()
-        print(json.dumps({"profile": "adjoint"}))
+        print(json.dumps({"profile": "adjoint", "launch_config": td.launch_config}))
         return
 
     # ---------------------------------------------------------- headline ----

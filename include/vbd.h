@@ -358,7 +358,8 @@ typedef struct {
                                    XCDs in turn, 3: each XCD a contiguous part of the
                                    color cut at mesh boundaries with about equal work
                                    (VBD_Q_XCD_SPLIT; the color solve only, elsewhere
-                                   as 1); other values: VBD_E_INVALID_ARG */
+                                   as 1); other values: VBD_E_INVALID_ARG.  The
+                                   backward's reverse phases always map as 1. */
     int32_t blocks_per_cu;      /* persistent kernel: resident blocks per CU (0 = max) */
     int32_t tet_unroll;         /* 1..3 tet entries per lane loaded together */
     int32_t compact_records;    /* 1: 32-B pair records (|m|^2 summed from w in the

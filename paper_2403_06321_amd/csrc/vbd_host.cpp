@@ -1179,11 +1179,17 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
         vbd_status st = prof_begin(T, s, ev);
         if (st) return st;
     }
+    // the reverse phases map each XCD to a contiguous range of vertices
+    // whatever the forward's mapping: a phase's senders and the cells they
+    // write then stay in one L2 (measured fastest on the 33^3 cube: 8.4 us
+    // against 8.9-9.8 us with the other mappings, at any block size)
+    LaunchCfg acfg = T.cfg;
+    acfg.xcd_remap = 1;
     for (int it = p->n_iters; it >= 1; --it) {
         const float4 *Sn = T.dev.snaps + nv * it, *Sp = Sn - nv;
         for (int c = T.n_colors - 1; c >= 0; --c) {
             HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T.color_off[c], T.color_off[c + 1], T.ell_info[c],
-                                         T.cfg, s));
+                                         acfg, s));
             if (T.color_off[c + 1] > T.color_off[c]) {
                 ++ev.launches;
                 ev.bytes += T.adj_phase_bytes[c];
