@@ -18,6 +18,24 @@ O_COLORS = N.Q_COLORS
 THREADS = min(16, os.cpu_count() or 1)
 
 
+@pytest.mark.parametrize("block,bpc", [(64, 0), (256, 0), (512, 1)])
+def test_persistent_barrier_bit_identical_at_scale(block, bpc):
+    """The persistent kernel's device barrier (one L2 write-back and one L2
+    invalidation per XCD, the XCD's other blocks invalidating their L1 only)
+    against per-color launches on a 33^3 cube, from 256 to several thousand
+    resident blocks: every vertex update reads the same neighbour values, so the
+    positions agree bit for bit; a neighbour read from a stale cache line
+    would not."""
+    w = W.tet_cube(33, 6, E_range=(5e4, 5e5), n_iters=12, frames=2)
+    cfg = dict(lanes_per_vertex=8, block_size=block, xcd_remap=1, blocks_per_cu=bpc, tet_unroll=3)
+    say(f"33^3 cube, persistent block {block} blocks_per_cu {bpc} against plain launches")
+    xa, va, _ = gpu_rollout(w, w.frames, cfg=cfg, launch_mode=0)
+    for mode in (2, 3):
+        xb, vb, _ = gpu_rollout(w, w.frames, cfg=cfg, launch_mode=mode)
+        for f in range(w.frames):
+            assert np.array_equal(xa[f], xb[f]) and np.array_equal(va[f], vb[f]), f"mode {mode} frame {f}"
+
+
 @pytest.fixture(scope="module")
 def small_cube_oracle():
     w = W.config_small_cube()
