@@ -89,6 +89,20 @@ def test_adjoint_full_depth_small_cube_vs_oracle():
     compare("7^3 dL/dx0", gx, gxo)
 
 
+def test_adjoint_smallest_last_coloring_vs_oracle():
+    """The benchmarked coloring (greedy in smallest-last order: 4 colors, every
+    tet holds one vertex of each, so a reverse phase writes whole runs of one
+    cell array per receiving color) on a 9^3 cube through 10 frames x 20
+    iterations; the oracle colors the same way, bit for bit."""
+    w = W.config_differentiable(n=9, frames=10, coloring="smallest_last")
+    lo, gEo, gvo, gxo = oracle_grad(w)
+    lg, gE, gv, gx = gpu_grad(w)
+    assert lg == pytest.approx(lo, rel=1e-4)
+    compare("9^3 smallest-last dL/dE", gE, gEo)
+    compare("9^3 smallest-last dL/dv0", gv, gvo)
+    compare("9^3 smallest-last dL/dx0", gx, gxo)
+
+
 def _star(n_ring=40, seed=7):
     """A center vertex shared by 2 * n_ring tets (a ring in the xy plane and two
     apexes), so the color holding it has a padded tet degree above 64: its
