@@ -103,6 +103,32 @@ def test_adjoint_smallest_last_coloring_vs_oracle():
     compare("9^3 smallest-last dL/dx0", gx, gxo)
 
 
+def test_adjoint_single_iteration_vs_oracle():
+    """One iteration per step: the recorded forward seeds snapshot 1 and stores
+    no update into a next snapshot (5^3 cube, 4 frames)."""
+    w = W.config_differentiable(n=5, frames=4, n_iters=1)
+    lo, gEo, gvo, gxo = oracle_grad(w)
+    lg, gE, gv, gx = gpu_grad(w)
+    assert lg == pytest.approx(lo, rel=1e-4)
+    compare("5^3 one iteration dL/dE", gE, gEo)
+    compare("5^3 one iteration dL/dv0", gv, gvo)
+    compare("5^3 one iteration dL/dx0", gx, gxo)
+
+
+def test_adjoint_fully_pinned_mesh():
+    """Every vertex pinned: no color phase runs, the snapshots hold the pinned
+    positions only, and the gradient is the loss's own: dL/dx0 = dL/dx_T,
+    dL/dE = dL/dv0 = 0."""
+    w = W.config_differentiable(n=4, frames=2)
+    w = dataclasses.replace(w, pinned=np.ones_like(w.pinned), x0=w.rest.copy(), v0=np.zeros_like(w.v0))
+    lo, gEo, gvo, gxo = oracle_grad(w)
+    lg, gE, gv, gx = gpu_grad(w)
+    assert lg == pytest.approx(lo, rel=1e-5)
+    assert np.all(gE == 0.0) and np.all(gv == 0.0)
+    assert np.all(gEo == 0.0) and np.all(gvo == 0.0)
+    assert np.allclose(gx, gxo, rtol=1e-5, atol=1e-9)
+
+
 def _star(n_ring=40, seed=7):
     """A center vertex shared by 2 * n_ring tets (a ring in the xy plane and two
     apexes), so the color holding it has a padded tet degree above 64: its
