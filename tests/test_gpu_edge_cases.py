@@ -61,6 +61,29 @@ def test_single_tet_matches_oracle():
         assert_parity(w, xg, xo, label=f"single tet mode {mode}")
 
 
+def test_massless_isolated_vertices_are_skipped():
+    """A single tet plus three free vertices with no element and zero mass:
+    their local system is zero, the determinant rule skips them, so they keep
+    their initial guess (the adaptive one of Sec. 3.7), on both sides; the tet
+    matches the oracle."""
+    st = _single_tet()
+    iso = np.array([[0.5, 0.0, 0.0], [0.6, 0.1, 0.0], [0.7, 0.0, 0.2]])
+    rest = np.concatenate([st.rest, iso])
+    mass = O.lumped_mass(rest.shape[0], st.tets, O.tet_rest(st.tets, st.rest)[1], W.DENSITY)
+    mass[4:] = 0.0
+    rng = np.random.default_rng(21)
+    v0 = np.zeros_like(rest)
+    v0[4:] = rng.normal(scale=0.1, size=(3, 3))
+    w = dataclasses.replace(st, name="single tet + massless vertices", rest=rest,
+                            pinned=np.concatenate([st.pinned, np.zeros(3, np.uint8)]),
+                            x0=np.concatenate([st.x0, iso]), v0=v0, mass=mass, frames=3)
+    xo, _ = oracle_rollout(w, w.frames)
+    for mode in (0, 3):
+        xg, _, t = gpu_rollout(w, w.frames, launch_mode=mode)
+        assert_parity(w, xg, xo, label=f"massless vertices mode {mode}")
+        assert t.counters()["n_skips"] >= 3 * w.params.n_iters * w.frames
+
+
 def test_ragged_batch_matches_oracle():
     """A single tet, five isolated vertices (inertia only), a 2x3x4 and a 5x2x3
     lattice in one batch; masses given explicitly (isolated vertices have no
