@@ -64,6 +64,8 @@ def lib():
         L.oracle_detect_edges.restype = i32
         L.oracle_edge_element.argtypes = [p, p, d, d, p]
         L.oracle_edge_element.restype = d
+        L.oracle_edge_element_friction.argtypes = [p, p, p, d, d, d, d, d, p]
+        L.oracle_edge_element_friction.restype = d
         L.oracle_winding_number.restype = C.c_double
         _lib = L
     return _lib
@@ -329,12 +331,18 @@ def detect_edges(model: Model, params, x, xt=None):
     return ov[:n].copy(), on[:n].copy()
 
 
-def edge_element(x4, n, k, delta):
-    """(d, grad [4, 3]) of one edge-edge element at positions x4 [4, 3]."""
+def edge_element(x4, n, k, delta, xt4=None, mu=0.0, eps_v=0.0, h=0.0):
+    """(d, grad [4, 3]) of one edge-edge element at positions x4 [4, 3]; with
+    xt4 (positions at the start of the step) its friction is included."""
     x4 = np.ascontiguousarray(x4, np.float64).reshape(12)
     nn = np.ascontiguousarray(n, np.float64)
     g = np.zeros(12)
-    d = lib().oracle_edge_element(_ptr(x4), _ptr(nn), float(k), float(delta), _ptr(g))
+    if xt4 is None:
+        d = lib().oracle_edge_element(_ptr(x4), _ptr(nn), float(k), float(delta), _ptr(g))
+    else:
+        xt = np.ascontiguousarray(xt4, np.float64).reshape(12)
+        d = lib().oracle_edge_element_friction(_ptr(x4), _ptr(xt), _ptr(nn), float(k), float(delta),
+                                               float(mu), float(eps_v), float(h), _ptr(g))
     return d, g.reshape(4, 3)
 
 

@@ -1340,6 +1340,30 @@ double oracle_edge_element(const double x[12], const double n[3], double k, doub
     return d;
 }
 
+double oracle_edge_element_friction(const double x[12], const double xt[12], const double n[3], double k,
+                                    double delta, double mu, double eps_v, double h, double grad[12])
+{
+    oracle_params P;
+    memset(&P, 0, sizeof(P));
+    P.contact_k = k;
+    P.contact_thickness = delta;
+    P.friction_mu = mu;
+    P.friction_eps_v = eps_v;
+    P.h = h;
+    const double *xv[4] = {x, x + 3, x + 6, x + 9};
+    const double *xvt[4] = {xt, xt + 3, xt + 6, xt + 9};
+    double s, u, d = delta;
+    segment_closest_R(xv[0], xv[1], xv[2], xv[3], &s, &u);
+    for (int a = 0; a < 3; ++a)
+        d -= (xv[0][a] + s * (xv[1][a] - xv[0][a]) - xv[2][a] - u * (xv[3][a] - xv[2][a])) * n[a];
+    for (int role = 0; role < 4; ++role) {
+        double f[3] = {0, 0, 0}, H[3][3] = {{0}};
+        ee_contact(&P, xv, xvt, n, role, f, H);
+        for (int a = 0; a < 3; ++a) grad[3 * role + a] = -f[a];
+    }
+    return d;
+}
+
 double oracle_winding_number(const oracle_model *M, int32_t mesh, const double p[3], const double *x)
 {
     return winding_number(M, mesh, p, x);

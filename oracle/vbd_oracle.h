@@ -120,6 +120,12 @@ int32_t oracle_detect_edges(const oracle_model *M, const oracle_params *P, const
  * (the element is active when d > 0; grad is zero otherwise). */
 double oracle_edge_element(const double x[12], const double n[3], double k, double delta,
                            double grad[12]);
+/* The same element with its friction (Sec. 3.6): the relative displacement
+ * (x_a - x_a^t) - (x_b - x_b^t) from positions xt at the start of the step,
+ * friction coefficient mu, eps_v and time step h; grad[12] = the negated
+ * forces of penalty and friction (lambda = k d, s, u and n held fixed). */
+double oracle_edge_element_friction(const double x[12], const double xt[12], const double n[3], double k,
+                                    double delta, double mu, double eps_v, double h, double grad[12]);
 /* Generalized winding number of mesh `mesh`'s surface at p (positions x). */
 double oracle_winding_number(const oracle_model *M, int32_t mesh, const double p[3], const double *x);
 

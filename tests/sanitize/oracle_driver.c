@@ -99,6 +99,9 @@ int main(void)
     double s, u, g12[12], x12[12] = {0, 0, 0, 1, 0, 0, 0.5, -0.5, 0.001, 0.5, 0.5, 0.001}, nn[3] = {0, 0, -1};
     CHECK(oracle_segment_closest(x12, x12 + 3, x12 + 6, x12 + 9, &s, &u) >= 0.0);
     oracle_edge_element(x12, nn, 1e4, 5e-3, g12);
+    double xe12[12];
+    for (int i = 0; i < 12; ++i) xe12[i] = x12[i] - 1e-4 * (i % 3 == 0);
+    oracle_edge_element_friction(x12, xe12, nn, 1e4, 5e-3, 0.3, 1e-2, 1.0 / 60.0, g12);
     double p0[3] = {0.1, 0.1, 0.5};
     (void)oracle_winding_number(&M, 1, p0, x);
     /* energies, derivatives, predict */

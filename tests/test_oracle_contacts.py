@@ -238,6 +238,55 @@ def test_edge_element_gradient_and_momentum():
     assert d < 0.0 and not grad.any()
 
 
+def test_edge_friction_is_the_gradient_of_the_smoothed_friction_potential():
+    """Friction of one edge-edge element (Sec. 3.6, Eq. IPC_friction), with the
+    contact force lambda = k d, the closest-point parameters and n held fixed:
+    the friction forces on the four vertices are minus the gradient of
+    mu lambda f0(|u|), u the tangential part of (x_a - x_a^t) - (x_b - x_b^t)
+    and f0 the antiderivative of f1 (f0(y) = y above h eps_v and
+    -y^3 / (3 (h eps_v)^2) + y^2 / (h eps_v) + h eps_v / 3 below), checked by
+    central differences of that potential in the static and the sliding
+    regime; with the penalty, the four forces sum to zero."""
+    rng = np.random.default_rng(5)
+    k, delta, mu, eps_v, h = 1e4, 5e-3, 0.3, 1e-2, 1.0 / 60.0
+    ev = h * eps_v
+
+    def f0(y):
+        return y if y >= ev else -y ** 3 / (3 * ev ** 2) + y ** 2 / ev + ev / 3
+
+    for scale, regime in ((2e-5, "static"), (2e-3, "sliding")):
+        for _ in range(10):
+            x = np.array([[-0.1, 0.0, 0.0], [0.1, 0.0, 0.0], [0.0, -0.1, 0.002], [0.0, 0.1, 0.002]])
+            x = x + rng.normal(size=x.shape) * np.array([0.01, 0.01, 5e-4])
+            n = np.array([0.0, 0.0, -1.0])
+            disp = rng.normal(size=x.shape) * np.array([scale, scale, 0.1 * scale])
+            xt = x - disp
+            d, g_all = O.edge_element(x, n, k, delta, xt, mu, eps_v, h)
+            _, g_pen = O.edge_element(x, n, k, delta)
+            assert d > 0.0
+            _, s, u = O.segment_closest(*x)
+            lam = k * d
+            w = np.array([1.0 - s, s, -(1.0 - u), -u])   # weights of x_a - x_b
+
+            def potential(y):
+                dx = w @ (y - xt)
+                ut = dx - (dx @ n) * n
+                return mu * lam * f0(np.linalg.norm(ut))
+            ut0 = w @ disp
+            ut0 = ut0 - (ut0 @ n) * n
+            assert (np.linalg.norm(ut0) < ev) == (regime == "static")
+            fd = np.zeros_like(x)
+            step = 1e-9 if regime == "static" else 1e-7
+            for i in range(4):
+                for a in range(3):
+                    e = np.zeros_like(x)
+                    e[i, a] = step
+                    fd[i, a] = (potential(x + e) - potential(x - e)) / (2 * step)
+            g_fric = g_all - g_pen
+            assert np.abs(g_fric - fd).max() <= 1e-5 * np.abs(fd).max(), regime
+            assert np.abs(g_all.sum(0)).max() <= 1e-12 * np.abs(g_all).max()
+
+
 def test_crossed_bars_detect_one_edge_element():
     """Two cubes crossed edge on edge: at rest the detection finds exactly one
     edge-edge element, between the middle segments of the two edges, with the
