@@ -608,6 +608,16 @@ def extras(dev, W, Topology):
     res["cloth_persistent_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
     secs, upd = time_frames(tc, wc, MODES["graph"], 10, 3, dev)
     res["cloth_graph"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
+    # the whole drop (frames 0-119, plain launches: no graph capture inside the
+    # timed frames), and frames 30-39 alone, when the cloth drapes over the
+    # sphere with most of its contacts active
+    secs, upd = time_frames(tc, wc, MODES["plain"], wc.frames, 0, dev, autotune=False)
+    res["cloth_plain_all_frames"] = dict(updates_per_s=upd * wc.frames / secs,
+                                         ms_per_frame=secs / wc.frames * 1e3, frames=wc.frames)
+    secs, upd = time_frames(tc, wc, MODES["graph"], 10, 30, dev, autotune=False)
+    res["cloth_graph_frames_30_39"] = dict(updates_per_s=upd * 10 / secs, ms_per_frame=secs * 100)
+    log(f"[bench] cloth all {wc.frames} frames {res['cloth_plain_all_frames']['updates_per_s']:.3e}, "
+        f"frames 30-39 {res['cloth_graph_frames_30_39']['updates_per_s']:.3e} v-upd/s")
     roof = kernel_roofline(tc, wc, dev, frames=2)
     res["cloth_solve_kernel"] = dict(avg_launch_us=roof["avg_ms"] * 1e3,
                                      achieved_gbs=roof["achieved_gbs"],
