@@ -220,6 +220,32 @@ def test_large_cube_late_state_in_the_benchmarked_configuration():
                   label=f"65^3 after 60 frames, {t.launch_config}")
 
 
+def test_large_cube_ten_frame_prefix_vs_stored_oracle():
+    """The benchmarked workload (65^3, greedy coloring in smallest-last order,
+    100 iterations per frame) rolled out for 10 frames from x^0 on the GPU in
+    the launch configuration the benchmark picks (graph launches, 8 lanes,
+    block 64, 16-block XCD chunks, 2 compact records per lane) against the
+    stored FP64 oracle rollout of the same 10 frames
+    (tests/golden/cube65_prefix.npz, written from the oracle alone by
+    make_cube65_prefix.py): 4096 seeded free vertices within 1e-5 of the
+    bounding-box diagonal after every frame."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cube65_prefix.npz")
+    g = np.load(path)
+    w = W.config_large_cube(frames=10, coloring="smallest_last")
+    assert int(g["n_iters"]) == w.params.n_iters == 100
+    cfg = dict(lanes_per_vertex=8, block_size=64, xcd_remap=2, tet_unroll=2, compact_records=1)
+    xs, _, t = gpu_rollout(w, 10, launch_mode=N.LAUNCH_GRAPH, cfg=cfg)
+    assert t.n_colors == int(g["colors"])
+    idx = g["idx"]
+    worst = 0.0
+    for f in range(10):
+        e = np.linalg.norm(xs[f][idx] - g["x"][f], axis=1).max() / g["diag"][f]
+        say(f"65^3 prefix frame {f}: max bbox-relative error {e:.2e}")
+        worst = max(worst, e)
+        assert e <= 1e-5, f"frame {f}: {e:.3e}"
+    say(f"65^3 ten-frame prefix: worst {worst:.2e}")
+
+
 @pytest.mark.parametrize("coloring", ["smallest_last", "id"])
 def test_large_cube_full_depth_frames(coloring):
     """The benchmarked 65^3 workload at its full depth (Alg. 1 with n_max =
