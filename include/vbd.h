@@ -383,8 +383,12 @@ vbd_status vbd_autotune(vbd_topology topo, const vbd_step_params *params, const 
  * vbd_step_backward, vbd_detect_edges, vbd_detect_contacts and vbd_autotune
  * each open a ROCTx range named after the call for its whole duration (host
  * time: the enqueue, plus the synchronizations the call itself makes), seen
- * by tools that trace markers (rocprofv3 --marker-trace); vbd_step_static
- * opens none.  Without such a tool the ranges cost a function call each.
+ * by tools that trace markers (rocprofv3 --marker-trace); inside them, the
+ * plain launch sequence of a step opens "vbd iteration" and "vbd color phase"
+ * ranges (the backward's "vbd reverse iteration" and "vbd reverse color
+ * phase"), around the enqueue of each (a graph replays them without host
+ * work, a persistent launch has no host-side phases); vbd_step_static opens
+ * none.  Without such a tool the ranges cost a function call each.
  *
  * Timing of the hot kernel (hipEvents on the launch stream).  When enabled,
  * vbd_step runs its plain launch sequence and records one event pair around

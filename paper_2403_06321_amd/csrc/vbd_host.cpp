@@ -31,13 +31,23 @@ namespace {
 thread_local std::string g_err;
 
 // A named host-side range for tools that trace ROCTx markers (rocprofv3
-// --marker-trace): the entry points below open one for their whole call, so a
-// trace shows which API call enqueued which kernels.
+// --marker-trace): the entry points below open one for their whole call, and
+// a step's plain launch sequence one per iteration and per color phase, so a
+// trace shows which call, iteration and phase enqueued which kernels.
 struct Range {
-    explicit Range(const char *name) { roctxRangePushA(name); }
-    ~Range() { roctxRangePop(); }
+    explicit Range(const char *name, bool on = true) : on_(on)
+    {
+        if (on_) roctxRangePushA(name);
+    }
+    ~Range()
+    {
+        if (on_) roctxRangePop();
+    }
     Range(const Range &) = delete;
     Range &operator=(const Range &) = delete;
+
+private:
+    bool on_;
 };
 
 vbd_status fail(vbd_status s, const char *fmt, ...)
@@ -1022,11 +1032,13 @@ vbd_status enqueue_step(vbd_topology_s &T, const DevTopo &D, const vbd_step_para
             HIP_TRY(launch_detect(D, T.surf_dev, D.xt, K, s));
         }
         for (int it = 1; it <= p->n_iters; ++it) {
+            Range iteration("vbd iteration", profile);
             // Alg. 1: detection on the current iterate before iterations
             // 1, 1 + n_col, ... (n mod n_col = 1; the first on the initial guess)
             if (mc && p->n_col > 0 && (it - 1) % p->n_col == 0)
                 HIP_TRY(launch_detect(D, T.surf_dev, D.x, K, s));
             for (int c = 0; c < T.n_colors; ++c) {
+                Range phase("vbd color phase", profile);
                 if (mc) {
                     if (T.color_off[c + 1] > T.color_off[c]) {
                         HIP_TRY(launch_solve_contacts(D, T.surf_dev, K, T.color_off[c], T.color_off[c + 1],
@@ -1129,12 +1141,15 @@ vbd_status enqueue_record(vbd_topology_s &T, const vbd_step_params *p, const Ste
     // n and, as the start of iteration n + 1, into snapshot n + 1
     HIP_TRY(launch_seed_snapshots(D, p->n_iters, s));
     for (int it = 1; it <= p->n_iters; ++it) {
+        Range iteration("vbd iteration");
         float4 *Sn = T.dev.snaps + nv * it;
         D.x = Sn;
         D.xnext = it < p->n_iters ? Sn + nv : nullptr;
-        for (int c = 0; c < T.n_colors; ++c)
+        for (int c = 0; c < T.n_colors; ++c) {
+            Range phase("vbd color phase");
             HIP_TRY(launch_solve(D, K, T.color_off[c], T.color_off[c + 1], incidence(T, c), true, false, T.cfg, s,
                                  xcd_split(T, c)));
+        }
     }
     return VBD_OK;
 }
@@ -1186,8 +1201,10 @@ vbd_status enqueue_backward(vbd_topology_s &T, const vbd_step_params *p, const S
     LaunchCfg acfg = T.cfg;
     acfg.xcd_remap = 1;
     for (int it = p->n_iters; it >= 1; --it) {
+        Range iteration("vbd reverse iteration");
         const float4 *Sn = T.dev.snaps + nv * it, *Sp = Sn - nv;
         for (int c = T.n_colors - 1; c >= 0; --c) {
+            Range phase("vbd reverse color phase");
             HIP_TRY(launch_adjoint_color(D, K, Sn, Sp, T.color_off[c], T.color_off[c + 1], T.ell_info[c],
                                          acfg, s));
             if (T.color_off[c + 1] > T.color_off[c]) {
